@@ -1,0 +1,201 @@
+"""Row absorption into a boundary MPS by a left-to-right zip-up (oracle).
+
+The environment approximation compresses the bundle of ket, PEPO and bra
+legs (dim D w D) of each new row into a bond of dimension chi (Sec. 2); the
+bond is truncated with the randomized SVD of Sec. 4. Reading (the paper's
+own scheme is a variational fit, Fig. 3): sweep the row from left to right;
+at site x the implicit operator M_x (rows (c, dk, dw, db), columns
+(b, rk, rw, rb)) is factorised as M_x ~ U R with U an isometry, which becomes
+the new environment site, and R is carried to site x+1. R is divided by its
+Frobenius norm after every step and the last site is normalised; the
+logarithms of those norms are accumulated.
+"""
+from __future__ import annotations
+
+import math
+import numpy as np
+
+from workloads.tensor import Leg, Tensor
+from .blocks import BT, to_tensor
+from .chain import (SiteOperator, ORDERS, R_NAMES, trivial_remainder, sketch_arrays, flip)
+from .rsvd import sketch_widths, global_cut, orth
+
+
+def _row_keys(bt, ji, jpos):
+    return sorted(k for k in bt.blocks if k[jpos] == ji)
+
+
+def _assemble(bt, keys, width):
+    if not keys:
+        return np.zeros((0, width))
+    return np.vstack([bt.blocks[k].reshape(-1, width) for k in keys])
+
+
+class SiteProblem:
+    """Glue between SiteOperator (block tensors) and per-sector matrices."""
+
+    def __init__(self, op: SiteOperator):
+        self.op = op
+        self.sect = op.sectors()
+        legs = op.col_legs()
+        self.col_dims = [[op.col_dim(t) for t in tup] for _, tup in self.sect]
+        self.n = [int(sum(c)) for c in self.col_dims]
+        ys = op.apply(op.omega_bt(self.sect, [1] * len(self.sect)), symbolic=True)
+        self.row_keys = [_row_keys(ys, ji, 4) for ji in range(len(self.sect))]
+        self.row_dims = [[int(np.prod([ys.legs[n].dims[s] for n, s in zip(ys.names[:4], k[:4])]))
+                          for k in keys] for keys in self.row_keys]
+        self.m = [int(sum(r)) for r in self.row_dims]
+        self.y_legs = ys.legs
+
+    def omega_from_mats(self, mats):
+        kd = [m.shape[1] for m in mats]
+        arrs = []
+        for ji, M in enumerate(mats):
+            rows, r0 = [], 0
+            for nd in self.col_dims[ji]:
+                rows.append(M[r0:r0 + nd]); r0 += nd
+            arrs.append(rows)
+        bt = self.op.omega_bt(self.sect, kd, arrs)
+        return bt
+
+    def y_from_mats(self, mats):
+        kd = [m.shape[1] for m in mats]
+        jl = self.op.j_leg([J for J, _ in self.sect], kd)
+        legs = dict(self.y_legs); legs["j"] = jl
+        bt = BT(list(ORDERS[5]), legs, {})
+        for ji, M in enumerate(mats):
+            r0 = 0
+            for key, rd in zip(self.row_keys[ji], self.row_dims[ji]):
+                shp = tuple(int(legs[n].dims[s]) for n, s in zip(ORDERS[5][:4], key[:4])) + (kd[ji],)
+                bt.blocks[key[:4] + (ji,)] = M[r0:r0 + rd].reshape(shp)
+                r0 += rd
+        return bt
+
+    def apply_m(self, mats):
+        Y = self.op.apply(self.omega_from_mats(mats))
+        out = []
+        for ji in range(len(self.sect)):
+            k = mats[ji].shape[1]
+            blocks = []
+            for key, rd in zip(self.row_keys[ji], self.row_dims[ji]):
+                b = Y.blocks.get(key[:4] + (ji,))
+                blocks.append(np.zeros((rd, k)) if b is None else b.reshape(rd, k))
+            out.append(np.vstack(blocks) if blocks else np.zeros((0, k)))
+        return out
+
+    def apply_mt(self, mats):
+        Z = self.op.apply_t(self.y_from_mats(mats))
+        out = []
+        for ji, (J, tuples) in enumerate(self.sect):
+            k = mats[ji].shape[1]
+            blocks = []
+            for tup, nd in zip(tuples, self.col_dims[ji]):
+                b = Z.blocks.get(tuple(tup) + (ji,))
+                blocks.append(np.zeros((nd, k)) if b is None else b.reshape(nd, k))
+            out.append(np.vstack(blocks) if blocks else np.zeros((0, k)))
+        return out
+
+
+def _env_site(sp: SiteProblem, U_mats, kept, labels):
+    """New environment site [a, k, w, b', b] from the kept U of every sector."""
+    op = sp.op
+    sel = [ji for ji in range(len(kept)) if kept[ji] > 0]
+    jl = Leg(np.array([labels[ji] for ji in sel], dtype=np.int32).reshape(len(sel), -1),
+             np.array([kept[ji] for ji in sel], dtype=np.int32), -1)
+    legs = [op.R.legs["c"], op.ket.legs["dk"], op.W.legs["dw"], op.bra.legs["db"], jl]
+    keys, arrs = [], []
+    for newj, ji in enumerate(sel):
+        r0 = 0
+        for key, rd in zip(sp.row_keys[ji], sp.row_dims[ji]):
+            shp = tuple(int(legs[i].dims[s]) for i, s in enumerate(key[:4])) + (kept[ji],)
+            keys.append(tuple(key[:4]) + (newj,))
+            arrs.append(U_mats[ji][r0:r0 + rd].reshape(shp))
+            r0 += rd
+    legs = [Leg(l.labels, l.dims, d) for l, d in zip(legs, (1, -1, -1, 1, -1))]
+    order = sorted(range(len(keys)), key=lambda i: keys[i])
+    return Tensor.from_blocks(legs, [keys[i] for i in order], [arrs[i] for i in order]), sel
+
+
+def _remainder(sp: SiteProblem, R_mats, kept, labels, sel):
+    """R for the next site, names [c, a, lk, lw, lb]."""
+    op = sp.op
+    cl = Leg(np.array([labels[ji] for ji in sel], dtype=np.int32).reshape(len(sel), -1),
+             np.array([kept[ji] for ji in sel], dtype=np.int32), 1)
+    legs = {"c": cl, "a": op.T.legs["b"], "lk": op.ket.legs["rk"], "lw": op.W.legs["rw"],
+            "lb": op.bra.legs["rb"]}
+    bt = BT(list(R_NAMES), legs, {})
+    for newj, ji in enumerate(sel):
+        c0 = 0
+        for tup, nd in zip(sp.sect[ji][1], sp.col_dims[ji]):
+            shp = (kept[ji],) + tuple(int(l.dims[s]) for l, s in zip(op.col_legs(), tup))
+            bt.blocks[(newj,) + tuple(tup)] = R_mats[ji][:, c0:c0 + nd].reshape(shp)
+            c0 += nd
+    return bt
+
+
+def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0.0,
+               bra=None, record=None):
+    """Absorb one row (ket A[x], PEPO W[x]) into the top environment T[x].
+
+    Returns (new environment sites, log_norm, info). With ``exact_svd`` the
+    operator of every sector is formed explicitly and factorised by LAPACK
+    (truncated SVD), which bounds the error of the randomized version."""
+    L = len(T)
+    R = trivial_remainder(sym, T[0], A[0], W[0])
+    env, info = [], dict(sigma=[], kept=[], k=[], m=[], n=[], discarded=[], gap=[], nu=[])
+    for x in range(L):
+        op = SiteOperator(sym, R, T[x], A[x], W[x], bra=None if bra is None else bra[x])
+        sp = SiteProblem(op)
+        labels = [J for J, _ in sp.sect]
+        if x == L - 1:
+            assert sum(sp.n) == 1, "right boundary legs must have dim 1"
+            ji = next(i for i, nn in enumerate(sp.n) if nn == 1)
+            mats = [np.zeros((nn, 0)) for nn in sp.n]
+            mats[ji] = np.ones((1, 1))
+            Y = sp.apply_m(mats)
+            nu = math.sqrt(sum(float(np.sum(y * y)) for y in Y))
+            kept = [m.shape[1] for m in Y]
+            site, _ = _env_site(sp, [y / nu for y in Y], kept, labels)
+            env.append(site)
+            log_norm += math.log(nu)
+            info["nu"].append(nu)
+            break
+        if exact_svd:
+            S_, U_, B_ = [], [], []
+            for ji in range(len(sp.sect)):
+                Mf = sp.apply_m([np.eye(sp.n[i]) if i == ji else np.zeros((sp.n[i], 0))
+                                 for i in range(len(sp.sect))])[ji]
+                if Mf.size == 0:
+                    U_.append(np.zeros((Mf.shape[0], 0))); S_.append(np.zeros(0)); B_.append(Mf)
+                    continue
+                u, s, vt = np.linalg.svd(Mf, full_matrices=False)
+                U_.append(u); S_.append(s); B_.append(Mf)
+            kept, disc, gap = global_cut(S_, chi, labels)
+            Umats = [U_[i][:, :kept[i]] for i in range(len(kept))]
+            Rmats = [Umats[i].T @ B_[i] for i in range(len(kept))]
+            kvec = [len(s) for s in S_]
+        else:
+            kvec = sketch_widths(sp.m, sp.n, chi, p)
+            oms = sketch_arrays(sp.sect, kvec, sp.col_dims, seed, 0, x, row, 0)
+            omats = [np.vstack(o) if len(o) else np.zeros((0, kvec[i])) for i, o in enumerate(oms)]
+            Q, Ut, S_, Bm = _rsvd(sp, omats, q)
+            kept, disc, gap = global_cut(S_, chi, labels)
+            Umats = [Q[i] @ Ut[i][:, :kept[i]] for i in range(len(kept))]
+            Rmats = [Ut[i][:, :kept[i]].T @ Bm[i] for i in range(len(kept))]
+        site, sel = _env_site(sp, Umats, kept, labels)
+        env.append(site)
+        R = _remainder(sp, Rmats, kept, labels, sel)
+        nu = math.sqrt(R.norm2())
+        R.scale(1.0 / nu)
+        log_norm += math.log(nu)
+        for key, val in (("sigma", S_), ("kept", kept), ("k", kvec), ("m", sp.m), ("n", sp.n),
+                         ("discarded", disc), ("gap", gap), ("nu", nu)):
+            info[key].append(val)
+        if record is not None:
+            record.append(dict(x=x, sp=sp, kvec=kvec))
+    return env, log_norm, info
+
+
+def _rsvd(sp, omats, q):
+    from .rsvd import rsvd_sectors
+    return rsvd_sectors(sp.apply_m, sp.apply_mt, omats, q)

@@ -1,0 +1,130 @@
+"""Pins of the oracle's randomized SVD and CBE against LAPACK and the
+published error bounds (no GPU)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.rsvd import rsvd_explicit, sketch_widths, global_cut
+from oracle.cbe import cbe_explicit
+
+
+def prescribed(m, n, sigma, seed):
+    rng = np.random.default_rng(seed)
+    r = len(sigma)
+    U, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    return U @ np.diag(sigma) @ V.T, U, V
+
+
+def test_exact_recovery_when_sketch_covers_rank():
+    """rank <= k: sigma and the projector U U^T equal LAPACK's."""
+    mats, want = [], []
+    for i, (m, n, r) in enumerate([(60, 45, 7), (30, 80, 5), (20, 20, 3)]):
+        s = np.sort(np.random.default_rng(i).uniform(0.5, 3.0, r))[::-1]
+        a, u, _ = prescribed(m, n, s, 10 + i)
+        mats.append(a)
+        want.append((s, u))
+    out = rsvd_explicit(mats, chi=15, p=8, q=0, seed=4)
+    allsig = np.sort(np.concatenate([w[0] for w in want]))[::-1]
+    got = np.sort(np.concatenate(out["sigma"]))[::-1]
+    assert np.allclose(got, allsig, rtol=1e-12, atol=0)
+    for (s, u), U, R, a in zip(want, out["U"], out["R"], mats):
+        assert U.shape[1] == len(s)
+        assert np.abs(U @ U.T - u @ u.T).max() < 1e-12
+        assert np.abs(U.T @ U - np.eye(U.shape[1])).max() < 1e-13
+        assert np.abs(U @ R - a).max() < 1e-12 * np.abs(a).max()
+
+
+def test_global_cut_across_sectors_matches_lapack():
+    """Truncated to chi over several sectors = the chi largest singular
+    values of the block-diagonal matrix (LAPACK on the assembled matrix)."""
+    rng = np.random.default_rng(0)
+    mats = [rng.standard_normal((12, 9)), rng.standard_normal((7, 15)), rng.standard_normal((5, 5))]
+    out = rsvd_explicit(mats, chi=10, p=20, q=0, seed=1)
+    big = np.zeros((24, 29))
+    big[:12, :9] = mats[0]; big[12:19, 9:24] = mats[1]; big[19:, 24:] = mats[2]
+    s = np.linalg.svd(big, compute_uv=False)
+    assert np.allclose(np.sort(np.concatenate(out["sigma"]))[::-1], s[:10], rtol=1e-12)
+    assert sum(out["kept"]) == 10
+
+
+def halko_expected_bound(sig, k, p):
+    """Halko, Martinsson, Tropp (2011) Thm. 10.6: expected spectral error of
+    the Gaussian range finder with k + p samples."""
+    tail = np.sqrt(np.sum(sig[k:] ** 2))
+    return (1 + math.sqrt(k / (p - 1))) * sig[k] + math.e * math.sqrt(k + p) / p * tail
+
+
+def test_range_finder_error_within_halko_bound_and_power_iterations_help():
+    m, n, k, p = 300, 250, 20, 10
+    sig = 1.0 / (1.0 + np.arange(150)) ** 1.2
+    a, _, _ = prescribed(m, n, sig, 3)
+    bound = halko_expected_bound(sig, k, p)
+    errs = {0: [], 1: [], 2: []}
+    for seed in range(8):
+        for q in (0, 1, 2):
+            out = rsvd_explicit([a], chi=k + p, p=0, q=q, seed=seed)
+            U = out["U"][0]
+            errs[q].append(np.linalg.norm(a - U @ (U.T @ a), 2))
+    mean0 = np.mean(errs[0])
+    assert mean0 <= bound
+    assert min(errs[0]) >= sig[k + p] * (1 - 1e-12)           # Eckart-Young
+    assert np.mean(errs[2]) < np.mean(errs[1]) < mean0
+
+
+def test_truncated_error_not_below_optimal():
+    """Eckart-Young: the truncated rSVD can never beat the truncated SVD."""
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal((80, 70)) @ np.diag(0.9 ** np.arange(70)) @ rng.standard_normal((70, 70))
+    s = np.linalg.svd(a, compute_uv=False)
+    for q in (0, 1, 2):
+        out = rsvd_explicit([a], chi=10, p=5, q=q, seed=2)
+        err = np.linalg.norm(a - out["U"][0] @ out["R"][0])
+        assert err >= np.sqrt(np.sum(s[10:] ** 2)) * (1 - 1e-12)
+
+
+def test_sketch_widths_rule():
+    assert sketch_widths([100, 50, 0], [80, 200, 10], chi=30, p=4) == [24, 14, 0]
+    assert sketch_widths([3], [1000], chi=500, p=20) == [3]
+
+
+def test_global_cut_ties_and_counts():
+    kept, disc, gap = global_cut([np.array([3.0, 1.0]), np.array([3.0, 2.0])], 3, ["b", "a"])
+    assert kept == [1, 2]
+    assert disc == pytest.approx(1.0 / 23.0)
+    assert gap == pytest.approx(0.5)
+
+
+def test_cbe_invariants_and_split_equals_explicit_projectors():
+    rng = np.random.default_rng(7)
+    mats, U, V = [], [], []
+    for (m, n, r) in [(40, 35, 5), (25, 50, 4), (12, 9, 2)]:
+        mats.append(rng.standard_normal((m, n)))
+        U.append(np.linalg.qr(rng.standard_normal((m, r)))[0])
+        V.append(np.linalg.qr(rng.standard_normal((n, r)))[0].T)
+    a = cbe_explicit(mats, U, V, chi_extra=8, p=4, seed=3)
+    b = cbe_explicit(mats, U, V, chi_extra=8, p=4, seed=3, split=False)
+    assert sum(a["kept"]) == 8 and a["kept"] == b["kept"]
+    for qa, qb, u in zip(a["Q"], b["Q"], U):
+        if qa.shape[1] == 0:
+            continue
+        assert np.abs(qa.T @ u).max() < 1e-13
+        assert np.abs(qa.T @ qa - np.eye(qa.shape[1])).max() < 1e-13
+        assert np.abs(qa @ qa.T - qb @ qb.T).max() < 1e-12
+
+
+def test_cbe_spans_top_subspace_of_residual():
+    """With the sketch covering the residual's rank, the expansion is the top
+    left singular subspace of (1 - U U^T) M (1 - V^T V) (LAPACK)."""
+    rng = np.random.default_rng(9)
+    m, n, r = 30, 26, 3
+    M = rng.standard_normal((m, 8)) @ rng.standard_normal((8, n))
+    u = np.linalg.qr(rng.standard_normal((m, r)))[0]
+    v = np.linalg.qr(rng.standard_normal((n, r)))[0].T
+    res = (np.eye(m) - u @ u.T) @ M @ (np.eye(n) - v.T @ v)
+    out = cbe_explicit([M], [u], [v], chi_extra=4, p=10, seed=0)
+    Ur, s, _ = np.linalg.svd(res)
+    Q = out["Q"][0]
+    assert np.abs(Q @ Q.T - Ur[:, :4] @ Ur[:, :4].T).max() < 1e-10
+    assert np.allclose(out["sigma"][0], s[:4], rtol=1e-10)
