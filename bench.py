@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 row absorption: one interior row of the 8x8
+SU(2)-reduced synthetic workload (reduced D = 6, w = 4, d = 3, chi = 500,
+oversampling 20, two power iterations) absorbed into its boundary MPS with
+randomized-SVD truncation at every bond.
+
+A step is one full row absorption (8 sites: sketch, chain applications,
+orthonormalisation, projection, core factorisation, cut, new environment and
+remainder) on inputs resident in HBM. Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--config 4]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "row-absorb+rSVD TFLOP/s, 8x8 D=6 χ=500; mixed vs FP64 speedup @ ≤1e-6 rel err"
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.6}   # dense MFMA TFLOP/s, MI355X
+
+
+def workload(cfg):
+    import workloads as wl
+    if cfg == 4:
+        row = wl.config4_row()
+        desc = ("SU(2)-reduced synthetic 8x8 interior row: D=6 (2j 0,1,2 x 3,2,1), w=4, d=3, "
+                "chi=500 (env 2j<=6), p=20, q=2, fermionic signs, random blocks N(0,1)/sqrt(numel)")
+        bond = wl.legs_su2(500)["env"]
+    elif cfg == 2:
+        row = wl.config2_row()
+        desc = "dense 8x8 interior row, Hubbard comb PEPO w=6, d=4, D=6, chi=128, p=8, q=1"
+        bond = wl.legs_dense(4, 6, 6, 128)["env"]
+    elif cfg == 3:
+        row = wl.config3_row()
+        desc = "U(1)xU(1) 8x8 interior row, D=6 (5 sectors), w=6, d=4, chi=256 (15 sectors), p=8, q=1"
+        bond = wl.legs_u1u1(256)["env"]
+    else:
+        raise SystemExit(f"unknown config {cfg}")
+    return row, desc, bond
+
+
+def cpu_baseline(row, budget_s=20.0):
+    """The FP64 oracle on a bounded sample of the same workload: the chain
+    product M_x X at the first interior site (x = 1, remainder from the
+    oracle's own truncation of site 0 would need the full site; a random
+    remainder of the same structure is used) for a few sketch columns per
+    sector, repeated with more columns until ~budget_s of CPU work."""
+    import numpy as np
+    import workloads as wl
+    from workloads.tensor import Leg
+    from oracle.blocks import BT
+    from oracle.chain import SiteOperator
+    from oracle.zipup import SiteProblem
+    from oracle.flops import chain_flops
+    x = 1
+    rng = np.random.default_rng(0)
+    T, A, W = row.T[x], row.A[x], row.W[x]
+    env = T.legs[0]
+    legs = [Leg(env.labels, env.dims, 1), T.legs[0].flipped(), A.legs[1].flipped(),
+            W.legs[2].flipped(), A.legs[1]]
+    legs = [Leg(l.labels, l.dims, d) for l, d in zip(legs, (1, -1, -1, -1, 1))]
+    Rt = wl.random_tensor(row.sym, legs, rng)
+    names = ["c", "a", "lk", "lw", "lb"]
+    R = BT(names, dict(zip(names, Rt.legs)), Rt.to_dict())
+    sp = SiteProblem(SiteOperator(row.sym, R, T, A, W))
+    width, done, flops, secs = 1, False, 0.0, 0.0
+    while not done:
+        k = [width] * len(sp.sect)
+        X = [rng.standard_normal((n, width)) for n in sp.n]
+        t0 = time.perf_counter()
+        sp.apply_m(X)
+        dt = time.perf_counter() - t0
+        flops, secs = float(chain_flops(sp, k)), dt
+        if dt > budget_s / 3 or width >= 64:
+            done = True
+        else:
+            width *= 2
+    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    return {"value": flops / secs / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"one product M_x X at site 1 of the same row, {width} column(s) per sector "
+                      f"({len(sp.sect)} sectors), {flops:.3e} flops in {secs:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the row absorption runs on a single MI355X in this "
+              "build; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2511_01039_amd import Context, DeviceTensor, opts_for
+    from paper_2511_01039_amd.binding import FLAG_TIME_KERNELS
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    row, desc, bond = workload(a.config)
+    dev = lambda ts: [DeviceTensor.from_host(t) for t in ts]
+    T, A, W = dev(row.T), dev(row.A), dev(row.W)
+    ctx = Context(0)
+    opts = opts_for(row.sym, chi=row.chi, oversample=row.oversample, power_iters=row.power_iters,
+                    seed=0, row=row.row, precision=a.precision)
+    topts = opts_for(row.sym, chi=row.chi, oversample=row.oversample, power_iters=row.power_iters,
+                     seed=0, row=row.row, precision=a.precision, flags=FLAG_TIME_KERNELS)
+    caps = None
+    for i in range(a.warmup):
+        out, lg, rep = ctx.env_absorb(T, A, W, opts, caps=caps)
+        print(f"warmup {i}: {rep['seconds']:.3f} s device, {rep['alg_flops']:.4e} flops",
+              file=sys.stderr, flush=True)
+        caps = [(max(256, max(l.nsect for l in t.legs)), max(t.blocks.shape[0], 1), max(t.nelem, 1))
+                for t in out]
+    torch.cuda.synchronize()
+    flops, kt_s, kt_f, kt_n, dev_s = 0.0, 0.0, 0.0, 0, 0.0
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        out, lg, rep = ctx.env_absorb(T, A, W, topts, caps=caps)
+        flops += rep["alg_flops"]
+        kt_s += rep["kernel_seconds"]
+        kt_f += rep["kernel_flops"]
+        kt_n += rep["kernel_launches"]
+        dev_s += rep["seconds"]
+        print(f"step {i}: {rep['seconds']:.3f} s device", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = (t1 - t0) / a.steps
+    value = flops / a.steps / sec / 1e12
+    achieved = kt_f / kt_s / 1e12 if kt_s > 0 else 0.0
+    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+            "frac": achieved / PEAK["fp64"], "traffic": None,
+            "kernel": "k_gemm_f64 (chain block-pair GEMMs)",
+            "launches_per_step": kt_n / a.steps,
+            "avg_launch_ms": 1e3 * kt_s / max(kt_n, 1),
+            "flops_per_launch": kt_f / max(kt_n, 1)}
+    line = {"metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": desc, "lattice": "8x8", "chi": row.chi,
+                       "precision": a.precision, "alg_flops_per_step": flops / a.steps,
+                       "device_seconds_per_step": dev_s / a.steps},
+            "roofline": roof}
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(row)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

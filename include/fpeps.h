@@ -1,0 +1,232 @@
+/*
+ * fpeps.h -- C ABI of the MI355X (gfx950) library for the boundary-MPS row
+ * absorption of finite PEPS-PEPO networks (Scheb, "Improved contraction of
+ * finite projected entangled pair states", arXiv:2511.01039).
+ *
+ * What the calls compute
+ *   fpeps_env_absorb     one row (ket, PEPO, bra = ket) absorbed into a
+ *                        boundary MPS (Sec. 2: bundles of D w D legs are
+ *                        compressed to a bond chi), each bond truncated by
+ *                        the randomized SVD of Sec. 4 (Halko et al. 2011,
+ *                        Example 1.6), optionally expanded by controlled bond
+ *                        expansion (Sec. 4, Figs. 3-5).
+ *   fpeps_site_shape /   the implicit site operator M_x (the (chi D w D) x
+ *   fpeps_site_apply     (chi D w D) matrix A of Sec. 4, never formed) and its
+ *                        transpose applied to blocks of vectors; the chain of
+ *                        block-sparse contractions of Sec. 3.
+ *   fpeps_rsvd_truncate  randomized SVD of explicit matrices with one
+ *                        truncation over the whole batch (Sec. 4).
+ *   fpeps_cbe_expand     truncated complement (CBE) of explicit matrices:
+ *                        the most weighty directions of (1 - U U^T) A
+ *                        (1 - V^T V), projectors split as in Fig. 5(b)-(g).
+ *   fpeps_expect         network value of a top and a bottom environment
+ *                        (the sandwich of Fig. 1 once environments exist).
+ *
+ * Conventions (all calls)
+ *   - Tensor data is double precision, on the device of the context, owned
+ *     by the caller. Structure arrays (legs, blocks) are host memory owned
+ *     by the caller. The library never frees caller memory; it keeps only
+ *     its own workspace (device, grown on demand, freed by fpeps_destroy).
+ *   - Block-sparse layout: a tensor has nlegs legs; leg l has nsect[l]
+ *     sectors with nlab integer labels and a dimension each. A block is the
+ *     dense sub-array of one sector tuple, stored row-major (last leg
+ *     fastest) at data[block_off[i]]. Blocks may appear in any order but must
+ *     not overlap.
+ *   - Leg orders: ket A[p, l, r, u, d]; PEPO W[q, p, l, r, u, d] (q bra-side,
+ *     p ket-side physical leg); environment site T[a, k, w, b', b] (left bond,
+ *     the downward ket, PEPO and bra legs, right bond). A bottom environment
+ *     uses the same order with the bundle legs facing up.
+ *   - Symmetry: FPEPS_SYM_NONE (any sector tuple may be present),
+ *     FPEPS_SYM_U1U1 (labels (dn, 2Sz); flux sum_l dir_l q_l = 0),
+ *     FPEPS_SYM_SU2 (labels (2j); synthetic reduced tensors whose block
+ *     pairs carry a recoupling scalar, see fpeps_opts.coef_seed).
+ *   - Asynchrony: calls run on the context's HIP stream. Calls that return
+ *     host values (reports, kept counts, fpeps_expect) synchronise it.
+ *   - Errors: every call returns fpeps_status; no exception or abort crosses
+ *     the ABI. fpeps_last_error(ctx) returns a message for the last failure.
+ *     On error, output buffers hold unspecified values.
+ */
+#ifndef FPEPS_H
+#define FPEPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fpeps_ctx_s* fpeps_ctx;
+
+typedef enum {
+  FPEPS_OK = 0,
+  FPEPS_ERR_ARG = -1,         /* null pointer, bad enum, negative size */
+  FPEPS_ERR_SHAPE = -2,       /* legs that must match do not, bad block */
+  FPEPS_ERR_SYMMETRY = -3,    /* block violating the symmetry rule */
+  FPEPS_ERR_NOMEM = -4,       /* device allocation failed */
+  FPEPS_ERR_HIP = -5,         /* a HIP runtime call failed */
+  FPEPS_ERR_NUMERIC = -6,     /* NaN / Inf met, or a factorisation broke down */
+  FPEPS_ERR_CAPACITY = -7,    /* an output buffer is too small; see report */
+  FPEPS_ERR_UNSUPPORTED = -8, /* valid request this build does not do */
+  FPEPS_ERR_NODEVICE = -9     /* no usable gfx950 device */
+} fpeps_status;
+
+typedef enum {
+  FPEPS_FP64 = 0,     /* every product in double precision */
+  FPEPS_FP32 = 1,     /* bulk chain products on FP32 MFMA, FP32 accumulate */
+  FPEPS_BF16X3 = 2    /* bulk chain products as three BF16 MFMA passes */
+} fpeps_precision;
+
+typedef enum {
+  FPEPS_SYM_NONE = 0,
+  FPEPS_SYM_U1U1 = 1,
+  FPEPS_SYM_SU2 = 2
+} fpeps_symmetry;
+
+/* Block-sparse tensor (input and output).
+ * Input: the library reads every field except the capacities.
+ * Output: the caller sets the capacities and the array pointers; the library
+ * fills nlegs, nsect, dirs, labels, dims, nblocks, block_sect, block_off,
+ * nelem and data. If a capacity is too small the call fails with
+ * FPEPS_ERR_CAPACITY and the report (when given) holds the required sizes. */
+typedef struct {
+  int32_t nlegs;
+  int32_t nlab;          /* labels per sector (1 or 2) */
+  int32_t max_sect;      /* row stride of labels/dims: sectors per leg */
+  int32_t* nsect;        /* host [nlegs] */
+  int32_t* dirs;         /* host [nlegs], +1 or -1 */
+  int32_t* labels;       /* host [nlegs * max_sect * nlab]; leg l, sector s at (l*max_sect+s)*nlab */
+  int32_t* dims;         /* host [nlegs * max_sect] */
+  int32_t nblocks;
+  int32_t max_blocks;    /* output capacity (blocks) */
+  int32_t* block_sect;   /* host [nblocks * nlegs] (capacity max_blocks * nlegs) */
+  int64_t* block_off;    /* host [nblocks] element offsets into data */
+  double* data;          /* device */
+  int64_t nelem;         /* elements used */
+  int64_t max_elem;      /* output capacity (elements) */
+} fpeps_tensor;
+
+typedef struct {
+  int32_t chi;            /* bond kept after truncation (multiplets for SU(2)) */
+  int32_t oversample;     /* p: sketch width k_J = min(m_J, n_J, ceil(chi m_J / sum m) + p) */
+  int32_t power_iters;    /* q: subspace iterations */
+  int32_t cbe_extra;      /* directions added by CBE per bond (0: none) */
+  uint64_t seed;          /* Philox4x32-10 key of the Gaussian sketch */
+  int32_t row;            /* row index, part of the sketch counter */
+  int32_t precision;      /* fpeps_precision */
+  int32_t symmetry;       /* fpeps_symmetry */
+  int32_t fermionic;      /* 1: parity sign on every contracted block pair */
+  uint64_t coef_seed;     /* SU(2): key of the synthetic recoupling scalars */
+  int64_t slice_budget;   /* bytes for chain intermediates per slice (0: automatic) */
+  uint32_t flags;         /* FPEPS_FLAG_* */
+  int32_t tag;            /* explicit-matrix calls: counter word c2 of the sketch */
+  double sv_cut;          /* singular values <= sv_cut * largest are never kept
+                             (numerically zero; no defined vectors). <= 0: 1e-7 */
+} fpeps_opts;
+
+#define FPEPS_FLAG_NO_GRAPH 1u      /* do not capture per-site launch sequences */
+#define FPEPS_FLAG_CHECK_FINITE 2u  /* scan inputs for NaN/Inf first */
+#define FPEPS_FLAG_TIME_KERNELS 4u  /* time every chain GEMM launch with HIP events */
+
+typedef struct {
+  double alg_flops;        /* algorithmic flop count (block-pair GEMMs + factorisations) */
+  double seconds;          /* device time of the call (HIP events) */
+  double discarded_weight; /* largest per-site sum(s^2 cut)/sum(s^2) */
+  double min_rel_gap;      /* smallest (s_kept_last - s_cut_first)/s_kept_last */
+  double log_norm;         /* sum of log of the norms divided out */
+  double peak_workspace;   /* bytes of chain intermediates (largest slice) */
+  int32_t kept_total;      /* sum of kept values over sites / matrices */
+  int32_t nslices;         /* chain slices used (largest site) */
+  uint32_t fallbacks;      /* bit 0: orthonormalisation used the shifted pass */
+  int32_t required_blocks; /* on FPEPS_ERR_CAPACITY: blocks needed */
+  int64_t required_elem;   /* on FPEPS_ERR_CAPACITY: elements needed */
+  int32_t required_sect;   /* on FPEPS_ERR_CAPACITY: sectors per leg needed */
+  int32_t kernel_launches; /* FPEPS_FLAG_TIME_KERNELS: chain GEMM launches timed */
+  double kernel_seconds;   /* FPEPS_FLAG_TIME_KERNELS: sum of their durations (HIP events) */
+  double kernel_flops;     /* algorithmic flops (2 m n k over block pairs) of those launches */
+} fpeps_report;
+
+/* Context: one per host thread. ``stream`` is a hipStream_t (NULL: default
+ * stream). Fails with FPEPS_ERR_NODEVICE when ``device`` is not a gfx950. */
+fpeps_status fpeps_create(fpeps_ctx* out, int32_t device, void* stream);
+fpeps_status fpeps_destroy(fpeps_ctx ctx);
+fpeps_status fpeps_set_stream(fpeps_ctx ctx, void* stream);
+const char* fpeps_last_error(fpeps_ctx ctx);
+const char* fpeps_version(void);
+
+/* Absorb one row of L sites into the top environment env_in[0..L-1].
+ * ket[x] (5 legs) and pepo[x] (6 legs) are the row tensors; the bra is the
+ * ket. env_out[x] receives the new environment sites (5 legs, layout above):
+ * sites 0..L-2 are isometries over (a, k, w, b') and site L-1 has unit norm.
+ * *log_norm (host, in/out) is increased by the logarithm of the norms that
+ * were divided out. Left and right boundary legs must have dimension 1.
+ * Synchronises the stream once per site (the kept sector sizes decide the
+ * next site's shapes). */
+fpeps_status fpeps_env_absorb(fpeps_ctx ctx, int32_t L, const fpeps_tensor* env_in,
+                              const fpeps_tensor* ket, const fpeps_tensor* pepo,
+                              const fpeps_opts* opts, fpeps_tensor* env_out,
+                              double* log_norm, fpeps_report* report);
+
+/* Per-site diagnostics of the last fpeps_env_absorb on this context:
+ * the singular values of every sector (sectors in label order, each
+ * descending), the sector of each value and the kept count per sector. */
+fpeps_status fpeps_absorb_diag(fpeps_ctx ctx, int32_t site, int32_t capacity, double* sigma,
+                               int32_t* sector, int32_t* count, int32_t* nsectors,
+                               int32_t* kept /* [capacity] per sector */);
+
+/* Sector structure of the site operator M_x with remainder R (legs
+ * [c, a, lk, lw, lb]), environment site T, ket A and PEPO W.
+ * nsect (out): number of sketch sectors J (label order). For each J:
+ * labels [nsect * nlab], m[J] (rows), n[J] (columns). Arrays have
+ * ``capacity`` entries. */
+fpeps_status fpeps_site_shape(fpeps_ctx ctx, const fpeps_tensor* R, const fpeps_tensor* T,
+                              const fpeps_tensor* A, const fpeps_tensor* W,
+                              const fpeps_opts* opts, int32_t capacity, int32_t* nsect,
+                              int32_t* labels, int64_t* m, int64_t* n);
+
+/* Apply M_x (transpose = 0) or M_x^T (transpose = 1) to per-sector blocks
+ * of k[J] vectors. x_in holds, for each sector J in order, the n[J] x k[J]
+ * (M) or m[J] x k[J] (M^T) row-major matrix; y_out receives m[J] x k[J]
+ * (or n[J] x k[J]). Rows follow the canonical order: sector tuples of the
+ * row legs (c, dk, dw, db) or column legs (b, rk, rw, rb) in lexicographic
+ * order of sector indices, row-major inside a tuple. Device pointers. */
+fpeps_status fpeps_site_apply(fpeps_ctx ctx, const fpeps_tensor* R, const fpeps_tensor* T,
+                              const fpeps_tensor* A, const fpeps_tensor* W,
+                              const fpeps_opts* opts, int32_t transpose, const int32_t* k,
+                              const double* x_in, double* y_out, fpeps_report* report);
+
+/* Randomized SVD of nmat explicit row-major matrices A_i (m_i x n_i, device),
+ * one truncation to opts->chi over the batch. Sketch of matrix i: Philox
+ * counter (element/2, i, opts->tag, 0). Outputs (device): U_i (m_i x kept_i,
+ * row-major, capacity m_i * min(m_i, n_i)), R_i = S V^T (kept_i x n_i,
+ * capacity min(m_i, n_i) * n_i). Host outputs: kept[nmat]; sigma (kept values
+ * of matrix 0, then 1, ...; capacity sum min(m_i, n_i)). */
+fpeps_status fpeps_rsvd_truncate(fpeps_ctx ctx, int32_t nmat, const int64_t* m,
+                                 const int64_t* n, const double* const* A,
+                                 const fpeps_opts* opts, double* const* U_out,
+                                 double* const* R_out, int32_t* kept, double* sigma,
+                                 fpeps_report* report);
+
+/* Controlled bond expansion of explicit matrices: for each A_i (m_i x n_i)
+ * with kept left space U_i (m_i x r_i, orthonormal columns) and kept right
+ * space V_i (r_i x n_i, orthonormal rows), the opts->cbe_extra most weighty
+ * directions (over the batch) of (1 - U U^T) A (1 - V^T V). Sketch of matrix
+ * i: Philox counter (element/2, i, opts->tag, 1 << 16). Output Q_i (device,
+ * m_i x e_i row-major, orthogonal to U_i; capacity m_i * min(m_i, n_i)),
+ * e_i in kept[i] (host), the matching singular values in sigma (host). */
+fpeps_status fpeps_cbe_expand(fpeps_ctx ctx, int32_t nmat, const int64_t* m, const int64_t* n,
+                              const double* const* A, const int32_t* r,
+                              const double* const* U, const double* const* V,
+                              const fpeps_opts* opts, double* const* Q_out, int32_t* kept,
+                              double* sigma, fpeps_report* report);
+
+/* Network value of a top environment (L sites) and a bottom environment
+ * whose bundle legs (k, w, b') match the top's: the contraction of all
+ * sites, left and right bonds of dimension 1 at the ends. Log-norms are not
+ * applied. *value is a host double. */
+fpeps_status fpeps_expect(fpeps_ctx ctx, int32_t L, const fpeps_tensor* top,
+                          const fpeps_tensor* bottom, double* value);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FPEPS_H */

@@ -20,7 +20,7 @@ from __future__ import annotations
 import numpy as np
 
 from .rng import gaussian_matrix
-from .rsvd import sketch_widths, global_cut, orth
+from .rsvd import sketch_widths, global_cut, orth, SV_CUT
 
 
 def residual_widths(mats, U, V, chi_extra, p):
@@ -29,7 +29,8 @@ def residual_widths(mats, U, V, chi_extra, p):
     return sketch_widths([max(x, 0) for x in m], [max(x, 0) for x in n], chi_extra, p)
 
 
-def cbe_explicit(mats, U, V, chi_extra, p, seed, tag=0, stream=1, split=True, q=0):
+def cbe_explicit(mats, U, V, chi_extra, p, seed, tag=0, stream=1, split=True, q=0,
+                 sv_cut=SV_CUT):
     """Truncated complement of every matrix; one global cut of size
     ``chi_extra``. Returns dict with Q (m_i x e_i, orthogonal to U_i),
     sigma of the kept complement directions, and counts."""
@@ -55,8 +56,10 @@ def cbe_explicit(mats, U, V, chi_extra, p, seed, tag=0, stream=1, split=True, q=
         else:
             Ut, s = np.zeros((0, 0)), np.zeros(0)
         Q_.append(Q); Ut_.append(Ut); S_.append(s)
-    kept, disc, gap = global_cut(S_, chi_extra)
+    kept, disc, gap = global_cut(S_, chi_extra, sv_cut=sv_cut)
+    from .zipup import fix_signs
     for i in range(len(mats)):
-        out_Q.append(Q_[i] @ Ut_[i][:, :kept[i]])
+        q = Q_[i] @ Ut_[i][:, :kept[i]]
+        out_Q.append(fix_signs(q, np.zeros((q.shape[1], 0)))[0])
     return dict(Q=out_Q, sigma=[S_[i][:kept[i]] for i in range(len(mats))], kept=kept, k=k,
                 gap=gap)

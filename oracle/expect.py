@@ -55,7 +55,8 @@ def closing_env(env):
     return out
 
 
-def network_value(sym, lattice_A, lattice_W, chi, p, q, seed, exact_svd=False, bra=None):
+def network_value(sym, lattice_A, lattice_W, chi, p, q, seed, exact_svd=False, bra=None,
+                  sv_cut=None):
     """Top-to-bottom contraction of the whole lattice. Returns (sign, log|Z|,
     info per row)."""
     from .zipup import absorb_row
@@ -65,9 +66,10 @@ def network_value(sym, lattice_A, lattice_W, chi, p, q, seed, exact_svd=False, b
     lg = 0.0
     infos = []
     for y in range(Ly):
+        kw = {} if sv_cut is None else dict(sv_cut=sv_cut)
         env, lg, info = absorb_row(sym, env, lattice_A[y], lattice_W[y], chi, p, q, seed, row=y,
                                    exact_svd=exact_svd, log_norm=lg,
-                                   bra=None if bra is None else bra[y])
+                                   bra=None if bra is None else bra[y], **kw)
         infos.append(info)
     v = overlap(env, closing_env(env))
     if v == 0.0:

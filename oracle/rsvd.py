@@ -27,18 +27,25 @@ def sketch_widths(m, n, chi, p):
     return out
 
 
-def global_cut(sigmas, chi, sector_keys=None):
-    """Keep the min(chi, total) largest values over all sectors. Ties are
-    broken by sector key (lexicographic), then by in-sector position.
-    Returns kept counts per sector, the discarded weight sum(s^2 cut) /
-    sum(s^2) and the relative gap (s_last_kept - s_first_cut)/s_last_kept."""
+SV_CUT = 1e-7
+
+
+def global_cut(sigmas, chi, sector_keys=None, sv_cut=SV_CUT):
+    """Keep the min(chi, total) largest values over all sectors, never one
+    below sv_cut times the largest (numerically zero singular values have no
+    defined vectors). Ties are broken by sector key (lexicographic), then by
+    in-sector position. Returns kept counts per sector, the discarded weight
+    sum(s^2 cut) / sum(s^2) and the relative gap
+    (s_last_kept - s_first_cut)/s_last_kept."""
     keys = sector_keys if sector_keys is not None else list(range(len(sigmas)))
     allv = []
     for si, s in enumerate(sigmas):
         for i, v in enumerate(s):
             allv.append((-float(v), keys[si], i, si))
     allv.sort()
-    nkeep = min(chi, len(allv))
+    smax = -allv[0][0] if allv else 0.0
+    above = sum(1 for v in allv if -v[0] > sv_cut * smax)
+    nkeep = min(chi, above)
     kept = [0] * len(sigmas)
     for e in allv[:nkeep]:
         kept[e[3]] += 1
@@ -82,7 +89,7 @@ def rsvd_sectors(apply_m, apply_mt, omegas, q):
     return Q, Us, Ss, Bs
 
 
-def rsvd_explicit(mats, chi, p, q, seed, tag=0, stream=0):
+def rsvd_explicit(mats, chi, p, q, seed, tag=0, stream=0, sv_cut=SV_CUT):
     """Batched rSVD of explicit matrices with one global cut (the
     ``fpeps_rsvd_truncate`` contract). Omega_i uses the counter stream
     (seed; c1 = i, c2 = tag, c3 = stream << 16)."""
@@ -93,8 +100,10 @@ def rsvd_explicit(mats, chi, p, q, seed, tag=0, stream=0):
     oms = [gaussian_matrix(seed, i, tag, (stream << 16), n[i], k[i]) for i in range(len(mats))]
     Q, Ut, S, B = rsvd_sectors(lambda X: [a @ x for a, x in zip(mats, X)],
                                lambda X: [a.T @ x for a, x in zip(mats, X)], oms, q)
-    kept, disc, gap = global_cut(S, chi)
-    U = [Q[i] @ Ut[i][:, :kept[i]] for i in range(len(mats))]
-    R = [Ut[i][:, :kept[i]].T @ B[i] for i in range(len(mats))]
+    kept, disc, gap = global_cut(S, chi, sv_cut=sv_cut)
+    from .zipup import fix_signs
+    UR = [fix_signs(Q[i] @ Ut[i][:, :kept[i]], Ut[i][:, :kept[i]].T @ B[i]) for i in range(len(mats))]
+    U = [u for u, _ in UR]
+    R = [r for _, r in UR]
     sig = [S[i][:kept[i]] for i in range(len(mats))]
     return dict(U=U, R=R, sigma=sig, sigma_all=S, kept=kept, k=k, discarded=disc, gap=gap)

@@ -18,7 +18,32 @@ import numpy as np
 from workloads.tensor import Leg, Tensor
 from .blocks import BT, to_tensor
 from .chain import (SiteOperator, ORDERS, R_NAMES, trivial_remainder, sketch_arrays, flip)
-from .rsvd import sketch_widths, global_cut, orth
+from .rsvd import sketch_widths, global_cut, orth, SV_CUT
+
+
+SIGN_TIE = 1e-10
+
+
+def fix_signs(U, R):
+    """Canonical gauge of a truncated factorisation U R: every column of U is
+    flipped (with the matching row of R) so that its leading entry is
+    positive, the leading entry being the first (in row order) whose
+    magnitude is within a relative 1e-10 of the column's largest. The
+    singular vectors of an SVD are unique only up to these signs; fixing them
+    makes the environment, and with it the sketch of the next row,
+    independent of the SVD routine. The tolerance matters when a symmetry
+    (the ket-bra exchange of <psi|W|psi> with a symmetric W) makes entries
+    of equal magnitude."""
+    U, R = U.copy(), R.copy()
+    for c in range(U.shape[1]):
+        a = np.abs(U[:, c])
+        if a.size == 0:
+            continue
+        i = int(np.nonzero(a >= a.max() * (1.0 - SIGN_TIE))[0][0])
+        if U[i, c] < 0:
+            U[:, c] *= -1.0
+            R[c, :] *= -1.0
+    return U, R
 
 
 def _row_keys(bt, ji, jpos):
@@ -32,10 +57,15 @@ def _assemble(bt, keys, width):
 
 
 class SiteProblem:
-    """Glue between SiteOperator (block tensors) and per-sector matrices."""
+    """Glue between SiteOperator (block tensors) and per-sector matrices.
 
-    def __init__(self, op: SiteOperator):
+    ``max_cols`` (optional) applies the operator to at most that many columns
+    of every sector at a time: the operator acts on each column on its own,
+    so this only bounds the memory of the intermediates."""
+
+    def __init__(self, op: SiteOperator, max_cols=None):
         self.op = op
+        self.max_cols = max_cols
         self.sect = op.sectors()
         legs = op.col_legs()
         self.col_dims = [[op.col_dim(t) for t in tup] for _, tup in self.sect]
@@ -71,7 +101,23 @@ class SiteProblem:
                 r0 += rd
         return bt
 
+    def _chunked(self, fn, mats, rows_out):
+        kmax = max([m.shape[1] for m in mats] + [0])
+        if not self.max_cols or kmax <= self.max_cols:
+            return fn(mats)
+        parts = []
+        for c0 in range(0, kmax, self.max_cols):
+            parts.append(fn([m[:, c0:c0 + self.max_cols] for m in mats]))
+        return [np.hstack([p[i] for p in parts]) if parts else np.zeros((rows_out[i], 0))
+                for i in range(len(mats))]
+
     def apply_m(self, mats):
+        return self._chunked(self._apply_m, mats, self.m)
+
+    def apply_mt(self, mats):
+        return self._chunked(self._apply_mt, mats, self.n)
+
+    def _apply_m(self, mats):
         Y = self.op.apply(self.omega_from_mats(mats))
         out = []
         for ji in range(len(self.sect)):
@@ -83,7 +129,7 @@ class SiteProblem:
             out.append(np.vstack(blocks) if blocks else np.zeros((0, k)))
         return out
 
-    def apply_mt(self, mats):
+    def _apply_mt(self, mats):
         Z = self.op.apply_t(self.y_from_mats(mats))
         out = []
         for ji, (J, tuples) in enumerate(self.sect):
@@ -134,7 +180,7 @@ def _remainder(sp: SiteProblem, R_mats, kept, labels, sel):
 
 
 def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0.0,
-               bra=None, record=None):
+               bra=None, record=None, max_cols=None, progress=None, sv_cut=SV_CUT):
     """Absorb one row (ket A[x], PEPO W[x]) into the top environment T[x].
 
     Returns (new environment sites, log_norm, info). With ``exact_svd`` the
@@ -145,7 +191,9 @@ def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0
     env, info = [], dict(sigma=[], kept=[], k=[], m=[], n=[], discarded=[], gap=[], nu=[])
     for x in range(L):
         op = SiteOperator(sym, R, T[x], A[x], W[x], bra=None if bra is None else bra[x])
-        sp = SiteProblem(op)
+        sp = SiteProblem(op, max_cols)
+        if progress:
+            progress(f"site {x}: sectors {len(sp.sect)} m {sum(sp.m)} n {sum(sp.n)}")
         labels = [J for J, _ in sp.sect]
         if x == L - 1:
             assert sum(sp.n) == 1, "right boundary legs must have dim 1"
@@ -170,7 +218,7 @@ def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0
                     continue
                 u, s, vt = np.linalg.svd(Mf, full_matrices=False)
                 U_.append(u); S_.append(s); B_.append(Mf)
-            kept, disc, gap = global_cut(S_, chi, labels)
+            kept, disc, gap = global_cut(S_, chi, labels, sv_cut=sv_cut)
             Umats = [U_[i][:, :kept[i]] for i in range(len(kept))]
             Rmats = [Umats[i].T @ B_[i] for i in range(len(kept))]
             kvec = [len(s) for s in S_]
@@ -179,9 +227,12 @@ def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0
             oms = sketch_arrays(sp.sect, kvec, sp.col_dims, seed, 0, x, row, 0)
             omats = [np.vstack(o) if len(o) else np.zeros((0, kvec[i])) for i, o in enumerate(oms)]
             Q, Ut, S_, Bm = _rsvd(sp, omats, q)
-            kept, disc, gap = global_cut(S_, chi, labels)
+            kept, disc, gap = global_cut(S_, chi, labels, sv_cut=sv_cut)
             Umats = [Q[i] @ Ut[i][:, :kept[i]] for i in range(len(kept))]
             Rmats = [Ut[i][:, :kept[i]].T @ Bm[i] for i in range(len(kept))]
+        fixed = [fix_signs(u, r) for u, r in zip(Umats, Rmats)]
+        Umats = [f[0] for f in fixed]
+        Rmats = [f[1] for f in fixed]
         site, sel = _env_site(sp, Umats, kept, labels)
         env.append(site)
         R = _remainder(sp, Rmats, kept, labels, sel)

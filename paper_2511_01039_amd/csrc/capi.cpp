@@ -1,0 +1,196 @@
+// extern "C" entry points (include/fpeps.h). No exception crosses the ABI.
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "driver.hpp"
+
+namespace {
+
+fpeps_status finish(fpeps_ctx ctx, const fp::Status& s) {
+  if (ctx) ctx->err = s.good() ? std::string() : s.msg;
+  return s.code;
+}
+
+template <class F>
+fpeps_status guarded(fpeps_ctx ctx, F&& f) {
+  if (!ctx) return FPEPS_ERR_ARG;
+  try {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return finish(ctx, fp::fail(FPEPS_ERR_HIP, hipGetErrorString(e)));
+    return finish(ctx, f());
+  } catch (const std::bad_alloc&) {
+    return finish(ctx, fp::fail(FPEPS_ERR_NOMEM, "host allocation failed"));
+  } catch (const std::exception& ex) {
+    return finish(ctx, fp::fail(FPEPS_ERR_ARG, std::string("internal error: ") + ex.what()));
+  } catch (...) {
+    return finish(ctx, fp::fail(FPEPS_ERR_ARG, "internal error"));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fpeps_version(void) { return "fpeps-gfx950 0.1 (fp64)"; }
+
+fpeps_status fpeps_create(fpeps_ctx* out, int32_t device, void* stream) {
+  if (!out) return FPEPS_ERR_ARG;
+  *out = nullptr;
+  try {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+      (void)hipGetLastError();
+      return FPEPS_ERR_NODEVICE;
+    }
+    if (device < 0 || device >= n) return FPEPS_ERR_NODEVICE;
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return FPEPS_ERR_NODEVICE;
+    if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) return FPEPS_ERR_NODEVICE;
+    if (hipSetDevice(device) != hipSuccess) return FPEPS_ERR_HIP;
+    fpeps_ctx c = new fpeps_ctx_s();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    *out = c;
+    return FPEPS_OK;
+  } catch (...) {
+    return FPEPS_ERR_NOMEM;
+  }
+}
+
+fpeps_status fpeps_destroy(fpeps_ctx ctx) {
+  if (!ctx) return FPEPS_ERR_ARG;
+  (void)hipSetDevice(ctx->device);
+  delete ctx;
+  return FPEPS_OK;
+}
+
+fpeps_status fpeps_set_stream(fpeps_ctx ctx, void* stream) {
+  if (!ctx) return FPEPS_ERR_ARG;
+  ctx->stream = (hipStream_t)stream;
+  return FPEPS_OK;
+}
+
+const char* fpeps_last_error(fpeps_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+fpeps_status fpeps_env_absorb(fpeps_ctx ctx, int32_t L, const fpeps_tensor* env_in,
+                              const fpeps_tensor* ket, const fpeps_tensor* pepo,
+                              const fpeps_opts* opts, fpeps_tensor* env_out, double* log_norm,
+                              fpeps_report* report) {
+  return guarded(ctx, [&] {
+    if (report) std::memset(report, 0, sizeof(*report));
+    return fp::absorb_row(ctx, L, env_in, ket, pepo, opts, env_out, log_norm, report);
+  });
+}
+
+fpeps_status fpeps_absorb_diag(fpeps_ctx ctx, int32_t site, int32_t capacity, double* sigma,
+                               int32_t* sector, int32_t* count, int32_t* nsectors,
+                               int32_t* kept) {
+  if (!ctx) return FPEPS_ERR_ARG;
+  if (site < 0 || site >= (int)ctx->diag.size() || !count || !nsectors)
+    return finish(ctx, fp::fail(FPEPS_ERR_ARG, "no diagnostics for this site"));
+  const fp::SiteDiag& d = ctx->diag[site];
+  *count = (int32_t)d.sigma.size();
+  *nsectors = (int32_t)d.kept.size();
+  if ((int)d.sigma.size() > capacity || (int)d.kept.size() > capacity)
+    return finish(ctx, fp::fail(FPEPS_ERR_CAPACITY, "diagnostic capacity too small"));
+  for (size_t i = 0; i < d.sigma.size(); ++i) {
+    if (sigma) sigma[i] = d.sigma[i];
+    if (sector) sector[i] = d.sector[i];
+  }
+  if (kept)
+    for (size_t i = 0; i < d.kept.size(); ++i) kept[i] = d.kept[i];
+  return finish(ctx, fp::Status::ok());
+}
+
+fpeps_status fpeps_site_shape(fpeps_ctx ctx, const fpeps_tensor* R, const fpeps_tensor* T,
+                              const fpeps_tensor* A, const fpeps_tensor* W,
+                              const fpeps_opts* opts, int32_t capacity, int32_t* nsect,
+                              int32_t* labels, int64_t* m, int64_t* n) {
+  return guarded(ctx, [&]() -> fp::Status {
+    if (!nsect) return fp::fail(FPEPS_ERR_ARG, "null nsect");
+    fp::SiteOp op;
+    FP_TRY(fp::make_site(ctx, R, T, A, W, opts, op));
+    const int ns = (int)op.sect.size();
+    *nsect = ns;
+    if (ns > capacity) return fp::fail(FPEPS_ERR_CAPACITY, "sector capacity too small");
+    for (int J = 0; J < ns; ++J) {
+      if (m) m[J] = op.sect[J].m;
+      if (n) n[J] = op.sect[J].n;
+      if (labels)
+        for (int i = 0; i < op.nlab; ++i) labels[J * op.nlab + i] = op.sect[J].label[i];
+    }
+    return fp::Status::ok();
+  });
+}
+
+fpeps_status fpeps_site_apply(fpeps_ctx ctx, const fpeps_tensor* R, const fpeps_tensor* T,
+                              const fpeps_tensor* A, const fpeps_tensor* W,
+                              const fpeps_opts* opts, int32_t transpose, const int32_t* k,
+                              const double* x_in, double* y_out, fpeps_report* report) {
+  return guarded(ctx, [&]() -> fp::Status {
+    if (!k || !x_in || !y_out) return fp::fail(FPEPS_ERR_ARG, "null argument");
+    if (opts->precision != FPEPS_FP64)
+      return fp::fail(FPEPS_ERR_UNSUPPORTED, "only FPEPS_FP64 is available in this build");
+    if (report) std::memset(report, 0, sizeof(*report));
+    fp::SiteOp op;
+    FP_TRY(fp::make_site(ctx, R, T, A, W, opts, op));
+    std::vector<int32_t> kk(k, k + op.sect.size());
+    for (int v : kk)
+      if (v < 0) return fp::fail(FPEPS_ERR_ARG, "negative width");
+    fp::SiteOp::Plans pl;
+    const int64_t budget = opts->slice_budget > 0 ? opts->slice_budget : ((int64_t)24 << 30);
+    ctx->peak_ws = 0;
+    ctx->nslices = 0;
+    FP_TRY(op.plan(ctx, kk, budget, pl, transpose != 0));
+    hipEvent_t e0, e1;
+    FP_HIP(hipEventCreate(&e0));
+    FP_HIP(hipEventCreate(&e1));
+    FP_HIP(hipEventRecord(e0, ctx->stream));
+    FP_TRY(op.apply(ctx, pl, transpose != 0, x_in, y_out));
+    FP_HIP(hipEventRecord(e1, ctx->stream));
+    FP_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    FP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (report) {
+      report->alg_flops = transpose ? pl.flops_bwd : pl.flops_fwd;
+      report->seconds = ms * 1e-3;
+      report->peak_workspace = ctx->peak_ws;
+      report->nslices = ctx->nslices;
+    }
+    return fp::Status::ok();
+  });
+}
+
+fpeps_status fpeps_rsvd_truncate(fpeps_ctx ctx, int32_t nmat, const int64_t* m, const int64_t* n,
+                                 const double* const* A, const fpeps_opts* opts,
+                                 double* const* U_out, double* const* R_out, int32_t* kept,
+                                 double* sigma, fpeps_report* report) {
+  return guarded(ctx, [&] {
+    if (report) std::memset(report, 0, sizeof(*report));
+    return fp::explicit_rsvd(ctx, nmat, m, n, A, opts, U_out, R_out, kept, sigma, report,
+                             nullptr, nullptr, nullptr, false);
+  });
+}
+
+fpeps_status fpeps_cbe_expand(fpeps_ctx ctx, int32_t nmat, const int64_t* m, const int64_t* n,
+                              const double* const* A, const int32_t* r, const double* const* U,
+                              const double* const* V, const fpeps_opts* opts,
+                              double* const* Q_out, int32_t* kept, double* sigma,
+                              fpeps_report* report) {
+  return guarded(ctx, [&] {
+    if (report) std::memset(report, 0, sizeof(*report));
+    return fp::explicit_rsvd(ctx, nmat, m, n, A, opts, Q_out, nullptr, kept, sigma, report, r,
+                             U, V, true);
+  });
+}
+
+fpeps_status fpeps_expect(fpeps_ctx ctx, int32_t L, const fpeps_tensor* top,
+                          const fpeps_tensor* bottom, double* value) {
+  return guarded(ctx, [&] { return fp::overlap(ctx, L, top, bottom, value); });
+}
+
+}  // extern "C"

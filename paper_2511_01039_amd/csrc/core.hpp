@@ -1,0 +1,112 @@
+// Context, device workspace and shared helpers of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/fpeps.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace fp {
+
+struct Status {
+  fpeps_status code = FPEPS_OK;
+  std::string msg;
+  static Status ok() { return Status(); }
+  bool good() const { return code == FPEPS_OK; }
+};
+inline Status fail(fpeps_status c, const std::string& m) {
+  Status s;
+  s.code = c;
+  s.msg = m;
+  return s;
+}
+
+#define FP_HIP(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return ::fp::fail(FPEPS_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+#define FP_TRY(expr)            \
+  do {                          \
+    ::fp::Status s_ = (expr);   \
+    if (!s_.good()) return s_;  \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Per-site diagnostics of the last absorption.
+struct SiteDiag {
+  std::vector<double> sigma;     // all sectors, descending within a sector
+  std::vector<int32_t> sector;   // sector ordinal of each value
+  std::vector<int32_t> kept;     // per sector
+  std::vector<int64_t> m, n;
+  std::vector<int32_t> k;
+};
+
+}  // namespace fp
+
+struct fpeps_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::map<std::string, fp::DevBuf> bufs;
+  std::vector<fp::SiteDiag> diag;
+  double peak_ws = 0;
+  int nslices = 0;
+  // per-launch timing of the chain GEMM kernel (FPEPS_FLAG_TIME_KERNELS)
+  bool time_kernels = false;
+  std::vector<hipEvent_t> evpool;
+  size_t evused = 0;
+  std::vector<double> evflops;
+  double kt_seconds = 0, kt_flops = 0;
+  long kt_launches = 0;
+  bool verbose = false;
+
+  ~fpeps_ctx_s();
+  // device buffer ``name`` of at least ``bytes`` (grown, contents lost on growth)
+  fp::Status buf(const std::string& name, size_t bytes, void** out);
+  template <class T>
+  fp::Status bufT(const std::string& name, size_t count, T** out) {
+    void* p = nullptr;
+    fp::Status s = buf(name, count * sizeof(T) + 256, &p);
+    *out = (T*)p;
+    return s;
+  }
+  fp::Status upload(const std::string& name, const void* host, size_t bytes, void** dev);
+  fp::Status sync();
+  // events bracketing one timed launch (pairs from the pool)
+  fp::Status timed_events(hipEvent_t* a, hipEvent_t* b);
+  // after a synchronisation: fold the recorded durations into kt_*
+  fp::Status harvest_timing();
+};
+
+namespace fp {
+
+// A set of GEMM plans uploaded together (one table pool).
+struct PlanSet {
+  TablePool pool;
+  std::vector<GemmPlan> plans;
+  std::vector<DevGemm> dev;
+  int32_t* dtab = nullptr;
+  Status upload(fpeps_ctx_s* ctx, const std::string& tag);
+  int add(GemmPlan&& p) {
+    plans.push_back(std::move(p));
+    return (int)plans.size() - 1;
+  }
+};
+
+Status run_gemm(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A, int64_t a_size,
+                const double* B, int64_t b_size, double* C, int64_t c_size, bool timed = false);
+
+}  // namespace fp

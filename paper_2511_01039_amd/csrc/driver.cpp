@@ -1,0 +1,1188 @@
+// Orchestration of the randomized SVD (Sec. 4; Halko et al. 2011, Example
+// 1.6 with subspace iteration), the zip-up row absorption, controlled bond
+// expansion on explicit matrices and the overlap of two environments.
+#include "driver.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+
+namespace fp {
+
+// ---------------------------------------------------------------------------
+// dense (data-independent) plans of one rSVD
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Layout {
+  std::vector<int64_t> rows;
+  std::vector<int32_t> k;
+  std::vector<int64_t> off;
+  int64_t total = 0;
+  void build(const std::vector<int64_t>& r, const std::vector<int32_t>& kk) {
+    rows = r;
+    k = kk;
+    off.assign(r.size(), 0);
+    total = 0;
+    for (size_t J = 0; J < r.size(); ++J) {
+      off[J] = total;
+      total += r[J] * (int64_t)kk[J];
+    }
+  }
+};
+
+int ksplit_for(int64_t K, int k) {
+  // enough K chunks that the Gram of a tall block fills the machine
+  const int64_t tiles = ((k + 63) / 64) * (int64_t)((k + 63) / 64);
+  int64_t want = std::max<int64_t>(1, 512 / std::max<int64_t>(tiles, 1));
+  want = std::min<int64_t>(want, std::max<int64_t>(1, K / 256));
+  return (int)std::min<int64_t>(want, 256);
+}
+
+struct DensePlans {
+  PlanSet ps;
+  int gram[2] = {-1, -1};   // 0: row layout, 1: column layout
+  int qmul[2] = {-1, -1};
+  std::vector<ReduceDesc> red[2];
+  int64_t part_total[2] = {0, 0};
+  std::vector<int64_t> small_off, lam_off;
+  int64_t S = 0, lam_total = 0;
+  int max_k = 0;
+  int max_red_mn = 0;
+};
+
+Status build_dense(fpeps_ctx_s* ctx, const Layout& L0, const Layout& L1, DensePlans& dp,
+                   const std::string& tag) {
+  const int ns = (int)L0.k.size();
+  dp.small_off.assign(ns, 0);
+  dp.lam_off.assign(ns, 0);
+  dp.S = 0;
+  dp.lam_total = 0;
+  for (int J = 0; J < ns; ++J) {
+    dp.small_off[J] = dp.S;
+    dp.lam_off[J] = dp.lam_total;
+    dp.S += (int64_t)L0.k[J] * L0.k[J];
+    dp.lam_total += L0.k[J];
+    dp.max_k = std::max(dp.max_k, (int)L0.k[J]);
+  }
+  const Layout* Ls[2] = {&L0, &L1};
+  std::string err;
+  for (int side = 0; side < 2; ++side) {
+    const Layout& L = *Ls[side];
+    std::vector<DenseOp> gops, qops;
+    dp.red[side].clear();
+    int64_t poff = 0;
+    for (int J = 0; J < ns; ++J) {
+      const int k = L.k[J];
+      if (k <= 0 || L.rows[J] <= 0) continue;
+      const int ks = ksplit_for(L.rows[J], k);
+      DenseOp g{};
+      g.a_off = L.off[J];
+      g.b_off = L.off[J];
+      g.c_off = poff;
+      g.M = k;
+      g.N = k;
+      g.K = (int32_t)L.rows[J];
+      g.a_rs = 1;
+      g.a_cs = k;
+      g.b_rs = k;
+      g.b_cs = 1;
+      g.c_rs = k;
+      g.c_cs = 1;
+      g.alpha = 1.0;
+      g.ksplit = std::max(ks, 2);
+      gops.push_back(g);
+      ReduceDesc r{};
+      r.c_off = dp.small_off[J];
+      r.c_rs = k;
+      r.c_cs = 1;
+      r.p_off = poff;
+      r.M = k;
+      r.N = k;
+      r.nsplit = g.ksplit;
+      dp.red[side].push_back(r);
+      dp.max_red_mn = std::max(dp.max_red_mn, k * k);
+      poff += (int64_t)g.ksplit * k * k;
+      DenseOp q{};
+      q.a_off = L.off[J];
+      q.b_off = dp.S + dp.small_off[J];
+      q.c_off = L.off[J];
+      q.M = (int32_t)L.rows[J];
+      q.N = k;
+      q.K = k;
+      q.a_rs = k;
+      q.a_cs = 1;
+      q.b_rs = k;
+      q.b_cs = 1;
+      q.c_rs = k;
+      q.c_cs = 1;
+      q.alpha = 1.0;
+      qops.push_back(q);
+    }
+    dp.part_total[side] = poff;
+    GemmPlan gp, qp;
+    if (!plan_dense(gops, dp.ps.pool, 64, 64, 1, gp, err)) return fail(FPEPS_ERR_SHAPE, err);
+    if (!plan_dense(qops, dp.ps.pool, 64, 64, 1, qp, err)) return fail(FPEPS_ERR_SHAPE, err);
+    dp.gram[side] = dp.ps.add(std::move(gp));
+    dp.qmul[side] = dp.ps.add(std::move(qp));
+  }
+  return dp.ps.upload(ctx, tag);
+}
+
+// Shifted CholeskyQR3 of the per-sector blocks in ``Y`` (layout ``side``),
+// ping-ponging with ``Wb``. Returns the buffer that holds Q.
+Status orth(fpeps_ctx_s* ctx, DensePlans& dp, int side, const Layout& L, double* Y, double* Wb,
+            double** Qout, uint32_t* fallbacks) {
+  double *part = nullptr, *small = nullptr;
+  int* status = nullptr;
+  FP_TRY(ctx->bufT("rs_part", (size_t)std::max<int64_t>(dp.part_total[side], 1), &part));
+  FP_TRY(ctx->bufT("rs_small", (size_t)(2 * dp.S + dp.lam_total + 1), &small));
+  FP_TRY(ctx->bufT("rs_status", L.k.size() + 2, &status));
+  ReduceDesc* dred = nullptr;
+  FP_TRY(ctx->upload("rs_red" + std::to_string(side), dp.red[side].data(),
+                     dp.red[side].size() * sizeof(ReduceDesc), (void**)&dred));
+  std::vector<SmallDesc> ch;
+  for (size_t J = 0; J < L.k.size(); ++J) {
+    if (L.k[J] <= 0 || L.rows[J] <= 0) continue;
+    SmallDesc d{};
+    d.a_off = dp.small_off[J];
+    d.b_off = dp.S + dp.small_off[J];
+    d.c_off = 2 * dp.S + dp.lam_off[J];
+    d.k = L.k[J];
+    d.rows = (int32_t)std::min<int64_t>(L.rows[J], INT32_MAX);
+    d.shift = 0.0;
+    ch.push_back(d);
+  }
+  SmallDesc* dch = nullptr;
+  std::vector<SmallDesc> ch_shift = ch;
+  for (auto& d : ch_shift) d.shift = 11.0;
+  FP_TRY(ctx->upload("rs_chol0", ch_shift.data(), ch_shift.size() * sizeof(SmallDesc), (void**)&dch));
+  SmallDesc* dch1 = nullptr;
+  FP_TRY(ctx->upload("rs_chol1", ch.data(), ch.size() * sizeof(SmallDesc), (void**)&dch1));
+  FP_HIP(hipMemsetAsync(status, 0, (L.k.size() + 2) * sizeof(int), ctx->stream));
+  const int64_t small_n = 2 * dp.S + dp.lam_total + 1;
+  // shifted CholeskyQR3: one shifted pass, then two plain passes. A plain
+  // pass that breaks down (a rank-deficient block: the shifted pass leaves
+  // its null directions at rounding level) is replaced by two SVQB passes
+  // (Stathopoulos & Wu, SIAM J. Sci. Comput. 23 (2002) 2165) in which the
+  // null directions become exact zero columns.
+  bool svqb = false;
+  for (int pass = 0; pass < 3; ++pass) {
+    FP_TRY(run_gemm(ctx, dp.ps, dp.gram[side], Y, L.total, Y, L.total, part,
+                    std::max<int64_t>(dp.part_total[side], 1)));
+    FP_HIP(launch_reduce_partials(dred, (int)dp.red[side].size(), dp.max_red_mn, small, part,
+                                  ctx->stream));
+    FP_HIP(launch_chol_inv(pass == 0 ? dch : dch1, (int)ch.size(), small, status, ctx->stream));
+    if (pass == 1) {
+      int hs = 0;
+      FP_HIP(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+      FP_TRY(ctx->sync());
+      if (hs & 1) {
+        svqb = true;
+        break;
+      }
+    }
+    FP_TRY(run_gemm(ctx, dp.ps, dp.qmul[side], Y, L.total, small, small_n, Wb, L.total));
+    std::swap(Y, Wb);
+  }
+  if (svqb) {
+    *fallbacks |= 4u;
+    for (int pass = 0; pass < 2; ++pass) {
+      FP_TRY(run_gemm(ctx, dp.ps, dp.gram[side], Y, L.total, Y, L.total, part,
+                      std::max<int64_t>(dp.part_total[side], 1)));
+      FP_HIP(launch_reduce_partials(dred, (int)dp.red[side].size(), dp.max_red_mn, small, part,
+                                    ctx->stream));
+      FP_HIP(launch_jacobi_eig(dch1, (int)ch.size(), dp.max_k, small, status + 1, ctx->stream));
+      FP_HIP(launch_svqb_scale(dch1, (int)ch.size(), small, 1e-12, ctx->stream));
+      FP_TRY(run_gemm(ctx, dp.ps, dp.qmul[side], Y, L.total, small, small_n, Wb, L.total));
+      std::swap(Y, Wb);
+    }
+  }
+  int hs = 0;
+  FP_HIP(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  FP_TRY(ctx->sync());
+  if (hs & 2) *fallbacks |= 1u;
+  if ((hs & 1) && !svqb)
+    return fail(FPEPS_ERR_NUMERIC, "Cholesky breakdown in the orthonormalisation");
+  *Qout = Y;
+  return Status::ok();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// generic randomized SVD over sectors
+// ---------------------------------------------------------------------------
+Status rsvd_run(fpeps_ctx_s* ctx, RsvdIO& io, int chi, int p, int q, uint64_t seed,
+                RsvdOut& out, double sv_cut) {
+  if (!(sv_cut > 0.0)) sv_cut = 1e-7;
+  const int ns = (int)io.m.size();
+  // sketch widths k_J = min(m_J, n_J, ceil(chi m_J / sum m) + p)
+  const std::vector<int64_t>& wm = io.width_m.empty() ? io.m : io.width_m;
+  const std::vector<int64_t>& wn = io.width_n.empty() ? io.n : io.width_n;
+  int64_t msum = 0;
+  for (auto v : wm) msum += std::max<int64_t>(v, 0);
+  out.k.assign(ns, 0);
+  for (int J = 0; J < ns; ++J) {
+    if (wm[J] <= 0 || wn[J] <= 0 || msum <= 0) continue;
+    const int64_t want = ((int64_t)chi * wm[J] + msum - 1) / msum + p;
+    out.k[J] = (int32_t)std::min({wm[J], wn[J], want});
+  }
+  FP_TRY(io.prepare(out.k));
+  Layout RL, CL;
+  RL.build(io.m, out.k);
+  CL.build(io.n, out.k);
+  DensePlans dp;
+  FP_TRY(build_dense(ctx, RL, CL, dp, "rsd"));
+  out.small_off = dp.small_off;
+  out.lam_off = dp.lam_off;
+  out.S = dp.S;
+  out.row_off = RL.off;
+  out.col_off = CL.off;
+  double *c0, *c1, *r0, *r1;
+  FP_TRY(ctx->bufT("rs_c0", (size_t)std::max<int64_t>(CL.total, 1), &c0));
+  FP_TRY(ctx->bufT("rs_c1", (size_t)std::max<int64_t>(CL.total, 1), &c1));
+  FP_TRY(ctx->bufT("rs_r0", (size_t)std::max<int64_t>(RL.total, 1), &r0));
+  FP_TRY(ctx->bufT("rs_r1", (size_t)std::max<int64_t>(RL.total, 1), &r1));
+  // Gaussian sketch per sector
+  std::vector<GaussDesc> gd;
+  int64_t maxe = 0;
+  for (int J = 0; J < ns; ++J) {
+    if (out.k[J] <= 0) continue;
+    GaussDesc g{};
+    g.off = CL.off[J];
+    g.nelem = io.n[J] * (int64_t)out.k[J];
+    g.c1 = io.c1[J];
+    g.c2 = io.c2;
+    g.c3 = io.c3;
+    gd.push_back(g);
+    maxe = std::max(maxe, g.nelem);
+  }
+  GaussDesc* dgd = nullptr;
+  FP_TRY(ctx->upload("rs_gauss", gd.data(), gd.size() * sizeof(GaussDesc), (void**)&dgd));
+  FP_HIP(launch_gaussian(dgd, (int)gd.size(), maxe, c0, seed, ctx->stream));
+  // stage A
+  FP_TRY(io.apply(false, c0, r0));
+  double* Q = nullptr;
+  FP_TRY(orth(ctx, dp, 0, RL, r0, r1, &Q, &out.fallbacks));
+  for (int it = 0; it < q; ++it) {
+    FP_TRY(io.apply(true, Q, c0));
+    double* Qz = nullptr;
+    FP_TRY(orth(ctx, dp, 1, CL, c0, c1, &Qz, &out.fallbacks));
+    double* Yb = (Q == r0) ? r1 : r0;
+    FP_TRY(io.apply(false, Qz, Yb));
+    double* other = (Yb == r0) ? r1 : r0;
+    FP_TRY(orth(ctx, dp, 0, RL, Yb, other, &Q, &out.fallbacks));
+  }
+  // stage B: B^T = M^T Q, core factorisation of B B^T
+  double* Bt = c0;
+  FP_TRY(io.apply(true, Q, Bt));
+  out.Q = Q;
+  out.Bt = Bt;
+  double *part = nullptr, *small = nullptr;
+  int* status = nullptr;
+  FP_TRY(ctx->bufT("rs_part", (size_t)std::max<int64_t>(dp.part_total[1], 1), &part));
+  FP_TRY(ctx->bufT("rs_small", (size_t)(2 * dp.S + dp.lam_total + 1), &small));
+  FP_TRY(ctx->bufT("rs_status", 4, &status));
+  ReduceDesc* dred = nullptr;
+  FP_TRY(ctx->upload("rs_red1", dp.red[1].data(), dp.red[1].size() * sizeof(ReduceDesc),
+                     (void**)&dred));
+  FP_TRY(run_gemm(ctx, dp.ps, dp.gram[1], Bt, CL.total, Bt, CL.total, part,
+                  std::max<int64_t>(dp.part_total[1], 1)));
+  FP_HIP(launch_reduce_partials(dred, (int)dp.red[1].size(), dp.max_red_mn, small, part,
+                                ctx->stream));
+  std::vector<SmallDesc> jd;
+  for (int J = 0; J < ns; ++J) {
+    if (out.k[J] <= 0) continue;
+    SmallDesc d{};
+    d.a_off = dp.small_off[J];
+    d.b_off = dp.S + dp.small_off[J];
+    d.c_off = 2 * dp.S + dp.lam_off[J];
+    d.k = out.k[J];
+    jd.push_back(d);
+  }
+  SmallDesc* djd = nullptr;
+  FP_TRY(ctx->upload("rs_jac", jd.data(), jd.size() * sizeof(SmallDesc), (void**)&djd));
+  FP_HIP(hipMemsetAsync(status, 0, sizeof(int), ctx->stream));
+  FP_HIP(launch_jacobi_eig(djd, (int)jd.size(), dp.max_k, small, status, ctx->stream));
+  // global cut
+  std::vector<int64_t> loff;
+  std::vector<int32_t> kk;
+  std::vector<int> sidx;
+  int total = 0;
+  for (int J = 0; J < ns; ++J) {
+    if (out.k[J] <= 0) continue;
+    loff.push_back(2 * dp.S + dp.lam_off[J]);
+    kk.push_back(out.k[J]);
+    sidx.push_back(J);
+    total += out.k[J];
+  }
+  int64_t* dloff = nullptr;
+  int32_t* dkk = nullptr;
+  int32_t* dkept = nullptr;
+  CutOut* dcut = nullptr;
+  FP_TRY(ctx->upload("rs_loff", loff.data(), loff.size() * sizeof(int64_t), (void**)&dloff));
+  FP_TRY(ctx->upload("rs_kk", kk.data(), kk.size() * sizeof(int32_t), (void**)&dkk));
+  FP_TRY(ctx->bufT("rs_kept", kk.size() + 1, &dkept));
+  FP_TRY(ctx->bufT("rs_cut", 1, &dcut));
+  if (total > 6144 || (int)kk.size() > 1024)
+    return fail(FPEPS_ERR_UNSUPPORTED, "too many singular values for the on-chip cut");
+  FP_HIP(launch_cut(dloff, dkk, (int)kk.size(), chi, total, sv_cut, small, dkept, dcut,
+                    ctx->stream));
+  std::vector<int32_t> kept_c(kk.size());
+  int hs = 0;
+  FP_HIP(hipMemcpyAsync(kept_c.data(), dkept, kk.size() * sizeof(int32_t),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  FP_HIP(hipMemcpyAsync(&out.cut, dcut, sizeof(CutOut), hipMemcpyDeviceToHost, ctx->stream));
+  FP_HIP(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  out.lam.assign(dp.lam_total, 0.0);
+  if (dp.lam_total)
+    FP_HIP(hipMemcpyAsync(out.lam.data(), small + 2 * dp.S, dp.lam_total * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+  FP_TRY(ctx->sync());
+  if (hs & 4) out.fallbacks |= 2u;
+  out.kept.assign(ns, 0);
+  for (size_t i = 0; i < sidx.size(); ++i) out.kept[sidx[i]] = kept_c[i];
+  out.small = small;
+  for (double v : out.lam)
+    if (!std::isfinite(v)) return fail(FPEPS_ERR_NUMERIC, "non-finite singular value");
+  return Status::ok();
+}
+
+// U_J = Q_J U~_J[:, :kept_J] into ``Uout`` (offsets uoff, row stride kept_J)
+// and R_J = U~_J[:, :kept_J]^T B_J into ``Rout`` (offsets roff, kept_J x n_J).
+Status rsvd_factors(fpeps_ctx_s* ctx, const RsvdIO& io, const RsvdOut& r,
+                    const std::vector<int64_t>& uoff, double* Uout, int64_t u_size,
+                    const std::vector<int64_t>& roff, double* Rout, int64_t r_size) {
+  const int ns = (int)io.m.size();
+  std::vector<DenseOp> uops, rops;
+  for (int J = 0; J < ns; ++J) {
+    const int k = r.k[J], c = r.kept[J];
+    if (k <= 0 || c <= 0) continue;
+    if (Uout) {
+      DenseOp u{};
+      u.a_off = r.row_off[J];
+      u.b_off = r.S + r.small_off[J];
+      u.c_off = uoff[J];
+      u.M = (int32_t)io.m[J];
+      u.N = c;
+      u.K = k;
+      u.a_rs = k;
+      u.a_cs = 1;
+      u.b_rs = k;
+      u.b_cs = 1;
+      u.c_rs = c;
+      u.c_cs = 1;
+      u.alpha = 1.0;
+      uops.push_back(u);
+    }
+    if (Rout) {
+      DenseOp v{};
+      v.a_off = r.S + r.small_off[J];
+      v.b_off = r.col_off[J];
+      v.c_off = roff[J];
+      v.M = c;
+      v.N = (int32_t)io.n[J];
+      v.K = k;
+      v.a_rs = 1;
+      v.a_cs = k;
+      v.b_rs = 1;
+      v.b_cs = k;
+      v.c_rs = io.n[J];
+      v.c_cs = 1;
+      v.alpha = 1.0;
+      rops.push_back(v);
+    }
+  }
+  PlanSet ps;
+  std::string err;
+  GemmPlan up, rp;
+  if (!plan_dense(uops, ps.pool, 64, 64, 1, up, err)) return fail(FPEPS_ERR_SHAPE, err);
+  if (!plan_dense(rops, ps.pool, 64, 64, 1, rp, err)) return fail(FPEPS_ERR_SHAPE, err);
+  int iu = ps.add(std::move(up)), ir = ps.add(std::move(rp));
+  FP_TRY(ps.upload(ctx, "fac"));
+  int64_t rowt = 0, colt = 0;
+  for (int J = 0; J < ns; ++J) {
+    rowt += io.m[J] * (int64_t)r.k[J];
+    colt += io.n[J] * (int64_t)r.k[J];
+  }
+  const int64_t small_n = 2 * r.S + (int64_t)r.lam.size() + 1;
+  if (Uout) FP_TRY(run_gemm(ctx, ps, iu, r.Q, rowt, r.small, small_n, Uout, u_size));
+  if (Rout) FP_TRY(run_gemm(ctx, ps, ir, r.small, small_n, r.Bt, colt, Rout, r_size));
+  if (Uout) {
+    // canonical gauge: largest-magnitude entry of every U column positive
+    std::vector<SignDesc> sd;
+    std::vector<int32_t> cd;
+    int ncols = 0;
+    for (int J = 0; J < ns; ++J) {
+      const int c = r.kept[J];
+      if (r.k[J] <= 0 || c <= 0) continue;
+      SignDesc g{};
+      g.u_off = uoff[J];
+      g.r_off = Rout ? roff[J] : 0;
+      g.m = (int32_t)io.m[J];
+      g.ncol = c;
+      g.n = (int32_t)io.n[J];
+      g.col0 = ncols;
+      for (int i = 0; i < c; ++i) cd.push_back((int32_t)sd.size());
+      sd.push_back(g);
+      ncols += c;
+    }
+    SignDesc* dsd = nullptr;
+    int32_t* dcd = nullptr;
+    FP_TRY(ctx->upload("sign_d", sd.data(), sd.size() * sizeof(SignDesc), (void**)&dsd));
+    FP_TRY(ctx->upload("sign_c", cd.data(), cd.size() * sizeof(int32_t), (void**)&dcd));
+    FP_HIP(launch_sign_fix(dsd, (int)sd.size(), ncols, dcd, Uout, Rout, ctx->stream));
+  }
+  return ctx->sync();
+}
+
+// ---------------------------------------------------------------------------
+// zip-up absorption of one row
+// ---------------------------------------------------------------------------
+namespace {
+
+// Writes the structure of one output site; *fits = false (and the required
+// sizes in the report) when a capacity is too small.
+Status write_structure(const std::vector<LegP>& legs, const std::vector<int>& dirs,
+                       const std::vector<std::array<uint16_t, 5>>& blocks,
+                       const std::vector<int64_t>& offs, int64_t nelem, fpeps_tensor* t,
+                       fpeps_report* rep, bool* fits) {
+  int need_sect = 0;
+  for (auto& l : legs) need_sect = std::max(need_sect, l->nsect());
+  const int nlab = legs[0]->nlab;
+  if (rep) {
+    rep->required_sect = std::max(rep->required_sect, need_sect);
+    rep->required_blocks = std::max(rep->required_blocks, (int32_t)blocks.size());
+    rep->required_elem = std::max(rep->required_elem, nelem);
+  }
+  *fits = !(need_sect > t->max_sect || (int64_t)blocks.size() > t->max_blocks ||
+            nelem > t->max_elem);
+  if (!*fits) return Status::ok();
+  if (!t->nsect || !t->dirs || !t->labels || !t->dims || !t->block_sect || !t->block_off)
+    return fail(FPEPS_ERR_ARG, "output tensor has null structure arrays");
+  t->nlegs = (int32_t)legs.size();
+  t->nlab = nlab;
+  for (size_t l = 0; l < legs.size(); ++l) {
+    t->nsect[l] = legs[l]->nsect();
+    t->dirs[l] = dirs[l];
+    for (int s = 0; s < legs[l]->nsect(); ++s) {
+      for (int i = 0; i < nlab; ++i)
+        t->labels[((int64_t)l * t->max_sect + s) * nlab + i] = legs[l]->label(s)[i];
+      t->dims[(int64_t)l * t->max_sect + s] = legs[l]->dim[s];
+    }
+  }
+  t->nblocks = (int32_t)blocks.size();
+  for (size_t b = 0; b < blocks.size(); ++b) {
+    for (int l = 0; l < 5; ++l) t->block_sect[b * 5 + l] = blocks[b][l];
+    t->block_off[b] = offs[b];
+  }
+  t->nelem = nelem;
+  return Status::ok();
+}
+
+}  // namespace
+
+Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpeps_tensor* ket,
+                  const fpeps_tensor* pepo, const fpeps_opts* o, fpeps_tensor* env_out,
+                  double* log_norm, fpeps_report* rep) {
+  if (L < 1 || !env_in || !ket || !pepo || !o || !env_out || !log_norm)
+    return fail(FPEPS_ERR_ARG, "null argument or L < 1");
+  if (o->precision != FPEPS_FP64)
+    return fail(FPEPS_ERR_UNSUPPORTED, "only FPEPS_FP64 is available in this build");
+  if (o->cbe_extra != 0)
+    return fail(FPEPS_ERR_UNSUPPORTED, "bond expansion inside the absorption is not available");
+  if (o->chi < 1 || o->oversample < 0 || o->power_iters < 0)
+    return fail(FPEPS_ERR_ARG, "chi >= 1, oversample >= 0, power_iters >= 0 required");
+  SymInfo sym;
+  sym.kind = o->symmetry;
+  sym.fermionic = o->fermionic != 0;
+  sym.coef_seed = o->coef_seed;
+  if (sym.kind < 0 || sym.kind > 2) return fail(FPEPS_ERR_ARG, "bad symmetry");
+  const int nlab = sym.kind == SYM_U1U1 ? 2 : 1;
+  const int64_t budget = o->slice_budget > 0 ? o->slice_budget : ((int64_t)24 << 30);
+  ctx->diag.assign(L, SiteDiag());
+  ctx->peak_ws = 0;
+  ctx->nslices = 0;
+  ctx->time_kernels = (o->flags & FPEPS_FLAG_TIME_KERNELS) != 0;
+  ctx->kt_seconds = ctx->kt_flops = 0;
+  ctx->kt_launches = 0;
+  ctx->evused = 0;
+  ctx->evflops.clear();
+  ctx->verbose = std::getenv("FPEPS_VERBOSE") != nullptr;
+  auto wall = [] { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
+  hipEvent_t ev0, ev1;
+  FP_HIP(hipEventCreate(&ev0));
+  FP_HIP(hipEventCreate(&ev1));
+  FP_HIP(hipEventRecord(ev0, ctx->stream));
+  double lg = 0.0, flops = 0.0, disc = 0.0, gap = INFINITY;
+  int kept_total = 0;
+  uint32_t fallbacks = 0;
+  bool cap_fail = false;
+
+  // remainder of the left edge: one element equal to 1
+  double* Rbuf[2] = {nullptr, nullptr};
+  FP_TRY(ctx->bufT("R_edge", 1, &Rbuf[0]));
+  FP_HIP(launch_fill(Rbuf[0], 1, 1.0, ctx->stream));
+  BT R;
+  int64_t R_size = 1;
+  const double* Rdev = Rbuf[0];
+  {
+    BT T0, K0, W0;
+    FP_TRY(tensor_to_bt(&env_in[0], {N_a, N_tk, N_tw, N_tb, N_b}, nlab, T0));
+    FP_TRY(tensor_to_bt(&ket[0], {N_p, N_lk, N_rk, N_tk, N_dk}, nlab, K0));
+    FP_TRY(tensor_to_bt(&pepo[0], {N_q, N_p, N_lw, N_rw, N_tw, N_dw}, nlab, W0));
+    auto zero = std::make_shared<Leg>();
+    zero->nlab = nlab;
+    zero->dir = 1;
+    zero->lab.assign(nlab, 0);
+    zero->dim = {1};
+    auto fl = [](const LegP& l) {
+      auto m = std::make_shared<Leg>(*l);
+      m->dir = -m->dir;
+      return LegP(m);
+    };
+    R.names = {N_c, N_a, N_lk, N_lw, N_lb};
+    R.cat = {zero, T0.cat[0], K0.cat[1], W0.cat[2], fl(K0.cat[1])};
+    for (int i = 1; i < 5; ++i)
+      if (R.cat[i]->total() != 1) return fail(FPEPS_ERR_SHAPE, "left boundary legs must have dim 1");
+    Block b;
+    b.base = 0;
+    set_rowmajor(R, b);
+    R.blocks.push_back(b);
+    R.size = 1;
+  }
+  int rcur = 0;
+  for (int x = 0; x < L; ++x) {
+    BT T, K, W;
+    FP_TRY(tensor_to_bt(&env_in[x], {N_a, N_tk, N_tw, N_tb, N_b}, nlab, T));
+    FP_TRY(tensor_to_bt(&ket[x], {N_p, N_lk, N_rk, N_tk, N_dk}, nlab, K));
+    FP_TRY(tensor_to_bt(&pepo[x], {N_q, N_p, N_lw, N_rw, N_tw, N_dw}, nlab, W));
+    SiteData d;
+    d.T = env_in[x].data;
+    d.T_size = env_in[x].nelem;
+    d.A = ket[x].data;
+    d.A_size = ket[x].nelem;
+    d.W = pepo[x].data;
+    d.W_size = pepo[x].nelem;
+    d.R = Rdev;
+    d.R_size = R_size;
+    if (o->flags & FPEPS_FLAG_CHECK_FINITE) {
+      int* flag = nullptr;
+      FP_TRY(ctx->bufT("finite_flag", 1, &flag));
+      FP_HIP(hipMemsetAsync(flag, 0, sizeof(int), ctx->stream));
+      FP_HIP(launch_check_finite(d.T, d.T_size, flag, ctx->stream));
+      FP_HIP(launch_check_finite(d.A, d.A_size, flag, ctx->stream));
+      FP_HIP(launch_check_finite(d.W, d.W_size, flag, ctx->stream));
+      int h = 0;
+      FP_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+      FP_TRY(ctx->sync());
+      if (h) return fail(FPEPS_ERR_NUMERIC, "non-finite input at site " + std::to_string(x));
+    }
+    const double tw0 = wall();
+    SiteOp op;
+    FP_TRY(op.init(sym, nlab, std::move(T), std::move(K), std::move(W), std::move(R), d));
+    FP_TRY(op.analyse());
+    const int ns = (int)op.sect.size();
+    SiteDiag& dg = ctx->diag[x];
+    for (auto& s : op.sect) {
+      dg.m.push_back(s.m);
+      dg.n.push_back(s.n);
+    }
+    std::vector<LegP> olegs = {op.R.cat[0], op.ket.cat[op.ket.pos(N_dk)], op.W.cat[op.W.pos(N_dw)],
+                               op.bra.cat[op.bra.pos(N_db)], nullptr};
+    if (x == L - 1) {
+      int64_t ntot = 0;
+      int J1 = -1;
+      for (int J = 0; J < ns; ++J) {
+        ntot += op.sect[J].n;
+        if (op.sect[J].n == 1) J1 = J;
+      }
+      if (ntot != 1 || J1 < 0) return fail(FPEPS_ERR_SHAPE, "right boundary legs must have dim 1");
+      std::vector<int32_t> k(ns, 0);
+      k[J1] = 1;
+      SiteOp::Plans pl;
+      FP_TRY(op.plan(ctx, k, budget, pl, false));
+      double *xin = nullptr, *y = nullptr, *part = nullptr, *nrm = nullptr;
+      FP_TRY(ctx->bufT("last_x", 1, &xin));
+      FP_TRY(ctx->bufT("last_y", (size_t)std::max<int64_t>(pl.row_total, 1), &y));
+      FP_TRY(ctx->bufT("nrm_part", 512, &part));
+      FP_TRY(ctx->bufT("nrm_out", 1, &nrm));
+      FP_HIP(launch_fill(xin, 1, 1.0, ctx->stream));
+      FP_TRY(op.apply(ctx, pl, false, xin, y));
+      FP_HIP(launch_sumsq(y, pl.row_total, part, nrm, ctx->stream));
+      double h = 0;
+      FP_HIP(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      FP_TRY(ctx->sync());
+      if (!(h > 0.0) || !std::isfinite(h)) return fail(FPEPS_ERR_NUMERIC, "last site has zero or non-finite norm");
+      const double nu = std::sqrt(h);
+      lg += std::log(nu);
+      auto jl = std::make_shared<Leg>();
+      jl->nlab = nlab;
+      jl->lab = op.sect[J1].label;
+      jl->dim = {1};
+      olegs[4] = jl;
+      std::vector<std::array<uint16_t, 5>> blocks;
+      std::vector<int64_t> offs;
+      for (size_t t = 0; t < op.sect[J1].rows.size(); ++t) {
+        auto& r = op.sect[J1].rows[t];
+        blocks.push_back({r[0], r[1], r[2], r[3], 0});
+        offs.push_back(op.sect[J1].rrow[t]);
+      }
+      std::vector<int> dirs = {1, op.ket.cat[op.ket.pos(N_dk)]->dir, op.W.cat[op.W.pos(N_dw)]->dir,
+                               op.bra.cat[op.bra.pos(N_db)]->dir, -1};
+      bool fits = false;
+      FP_TRY(write_structure(olegs, dirs, blocks, offs, pl.row_total, &env_out[x], rep, &fits));
+      if (fits) {
+        FP_HIP(hipMemcpyAsync(env_out[x].data, y, pl.row_total * sizeof(double),
+                              hipMemcpyDeviceToDevice, ctx->stream));
+        FP_HIP(launch_scale(env_out[x].data, pl.row_total, 1.0 / nu, ctx->stream));
+      } else {
+        cap_fail = true;
+      }
+      dg.k = k;
+      dg.kept = k;
+      break;
+    }
+    // randomized SVD of M_x
+    RsvdIO io;
+    SiteOp::Plans pl;
+    for (int J = 0; J < ns; ++J) {
+      io.m.push_back(op.sect[J].m);
+      io.n.push_back(op.sect[J].n);
+      io.c1.push_back((uint32_t)J);
+    }
+    io.c2 = (uint32_t)x;
+    io.c3 = (uint32_t)(o->row & 0xFFFF);
+    io.prepare = [&](const std::vector<int32_t>& k) { return op.plan(ctx, k, budget, pl, true); };
+    io.apply = [&](bool t, const double* xi, double* yo) { return op.apply(ctx, pl, t, xi, yo); };
+    RsvdOut rs;
+    const double tw1 = wall();
+    {
+      Status st = rsvd_run(ctx, io, o->chi, o->oversample, o->power_iters, o->seed, rs, o->sv_cut);
+      if (!st.good()) return fail(st.code, "site " + std::to_string(x) + ": " + st.msg);
+    }
+    fallbacks |= rs.fallbacks;
+    if (ctx->verbose) {
+      int64_t mt = 0, nt = 0;
+      for (int J = 0; J < ns; ++J) {
+        mt += op.sect[J].m;
+        nt += op.sect[J].n;
+      }
+      std::fprintf(stderr,
+                   "[fpeps] site %d: sectors %d m %lld n %lld analyse %.3fs rsvd(incl. plan) %.3fs "
+                   "chain flops/app %.3e slices %zu ws %.2f GB pairs %zu\n",
+                   x, ns, (long long)mt, (long long)nt, tw1 - tw0, wall() - tw1, pl.flops_fwd,
+                   pl.slices.size(), (pl.ws1 + pl.ws2) * 8e-9, pl.ps.pool.data.size());
+    }
+    // outputs: environment site (U) and the next remainder (R)
+    std::vector<int> sel;
+    for (int J = 0; J < ns; ++J)
+      if (rs.kept[J] > 0) sel.push_back(J);
+    auto jl = std::make_shared<Leg>();
+    jl->nlab = nlab;
+    for (int J : sel) {
+      for (int32_t v : op.sect[J].label) jl->lab.push_back(v);
+      jl->dim.push_back(rs.kept[J]);
+    }
+    olegs[4] = jl;
+    std::vector<int64_t> uoff(ns, 0), roff(ns, 0);
+    int64_t ut = 0, rt = 0;
+    std::vector<std::array<uint16_t, 5>> blocks;
+    std::vector<int64_t> offs;
+    for (size_t si = 0; si < sel.size(); ++si) {
+      const int J = sel[si];
+      uoff[J] = ut;
+      roff[J] = rt;
+      for (size_t t = 0; t < op.sect[J].rows.size(); ++t) {
+        auto& r = op.sect[J].rows[t];
+        blocks.push_back({r[0], r[1], r[2], r[3], (uint16_t)si});
+        offs.push_back(ut + op.sect[J].rrow[t] * rs.kept[J]);
+      }
+      ut += op.sect[J].m * (int64_t)rs.kept[J];
+      rt += op.sect[J].n * (int64_t)rs.kept[J];
+    }
+    std::vector<int> dirs = {1, op.ket.cat[op.ket.pos(N_dk)]->dir, op.W.cat[op.W.pos(N_dw)]->dir,
+                             op.bra.cat[op.bra.pos(N_db)]->dir, -1};
+    bool fits = false;
+    FP_TRY(write_structure(olegs, dirs, blocks, offs, ut, &env_out[x], rep, &fits));
+    const int rn = 1 - rcur;
+    FP_TRY(ctx->bufT(rn == 0 ? "R_a" : "R_b", (size_t)std::max<int64_t>(rt, 1), &Rbuf[rn]));
+    double* ubuf = nullptr;
+    FP_TRY(ctx->bufT("U_site", (size_t)std::max<int64_t>(ut, 1), &ubuf));
+    FP_TRY(rsvd_factors(ctx, io, rs, uoff, ubuf, std::max<int64_t>(ut, 1), roff, Rbuf[rn],
+                        std::max<int64_t>(rt, 1)));
+    if (fits) {
+      if (ut > 0)
+        FP_HIP(hipMemcpyAsync(env_out[x].data, ubuf, ut * sizeof(double), hipMemcpyDeviceToDevice,
+                              ctx->stream));
+    } else {
+      cap_fail = true;
+    }
+    // normalise the remainder
+    double *part = nullptr, *nrm = nullptr;
+    FP_TRY(ctx->bufT("nrm_part", 512, &part));
+    FP_TRY(ctx->bufT("nrm_out", 1, &nrm));
+    FP_HIP(launch_sumsq(Rbuf[rn], rt, part, nrm, ctx->stream));
+    double h = 0;
+    FP_HIP(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    FP_TRY(ctx->sync());
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(FPEPS_ERR_NUMERIC, "remainder has zero or non-finite norm");
+    const double nu = std::sqrt(h);
+    FP_HIP(launch_scale(Rbuf[rn], rt, 1.0 / nu, ctx->stream));
+    lg += std::log(nu);
+    // R for the next site: per-sector matrices (kept_J x n_J), blocks by column tuple
+    BT Rn;
+    Rn.names = {N_c, N_a, N_lk, N_lw, N_lb};
+    auto cl = std::make_shared<Leg>(*jl);
+    cl->dir = 1;
+    Rn.cat = {cl, op.T.cat[op.T.pos(N_b)], op.ket.cat[op.ket.pos(N_rk)], op.W.cat[op.W.pos(N_rw)],
+              op.bra.cat[op.bra.pos(N_rb)]};
+    for (size_t si = 0; si < sel.size(); ++si) {
+      const int J = sel[si];
+      const Sector& s = op.sect[J];
+      for (size_t t = 0; t < s.cols.size(); ++t) {
+        Block b;
+        b.sect[0] = (uint16_t)si;
+        for (int i = 0; i < 4; ++i) b.sect[i + 1] = s.cols[t][i];
+        b.base = roff[J] + s.crow[t];
+        int64_t st = 1;
+        for (int i = 4; i >= 1; --i) {
+          b.stride[i] = st;
+          st *= Rn.cat[i]->dim[b.sect[i]];
+        }
+        b.stride[0] = s.n;
+        Rn.blocks.push_back(b);
+      }
+    }
+    Rn.size = std::max<int64_t>(rt, 1);
+    R = std::move(Rn);
+    Rdev = Rbuf[rn];
+    R_size = std::max<int64_t>(rt, 1);
+    rcur = rn;
+    // diagnostics and report
+    dg.k = rs.k;
+    dg.kept = rs.kept;
+    for (int J = 0; J < ns; ++J)
+      for (int i = 0; i < rs.k[J]; ++i) {
+        const double l = rs.lam[rs.lam_off[J] + i];
+        dg.sigma.push_back(l > 0 ? std::sqrt(l) : 0.0);
+        dg.sector.push_back(J);
+      }
+    double site_flops = pl.flops_fwd * (2 + 2 * o->power_iters);
+    for (int J = 0; J < ns; ++J) {
+      const double m = (double)op.sect[J].m, n = (double)op.sect[J].n, k = rs.k[J],
+                   c = rs.kept[J];
+      if (k <= 0) continue;
+      const int q = o->power_iters;
+      site_flops += (q + 1) * (2 * m * k * k - 2 * k * k * k / 3.0) +
+                    q * (2 * n * k * k - 2 * k * k * k / 3.0);
+      site_flops += 2 * n * k * k + 12 * k * k * k;
+      site_flops += 2 * m * k * c + 2 * k * c * n;
+    }
+    flops += site_flops;
+    for (int v : rs.kept) kept_total += v;
+    if (rs.cut.total2 > 0) disc = std::max(disc, 1.0 - rs.cut.kept2 / rs.cut.total2);
+    if (rs.cut.s_next >= 0 && rs.cut.s_last > 0)
+      gap = std::min(gap, (rs.cut.s_last - rs.cut.s_next) / rs.cut.s_last);
+  }
+  FP_HIP(hipEventRecord(ev1, ctx->stream));
+  FP_HIP(hipEventSynchronize(ev1));
+  float ms = 0;
+  FP_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  FP_TRY(ctx->sync());
+  if (cap_fail) return fail(FPEPS_ERR_CAPACITY, "output tensor capacity too small (see report)");
+  *log_norm += lg;
+  if (rep) {
+    rep->alg_flops = flops;
+    rep->seconds = ms * 1e-3;
+    rep->discarded_weight = disc;
+    rep->min_rel_gap = std::isfinite(gap) ? gap : -1.0;
+    rep->log_norm = lg;
+    rep->peak_workspace = ctx->peak_ws;
+    rep->kept_total = kept_total;
+    rep->nslices = ctx->nslices;
+    rep->fallbacks = fallbacks;
+    rep->kernel_launches = (int32_t)ctx->kt_launches;
+    rep->kernel_seconds = ctx->kt_seconds;
+    rep->kernel_flops = ctx->kt_flops;
+  }
+  ctx->time_kernels = false;
+  return Status::ok();
+}
+
+// ---------------------------------------------------------------------------
+// site operator shape / application (chain on its own)
+// ---------------------------------------------------------------------------
+Status make_site(fpeps_ctx_s* ctx, const fpeps_tensor* R, const fpeps_tensor* T,
+                 const fpeps_tensor* A, const fpeps_tensor* W, const fpeps_opts* o, SiteOp& op) {
+  if (!R || !T || !A || !W || !o) return fail(FPEPS_ERR_ARG, "null argument");
+  SymInfo sym;
+  sym.kind = o->symmetry;
+  sym.fermionic = o->fermionic != 0;
+  sym.coef_seed = o->coef_seed;
+  if (sym.kind < 0 || sym.kind > 2) return fail(FPEPS_ERR_ARG, "bad symmetry");
+  const int nlab = sym.kind == SYM_U1U1 ? 2 : 1;
+  BT bT, bK, bW, bR;
+  FP_TRY(tensor_to_bt(T, {N_a, N_tk, N_tw, N_tb, N_b}, nlab, bT));
+  FP_TRY(tensor_to_bt(A, {N_p, N_lk, N_rk, N_tk, N_dk}, nlab, bK));
+  FP_TRY(tensor_to_bt(W, {N_q, N_p, N_lw, N_rw, N_tw, N_dw}, nlab, bW));
+  FP_TRY(tensor_to_bt(R, {N_c, N_a, N_lk, N_lw, N_lb}, nlab, bR));
+  SiteData d;
+  d.T = T->data;
+  d.T_size = T->nelem;
+  d.A = A->data;
+  d.A_size = A->nelem;
+  d.W = W->data;
+  d.W_size = W->nelem;
+  d.R = R->data;
+  d.R_size = R->nelem;
+  FP_TRY(op.init(sym, nlab, std::move(bT), std::move(bK), std::move(bW), std::move(bR), d));
+  return op.analyse();
+}
+
+// ---------------------------------------------------------------------------
+// explicit matrices: rSVD and CBE
+// ---------------------------------------------------------------------------
+namespace {
+
+struct ExplicitOp {
+  std::vector<int64_t> m, n, aoff;
+  int64_t atotal = 0;
+  double* A = nullptr;          // all matrices, row-major, concatenated
+  // optional projectors (CBE): U_i (m x r), V_i (r x n)
+  std::vector<int32_t> r;
+  std::vector<int64_t> uoff, voff;
+  double* U = nullptr;
+  double* V = nullptr;
+  int64_t utotal = 0, vtotal = 0;
+  PlanSet ps;
+  int pm = -1, pt = -1;
+  // projection plans
+  int p_v1 = -1, p_v2 = -1, p_u1 = -1, p_u2 = -1;
+  int pt_u1 = -1, pt_u2 = -1, pt_v1 = -1, pt_v2 = -1;
+  std::vector<int64_t> col_off, row_off, s_off;
+  int64_t col_total = 0, row_total = 0, s_total = 0;
+};
+
+Status explicit_prepare(fpeps_ctx_s* ctx, ExplicitOp& e, const std::vector<int32_t>& k) {
+  const int nm = (int)e.m.size();
+  e.col_off.assign(nm, 0);
+  e.row_off.assign(nm, 0);
+  e.s_off.assign(nm, 0);
+  e.col_total = e.row_total = e.s_total = 0;
+  for (int i = 0; i < nm; ++i) {
+    e.col_off[i] = e.col_total;
+    e.row_off[i] = e.row_total;
+    e.s_off[i] = e.s_total;
+    e.col_total += e.n[i] * (int64_t)k[i];
+    e.row_total += e.m[i] * (int64_t)k[i];
+    e.s_total += (e.r.empty() ? 0 : (int64_t)e.r[i]) * k[i];
+  }
+  std::vector<DenseOp> fm, ft, v1, v2, u1, u2, tu1, tu2, tv1, tv2;
+  for (int i = 0; i < nm; ++i) {
+    if (k[i] <= 0) continue;
+    DenseOp d{};
+    d.alpha = 1.0;
+    // y = A x
+    d.a_off = e.aoff[i]; d.a_rs = e.n[i]; d.a_cs = 1;
+    d.b_off = e.col_off[i]; d.b_rs = k[i]; d.b_cs = 1;
+    d.c_off = e.row_off[i]; d.c_rs = k[i]; d.c_cs = 1;
+    d.M = (int32_t)e.m[i]; d.N = k[i]; d.K = (int32_t)e.n[i];
+    fm.push_back(d);
+    // y = A^T x
+    DenseOp t{};
+    t.alpha = 1.0;
+    t.a_off = e.aoff[i]; t.a_rs = 1; t.a_cs = e.n[i];
+    t.b_off = e.row_off[i]; t.b_rs = k[i]; t.b_cs = 1;
+    t.c_off = e.col_off[i]; t.c_rs = k[i]; t.c_cs = 1;
+    t.M = (int32_t)e.n[i]; t.N = k[i]; t.K = (int32_t)e.m[i];
+    ft.push_back(t);
+    if (!e.r.empty() && e.r[i] > 0) {
+      const int ri = e.r[i];
+      // s = V x (r x k) ; x -= V^T s   (on the column side)
+      DenseOp a{};
+      a.alpha = 1.0;
+      a.a_off = e.voff[i]; a.a_rs = e.n[i]; a.a_cs = 1;
+      a.b_off = e.col_off[i]; a.b_rs = k[i]; a.b_cs = 1;
+      a.c_off = e.s_off[i]; a.c_rs = k[i]; a.c_cs = 1;
+      a.M = ri; a.N = k[i]; a.K = (int32_t)e.n[i];
+      v1.push_back(a);
+      DenseOp b{};
+      b.alpha = -1.0;
+      b.a_off = e.voff[i]; b.a_rs = 1; b.a_cs = e.n[i];
+      b.b_off = e.s_off[i]; b.b_rs = k[i]; b.b_cs = 1;
+      b.c_off = e.col_off[i]; b.c_rs = k[i]; b.c_cs = 1;
+      b.M = (int32_t)e.n[i]; b.N = k[i]; b.K = ri;
+      v2.push_back(b);
+      // s = U^T y ; y -= U s  (on the row side)
+      DenseOp c{};
+      c.alpha = 1.0;
+      c.a_off = e.uoff[i]; c.a_rs = 1; c.a_cs = ri;
+      c.b_off = e.row_off[i]; c.b_rs = k[i]; c.b_cs = 1;
+      c.c_off = e.s_off[i]; c.c_rs = k[i]; c.c_cs = 1;
+      c.M = ri; c.N = k[i]; c.K = (int32_t)e.m[i];
+      u1.push_back(c);
+      DenseOp dd{};
+      dd.alpha = -1.0;
+      dd.a_off = e.uoff[i]; dd.a_rs = ri; dd.a_cs = 1;
+      dd.b_off = e.s_off[i]; dd.b_rs = k[i]; dd.b_cs = 1;
+      dd.c_off = e.row_off[i]; dd.c_rs = k[i]; dd.c_cs = 1;
+      dd.M = (int32_t)e.m[i]; dd.N = k[i]; dd.K = ri;
+      u2.push_back(dd);
+    }
+  }
+  std::string err;
+  e.ps = PlanSet();
+  GemmPlan a, b, c1, c2, c3, c4;
+  if (!plan_dense(fm, e.ps.pool, 64, 64, 1, a, err)) return fail(FPEPS_ERR_SHAPE, err);
+  if (!plan_dense(ft, e.ps.pool, 64, 64, 1, b, err)) return fail(FPEPS_ERR_SHAPE, err);
+  if (!plan_dense(v1, e.ps.pool, 64, 64, 1, c1, err)) return fail(FPEPS_ERR_SHAPE, err);
+  if (!plan_dense(v2, e.ps.pool, 64, 64, 1, c2, err)) return fail(FPEPS_ERR_SHAPE, err);
+  if (!plan_dense(u1, e.ps.pool, 64, 64, 1, c3, err)) return fail(FPEPS_ERR_SHAPE, err);
+  if (!plan_dense(u2, e.ps.pool, 64, 64, 1, c4, err)) return fail(FPEPS_ERR_SHAPE, err);
+  e.pm = e.ps.add(std::move(a));
+  e.pt = e.ps.add(std::move(b));
+  e.p_v1 = e.ps.add(std::move(c1));
+  e.p_v2 = e.ps.add(std::move(c2));
+  e.p_u1 = e.ps.add(std::move(c3));
+  e.p_u2 = e.ps.add(std::move(c4));
+  return e.ps.upload(ctx, "expl");
+}
+
+// The subtractions x - V^T (V x) and y - U (U^T y) accumulate into the
+// operand in place: the GEMM writes C = alpha * A B, so they are done as
+// separate products into scratch followed by an in-place axpy-free form:
+// here the projected vector is formed as x' = x + (-V^T) s by a GEMM whose
+// output is a scratch copy, then copied back.
+Status project(fpeps_ctx_s* ctx, ExplicitOp& e, bool row_side, double* x, int64_t xtotal) {
+  double *s = nullptr, *tmp = nullptr;
+  FP_TRY(ctx->bufT("expl_s", (size_t)std::max<int64_t>(e.s_total, 1), &s));
+  FP_TRY(ctx->bufT("expl_tmp", (size_t)std::max<int64_t>(xtotal, 1), &tmp));
+  if (!row_side) {
+    FP_TRY(run_gemm(ctx, e.ps, e.p_v1, e.V, e.vtotal, x, xtotal, s, std::max<int64_t>(e.s_total, 1)));
+    FP_TRY(run_gemm(ctx, e.ps, e.p_v2, e.V, e.vtotal, s, std::max<int64_t>(e.s_total, 1), tmp, xtotal));
+  } else {
+    FP_TRY(run_gemm(ctx, e.ps, e.p_u1, e.U, e.utotal, x, xtotal, s, std::max<int64_t>(e.s_total, 1)));
+    FP_TRY(run_gemm(ctx, e.ps, e.p_u2, e.U, e.utotal, s, std::max<int64_t>(e.s_total, 1), tmp, xtotal));
+  }
+  return axpy_inplace(ctx, x, tmp, xtotal);
+}
+
+}  // namespace
+
+Status axpy_inplace(fpeps_ctx_s* ctx, double* x, const double* y, int64_t n) {
+  FP_HIP(launch_add(x, y, n, ctx->stream));
+  return Status::ok();
+}
+
+Status explicit_rsvd(fpeps_ctx_s* ctx, int nmat, const int64_t* m, const int64_t* n,
+                     const double* const* A, const fpeps_opts* o, double* const* U_out,
+                     double* const* R_out, int32_t* kept, double* sigma, fpeps_report* rep,
+                     const int32_t* rr, const double* const* Uin, const double* const* Vin,
+                     bool cbe) {
+  if (nmat < 1 || !m || !n || !A || !o || !kept) return fail(FPEPS_ERR_ARG, "null argument");
+  if (o->precision != FPEPS_FP64)
+    return fail(FPEPS_ERR_UNSUPPORTED, "only FPEPS_FP64 is available in this build");
+  hipEvent_t ev0, ev1;
+  FP_HIP(hipEventCreate(&ev0));
+  FP_HIP(hipEventCreate(&ev1));
+  FP_HIP(hipEventRecord(ev0, ctx->stream));
+  ExplicitOp e;
+  for (int i = 0; i < nmat; ++i) {
+    if (m[i] < 0 || n[i] < 0 || m[i] > INT32_MAX || n[i] > INT32_MAX)
+      return fail(FPEPS_ERR_ARG, "bad matrix size");
+    if (m[i] * n[i] > 0 && !A[i]) return fail(FPEPS_ERR_ARG, "null matrix");
+    e.m.push_back(m[i]);
+    e.n.push_back(n[i]);
+    e.aoff.push_back(e.atotal);
+    e.atotal += m[i] * n[i];
+  }
+  FP_TRY(ctx->bufT("expl_A", (size_t)std::max<int64_t>(e.atotal, 1), &e.A));
+  for (int i = 0; i < nmat; ++i)
+    if (m[i] * n[i] > 0)
+      FP_HIP(hipMemcpyAsync(e.A + e.aoff[i], A[i], m[i] * n[i] * sizeof(double),
+                            hipMemcpyDeviceToDevice, ctx->stream));
+  std::vector<int64_t> mm = e.m, nn = e.n;
+  if (cbe) {
+    if (!rr || !Uin || !Vin) return fail(FPEPS_ERR_ARG, "null projector argument");
+    for (int i = 0; i < nmat; ++i) {
+      if (rr[i] < 0 || rr[i] > m[i] || rr[i] > n[i]) return fail(FPEPS_ERR_ARG, "bad kept rank");
+      e.r.push_back(rr[i]);
+      e.uoff.push_back(e.utotal);
+      e.voff.push_back(e.vtotal);
+      e.utotal += m[i] * rr[i];
+      e.vtotal += rr[i] * n[i];
+      mm[i] = m[i] - rr[i];
+      nn[i] = n[i] - rr[i];
+    }
+    FP_TRY(ctx->bufT("expl_U", (size_t)std::max<int64_t>(e.utotal, 1), &e.U));
+    FP_TRY(ctx->bufT("expl_V", (size_t)std::max<int64_t>(e.vtotal, 1), &e.V));
+    for (int i = 0; i < nmat; ++i) {
+      if (rr[i] == 0) continue;
+      FP_HIP(hipMemcpyAsync(e.U + e.uoff[i], Uin[i], m[i] * rr[i] * sizeof(double),
+                            hipMemcpyDeviceToDevice, ctx->stream));
+      FP_HIP(hipMemcpyAsync(e.V + e.voff[i], Vin[i], rr[i] * n[i] * sizeof(double),
+                            hipMemcpyDeviceToDevice, ctx->stream));
+    }
+  }
+  RsvdIO io;
+  io.m = e.m;
+  io.n = e.n;
+  for (int i = 0; i < nmat; ++i) io.c1.push_back((uint32_t)i);
+  io.c2 = (uint32_t)o->tag;
+  io.c3 = cbe ? (1u << 16) : 0u;
+  // widths follow the (residual) sizes: k_i = min(m_i', n_i', ceil(chi m_i'/sum m') + p)
+  const int chi = cbe ? o->cbe_extra : o->chi;
+  io.width_m = mm;
+  io.width_n = nn;
+  io.prepare = [&](const std::vector<int32_t>& k) { return explicit_prepare(ctx, e, k); };
+  io.apply = [&](bool t, const double* x, double* y) -> Status {
+    if (!t) {
+      double* xc = const_cast<double*>(x);
+      if (cbe) FP_TRY(project(ctx, e, false, xc, e.col_total));
+      FP_TRY(run_gemm(ctx, e.ps, e.pm, e.A, e.atotal, xc, e.col_total, y, e.row_total));
+      if (cbe) FP_TRY(project(ctx, e, true, y, e.row_total));
+    } else {
+      double* xc = const_cast<double*>(x);
+      if (cbe) FP_TRY(project(ctx, e, true, xc, e.row_total));
+      FP_TRY(run_gemm(ctx, e.ps, e.pt, e.A, e.atotal, xc, e.row_total, y, e.col_total));
+      if (cbe) FP_TRY(project(ctx, e, false, y, e.col_total));
+    }
+    return Status::ok();
+  };
+  RsvdOut rs;
+  FP_TRY(rsvd_run(ctx, io, chi, o->oversample, cbe ? 0 : o->power_iters, o->seed, rs, o->sv_cut));
+  // outputs
+  std::vector<int64_t> uoff(nmat), roff(nmat);
+  int64_t ut = 0, rt = 0;
+  for (int i = 0; i < nmat; ++i) {
+    uoff[i] = ut;
+    roff[i] = rt;
+    ut += e.m[i] * (int64_t)rs.kept[i];
+    rt += e.n[i] * (int64_t)rs.kept[i];
+  }
+  double *ub = nullptr, *rb = nullptr;
+  FP_TRY(ctx->bufT("expl_Uo", (size_t)std::max<int64_t>(ut, 1), &ub));
+  if (!cbe) FP_TRY(ctx->bufT("expl_Ro", (size_t)std::max<int64_t>(rt, 1), &rb));
+  FP_TRY(rsvd_factors(ctx, io, rs, uoff, ub, std::max<int64_t>(ut, 1), roff, cbe ? nullptr : rb,
+                      std::max<int64_t>(rt, 1)));
+  int64_t sp = 0;
+  for (int i = 0; i < nmat; ++i) {
+    kept[i] = rs.kept[i];
+    const int64_t c = rs.kept[i];
+    if (c > 0 && U_out && U_out[i])
+      FP_HIP(hipMemcpyAsync(U_out[i], ub + uoff[i], e.m[i] * c * sizeof(double),
+                            hipMemcpyDeviceToDevice, ctx->stream));
+    if (!cbe && c > 0 && R_out && R_out[i])
+      FP_HIP(hipMemcpyAsync(R_out[i], rb + roff[i], e.n[i] * c * sizeof(double),
+                            hipMemcpyDeviceToDevice, ctx->stream));
+    if (sigma)
+      for (int j = 0; j < c; ++j) {
+        const double l = rs.lam[rs.lam_off[i] + j];
+        sigma[sp++] = l > 0 ? std::sqrt(l) : 0.0;
+      }
+  }
+  FP_HIP(hipEventRecord(ev1, ctx->stream));
+  FP_HIP(hipEventSynchronize(ev1));
+  float ms = 0;
+  FP_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  if (rep) {
+    rep->seconds = ms * 1e-3;
+    rep->fallbacks = rs.fallbacks;
+    int tot = 0;
+    for (int v : rs.kept) tot += v;
+    rep->kept_total = tot;
+    rep->min_rel_gap = (rs.cut.s_next >= 0 && rs.cut.s_last > 0)
+                           ? (rs.cut.s_last - rs.cut.s_next) / rs.cut.s_last
+                           : -1.0;
+    rep->discarded_weight = rs.cut.total2 > 0 ? 1.0 - rs.cut.kept2 / rs.cut.total2 : 0.0;
+  }
+  return Status::ok();
+}
+
+// ---------------------------------------------------------------------------
+// overlap of two environments
+// ---------------------------------------------------------------------------
+Status overlap(fpeps_ctx_s* ctx, int L, const fpeps_tensor* top, const fpeps_tensor* bot,
+               double* value) {
+  if (L < 1 || !top || !bot || !value) return fail(FPEPS_ERR_ARG, "null argument");
+  const int nlab = top[0].nlab;
+  SymInfo none;
+  // E[at, ab]
+  BT E;
+  double* Ebuf[2] = {nullptr, nullptr};
+  FP_TRY(ctx->bufT("ov_E0", 1, &Ebuf[0]));
+  FP_HIP(launch_fill(Ebuf[0], 1, 1.0, ctx->stream));
+  int cur = 0;
+  int64_t Esize = 1;
+  for (int x = 0; x < L; ++x) {
+    BT T, B;
+    FP_TRY(tensor_to_bt(&top[x], {N_a, N_tk, N_tw, N_tb, N_b}, nlab, T));
+    FP_TRY(tensor_to_bt(&bot[x], {N_c, N_tk, N_tw, N_tb, N_j}, nlab, B));
+    if (x == 0) {
+      if (T.cat[0]->total() != 1 || B.cat[0]->total() != 1)
+        return fail(FPEPS_ERR_SHAPE, "left bonds of the environments must have dim 1");
+      E.names = {N_a, N_c};
+      E.cat = {T.cat[0], B.cat[0]};
+      Block b;
+      b.base = 0;
+      set_rowmajor(E, b);
+      E.blocks.push_back(b);
+      E.size = 1;
+    }
+    PlanSet ps;
+    std::string err;
+    StepSpec s1;
+    s1.step = 1;
+    s1.m_is_x = false;
+    s1.out_names = {N_c, N_tk, N_tw, N_tb, N_b};
+    s1.key_order = {N_a, N_c};
+    StepResult r1;
+    if (!plan_step(E, T, s1, none, ps.pool, nullptr, r1, err)) return fail(FPEPS_ERR_SHAPE, err);
+    StepSpec s2;
+    s2.step = 2;
+    s2.m_is_x = true;
+    s2.out_names = {N_b, N_j};
+    s2.key_order = {N_c, N_tk, N_tw, N_tb, N_b};
+    StepResult r2;
+    if (!plan_step(r1.out, B, s2, none, ps.pool, nullptr, r2, err))
+      return fail(FPEPS_ERR_SHAPE, err);
+    const int64_t xs = std::max<int64_t>(r1.out.size, 1), es = std::max<int64_t>(r2.out.size, 1);
+    int i1 = ps.add(std::move(r1.plan)), i2 = ps.add(std::move(r2.plan));
+    FP_TRY(ps.upload(ctx, "ov"));
+    double* X = nullptr;
+    FP_TRY(ctx->bufT("ov_X", (size_t)xs, &X));
+    const int nx = 1 - cur;
+    FP_TRY(ctx->bufT(nx ? "ov_E1" : "ov_E0b", (size_t)es, &Ebuf[nx]));
+    FP_TRY(run_gemm(ctx, ps, i1, top[x].data, top[x].nelem, Ebuf[cur], Esize, X, xs));
+    FP_TRY(run_gemm(ctx, ps, i2, X, xs, bot[x].data, bot[x].nelem, Ebuf[nx], es));
+    FP_TRY(ctx->sync());
+    E = BT();
+    E.names = {N_a, N_c};
+    E.cat = r2.out.cat;
+    E.blocks = r2.out.blocks;
+    E.size = es;
+    Esize = es;
+    cur = nx;
+  }
+  // sum of all entries of the final (1 x 1 per block) E
+  std::vector<double> h(Esize);
+  FP_HIP(hipMemcpyAsync(h.data(), Ebuf[cur], Esize * sizeof(double), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  FP_TRY(ctx->sync());
+  double v = 0;
+  for (const Block& b : E.blocks) v += h[b.base];
+  *value = v;
+  return Status::ok();
+}
+
+}  // namespace fp

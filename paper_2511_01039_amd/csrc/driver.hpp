@@ -1,0 +1,56 @@
+// Randomized SVD driver, row absorption, explicit-matrix rSVD / CBE and the
+// overlap of two environments (see driver.cpp).
+#pragma once
+
+#include <functional>
+#include <vector>
+
+#include "core.hpp"
+#include "site.hpp"
+
+namespace fp {
+
+// An operator given as independent sectors with per-sector row/column
+// counts m, n. ``prepare`` receives the sketch widths before the first
+// application; ``apply`` maps per-sector n_J x k_J matrices (concatenated in
+// sector order) to m_J x k_J ones, or back when transposed.
+struct RsvdIO {
+  std::vector<int64_t> m, n;
+  std::vector<int64_t> width_m, width_n;   // sizes deciding the widths (default m, n)
+  std::vector<uint32_t> c1;                // sketch counter word per sector
+  uint32_t c2 = 0, c3 = 0;
+  std::function<Status(const std::vector<int32_t>&)> prepare;
+  std::function<Status(bool, const double*, double*)> apply;
+};
+
+struct RsvdOut {
+  std::vector<int32_t> k, kept;
+  std::vector<int64_t> row_off, col_off, small_off, lam_off;
+  int64_t S = 0;
+  double* Q = nullptr;       // row layout
+  double* Bt = nullptr;      // column layout, B^T = M^T Q
+  double* small = nullptr;   // [G | eigenvectors | eigenvalues]
+  std::vector<double> lam;   // eigenvalues of B B^T, per sector descending
+  CutOut cut{};
+  uint32_t fallbacks = 0;
+};
+
+Status rsvd_run(fpeps_ctx_s* ctx, RsvdIO& io, int chi, int p, int q, uint64_t seed, RsvdOut& out,
+                double sv_cut);
+Status rsvd_factors(fpeps_ctx_s* ctx, const RsvdIO& io, const RsvdOut& r,
+                    const std::vector<int64_t>& uoff, double* Uout, int64_t u_size,
+                    const std::vector<int64_t>& roff, double* Rout, int64_t r_size);
+Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpeps_tensor* ket,
+                  const fpeps_tensor* pepo, const fpeps_opts* o, fpeps_tensor* env_out,
+                  double* log_norm, fpeps_report* rep);
+Status make_site(fpeps_ctx_s* ctx, const fpeps_tensor* R, const fpeps_tensor* T,
+                 const fpeps_tensor* A, const fpeps_tensor* W, const fpeps_opts* o, SiteOp& op);
+Status explicit_rsvd(fpeps_ctx_s* ctx, int nmat, const int64_t* m, const int64_t* n,
+                     const double* const* A, const fpeps_opts* o, double* const* U_out,
+                     double* const* R_out, int32_t* kept, double* sigma, fpeps_report* rep,
+                     const int32_t* r, const double* const* U, const double* const* V, bool cbe);
+Status overlap(fpeps_ctx_s* ctx, int L, const fpeps_tensor* top, const fpeps_tensor* bot,
+               double* value);
+Status axpy_inplace(fpeps_ctx_s* ctx, double* x, const double* y, int64_t n);
+
+}  // namespace fp

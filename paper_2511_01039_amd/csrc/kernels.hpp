@@ -1,0 +1,93 @@
+// Device kernel launchers (implemented in gemm.hip and linalg.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.hpp"
+
+namespace fp {
+
+// A GEMM plan resident on the device.
+struct DevGemm {
+  const GemmJob* jobs = nullptr;
+  const GemmPair* pairs = nullptr;
+  int njobs = 0;
+  int mt = 64, nt = 64;
+};
+
+// C[job tiles] = sum over pairs alpha * A(tables) * B(tables), FP64 MFMA.
+hipError_t launch_gemm_f64(const DevGemm& g, const double* A, const double* B, double* C,
+                           const int32_t* tables, hipStream_t s);
+
+// Sum of split-K partials: C(m, n) = sum_s P[p_off + s*M*N + m*N + n].
+struct ReduceDesc {
+  int64_t c_off, c_rs, c_cs, p_off;
+  int32_t M, N, nsplit, pad;
+};
+hipError_t launch_reduce_partials(const ReduceDesc* d, int nd, int max_mn, double* C,
+                                  const double* P, hipStream_t s);
+
+// Gaussian sketch: out[off + e] for e < nelem from Philox4x32-10 with
+// counter (e >> 1, c1, c2, c3) and key (seed lo, seed hi), Box-Muller.
+struct GaussDesc {
+  int64_t off, nelem;
+  uint32_t c1, c2, c3, pad;
+};
+hipError_t launch_gaussian(const GaussDesc* d, int nd, int64_t max_elem, double* out,
+                           uint64_t seed, hipStream_t s);
+
+// Cholesky with shift and triangular inverse per matrix (one workgroup each).
+struct SmallDesc {
+  int64_t a_off;    // k x k input (overwritten)
+  int64_t b_off;    // k x k output
+  int64_t c_off;    // k output values (eigenvalues)
+  int32_t k;
+  int32_t rows;     // rows of the tall matrix whose Gram this is (shift size)
+  double shift;     // relative shift (0: none)
+};
+hipError_t launch_chol_inv(const SmallDesc* d, int nd, double* buf, int* status, hipStream_t s);
+
+// Symmetric Jacobi eigensolver per matrix: A (k x k) -> eigenvalues
+// descending at c_off, eigenvectors as columns of the k x k matrix at b_off.
+hipError_t launch_jacobi_eig(const SmallDesc* d, int nd, int max_k, double* buf, int* status,
+                             hipStream_t s);
+
+// Global truncation over sectors: eigenvalues (descending per sector) at
+// lam_off[i] with k[i] entries; keeps the ``chi`` largest sqrt(lam).
+struct CutOut {
+  double total2;      // sum of all s^2
+  double kept2;       // sum of kept s^2
+  double s_last;      // smallest kept s
+  double s_next;      // largest cut s (or -1)
+};
+hipError_t launch_cut(const int64_t* lam_off, const int32_t* k, int nsect, int chi, int total,
+                      double sv_cut, const double* buf, int32_t* kept, CutOut* out, hipStream_t s);
+// SVQB scaling: column i of the k x k eigenvector matrix at b_off is
+// multiplied by 1/sqrt(lambda_i) (eigenvalues at c_off, descending), or set to
+// zero when lambda_i <= tau * lambda_0 (numerically null direction).
+hipError_t launch_svqb_scale(const SmallDesc* d, int nd, double* buf, double tau, hipStream_t s);
+
+// Canonical signs of a truncated factorisation: column c of U (m x ncol,
+// row-major at u_off) is flipped together with row c of R (ncol x n at
+// r_off) so that the column's leading entry is positive: the first row whose
+// magnitude is within a relative 1e-10 of the column's largest. One
+// workgroup per (matrix, column).
+struct SignDesc {
+  int64_t u_off, r_off;
+  int32_t m, ncol, n, col0;   // col0: first global column index of this matrix
+};
+hipError_t launch_sign_fix(const SignDesc* d, int nd, int total_cols, const int32_t* col_desc,
+                           double* U, double* R, hipStream_t s);
+
+// sum of squares of x[0..n) into *out (deterministic two-pass reduction).
+hipError_t launch_sumsq(const double* x, int64_t n, double* partial, double* out, hipStream_t s);
+hipError_t launch_scale(double* x, int64_t n, double a, hipStream_t s);
+hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
+// x[i] += y[i]
+hipError_t launch_add(double* x, const double* y, int64_t n, hipStream_t s);
+// 1 in *flag if any x is not finite
+hipError_t launch_check_finite(const double* x, int64_t n, int* flag, hipStream_t s);
+
+}  // namespace fp

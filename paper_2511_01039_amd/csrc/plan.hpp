@@ -1,0 +1,178 @@
+// Host planner of the block-sparse contraction chain.
+//
+// Every contraction of the chain (Sec. 3: the environment T, L, B contracted
+// with the ket, PEPO and bra layers) is planned as a list of small dense
+// products, one per pair of blocks that agree on the contracted legs. The
+// planner turns them into GEMM work for the device: for each output block a
+// list of (A block, B block, alpha) pairs and, for every operand, tables of
+// element offsets along the M, N and K index of the product. Output blocks
+// are disjoint, so each output tile is owned by one workgroup and needs no
+// atomics (the slices of Sec. 3 "do not overlap").
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+namespace fp {
+
+enum SymKind { SYM_NONE = 0, SYM_U1U1 = 1, SYM_SU2 = 2 };
+
+// Leg names of the chain (identifiers only; data layouts are per tensor).
+enum LegName : int {
+  N_a = 0, N_tk, N_tw, N_tb, N_b, N_rk, N_rw, N_rb, N_j, N_p, N_q, N_lk, N_lw, N_lb,
+  N_dk, N_dw, N_db, N_c, N_COUNT
+};
+
+constexpr int MAXL = 10;
+
+struct Leg {
+  int nlab = 1;
+  int dir = 1;
+  std::vector<int32_t> lab;  // nsect * nlab
+  std::vector<int32_t> dim;  // nsect
+  int nsect() const { return (int)dim.size(); }
+  const int32_t* label(int s) const { return lab.data() + (size_t)s * nlab; }
+  int64_t total() const {
+    int64_t t = 0;
+    for (int d : dim) t += d;
+    return t;
+  }
+  bool same_sectors(const Leg& o) const { return nlab == o.nlab && lab == o.lab && dim == o.dim; }
+};
+using LegP = std::shared_ptr<const Leg>;
+
+struct Block {
+  std::array<uint16_t, MAXL> sect{};   // sector index per storage position
+  int64_t base = 0;                    // element offset of element (0,...,0)
+  std::array<int64_t, MAXL> stride{};  // element stride per storage position
+};
+
+// Structure of a block-sparse tensor: leg names and catalogues in storage
+// order, and its blocks. ``size`` is the number of elements of the buffer
+// holding it (for bounds checks).
+struct BT {
+  std::vector<int> names;
+  std::vector<LegP> cat;
+  std::vector<Block> blocks;
+  int64_t size = 0;
+  int pos(int name) const {
+    for (size_t i = 0; i < names.size(); ++i)
+      if (names[i] == name) return (int)i;
+    return -1;
+  }
+  int nlegs() const { return (int)names.size(); }
+  int dim(const Block& b, int p) const { return cat[p]->dim[b.sect[p]]; }
+  int64_t block_elems(const Block& b) const {
+    int64_t n = 1;
+    for (int p = 0; p < nlegs(); ++p) n *= dim(b, p);
+    return n;
+  }
+};
+
+// Row-major contiguous strides for a block of ``bt`` given its sectors.
+void set_rowmajor(const BT& bt, Block& b);
+
+struct SymInfo {
+  int kind = SYM_NONE;
+  bool fermionic = false;
+  uint64_t coef_seed = 0;
+};
+
+// One block-pair product inside a GEMM job. Offsets are element offsets
+// relative to the A / B buffers; t* are offsets into the table pool.
+struct GemmPair {
+  int64_t a_off;
+  int64_t b_off;
+  int32_t K;
+  int32_t tam, tak, tbk, tbn;
+  int32_t flags;   // bit0: A rows contiguous along K; bit1: B contiguous along N
+  double alpha;
+};
+
+struct GemmJob {
+  int64_t c_off;
+  int32_t M, N;
+  int32_t m0, n0;
+  int32_t tcm, tcn;
+  int32_t p0, p1;   // pair range
+  int32_t k0, k1;   // K range inside each pair (split-K), k1 = INT32_MAX for all
+};
+
+struct TablePool {
+  std::vector<int32_t> data;
+  std::unordered_map<std::string, int32_t> index;
+  int32_t add(const std::vector<int32_t>& dims, const std::vector<int64_t>& strides, bool* ok);
+};
+
+struct GemmPlan {
+  std::vector<GemmJob> jobs;
+  std::vector<GemmPair> pairs;
+  double flops = 0;        // 2 m n k over all pairs (algorithmic)
+  int64_t a_extent = 0;    // largest element index + 1 read from A
+  int64_t b_extent = 0;
+  int64_t c_extent = 0;
+  int mt = 64, nt = 64;    // tile used for the jobs
+};
+
+// Tile shape choice for a list of output blocks (M, N) sizes.
+void choose_tile(const std::vector<std::pair<int64_t, int64_t>>& mn, int* mt, int* nt);
+
+// Per-pair scalar of a chain step: synthetic recoupling coefficient (SU(2))
+// times the parity sign. ``xlabs`` are the labels of the sketch-side
+// intermediate block in its canonical leg order, ``tlabs`` those of the step
+// tensor block; ``xshared``/``tshared`` flag the contracted legs.
+double pair_alpha(const SymInfo& sym, int step, const std::vector<const int32_t*>& xlabs,
+                  const std::vector<const int32_t*>& tlabs, const std::vector<bool>& xshared,
+                  const std::vector<bool>& tshared, int nlab);
+
+uint64_t splitmix64_mix(uint64_t z);
+
+// One contraction step. X and S are contracted over their shared leg names.
+// The output is created with leg storage order ``out_names`` (blocks sorted
+// by sector tuple, contiguous row-major, starting at offset 0) unless
+// ``fixed_out`` is given, in which case exactly those blocks are produced
+// (blocks of fixed_out without contributions are written as zeros).
+// ``m_is_x`` selects the operand whose free legs form the M index.
+// ``key_side`` (0: X, 1: output) names the tensor whose block labels, in
+// the canonical order ``key_order``, key the per-pair scalar.
+struct StepSpec {
+  int step = 0;                 // 1..5
+  bool m_is_x = true;
+  int key_side = 0;
+  std::vector<int> out_names;
+  std::vector<int> key_order;   // canonical leg order of the sketch-side intermediate
+  bool symbolic = false;        // only produce the output block structure
+  // with a fixed output layout: drop pairs whose output block lies outside it
+  // (restriction of the product to the layout's blocks) instead of failing
+  bool restrict_to_fixed = false;
+};
+
+struct StepResult {
+  BT out;
+  GemmPlan plan;
+};
+
+bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sym,
+               TablePool& pool, const BT* fixed_out, StepResult& res, std::string& err);
+
+// Build the GEMM jobs of a plain dense product C = alpha op(A) op(B) where all
+// three are strided matrices (used by the factorisation steps).
+struct DenseOp {
+  int64_t a_off, b_off, c_off;
+  int32_t M, N, K;
+  int64_t a_rs, a_cs;   // A(m, k) at a_off + m*a_rs + k*a_cs
+  int64_t b_rs, b_cs;   // B(k, n) at b_off + k*b_rs + n*b_cs
+  int64_t c_rs, c_cs;   // C(m, n) at c_off + m*c_rs + n*c_cs
+  double alpha;
+  int32_t ksplit = 0;   // > 1: this op's own K split (overrides the plan's)
+};
+// ``ksplit`` > 1 splits K into that many chunks written to consecutive
+// partial matrices (c_off + chunk * M * N, row-major M x N) for a later sum.
+bool plan_dense(const std::vector<DenseOp>& ops, TablePool& pool, int mt, int nt, int ksplit,
+                GemmPlan& plan, std::string& err);
+
+}  // namespace fp

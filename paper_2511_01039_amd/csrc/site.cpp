@@ -1,0 +1,423 @@
+// Site operator M_x: sector structure, sliced chain plans, application.
+#include "site.hpp"
+
+#include <algorithm>
+#include <map>
+
+namespace fp {
+
+const std::vector<int> ORDER_X[6] = {
+    {N_b, N_rk, N_rw, N_rb, N_j},
+    {N_a, N_tk, N_tw, N_tb, N_rk, N_rw, N_rb, N_j},
+    {N_a, N_tw, N_tb, N_rw, N_rb, N_j, N_p, N_lk, N_dk},
+    {N_a, N_tb, N_rb, N_j, N_lk, N_dk, N_q, N_lw, N_dw},
+    {N_a, N_j, N_lk, N_dk, N_lw, N_dw, N_lb, N_db},
+    {N_c, N_dk, N_dw, N_db, N_j},
+};
+
+// storage orders of the intermediates (chosen for contiguous access of the
+// two large products, steps 1 and 5 and their transposes)
+static const std::vector<int> STORE_X1 = {N_a, N_tk, N_tw, N_tb, N_rk, N_rw, N_rb, N_j};
+static const std::vector<int> STORE_X2 = {N_a, N_tw, N_tb, N_rw, N_rb, N_j, N_p, N_lk, N_dk};
+static const std::vector<int> STORE_X3 = {N_a, N_tb, N_rb, N_j, N_lk, N_dk, N_q, N_lw, N_dw};
+static const std::vector<int> STORE_X4 = {N_a, N_lk, N_lw, N_lb, N_dk, N_dw, N_db, N_j};
+
+Status tensor_to_bt(const fpeps_tensor* t, const std::vector<int>& names, int nlab, BT& out,
+                    bool flip_dirs) {
+  if (!t) return fail(FPEPS_ERR_ARG, "null tensor");
+  if (t->nlegs != (int)names.size())
+    return fail(FPEPS_ERR_SHAPE, "tensor has " + std::to_string(t->nlegs) + " legs, expected " +
+                                     std::to_string(names.size()));
+  if (t->nlab != nlab) return fail(FPEPS_ERR_SHAPE, "label count differs from the symmetry's");
+  if (!t->nsect || !t->dims || !t->labels || !t->dirs || (t->nblocks > 0 && (!t->block_sect || !t->block_off)))
+    return fail(FPEPS_ERR_ARG, "null structure array");
+  if (t->nblocks > 0 && !t->data) return fail(FPEPS_ERR_ARG, "null tensor data");
+  out = BT();
+  out.names = names;
+  for (int l = 0; l < t->nlegs; ++l) {
+    auto leg = std::make_shared<Leg>();
+    leg->nlab = nlab;
+    leg->dir = flip_dirs ? -t->dirs[l] : t->dirs[l];
+    const int ns = t->nsect[l];
+    if (ns <= 0 || ns > t->max_sect || ns > 65535)
+      return fail(FPEPS_ERR_SHAPE, "bad sector count");
+    for (int s = 0; s < ns; ++s) {
+      for (int i = 0; i < nlab; ++i)
+        leg->lab.push_back(t->labels[((int64_t)l * t->max_sect + s) * nlab + i]);
+      const int d = t->dims[(int64_t)l * t->max_sect + s];
+      if (d <= 0) return fail(FPEPS_ERR_SHAPE, "non-positive sector dimension");
+      leg->dim.push_back(d);
+    }
+    out.cat.push_back(leg);
+  }
+  for (int b = 0; b < t->nblocks; ++b) {
+    Block bk;
+    for (int l = 0; l < t->nlegs; ++l) {
+      const int s = t->block_sect[(int64_t)b * t->nlegs + l];
+      if (s < 0 || s >= t->nsect[l]) return fail(FPEPS_ERR_SHAPE, "block sector out of range");
+      bk.sect[l] = (uint16_t)s;
+    }
+    bk.base = t->block_off[b];
+    set_rowmajor(out, bk);
+    if (bk.base < 0 || bk.base + out.block_elems(bk) > t->nelem)
+      return fail(FPEPS_ERR_SHAPE, "block outside the tensor data");
+    out.blocks.push_back(bk);
+  }
+  out.size = t->nelem;
+  return Status::ok();
+}
+
+Status SiteOp::init(const SymInfo& s, int nlab_, BT&& T_, BT&& ket_, BT&& W_, BT&& R_,
+                    const SiteData& d) {
+  sym = s;
+  nlab = nlab_;
+  T = std::move(T_);
+  ket = std::move(ket_);
+  W = std::move(W_);
+  R = std::move(R_);
+  dev = d;
+  // the bra is the ket with reversed directions and its own leg names
+  bra = ket;
+  bra.names = {N_q, N_lb, N_rb, N_tb, N_db};
+  for (auto& c : bra.cat) {
+    auto l = std::make_shared<Leg>(*c);
+    l->dir = -l->dir;
+    c = l;
+  }
+  return Status::ok();
+}
+
+namespace {
+std::vector<std::vector<int32_t>> col_labels(const SymInfo& sym, int nlab,
+                                             const std::vector<const Leg*>& legs,
+                                             const std::array<uint16_t, 4>& t) {
+  std::vector<std::vector<int32_t>> out;
+  if (sym.kind == SYM_NONE) {
+    out.push_back(std::vector<int32_t>(nlab, 0));
+  } else if (sym.kind == SYM_U1U1) {
+    std::vector<int32_t> tot(nlab, 0);
+    for (int i = 0; i < 4; ++i)
+      for (int c = 0; c < nlab; ++c) tot[c] -= legs[i]->dir * legs[i]->label(t[i])[c];
+    out.push_back(tot);
+  } else {
+    int s = 0, mx = 0;
+    for (int i = 0; i < 4; ++i) {
+      const int tj = legs[i]->label(t[i])[0];
+      s += tj;
+      mx = std::max(mx, tj);
+    }
+    for (int J = 0; J <= s; ++J) {
+      const int tot = s + J;
+      if (tot % 2 == 0 && 2 * std::max(mx, J) <= tot) out.push_back(std::vector<int32_t>{J});
+    }
+  }
+  return out;
+}
+
+void sizes_by_sector(const BT& bt, int jpos, std::vector<int64_t>& acc) {
+  for (const Block& b : bt.blocks) acc[b.sect[jpos]] += bt.block_elems(b);
+}
+}  // namespace
+
+Status SiteOp::analyse() {
+  const int pb = T.pos(N_b), prk = ket.pos(N_rk), prw = W.pos(N_rw), prb = bra.pos(N_rb);
+  std::vector<const Leg*> cl = {T.cat[pb].get(), ket.cat[prk].get(), W.cat[prw].get(),
+                                bra.cat[prb].get()};
+  std::map<std::vector<int32_t>, Sector> by;
+  std::array<uint16_t, 4> t{};
+  for (t[0] = 0; t[0] < cl[0]->nsect(); ++t[0])
+    for (t[1] = 0; t[1] < cl[1]->nsect(); ++t[1])
+      for (t[2] = 0; t[2] < cl[2]->nsect(); ++t[2])
+        for (t[3] = 0; t[3] < cl[3]->nsect(); ++t[3]) {
+          int64_t d = 1;
+          for (int i = 0; i < 4; ++i) d *= cl[i]->dim[t[i]];
+          for (auto& J : col_labels(sym, nlab, cl, t)) {
+            Sector& s = by[J];
+            s.label = J;
+            s.cols.push_back(t);
+            s.crow.push_back(s.n);
+            s.cdim.push_back(d);
+            s.n += d;
+          }
+        }
+  sect.clear();
+  for (auto& kv : by) sect.push_back(std::move(kv.second));
+  const int ns = (int)sect.size();
+  if (ns == 0) return fail(FPEPS_ERR_SHAPE, "empty column space");
+
+  // structure-only pass with one column per sector: the rows of Y_J and the
+  // size of every intermediate per unit of width
+  std::vector<int32_t> k1(ns, 1);
+  std::vector<int64_t> off(ns);
+  int64_t tot = 0;
+  for (int J = 0; J < ns; ++J) {
+    off[J] = tot;
+    tot += sect[J].n;
+  }
+  std::vector<SliceCol> all;
+  for (int J = 0; J < ns; ++J) all.push_back({J, 0, 1});
+  BT X = omega_layout(all, k1, off, tot, false);
+  TablePool dummy;
+  std::string err;
+  const std::vector<int>* store[5] = {&STORE_X1, &STORE_X2, &STORE_X3, &STORE_X4, &ORDER_X[5]};
+  const BT* S[5] = {&T, &ket, &W, &bra, &R};
+  const bool mx[5] = {false, true, true, true, false};
+  unit_size.assign(ns, std::vector<int64_t>(8, 0));
+  std::vector<BT> fwd(5);
+  for (int s = 0; s < 5; ++s) {
+    StepSpec sp;
+    sp.step = s + 1;
+    sp.m_is_x = mx[s];
+    sp.key_side = 0;
+    sp.out_names = *store[s];
+    sp.key_order = ORDER_X[s];
+    sp.symbolic = true;
+    StepResult r;
+    if (!plan_step(s == 0 ? X : fwd[s - 1], *S[s], sp, sym, dummy, nullptr, r, err))
+      return fail(FPEPS_ERR_SHAPE, "chain step " + std::to_string(s + 1) + ": " + err);
+    fwd[s] = std::move(r.out);
+    if (s < 4) {
+      std::vector<int64_t> acc(ns, 0);
+      sizes_by_sector(fwd[s], fwd[s].pos(N_j), acc);
+      for (int J = 0; J < ns; ++J) unit_size[J][s] = acc[J];
+    }
+  }
+  // rows of every sector, lexicographic in (c, dk, dw, db)
+  const BT& Y = fwd[4];
+  for (const Block& b : Y.blocks) {
+    std::array<uint16_t, 4> r = {b.sect[0], b.sect[1], b.sect[2], b.sect[3]};
+    sect[b.sect[4]].rows.push_back(r);
+  }
+  for (auto& s : sect) {
+    std::sort(s.rows.begin(), s.rows.end());
+    s.m = 0;
+    for (auto& r : s.rows) {
+      int64_t d = R.cat[R.pos(N_c)]->dim[r[0]] * (int64_t)ket.cat[ket.pos(N_dk)]->dim[r[1]] *
+                  W.cat[W.pos(N_dw)]->dim[r[2]] * bra.cat[bra.pos(N_db)]->dim[r[3]];
+      s.rrow.push_back(s.m);
+      s.rdim.push_back(d);
+      s.m += d;
+    }
+  }
+  // backward structure from the row layout
+  int64_t rtot = 0;
+  std::vector<int64_t> roff(ns);
+  for (int J = 0; J < ns; ++J) {
+    roff[J] = rtot;
+    rtot += sect[J].m;
+  }
+  BT Z = omega_layout(all, k1, roff, rtot, true);
+  const std::vector<int>* bstore[5] = {&STORE_X4, &STORE_X3, &STORE_X2, &STORE_X1, &ORDER_X[0]};
+  const bool bmx[5] = {false, true, true, true, false};
+  const int bstep[5] = {5, 4, 3, 2, 1};
+  for (int s = 0; s < 4; ++s) {
+    StepSpec sp;
+    sp.step = bstep[s];
+    sp.m_is_x = bmx[s];
+    sp.key_side = 1;
+    sp.out_names = *bstore[s];
+    sp.key_order = ORDER_X[bstep[s] - 1];
+    sp.symbolic = true;
+    StepResult r;
+    if (!plan_step(Z, *S[bstep[s] - 1], sp, sym, dummy, nullptr, r, err))
+      return fail(FPEPS_ERR_SHAPE, "transposed chain step " + std::to_string(bstep[s]) + ": " + err);
+    Z = std::move(r.out);
+    std::vector<int64_t> acc(ns, 0);
+    sizes_by_sector(Z, Z.pos(N_j), acc);
+    for (int J = 0; J < ns; ++J) unit_size[J][4 + s] = acc[J];
+  }
+  return Status::ok();
+}
+
+BT SiteOp::omega_layout(const std::vector<SliceCol>& cols, const std::vector<int32_t>& k,
+                        const std::vector<int64_t>& off, int64_t total, bool rows) const {
+  BT bt;
+  auto jl = std::make_shared<Leg>();
+  jl->nlab = nlab;
+  jl->dir = -1;
+  for (auto& c : cols) {
+    for (int32_t v : sect[c.sect].label) jl->lab.push_back(v);
+    jl->dim.push_back(c.j1 - c.j0);
+  }
+  if (!rows) {
+    bt.names = {N_b, N_rk, N_rw, N_rb, N_j};
+    auto f = [](const LegP& l) {
+      auto m = std::make_shared<Leg>(*l);
+      m->dir = -m->dir;
+      return LegP(m);
+    };
+    bt.cat = {f(T.cat[T.pos(N_b)]), f(ket.cat[ket.pos(N_rk)]), f(W.cat[W.pos(N_rw)]),
+              f(bra.cat[bra.pos(N_rb)]), jl};
+  } else {
+    bt.names = {N_c, N_dk, N_dw, N_db, N_j};
+    bt.cat = {R.cat[R.pos(N_c)], ket.cat[ket.pos(N_dk)], W.cat[W.pos(N_dw)],
+              bra.cat[bra.pos(N_db)], jl};
+  }
+  for (int si = 0; si < (int)cols.size(); ++si) {
+    const SliceCol& c = cols[si];
+    const Sector& s = sect[c.sect];
+    const auto& tup = rows ? s.rows : s.cols;
+    const auto& r0 = rows ? s.rrow : s.crow;
+    const int64_t kj = k[c.sect];
+    for (size_t t = 0; t < tup.size(); ++t) {
+      Block b;
+      for (int i = 0; i < 4; ++i) b.sect[i] = tup[t][i];
+      b.sect[4] = (uint16_t)si;
+      b.base = off[c.sect] + r0[t] * kj + c.j0;
+      int64_t st = kj;
+      b.stride[4] = 1;
+      for (int i = 3; i >= 0; --i) {
+        b.stride[i] = st;
+        st *= bt.cat[i]->dim[tup[t][i]];
+      }
+      bt.blocks.push_back(b);
+    }
+  }
+  bt.size = total;
+  return bt;
+}
+
+Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t budget, Plans& out,
+                    bool with_bwd) {
+  const int ns = (int)sect.size();
+  if ((int)k.size() != ns) return fail(FPEPS_ERR_ARG, "width list does not match the sectors");
+  out = Plans();
+  out.col_off.resize(ns);
+  out.row_off.resize(ns);
+  for (int J = 0; J < ns; ++J) {
+    out.col_off[J] = out.col_total;
+    out.row_off[J] = out.row_total;
+    out.col_total += sect[J].n * (int64_t)k[J];
+    out.row_total += sect[J].m * (int64_t)k[J];
+  }
+  // slices: whole sectors packed greedily; a sector larger than the budget
+  // is split into column ranges
+  const double elem_budget = (double)budget / sizeof(double);
+  std::vector<std::vector<SliceCol>> slices;
+  std::vector<SliceCol> cur;
+  double used = 0;
+  for (int J = 0; J < ns; ++J) {
+    if (k[J] <= 0 || sect[J].m == 0) continue;
+    const auto& u = unit_size[J];
+    const double per = (double)std::max({u[0], u[2], u[5], u[7]}) +
+                       (double)std::max({u[1], u[3], u[4], u[6]});
+    if (used + per * k[J] <= elem_budget) {
+      cur.push_back({J, 0, k[J]});
+      used += per * k[J];
+      continue;
+    }
+    if (!cur.empty()) {
+      slices.push_back(cur);
+      cur.clear();
+      used = 0;
+    }
+    int w = per > 0 ? (int)std::max(1.0, std::floor(elem_budget / per)) : k[J];
+    w = std::min(w, (int)k[J]);
+    for (int j0 = 0; j0 < k[J]; j0 += w) {
+      const int j1 = std::min((int)k[J], j0 + w);
+      if (j1 - j0 == w && j1 < k[J]) {
+        slices.push_back({{J, j0, j1}});
+      } else {
+        cur.push_back({J, j0, j1});
+        used = per * (j1 - j0);
+      }
+    }
+  }
+  if (!cur.empty()) slices.push_back(cur);
+
+  std::string err;
+  const std::vector<int>* store[5] = {&STORE_X1, &STORE_X2, &STORE_X3, &STORE_X4, &ORDER_X[5]};
+  const BT* S[5] = {&T, &ket, &W, &bra, &R};
+  const bool mx[5] = {false, true, true, true, false};
+  const std::vector<int>* bstore[5] = {&STORE_X4, &STORE_X3, &STORE_X2, &STORE_X1, &ORDER_X[0]};
+  const int bstep[5] = {5, 4, 3, 2, 1};
+  for (auto& sc : slices) {
+    Slice sl;
+    sl.cols = sc;
+    BT colL = omega_layout(sc, k, out.col_off, out.col_total, false);
+    BT rowL = omega_layout(sc, k, out.row_off, out.row_total, true);
+    BT X = colL;
+    for (int s = 0; s < 5; ++s) {
+      StepSpec sp;
+      sp.step = s + 1;
+      sp.m_is_x = mx[s];
+      sp.key_side = 0;
+      sp.out_names = *store[s];
+      sp.key_order = ORDER_X[s];
+      StepResult r;
+      if (!plan_step(X, *S[s], sp, sym, out.ps.pool, s == 4 ? &rowL : nullptr, r, err))
+        return fail(FPEPS_ERR_SHAPE, "chain step " + std::to_string(s + 1) + ": " + err);
+      out.flops_fwd += r.plan.flops;
+      if (s < 4) {
+        if (s % 2 == 0)
+          sl.size1 = std::max(sl.size1, r.out.size);
+        else
+          sl.size2 = std::max(sl.size2, r.out.size);
+      }
+      sl.fwd[s] = out.ps.add(std::move(r.plan));
+      X = std::move(r.out);
+    }
+    if (with_bwd) {
+      BT Z = rowL;
+      for (int s = 0; s < 5; ++s) {
+        StepSpec sp;
+        sp.step = bstep[s];
+        sp.m_is_x = mx[bstep[s] - 1];
+        sp.key_side = 1;
+        sp.out_names = *bstore[s];
+        sp.key_order = ORDER_X[bstep[s] - 1];
+        // M^T is the transpose of M on M's domain: the column tuples of each
+        // sector (synthetic SU(2) scalars can reach others, which are dropped)
+        sp.restrict_to_fixed = true;
+        StepResult r;
+        if (!plan_step(Z, *S[bstep[s] - 1], sp, sym, out.ps.pool, s == 4 ? &colL : nullptr, r, err))
+          return fail(FPEPS_ERR_SHAPE,
+                      "transposed chain step " + std::to_string(bstep[s]) + ": " + err);
+        out.flops_bwd += r.plan.flops;
+        if (s < 4) {
+          if (s % 2 == 0)
+            sl.size2 = std::max(sl.size2, r.out.size);
+          else
+            sl.size1 = std::max(sl.size1, r.out.size);
+        }
+        sl.bwd[s] = out.ps.add(std::move(r.plan));
+        Z = std::move(r.out);
+      }
+    } else {
+      for (int s = 0; s < 5; ++s) sl.bwd[s] = -1;
+    }
+    out.ws1 = std::max(out.ws1, sl.size1);
+    out.ws2 = std::max(out.ws2, sl.size2);
+    out.slices.push_back(sl);
+  }
+  FP_TRY(out.ps.upload(ctx, "site"));
+  ctx->peak_ws = std::max(ctx->peak_ws, (double)(out.ws1 + out.ws2) * sizeof(double));
+  ctx->nslices = std::max(ctx->nslices, (int)out.slices.size());
+  return Status::ok();
+}
+
+Status SiteOp::apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const double* x, double* y) {
+  double *b1 = nullptr, *b2 = nullptr;
+  FP_TRY(ctx->bufT("chain1", (size_t)std::max<int64_t>(pl.ws1, 1), &b1));
+  FP_TRY(ctx->bufT("chain2", (size_t)std::max<int64_t>(pl.ws2, 1), &b2));
+  const int64_t s1 = std::max<int64_t>(pl.ws1, 1), s2 = std::max<int64_t>(pl.ws2, 1);
+  for (const Slice& sl : pl.slices) {
+    if (!transpose) {
+      FP_TRY(run_gemm(ctx, pl.ps, sl.fwd[0], dev.T, dev.T_size, x, pl.col_total, b1, s1, true));
+      FP_TRY(run_gemm(ctx, pl.ps, sl.fwd[1], b1, s1, dev.A, dev.A_size, b2, s2, true));
+      FP_TRY(run_gemm(ctx, pl.ps, sl.fwd[2], b2, s2, dev.W, dev.W_size, b1, s1, true));
+      FP_TRY(run_gemm(ctx, pl.ps, sl.fwd[3], b1, s1, dev.A, dev.A_size, b2, s2, true));
+      FP_TRY(run_gemm(ctx, pl.ps, sl.fwd[4], dev.R, dev.R_size, b2, s2, y, pl.row_total, true));
+    } else {
+      if (sl.bwd[0] < 0) return fail(FPEPS_ERR_ARG, "transposed chain was not planned");
+      FP_TRY(run_gemm(ctx, pl.ps, sl.bwd[0], dev.R, dev.R_size, x, pl.row_total, b2, s2, true));
+      FP_TRY(run_gemm(ctx, pl.ps, sl.bwd[1], b2, s2, dev.A, dev.A_size, b1, s1, true));
+      FP_TRY(run_gemm(ctx, pl.ps, sl.bwd[2], b1, s1, dev.W, dev.W_size, b2, s2, true));
+      FP_TRY(run_gemm(ctx, pl.ps, sl.bwd[3], b2, s2, dev.A, dev.A_size, b1, s1, true));
+      FP_TRY(run_gemm(ctx, pl.ps, sl.bwd[4], dev.T, dev.T_size, b1, s1, y, pl.col_total, true));
+    }
+  }
+  return Status::ok();
+}
+
+}  // namespace fp

@@ -1,0 +1,87 @@
+// The implicit site operator M_x of one zip-up step and its transpose, as a
+// chain of planned block-sparse contractions (Sec. 3 contraction pattern
+// 2(a), applied layer by layer; Sec. 4 matrix A).
+#pragma once
+
+#include <array>
+#include <vector>
+
+#include "core.hpp"
+
+namespace fp {
+
+struct Sector {
+  std::vector<int32_t> label;                     // nlab ints
+  std::vector<std::array<uint16_t, 4>> cols;      // (b, rk, rw, rb) sector tuples
+  std::vector<int64_t> crow;                      // first row of each tuple in the n x k matrix
+  std::vector<int64_t> cdim;                      // rows of each tuple
+  int64_t n = 0;
+  std::vector<std::array<uint16_t, 4>> rows;      // (c, dk, dw, db) tuples
+  std::vector<int64_t> rrow, rdim;
+  int64_t m = 0;
+};
+
+struct SliceCol {
+  int sect;      // sector ordinal
+  int j0, j1;    // column range of that sector
+};
+
+// Device tensors of one site (all double, caller or library memory).
+struct SiteData {
+  const double* T = nullptr;
+  const double* A = nullptr;
+  const double* W = nullptr;
+  const double* R = nullptr;
+  int64_t T_size = 0, A_size = 0, W_size = 0, R_size = 0;
+};
+
+class SiteOp {
+ public:
+  SymInfo sym;
+  int nlab = 1;
+  BT T, ket, W, bra, R;
+  SiteData dev;
+  std::vector<Sector> sect;
+  std::vector<std::vector<int64_t>> unit_size;  // [sector][8]: elements per unit width of X1..X4, Z4..Z1
+
+  // Build legs/blocks. R is the remainder [c, a, lk, lw, lb].
+  Status init(const SymInfo& s, int nlab_, BT&& T_, BT&& ket_, BT&& W_, BT&& R_,
+              const SiteData& d);
+  // Sector structure (columns, rows via a structure-only forward pass).
+  Status analyse();
+
+  // Plans of M (fwd) and M^T (bwd) for per-sector widths k, sliced so that
+  // the chain intermediates of one slice fit ``budget`` bytes.
+  struct Slice {
+    std::vector<SliceCol> cols;
+    int fwd[5], bwd[5];       // plan indices in the PlanSet
+    int64_t size1 = 0, size2 = 0;  // ping-pong intermediate buffer sizes (elements)
+  };
+  struct Plans {
+    PlanSet ps;
+    std::vector<Slice> slices;
+    std::vector<int64_t> col_off, row_off;   // per sector offsets for width k
+    int64_t col_total = 0, row_total = 0;
+    int64_t ws1 = 0, ws2 = 0;
+    double flops_fwd = 0, flops_bwd = 0;
+  };
+  Status plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t budget, Plans& out,
+              bool with_bwd = true);
+  // y = M x (transpose = false) or M^T x, per-sector matrices at the offsets
+  // of ``pl`` (x: col layout for M, row layout for M^T).
+  Status apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const double* x, double* y);
+
+ private:
+  BT omega_layout(const std::vector<SliceCol>& cols, const std::vector<int32_t>& k,
+                  const std::vector<int64_t>& off, int64_t total, bool rows) const;
+};
+
+// Convert an fpeps_tensor into a planner BT with the given leg names.
+Status tensor_to_bt(const fpeps_tensor* t, const std::vector<int>& names, int nlab, BT& out,
+                    bool flip_dirs = false);
+
+// Canonical leg orders of the chain intermediates (the keys of the per-pair
+// scalars): X0 = Omega, X1 .. X4, Y.
+extern const std::vector<int> ORDER_X[6];
+
+}  // namespace fp

@@ -128,3 +128,13 @@ def test_cbe_spans_top_subspace_of_residual():
     Q = out["Q"][0]
     assert np.abs(Q @ Q.T - Ur[:, :4] @ Ur[:, :4].T).max() < 1e-10
     assert np.allclose(out["sigma"][0], s[:4], rtol=1e-10)
+
+
+def test_numerically_zero_singular_values_are_never_kept():
+    """Rank-deficient sectors: with chi above the total rank the cut keeps
+    exactly the rank (values below sv_cut * max carry no defined vectors)."""
+    mats = [prescribed(40, 30, np.linspace(3, 1, 6), 1)[0], prescribed(20, 50, np.linspace(2, 1, 3), 2)[0]]
+    out = rsvd_explicit(mats, chi=25, p=10, q=1, seed=3)
+    assert out["kept"] == [6, 3]
+    for U in out["U"]:
+        assert np.abs(U.T @ U - np.eye(U.shape[1])).max() < 1e-13

@@ -8,5 +8,5 @@ from .configs import (Sym, Lattice, RowProblem, block_allowed, largest_remainder
                       legs_dense, legs_u1u1, legs_su2, legs_u1u1_mini, legs_su2_mini, random_tensor, hubbard_pepo,
                       hubbard_pepo_site, hubbard_local_ops, identity_pepo, trivial_env,
                       random_top_env, random_peps, random_symmetric_pepo, config1_lattice,
-                      config1_params, config2_row, config3_row, config4_row, small_row,
+                      config1_params, config2_row, random_bottom_env, config3_row, config4_row, small_row,
                       KET_DIRS, PEPO_DIRS, ENV_DIRS)

@@ -446,3 +446,19 @@ def small_row(kind="none", L=3, d=2, D=2, w=2, chi=4, seed=0, oversample=2, powe
     T = random_top_env(sym, cat, A, W, rng) if interior else trivial_env(sym, L)
     return RowProblem(sym, T, A, W, chi, oversample, power_iters, seed, y,
                       meta=dict(config="small", kind=kind, cat=cat))
+
+
+def random_bottom_env(sym, top_env, bond_leg, rng):
+    """A random environment whose bundle legs face those of ``top_env``
+    (same sectors, reversed directions) with bonds ``bond_leg`` (dim 1 at the
+    two ends). Used to read a gauge-invariant number off a new environment."""
+    L = len(top_env)
+    bnd = Leg.make([(sym.zero_label(), 1)])
+    out = []
+    for x, t in enumerate(top_env):
+        a = bnd if x == 0 else bond_leg
+        b = bnd if x == L - 1 else bond_leg
+        legs = [Leg(a.labels, a.dims, -1)] + [t.legs[i].flipped() for i in (1, 2, 3)] + \
+               [Leg(b.labels, b.dims, 1)]
+        out.append(random_tensor(sym, legs, rng))
+    return out
