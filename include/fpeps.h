@@ -125,7 +125,7 @@ typedef struct {
 
 #define FPEPS_FLAG_NO_GRAPH 1u      /* do not capture per-site launch sequences */
 #define FPEPS_FLAG_CHECK_FINITE 2u  /* scan inputs for NaN/Inf first */
-#define FPEPS_FLAG_TIME_KERNELS 4u  /* time every chain GEMM launch with HIP events */
+#define FPEPS_FLAG_TIME_KERNELS 4u  /* time every chain launch with HIP events */
 
 typedef struct {
   double alg_flops;        /* algorithmic flop count (block-pair GEMMs + factorisations) */
@@ -140,9 +140,21 @@ typedef struct {
   int32_t required_blocks; /* on FPEPS_ERR_CAPACITY: blocks needed */
   int64_t required_elem;   /* on FPEPS_ERR_CAPACITY: elements needed */
   int32_t required_sect;   /* on FPEPS_ERR_CAPACITY: sectors per leg needed */
-  int32_t kernel_launches; /* FPEPS_FLAG_TIME_KERNELS: chain GEMM launches timed */
+  int32_t kernel_launches; /* FPEPS_FLAG_TIME_KERNELS: chain launches timed */
   double kernel_seconds;   /* FPEPS_FLAG_TIME_KERNELS: sum of their durations (HIP events) */
   double kernel_flops;     /* algorithmic flops (2 m n k over block pairs) of those launches */
+  /* the same split by kernel class (FPEPS_FLAG_TIME_KERNELS):
+   * layer steps = ket, PEPO and bra contractions and their transposes
+   * (HBM bound; bytes = distinct input blocks read once + output written once),
+   * contractions = environment site and remainder products (MFMA) */
+  int32_t layer_launches;
+  double layer_seconds;
+  double layer_flops;
+  double layer_bytes;
+  int32_t gemm_launches;
+  double gemm_seconds;
+  double gemm_flops;
+  double gemm_bytes;
 } fpeps_report;
 
 /* Context: one per host thread. ``stream`` is a hipStream_t (NULL: default

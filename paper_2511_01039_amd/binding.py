@@ -55,7 +55,11 @@ class CReport(C.Structure):
                 ("kept_total", C.c_int32), ("nslices", C.c_int32), ("fallbacks", C.c_uint32),
                 ("required_blocks", C.c_int32), ("required_elem", C.c_int64),
                 ("required_sect", C.c_int32), ("kernel_launches", C.c_int32),
-                ("kernel_seconds", C.c_double), ("kernel_flops", C.c_double)]
+                ("kernel_seconds", C.c_double), ("kernel_flops", C.c_double),
+                ("layer_launches", C.c_int32), ("layer_seconds", C.c_double),
+                ("layer_flops", C.c_double), ("layer_bytes", C.c_double),
+                ("gemm_launches", C.c_int32), ("gemm_seconds", C.c_double),
+                ("gemm_flops", C.c_double), ("gemm_bytes", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

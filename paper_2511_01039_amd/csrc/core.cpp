@@ -70,9 +70,16 @@ fp::Status fpeps_ctx_s::harvest_timing() {
     kt_seconds += ms * 1e-3;
     kt_flops += evflops[i / 2];
     ++kt_launches;
+    auto& b = kt_by_label[evlabel[i / 2]];
+    b[0] += ms * 1e-3;
+    b[1] += evflops[i / 2];
+    b[2] += 1;
+    b[3] += evbytes[i / 2];
   }
   evused = 0;
   evflops.clear();
+  evlabel.clear();
+  evbytes.clear();
   return fp::Status::ok();
 }
 
@@ -81,8 +88,12 @@ namespace fp {
 Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
   std::vector<GemmJob> jobs;
   std::vector<GemmPair> pairs;
+  std::vector<ReduceTab> reds;
+  std::vector<size_t> red0;
   std::vector<std::pair<size_t, size_t>> range;
   for (auto& p : plans) {
+    red0.push_back(reds.size());
+    reds.insert(reds.end(), p.reduces.begin(), p.reduces.end());
     const int32_t base = (int32_t)pairs.size();
     const size_t j0 = jobs.size();
     for (auto j : p.jobs) {
@@ -95,11 +106,71 @@ Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
   }
   if (pairs.size() > (size_t)INT32_MAX || jobs.size() > (size_t)INT32_MAX)
     return fail(FPEPS_ERR_UNSUPPORTED, "plan too large");
+  // row-thread plans, concatenated with rebased ranges
+  std::vector<RtGroup> rg;
+  std::vector<RtOut> ro;
+  std::vector<RtPair> rp;
+  std::vector<RtPack> rk;
+  struct R4 {
+    size_t g, o, p, k;
+  };
+  std::vector<R4> rr;
+  pack_off.clear();
+  pack_total = 0;
+  for (auto& r : rts) {
+    R4 b{rg.size(), ro.size(), rp.size(), rk.size()};
+    rr.push_back(b);
+    pack_off.push_back(pack_total);
+    for (auto g : r.groups) {
+      g.o0 += (int32_t)b.o;
+      g.o1 += (int32_t)b.o;
+      rg.push_back(g);
+    }
+    for (auto o : r.outs) {
+      o.p0 += (int32_t)b.p;
+      o.p1 += (int32_t)b.p;
+      ro.push_back(o);
+    }
+    for (auto p : r.pairs) {
+      p.pk += pack_total;
+      rp.push_back(p);
+    }
+    for (auto k : r.packs) {
+      k.dst += pack_total;
+      rk.push_back(k);
+    }
+    pack_total += r.pack_size;
+    if (ro.size() > (size_t)INT32_MAX || rp.size() > (size_t)INT32_MAX ||
+        rk.size() > (size_t)INT32_MAX)
+      return fail(FPEPS_ERR_UNSUPPORTED, "layer plan too large");
+  }
   void *dj = nullptr, *dp = nullptr, *dt = nullptr;
   FP_TRY(ctx->upload(tag + "_jobs", jobs.data(), jobs.size() * sizeof(GemmJob), &dj));
   FP_TRY(ctx->upload(tag + "_pairs", pairs.data(), pairs.size() * sizeof(GemmPair), &dp));
   FP_TRY(ctx->upload(tag + "_tab", pool.data.data(), pool.data.size() * sizeof(int32_t), &dt));
   dtab = (int32_t*)dt;
+  void* dr = nullptr;
+  FP_TRY(ctx->upload(tag + "_red", reds.data(), reds.size() * sizeof(ReduceTab), &dr));
+  void *dg = nullptr, *dO = nullptr, *dP = nullptr, *dK = nullptr, *dpk = nullptr;
+  FP_TRY(ctx->upload(tag + "_rtg", rg.data(), rg.size() * sizeof(RtGroup), &dg));
+  FP_TRY(ctx->upload(tag + "_rto", ro.data(), ro.size() * sizeof(RtOut), &dO));
+  FP_TRY(ctx->upload(tag + "_rtp", rp.data(), rp.size() * sizeof(RtPair), &dP));
+  FP_TRY(ctx->upload(tag + "_rtk", rk.data(), rk.size() * sizeof(RtPack), &dK));
+  FP_TRY(ctx->buf(tag + "_pack", (size_t)std::max<int64_t>(pack_total, 1) * sizeof(double), &dpk));
+  dpack = (double*)dpk;
+  this->tag = tag;
+  drt.clear();
+  for (size_t i = 0; i < rts.size(); ++i) {
+    DevRt d;
+    d.groups = (const RtGroup*)dg + rr[i].g;
+    d.outs = (const RtOut*)dO;
+    d.pairs = (const RtPair*)dP;
+    d.packs = (const RtPack*)dK + rr[i].k;
+    d.ngroups = (int)rts[i].groups.size();
+    d.ntiles = rts[i].ntiles;
+    d.npacks = (int)rts[i].packs.size();
+    drt.push_back(d);
+  }
   dev.clear();
   for (size_t i = 0; i < plans.size(); ++i) {
     DevGemm g;
@@ -108,13 +179,51 @@ Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
     g.njobs = (int)range[i].second;
     g.mt = plans[i].mt;
     g.nt = plans[i].nt;
+    g.reduces = (const ReduceTab*)dr + red0[i];
+    g.nred = (int)plans[i].reduces.size();
     dev.push_back(g);
   }
   return Status::ok();
 }
 
+Status PlanSet::pack(fpeps_ctx_s* ctx, int idx, const double* S, int64_t s_size) {
+  const RtPlan& r = rts[idx];
+  if (r.packs.empty()) return Status::ok();
+  if (r.s_extent > s_size)
+    return fail(FPEPS_ERR_SHAPE, "layer pack reaches outside the layer tensor");
+  if (!S || !dpack) return fail(FPEPS_ERR_ARG, "null layer tensor");
+  FP_HIP(launch_rt_pack(drt[idx], S, dtab, dpack, ctx->stream));
+  return Status::ok();
+}
+
+Status run_rt(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* X, int64_t x_size,
+              double* Y, int64_t y_size, bool timed, int label) {
+  const RtPlan& p = ps.rts[idx];
+  if (p.ntiles == 0) return Status::ok();
+  if (p.x_extent > x_size || p.c_extent > y_size)
+    return fail(FPEPS_ERR_SHAPE, "layer plan reaches outside a buffer (x " +
+                                     std::to_string(p.x_extent) + "/" + std::to_string(x_size) +
+                                     ", y " + std::to_string(p.c_extent) + "/" +
+                                     std::to_string(y_size) + ")");
+  if (!X || !Y) return fail(FPEPS_ERR_ARG, "null operand buffer");
+  if (timed && ctx->time_kernels) {
+    hipEvent_t a, b;
+    FP_TRY(ctx->timed_events(&a, &b));
+    ctx->evflops.push_back(p.flops);
+    ctx->evlabel.push_back(label);
+    ctx->evbytes.push_back(p.bytes);
+    FP_HIP(hipEventRecord(a, ctx->stream));
+    FP_HIP(launch_rt_f64(ps.drt[idx], X, ps.dpack, Y, ps.dtab, ctx->stream));
+    FP_HIP(hipEventRecord(b, ctx->stream));
+    return Status::ok();
+  }
+  FP_HIP(launch_rt_f64(ps.drt[idx], X, ps.dpack, Y, ps.dtab, ctx->stream));
+  return Status::ok();
+}
+
 Status run_gemm(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A, int64_t a_size,
-                const double* B, int64_t b_size, double* C, int64_t c_size, bool timed) {
+                const double* B, int64_t b_size, double* C, int64_t c_size, bool timed,
+                int label) {
   const GemmPlan& p = ps.plans[idx];
   if (p.jobs.empty()) return Status::ok();
   // every table-addressed access must stay inside its buffer
@@ -125,16 +234,22 @@ Status run_gemm(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A, i
                                      ", c " + std::to_string(p.c_extent) + "/" +
                                      std::to_string(c_size) + ")");
   if (!A || !B || !C) return fail(FPEPS_ERR_ARG, "null operand buffer");
-  if (timed && ctx->time_kernels) {
-    hipEvent_t a, b;
-    FP_TRY(ctx->timed_events(&a, &b));
+  double* target = C;
+  if (p.partial_size > 0) FP_TRY(ctx->bufT("gemm_part", (size_t)p.partial_size, &target));
+  hipEvent_t ea = nullptr, eb = nullptr;
+  const bool tk = timed && ctx->time_kernels;
+  if (tk) {
+    FP_TRY(ctx->timed_events(&ea, &eb));
     ctx->evflops.push_back(p.flops);
-    FP_HIP(hipEventRecord(a, ctx->stream));
-    FP_HIP(launch_gemm_f64(ps.dev[idx], A, B, C, ps.dtab, ctx->stream));
-    FP_HIP(hipEventRecord(b, ctx->stream));
-    return Status::ok();
+    ctx->evlabel.push_back(label);
+    ctx->evbytes.push_back(p.bytes);
+    FP_HIP(hipEventRecord(ea, ctx->stream));
   }
-  FP_HIP(launch_gemm_f64(ps.dev[idx], A, B, C, ps.dtab, ctx->stream));
+  FP_HIP(launch_gemm_f64(ps.dev[idx], A, B, target, ps.dtab, ctx->stream));
+  if (p.partial_size > 0)
+    FP_HIP(launch_reduce_tab(ps.dev[idx].reduces, ps.dev[idx].nred, p.max_red_mn, C, target,
+                             ps.dtab, ctx->stream));
+  if (tk) FP_HIP(hipEventRecord(eb, ctx->stream));
   return Status::ok();
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <array>
 #include <map>
 #include <memory>
 #include <string>
@@ -69,6 +70,10 @@ struct fpeps_ctx_s {
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
   std::vector<double> evflops;
+  std::vector<int> evlabel;
+  std::vector<double> evbytes;
+  // label -> {seconds, flops, launches, algorithmic bytes}
+  std::map<int, std::array<double, 4>> kt_by_label;
   double kt_seconds = 0, kt_flops = 0;
   long kt_launches = 0;
   bool verbose = false;
@@ -98,15 +103,30 @@ struct PlanSet {
   TablePool pool;
   std::vector<GemmPlan> plans;
   std::vector<DevGemm> dev;
+  std::vector<RtPlan> rts;
+  std::vector<DevRt> drt;
+  std::vector<int64_t> pack_off;   // per row-thread plan, into the pack buffer
+  int64_t pack_total = 0;
+  double* dpack = nullptr;
   int32_t* dtab = nullptr;
+  std::string tag;
   Status upload(fpeps_ctx_s* ctx, const std::string& tag);
   int add(GemmPlan&& p) {
     plans.push_back(std::move(p));
     return (int)plans.size() - 1;
   }
+  int add_rt(RtPlan&& p) {
+    rts.push_back(std::move(p));
+    return (int)rts.size() - 1;
+  }
+  // fill the packed layer sub-blocks of row-thread plan ``idx`` from S
+  Status pack(fpeps_ctx_s* ctx, int idx, const double* S, int64_t s_size);
 };
 
 Status run_gemm(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A, int64_t a_size,
-                const double* B, int64_t b_size, double* C, int64_t c_size, bool timed = false);
+                const double* B, int64_t b_size, double* C, int64_t c_size, bool timed = false,
+                int label = 0);
+Status run_rt(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* X, int64_t x_size,
+              double* Y, int64_t y_size, bool timed = false, int label = 0);
 
 }  // namespace fp

@@ -513,6 +513,9 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
   ctx->kt_launches = 0;
   ctx->evused = 0;
   ctx->evflops.clear();
+  ctx->evlabel.clear();
+  ctx->evbytes.clear();
+  ctx->kt_by_label.clear();
   ctx->verbose = std::getenv("FPEPS_VERBOSE") != nullptr;
   auto wall = [] { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
   hipEvent_t ev0, ev1;
@@ -658,7 +661,13 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     }
     io.c2 = (uint32_t)x;
     io.c3 = (uint32_t)(o->row & 0xFFFF);
-    io.prepare = [&](const std::vector<int32_t>& k) { return op.plan(ctx, k, budget, pl, true); };
+    double t_plan = 0;
+    io.prepare = [&](const std::vector<int32_t>& k) {
+      const double t0 = wall();
+      Status st = op.plan(ctx, k, budget, pl, true);
+      t_plan += wall() - t0;
+      return st;
+    };
     io.apply = [&](bool t, const double* xi, double* yo) { return op.apply(ctx, pl, t, xi, yo); };
     RsvdOut rs;
     const double tw1 = wall();
@@ -673,11 +682,17 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
         mt += op.sect[J].m;
         nt += op.sect[J].n;
       }
+      double xl = 0, pk = 0;
+      for (const RtPlan& r : pl.ps.rts) {
+        xl += r.x_loads;
+        pk += (double)r.pack_size;
+      }
       std::fprintf(stderr,
-                   "[fpeps] site %d: sectors %d m %lld n %lld analyse %.3fs rsvd(incl. plan) %.3fs "
-                   "chain flops/app %.3e slices %zu ws %.2f GB pairs %zu\n",
-                   x, ns, (long long)mt, (long long)nt, tw1 - tw0, wall() - tw1, pl.flops_fwd,
-                   pl.slices.size(), (pl.ws1 + pl.ws2) * 8e-9, pl.ps.pool.data.size());
+                   "[fpeps] site %d: sectors %d m %lld n %lld analyse %.3fs rsvd %.3fs (plan %.3fs) "
+                   "chain flops/app %.3e slices %zu ws %.2f GB table entries %zu layer loads "
+                   "%.3e pack %.3e\n",
+                   x, ns, (long long)mt, (long long)nt, tw1 - tw0, wall() - tw1, t_plan, pl.flops_fwd,
+                   pl.slices.size(), (pl.ws1 + pl.ws2) * 8e-9, pl.ps.pool.data.size(), xl, pk);
     }
     // outputs: environment site (U) and the next remainder (R)
     std::vector<int> sel;
@@ -812,6 +827,23 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     rep->kernel_launches = (int32_t)ctx->kt_launches;
     rep->kernel_seconds = ctx->kt_seconds;
     rep->kernel_flops = ctx->kt_flops;
+    for (auto& kv : ctx->kt_by_label) {
+      const int st = kv.first % 10;
+      const bool layer = st >= 2 && st <= 4;
+      (layer ? rep->layer_launches : rep->gemm_launches) += (int32_t)kv.second[2];
+      (layer ? rep->layer_seconds : rep->gemm_seconds) += kv.second[0];
+      (layer ? rep->layer_flops : rep->gemm_flops) += kv.second[1];
+      (layer ? rep->layer_bytes : rep->gemm_bytes) += kv.second[3];
+    }
+  }
+  if (ctx->verbose && ctx->time_kernels) {
+    for (auto& kv : ctx->kt_by_label)
+      std::fprintf(stderr,
+                   "[fpeps] chain step %s%d: %6.0f launches %9.3f s %10.3e flops %7.2f TFLOP/s "
+                   "%9.1f GB %7.2f TB/s\n",
+                   kv.first >= 10 ? "T" : "", kv.first >= 10 ? kv.first - 10 : kv.first,
+                   kv.second[2], kv.second[0], kv.second[1], kv.second[1] / kv.second[0] * 1e-12,
+                   kv.second[3] * 1e-9, kv.second[3] / kv.second[0] * 1e-12);
   }
   ctx->time_kernels = false;
   return Status::ok();

@@ -7,8 +7,8 @@
 // in place: A(m, k) = A[a_off + tam[m] + tak[k]], B(k, n) likewise, and the
 // tile is written to C[c_off + tcm[m] + tcn[n]].
 //
-// Tiles are staged through LDS (KT = 16 deep); each of the four waves runs
-// v_mfma_f64_16x16x4f64 on its sub-tile. Register layout of that
+// Tiles are staged through LDS (KT = 16 deep, double-buffered); each of the
+// four waves runs v_mfma_f64_16x16x4f64 on its sub-tile. Register layout of that
 // instruction (checked on the device): A[i][k] in lane i + 16k, B[k][j] in
 // lane j + 16k, result register r of lane l holds D[4r + l/16][l % 16].
 #include <hip/hip_runtime.h>
@@ -19,6 +19,94 @@ namespace fp {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// Position of one K tile in a job's sequence of (pair, K range) tiles.
+struct TileCursor {
+  int p;    // pair index
+  int kb;   // first K of the tile
+};
+
+template <int MT, int NT, int KT>
+struct TileRegs {
+  double a[(MT * KT) / 256];
+  double b[(NT * KT) / 256];
+  bool akf, bnf;
+};
+
+template <int MT, int NT, int KT>
+__device__ __forceinline__ void load_tile(const double* __restrict__ A,
+                                          const double* __restrict__ B,
+                                          const GemmPair* __restrict__ pairs,
+                                          const int32_t* __restrict__ tab, const GemmJob& job,
+                                          const TileCursor& t, int tid,
+                                          TileRegs<MT, NT, KT>& r) {
+  const GemmPair pr = pairs[t.p];
+  const int kend = job.k1 < pr.K ? job.k1 : pr.K;
+  const double* Ab = A + pr.a_off;
+  const double* Bb = B + pr.b_off;
+  const int32_t* tam = tab + pr.tam;
+  const int32_t* tak = tab + pr.tak;
+  const int32_t* tbk = tab + pr.tbk;
+  const int32_t* tbn = tab + pr.tbn;
+  r.akf = pr.flags & 1;
+  r.bnf = pr.flags & 2;
+#pragma unroll
+  for (int i = 0; i < (MT * KT) / 256; ++i) {
+    const int e = tid + i * 256;
+    const int mm = r.akf ? e / KT : e % MT;
+    const int kk = r.akf ? e % KT : e / MT;
+    const int m = job.m0 + mm, k = t.kb + kk;
+    double v = 0.0;
+    if (m < job.M && k < kend) v = Ab[(int64_t)tam[m] + tak[k]] * pr.alpha;
+    r.a[i] = v;
+  }
+#pragma unroll
+  for (int i = 0; i < (NT * KT) / 256; ++i) {
+    const int e = tid + i * 256;
+    const int nn = r.bnf ? e % NT : e / KT;
+    const int kk = r.bnf ? e / NT : e % KT;
+    const int n = job.n0 + nn, k = t.kb + kk;
+    double v = 0.0;
+    if (n < job.N && k < kend) v = Bb[(int64_t)tbk[k] + tbn[n]];
+    r.b[i] = v;
+  }
+}
+
+template <int MT, int NT, int KT>
+__device__ __forceinline__ void store_tile(double (*sA)[MT + 1], double (*sB)[NT + 1], int tid,
+                                           const TileRegs<MT, NT, KT>& r) {
+#pragma unroll
+  for (int i = 0; i < (MT * KT) / 256; ++i) {
+    const int e = tid + i * 256;
+    const int mm = r.akf ? e / KT : e % MT;
+    const int kk = r.akf ? e % KT : e / MT;
+    sA[kk][mm] = r.a[i];
+  }
+#pragma unroll
+  for (int i = 0; i < (NT * KT) / 256; ++i) {
+    const int e = tid + i * 256;
+    const int nn = r.bnf ? e % NT : e / KT;
+    const int kk = r.bnf ? e / NT : e % KT;
+    sB[kk][nn] = r.b[i];
+  }
+}
+
+// Next tile of the job; false at the end.
+__device__ __forceinline__ bool next_tile(const GemmPair* __restrict__ pairs, const GemmJob& job,
+                                          TileCursor& t, int KT) {
+  const int kend = job.k1 < pairs[t.p].K ? job.k1 : pairs[t.p].K;
+  t.kb += KT;
+  if (t.kb < kend) return true;
+  for (++t.p; t.p < job.p1; ++t.p) {
+    t.kb = job.k0 > 0 ? job.k0 : 0;
+    const int ke = job.k1 < pairs[t.p].K ? job.k1 : pairs[t.p].K;
+    if (t.kb < ke) return true;
+  }
+  return false;
+}
+
+// One workgroup (four waves, WM x WN) per output tile; K tiles are
+// prefetched into registers while the previous tile is multiplied out of
+// LDS (double-buffered, one barrier per tile).
 template <int MT, int NT, int WM, int WN>
 __global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ A,
                                                   const double* __restrict__ B,
@@ -31,8 +119,9 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ A,
   constexpr int FM = WTM / 16, FN = WTN / 16;
   static_assert(WM * WN == 4, "four waves");
   static_assert(FM >= 1 && FN >= 1, "wave tile at least 16x16");
-  __shared__ double sA[KT][MT + 1];
-  __shared__ double sB[KT][NT + 1];
+  static_assert((MT * KT) % 256 == 0 && (NT * KT) % 256 == 0, "tile loads cover 256 threads");
+  __shared__ double sA[2][KT][MT + 1];
+  __shared__ double sB[2][KT][NT + 1];
 
   const GemmJob job = jobs[blockIdx.x];
   const int tid = threadIdx.x;
@@ -47,66 +136,43 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ A,
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int p = job.p0; p < job.p1; ++p) {
-    const GemmPair pr = pairs[p];
-    const int kbeg = job.k0 > 0 ? job.k0 : 0;
-    const int kend = job.k1 < pr.K ? job.k1 : pr.K;
-    const double* Ab = A + pr.a_off;
-    const double* Bb = B + pr.b_off;
-    const int32_t* tam = tab + pr.tam;
-    const int32_t* tak = tab + pr.tak;
-    const int32_t* tbk = tab + pr.tbk;
-    const int32_t* tbn = tab + pr.tbn;
-    const bool a_kfast = pr.flags & 1;
-    const bool b_nfast = pr.flags & 2;
-    for (int kb = kbeg; kb < kend; kb += KT) {
-#pragma unroll
-      for (int i = 0; i < (MT * KT) / 256; ++i) {
-        const int e = tid + i * 256;
-        int mm, kk;
-        if (a_kfast) {
-          kk = e % KT;
-          mm = e / KT;
-        } else {
-          mm = e % MT;
-          kk = e / MT;
-        }
-        const int m = job.m0 + mm, k = kb + kk;
-        double v = 0.0;
-        if (m < job.M && k < kend) v = Ab[(int64_t)tam[m] + tak[k]];
-        sA[kk][mm] = v * pr.alpha;
-      }
-#pragma unroll
-      for (int i = 0; i < (NT * KT) / 256; ++i) {
-        const int e = tid + i * 256;
-        int nn, kk;
-        if (b_nfast) {
-          nn = e % NT;
-          kk = e / NT;
-        } else {
-          kk = e % KT;
-          nn = e / KT;
-        }
-        const int n = job.n0 + nn, k = kb + kk;
-        double v = 0.0;
-        if (n < job.N && k < kend) v = Bb[(int64_t)tbk[k] + tbn[n]];
-        sB[kk][nn] = v;
-      }
-      __syncthreads();
+  // first tile of the job (jobs without any tile write zeros)
+  TileCursor cur{job.p0, job.k0 > 0 ? job.k0 : 0};
+  bool have = false;
+  for (; cur.p < job.p1; ++cur.p) {
+    const int ke = job.k1 < pairs[cur.p].K ? job.k1 : pairs[cur.p].K;
+    if (cur.kb < ke) {
+      have = true;
+      break;
+    }
+    cur.kb = job.k0 > 0 ? job.k0 : 0;
+  }
+  if (have) {
+    TileRegs<MT, NT, KT> regs;
+    load_tile<MT, NT, KT>(A, B, pairs, tab, job, cur, tid, regs);
+    store_tile<MT, NT, KT>(sA[0], sB[0], tid, regs);
+    __syncthreads();
+    int buf = 0;
+    while (true) {
+      const bool more = next_tile(pairs, job, cur, KT);
+      if (more) load_tile<MT, NT, KT>(A, B, pairs, tab, job, cur, tid, regs);
 #pragma unroll
       for (int kk = 0; kk < KT; kk += 4) {
         double a[FM], b[FN];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) a[i] = sA[kk + lk][wm * WTM + i * 16 + lrow];
+        for (int i = 0; i < FM; ++i) a[i] = sA[buf][kk + lk][wm * WTM + i * 16 + lrow];
 #pragma unroll
-        for (int j = 0; j < FN; ++j) b[j] = sB[kk + lk][wn * WTN + j * 16 + lrow];
+        for (int j = 0; j < FN; ++j) b[j] = sB[buf][kk + lk][wn * WTN + j * 16 + lrow];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
       }
+      if (!more) break;
+      store_tile<MT, NT, KT>(sA[buf ^ 1], sB[buf ^ 1], tid, regs);
       __syncthreads();
+      buf ^= 1;
     }
   }
 
@@ -128,18 +194,47 @@ hipError_t launch_gemm_f64(const DevGemm& g, const double* A, const double* B, d
                            const int32_t* tables, hipStream_t s) {
   if (g.njobs <= 0) return hipSuccess;
   dim3 grid(g.njobs), block(256);
-  if (g.mt == 64 && g.nt == 64)
-    k_gemm_f64<64, 64, 2, 2><<<grid, block, 0, s>>>(A, B, C, g.jobs, g.pairs, tables);
-  else if (g.mt == 128 && g.nt == 32)
-    k_gemm_f64<128, 32, 4, 1><<<grid, block, 0, s>>>(A, B, C, g.jobs, g.pairs, tables);
-  else if (g.mt == 32 && g.nt == 128)
-    k_gemm_f64<32, 128, 1, 4><<<grid, block, 0, s>>>(A, B, C, g.jobs, g.pairs, tables);
-  else if (g.mt == 256 && g.nt == 16)
-    k_gemm_f64<256, 16, 4, 1><<<grid, block, 0, s>>>(A, B, C, g.jobs, g.pairs, tables);
-  else if (g.mt == 16 && g.nt == 256)
-    k_gemm_f64<16, 256, 1, 4><<<grid, block, 0, s>>>(A, B, C, g.jobs, g.pairs, tables);
-  else
-    return hipErrorInvalidValue;
+#define FP_GEMM_TILE(mt_, nt_, wm_, wn_)                                                  \
+  if (g.mt == mt_ && g.nt == nt_) {                                                       \
+    k_gemm_f64<mt_, nt_, wm_, wn_><<<grid, block, 0, s>>>(A, B, C, g.jobs, g.pairs, tables); \
+    return hipGetLastError();                                                             \
+  }
+  FP_GEMM_TILE(128, 128, 2, 2)
+  FP_GEMM_TILE(128, 64, 2, 2)
+  FP_GEMM_TILE(64, 128, 2, 2)
+  FP_GEMM_TILE(64, 64, 2, 2)
+  FP_GEMM_TILE(128, 32, 4, 1)
+  FP_GEMM_TILE(32, 128, 1, 4)
+  FP_GEMM_TILE(256, 16, 4, 1)
+  FP_GEMM_TILE(16, 256, 1, 4)
+#undef FP_GEMM_TILE
+  return hipErrorInvalidValue;
+}
+
+// Sum of the split parts of table-addressed output blocks:
+// C[c_off + tcm[m] + tcn[n]] = sum_q P[p_off + q M N + m N + n].
+__global__ void k_reduce_tab(const ReduceTab* __restrict__ d, double* __restrict__ C,
+                             const double* __restrict__ P, const int32_t* __restrict__ tab) {
+  const ReduceTab r = d[blockIdx.y];
+  const int64_t mn = (int64_t)r.M * r.N;
+  const int32_t* tcm = tab + r.tcm;
+  const int32_t* tcn = tab + r.tcn;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < mn;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int q = 0; q < r.nsplit; ++q) s += P[r.p_off + (int64_t)q * mn + e];
+    const int m = (int)(e / r.N), n = (int)(e % r.N);
+    C[r.c_off + (int64_t)tcm[m] + tcn[n]] = s;
+  }
+}
+
+hipError_t launch_reduce_tab(const ReduceTab* d, int nd, int64_t max_mn, double* C,
+                             const double* P, const int32_t* tab, hipStream_t s) {
+  if (nd <= 0) return hipSuccess;
+  int64_t bx = (max_mn + 255) / 256;
+  if (bx > 256) bx = 256;
+  if (bx < 1) bx = 1;
+  k_reduce_tab<<<dim3((unsigned)bx, nd), 256, 0, s>>>(d, C, P, tab);
   return hipGetLastError();
 }
 

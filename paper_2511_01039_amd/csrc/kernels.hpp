@@ -15,11 +15,32 @@ struct DevGemm {
   const GemmPair* pairs = nullptr;
   int njobs = 0;
   int mt = 64, nt = 64;
+  const ReduceTab* reduces = nullptr;   // split-K parts (see GemmPlan)
+  int nred = 0;
 };
 
 // C[job tiles] = sum over pairs alpha * A(tables) * B(tables), FP64 MFMA.
 hipError_t launch_gemm_f64(const DevGemm& g, const double* A, const double* B, double* C,
                            const int32_t* tables, hipStream_t s);
+
+// A row-thread layer-step plan resident on the device.
+struct DevRt {
+  const RtGroup* groups = nullptr;
+  const RtOut* outs = nullptr;
+  const RtPair* pairs = nullptr;
+  const RtPack* packs = nullptr;
+  int ngroups = 0, ntiles = 0, npacks = 0;
+};
+// Y[rows of every group] = X rows times the packed layer sub-blocks PK.
+hipError_t launch_rt_f64(const DevRt& r, const double* X, const double* PK, double* Y,
+                         const int32_t* tab, hipStream_t s);
+// PK[dst + k nc + c] = alpha S[sbase + sk[k] + sn[c]] for every pack entry.
+hipError_t launch_rt_pack(const DevRt& r, const double* S, const int32_t* tab, double* PK,
+                          hipStream_t s);
+
+// Sum of the split parts of table-addressed output blocks (see GemmPlan).
+hipError_t launch_reduce_tab(const ReduceTab* d, int nd, int64_t max_mn, double* C,
+                             const double* P, const int32_t* tab, hipStream_t s);
 
 // Sum of split-K partials: C(m, n) = sum_s P[p_off + s*M*N + m*N + n].
 struct ReduceDesc {

@@ -97,6 +97,22 @@ int32_t TablePool::add(const std::vector<int32_t>& dims, const std::vector<int64
   return id;
 }
 
+int32_t TablePool::add_raw(const std::vector<int32_t>& v, bool* ok) {
+  std::string key(v.size() * 4 + 1, '\0');
+  key[0] = 'r';
+  std::memcpy(&key[1], v.data(), v.size() * 4);
+  auto it = index.find(key);
+  if (it != index.end()) return it->second;
+  if ((int64_t)data.size() + (int64_t)v.size() > (int64_t)INT32_MAX) {
+    *ok = false;
+    return 0;
+  }
+  int32_t id = (int32_t)data.size();
+  data.insert(data.end(), v.begin(), v.end());
+  index.emplace(std::move(key), id);
+  return id;
+}
+
 namespace {
 
 struct SectKey {
@@ -142,6 +158,12 @@ TabRef make_table(TablePool& pool, const BT& bt, const Block& b, const std::vect
   return {pool.add(dims, strides, ok), mx};
 }
 
+TabRef make_table_dense(TablePool& pool, int32_t n, int64_t stride, bool* ok) {
+  std::vector<int32_t> d{std::max(n, 1)};
+  std::vector<int64_t> st{stride};
+  return {pool.add(d, st, ok), (int64_t)(std::max(n, 1) - 1) * stride};
+}
+
 int64_t prod_dims(const BT& bt, const Block& b, const std::vector<int>& pos) {
   int64_t n = 1;
   for (int p : pos) n *= bt.dim(b, p);
@@ -150,34 +172,58 @@ int64_t prod_dims(const BT& bt, const Block& b, const std::vector<int>& pos) {
 
 }  // namespace
 
-void choose_tile(const std::vector<std::pair<int64_t, int64_t>>& mn, int* mt, int* nt) {
-  static const int cand[][2] = {{64, 64}, {128, 32}, {32, 128}, {256, 16}, {16, 256}};
-  double best = -1;
-  int bi = 0;
-  for (int c = 0; c < 5; ++c) {
+void choose_tile(const std::vector<std::pair<int64_t, int64_t>>& mn,
+                 const std::vector<int64_t>& ktot, int* mt, int* nt) {
+  static const int cand[][2] = {{128, 128}, {128, 64}, {64, 128}, {64, 64},
+                                {128, 32},  {32, 128}, {256, 16}, {16, 256}};
+  constexpr int NC = sizeof(cand) / sizeof(cand[0]);
+  double eff[NC];
+  double best = 0;
+  for (int c = 0; c < NC; ++c) {
     double padded = 0, useful = 0;
-    for (auto& p : mn) {
-      int64_t M = p.first, N = p.second;
-      padded += (double)((M + cand[c][0] - 1) / cand[c][0] * cand[c][0]) *
+    for (size_t i = 0; i < mn.size(); ++i) {
+      const int64_t M = mn[i].first, N = mn[i].second;
+      const double w = (double)std::max<int64_t>(ktot[i], 1);
+      padded += w * (double)((M + cand[c][0] - 1) / cand[c][0] * cand[c][0]) *
                 (double)((N + cand[c][1] - 1) / cand[c][1] * cand[c][1]);
-      useful += (double)M * (double)N;
+      useful += w * (double)M * (double)N;
     }
-    double eff = padded > 0 ? useful / padded : 1.0;
-    // prefer the square tile unless another is clearly better
-    if (c == 0) eff *= 1.15;
-    if (eff > best) {
-      best = eff;
-      bi = c;
-    }
+    eff[c] = padded > 0 ? useful / padded : 1.0;
+    best = std::max(best, eff[c]);
   }
-  *mt = cand[bi][0];
-  *nt = cand[bi][1];
+  // the largest tile (most reuse per loaded element) among those within 15%
+  // of the best padding efficiency; candidates are ordered by preference
+  for (int c = 0; c < NC; ++c)
+    if (eff[c] >= 0.85 * best) {
+      *mt = cand[c][0];
+      *nt = cand[c][1];
+      return;
+    }
+  *mt = 64;
+  *nt = 64;
 }
 
-bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sym,
-               TablePool& pool, const BT* fixed_out, StepResult& res, std::string& err) {
-  // shared legs in X order
+namespace {
+
+struct P3 {
+  int xb, sb, ob;
+};
+
+// Pair enumeration shared by both plan forms: contracted/free legs, the
+// output structure, and every (X block, S block, output block) triple,
+// sorted by output block.
+struct StepEnum {
   std::vector<int> xs, ss, xfree, sfree;
+  std::vector<P3> trip;
+  // per-pair scalar keys
+  std::vector<int> kpos;
+  std::vector<bool> kshared, sshared;
+  int nlab = 1;
+};
+
+bool enumerate_step(const BT& X, const BT& S, const StepSpec& spec, const BT* fixed_out, BT& out,
+                    StepEnum& E, std::string& err) {
+  std::vector<int>&xs = E.xs, &ss = E.ss, &xfree = E.xfree, &sfree = E.sfree;
   for (int p = 0; p < X.nlegs(); ++p) {
     int q = S.pos(X.names[p]);
     if (q >= 0) {
@@ -195,7 +241,6 @@ bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sy
       return false;
     }
   }
-  // output leg sources
   const int no = (int)spec.out_names.size();
   if (no != (int)(xfree.size() + sfree.size())) {
     err = "output leg count mismatch";
@@ -216,7 +261,6 @@ bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sy
       return false;
     }
   }
-  BT& out = res.out;
   out = BT();
   out.names = spec.out_names;
   for (int o = 0; o < no; ++o) out.cat.push_back(src_side[o] ? S.cat[src_pos[o]] : X.cat[src_pos[o]]);
@@ -230,7 +274,6 @@ bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sy
     for (size_t i = 0; i < ss.size(); ++i) k.v[i] = S.blocks[sb].sect[ss[i]];
     groups[k].push_back(sb);
   }
-  // enumerate pairs
   std::unordered_map<SectKey, int, SectKeyHash> out_index;
   std::vector<SectKey> out_keys;
   if (fixed_out) {
@@ -247,10 +290,7 @@ bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sy
       out_keys.push_back(k);
     }
   }
-  struct P3 {
-    int xb, sb, ob;
-  };
-  std::vector<P3> trip;
+  std::vector<P3>& trip = E.trip;
   for (int xb = 0; xb < (int)X.blocks.size(); ++xb) {
     SectKey k;
     k.n = (uint8_t)xs.size();
@@ -279,7 +319,7 @@ bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sy
       trip.push_back({xb, sb, ob});
     }
   }
-  // assign output blocks (sorted by sector tuple) when not fixed
+  // output blocks sorted by sector tuple when not fixed
   std::vector<int> remap(out_keys.size());
   if (!fixed_out) {
     std::vector<int> order(out_keys.size());
@@ -303,34 +343,56 @@ bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sy
   if (spec.symbolic) return true;
   std::stable_sort(trip.begin(), trip.end(), [](const P3& a, const P3& b) { return a.ob < b.ob; });
 
-  // operand roles
-  const BT& A = spec.m_is_x ? X : S;
-  const BT& B = spec.m_is_x ? S : X;
-  const std::vector<int>& afree = spec.m_is_x ? xfree : sfree;
-  const std::vector<int>& bfree = spec.m_is_x ? sfree : xfree;
-  const std::vector<int>& ak = spec.m_is_x ? xs : ss;
-  const std::vector<int>& bk = spec.m_is_x ? ss : xs;
-  // positions in the output of the M and N legs
-  std::vector<int> cm, cn;
-  for (int p : afree) cm.push_back(out.pos(A.names[p]));
-  for (int p : bfree) cn.push_back(out.pos(B.names[p]));
-
-  // key tensor for alpha
+  // keys of the per-pair scalar
   const BT& KT = spec.key_side == 0 ? X : out;
-  std::vector<int> kpos;
-  std::vector<bool> kshared;
   for (int n : spec.key_order) {
     int p = KT.pos(n);
     if (p < 0) {
       err = "key order names a leg the keyed tensor lacks";
       return false;
     }
-    kpos.push_back(p);
-    kshared.push_back(S.pos(n) >= 0);
+    E.kpos.push_back(p);
+    E.kshared.push_back(S.pos(n) >= 0);
   }
-  std::vector<bool> sshared(S.nlegs());
-  for (int q = 0; q < S.nlegs(); ++q) sshared[q] = KT.pos(S.names[q]) >= 0;
-  const int nlab = S.cat.empty() ? 1 : S.cat[0]->nlab;
+  E.sshared.resize(S.nlegs());
+  for (int q = 0; q < S.nlegs(); ++q) E.sshared[q] = KT.pos(S.names[q]) >= 0;
+  E.nlab = S.cat.empty() ? 1 : S.cat[0]->nlab;
+  return true;
+}
+
+double trip_alpha(const StepEnum& E, const BT& X, const BT& S, const BT& out,
+                  const StepSpec& spec, const SymInfo& sym, const P3& t) {
+  if (sym.kind != SYM_SU2 && !sym.fermionic) return 1.0;
+  const BT& KT = spec.key_side == 0 ? X : out;
+  const Block& kb = spec.key_side == 0 ? X.blocks[t.xb] : out.blocks[t.ob];
+  const Block& sbk = S.blocks[t.sb];
+  std::vector<const int32_t*> xl(E.kpos.size()), tl(S.nlegs());
+  for (size_t i = 0; i < E.kpos.size(); ++i) xl[i] = KT.cat[E.kpos[i]]->label(kb.sect[E.kpos[i]]);
+  for (int q = 0; q < S.nlegs(); ++q) tl[q] = S.cat[q]->label(sbk.sect[q]);
+  return pair_alpha(sym, spec.step, xl, tl, E.kshared, E.sshared, E.nlab);
+}
+
+}  // namespace
+
+bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sym,
+               TablePool& pool, const BT* fixed_out, StepResult& res, std::string& err) {
+  StepEnum E;
+  BT& out = res.out;
+  if (!enumerate_step(X, S, spec, fixed_out, out, E, err)) return false;
+  if (spec.symbolic) return true;
+  const std::vector<P3>& trip = E.trip;
+
+  // operand roles
+  const BT& A = spec.m_is_x ? X : S;
+  const BT& B = spec.m_is_x ? S : X;
+  const std::vector<int>& afree = spec.m_is_x ? E.xfree : E.sfree;
+  const std::vector<int>& bfree = spec.m_is_x ? E.sfree : E.xfree;
+  const std::vector<int>& ak = spec.m_is_x ? E.xs : E.ss;
+  const std::vector<int>& bk = spec.m_is_x ? E.ss : E.xs;
+  // positions in the output of the M and N legs
+  std::vector<int> cm, cn;
+  for (int p : afree) cm.push_back(out.pos(A.names[p]));
+  for (int p : bfree) cn.push_back(out.pos(B.names[p]));
 
   // tables and pairs
   GemmPlan& plan = res.plan;
@@ -338,7 +400,6 @@ bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sy
   std::vector<std::pair<int64_t, int64_t>> mn;
   mn.reserve(out.blocks.size());
   for (auto& b : out.blocks) mn.emplace_back(prod_dims(out, b, cm), prod_dims(out, b, cn));
-  choose_tile(mn, &plan.mt, &plan.nt);
   bool ok = true;
   std::vector<int> pstart(out.blocks.size() + 1, 0);
   {
@@ -349,8 +410,12 @@ bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sy
     }
     pstart[out.blocks.size()] = (int)trip.size();
   }
+  std::vector<int64_t> ktot(out.blocks.size(), 0);
+  for (size_t ob = 0; ob < out.blocks.size(); ++ob)
+    for (int t = pstart[ob]; t < pstart[ob + 1]; ++t)
+      ktot[ob] += prod_dims(A, spec.m_is_x ? X.blocks[trip[t].xb] : S.blocks[trip[t].sb], ak);
+  choose_tile(mn, ktot, &plan.mt, &plan.nt);
   plan.pairs.reserve(trip.size());
-  std::vector<const int32_t*> xl(kpos.size()), tl(S.nlegs());
   for (auto& t : trip) {
     const Block& xbk = X.blocks[t.xb];
     const Block& sbk = S.blocks[t.sb];
@@ -371,47 +436,356 @@ bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sy
     gp.flags = 0;
     if (!ak.empty() && abk.stride[ak.back()] == 1) gp.flags |= 1;
     if (!bfree.empty() && bbk.stride[bfree.back()] == 1) gp.flags |= 2;
-    // alpha keyed by the sketch-side block
-    const Block& kb = spec.key_side == 0 ? xbk : out.blocks[t.ob];
-    for (size_t i = 0; i < kpos.size(); ++i) xl[i] = KT.cat[kpos[i]]->label(kb.sect[kpos[i]]);
-    for (int q = 0; q < S.nlegs(); ++q) tl[q] = S.cat[q]->label(sbk.sect[q]);
-    gp.alpha = pair_alpha(sym, spec.step, xl, tl, kshared, sshared, nlab);
+    gp.alpha = trip_alpha(E, X, S, out, spec, sym, t);
     plan.a_extent = std::max(plan.a_extent, gp.a_off + tam.maxoff + tak.maxoff + 1);
     plan.b_extent = std::max(plan.b_extent, gp.b_off + tbk.maxoff + tbn.maxoff + 1);
     int64_t M = prod_dims(A, abk, afree), N = prod_dims(B, bbk, bfree);
     plan.flops += 2.0 * (double)M * (double)N * (double)gp.K;
     plan.pairs.push_back(gp);
   }
-  // jobs: one per output tile
+  {
+    std::vector<char> ua(A.blocks.size(), 0), ub(B.blocks.size(), 0);
+    for (const P3& t : trip) {
+      ua[spec.m_is_x ? t.xb : t.sb] = 1;
+      ub[spec.m_is_x ? t.sb : t.xb] = 1;
+    }
+    double e = 0;
+    for (size_t b = 0; b < A.blocks.size(); ++b)
+      if (ua[b]) e += (double)A.block_elems(A.blocks[b]);
+    for (size_t b = 0; b < B.blocks.size(); ++b)
+      if (ub[b]) e += (double)B.block_elems(B.blocks[b]);
+    for (const Block& b : out.blocks) e += (double)out.block_elems(b);
+    plan.bytes = 8.0 * e;
+  }
+  // jobs: one per output tile and split part. Launches with too few tiles
+  // for the chip split the pair list of long-K blocks into parts (pair
+  // boundaries, or K ranges of a single pair) summed by a reduction.
+  int64_t ntiles = 0;
+  for (size_t ob = 0; ob < out.blocks.size(); ++ob)
+    ntiles += (mn[ob].first + plan.mt - 1) / plan.mt * ((mn[ob].second + plan.nt - 1) / plan.nt);
+  constexpr int64_t TARGET_JOBS = 2048, MIN_PART_K = 256, MAX_SPLIT = 16;
+  int64_t want = ntiles > 0 ? (TARGET_JOBS + ntiles - 1) / ntiles : 1;
+  want = std::min<int64_t>(want, MAX_SPLIT);
+  bool split = false;
+  if (want > 1)
+    for (size_t ob = 0; ob < out.blocks.size(); ++ob)
+      if (ktot[ob] >= 2 * MIN_PART_K) split = true;
   for (size_t ob = 0; ob < out.blocks.size(); ++ob) {
     const Block& cb = out.blocks[ob];
-    int64_t M = prod_dims(out, cb, cm), N = prod_dims(out, cb, cn);
-    if (M > INT32_MAX || N > INT32_MAX) {
+    int64_t M = mn[ob].first, N = mn[ob].second;
+    if (M > INT32_MAX || N > INT32_MAX || (split && M * N > INT32_MAX)) {
       err = "block too large";
       return false;
     }
     TabRef tcm = make_table(pool, out, cb, cm, &ok);
     TabRef tcn = make_table(pool, out, cb, cn, &ok);
     plan.c_extent = std::max(plan.c_extent, cb.base + tcm.maxoff + tcn.maxoff + 1);
-    for (int64_t m0 = 0; m0 < M; m0 += plan.mt)
-      for (int64_t n0 = 0; n0 < N; n0 += plan.nt) {
-        GemmJob j;
-        j.c_off = cb.base;
-        j.M = (int32_t)M;
-        j.N = (int32_t)N;
-        j.m0 = (int32_t)m0;
-        j.n0 = (int32_t)n0;
-        j.tcm = tcm.id;
-        j.tcn = tcn.id;
-        j.p0 = pstart[ob];
-        j.p1 = pstart[ob + 1];
-        j.k0 = 0;
-        j.k1 = INT32_MAX;
-        plan.jobs.push_back(j);
+    // parts: (p0, p1, k0, k1)
+    struct Part {
+      int p0, p1, k0, k1;
+    };
+    std::vector<Part> parts;
+    const int p0 = pstart[ob], p1 = pstart[ob + 1];
+    const int64_t nparts = split ? std::max<int64_t>(1, std::min(want, ktot[ob] / MIN_PART_K)) : 1;
+    if (nparts <= 1 || p1 - p0 == 0) {
+      parts.push_back({p0, p1, 0, INT32_MAX});
+    } else if (p1 - p0 == 1) {
+      const int K = plan.pairs[p0].K;
+      int chunk = (int)((K + nparts - 1) / nparts);
+      chunk = (chunk + 15) / 16 * 16;
+      for (int k0 = 0; k0 < K; k0 += chunk) parts.push_back({p0, p1, k0, std::min(K, k0 + chunk)});
+    } else {
+      // contiguous pair ranges with about ktot / nparts contracted extent each
+      const double per = (double)ktot[ob] / (double)nparts;
+      double acc = 0;
+      int start = p0;
+      for (int t = p0; t < p1; ++t) {
+        acc += plan.pairs[t].K;
+        if ((acc >= per * (double)(parts.size() + 1) || t == p1 - 1) && t + 1 > start) {
+          parts.push_back({start, t + 1, 0, INT32_MAX});
+          start = t + 1;
+        }
       }
+    }
+    int32_t pm = 0, pn = 0;
+    int64_t p_off = 0;
+    if (split) {
+      TabRef rm = make_table_dense(pool, (int32_t)M, N, &ok);
+      TabRef rn = make_table_dense(pool, (int32_t)N, 1, &ok);
+      pm = rm.id;
+      pn = rn.id;
+      p_off = plan.partial_size;
+      ReduceTab rd;
+      rd.c_off = cb.base;
+      rd.p_off = p_off;
+      rd.tcm = tcm.id;
+      rd.tcn = tcn.id;
+      rd.M = (int32_t)M;
+      rd.N = (int32_t)N;
+      rd.nsplit = (int32_t)parts.size();
+      rd.pad = 0;
+      plan.reduces.push_back(rd);
+      plan.partial_size += (int64_t)parts.size() * M * N;
+      plan.max_red_mn = std::max(plan.max_red_mn, M * N);
+    }
+    for (size_t q = 0; q < parts.size(); ++q)
+      for (int64_t m0 = 0; m0 < M; m0 += plan.mt)
+        for (int64_t n0 = 0; n0 < N; n0 += plan.nt) {
+          GemmJob j;
+          j.c_off = split ? p_off + (int64_t)q * M * N : cb.base;
+          j.M = (int32_t)M;
+          j.N = (int32_t)N;
+          j.m0 = (int32_t)m0;
+          j.n0 = (int32_t)n0;
+          j.tcm = split ? pm : tcm.id;
+          j.tcn = split ? pn : tcn.id;
+          j.p0 = parts[q].p0;
+          j.p1 = parts[q].p1;
+          j.k0 = parts[q].k0;
+          j.k1 = parts[q].k1;
+          plan.jobs.push_back(j);
+        }
   }
   if (!ok) {
     err = "offset table overflow (block or pool exceeds 2^31 elements)";
+    return false;
+  }
+  return true;
+}
+
+bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sym,
+                  TablePool& pool, StepResult& res, RtPlan& rt, std::string& err) {
+  StepEnum E;
+  BT& out = res.out;
+  rt = RtPlan();
+  if (!enumerate_step(X, S, spec, nullptr, out, E, err)) return false;
+  if (spec.symbolic) return true;
+  const std::vector<P3>& trip = E.trip;
+  // levels: runs of X's free legs adjacent, in the same order, in X and in
+  // the output
+  std::vector<int> opos;
+  for (int p : E.xfree) opos.push_back(out.pos(X.names[p]));
+  std::vector<std::vector<int>> lev;   // X positions per level
+  for (size_t i = 0; i < E.xfree.size(); ++i) {
+    if (i > 0 && E.xfree[i] == E.xfree[i - 1] + 1 && opos[i] == opos[i - 1] + 1)
+      lev.back().push_back((int)i);
+    else
+      lev.push_back({(int)i});
+  }
+  const int nlev = (int)lev.size();
+  if (nlev > RT_MAXLEV) {
+    err = "layer step needs " + std::to_string(nlev) + " row levels (at most " +
+          std::to_string(RT_MAXLEV) + ")";
+    return false;
+  }
+  const int pad = RT_MAXLEV - nlev;
+  // per-level dims and strides of a block (legs of a level are contiguous
+  // row-major inside the block: the level stride is its last leg's)
+  auto level_geom = [&](const BT& bt, const Block& b, const std::vector<int>& pos_of,
+                        int32_t* md, int32_t* st) -> bool {
+    for (int l = 0; l < RT_MAXLEV; ++l) {
+      md[l] = 1;
+      st[l] = 0;
+    }
+    for (int l = 0; l < nlev; ++l) {
+      int64_t d = 1;
+      for (size_t u = 0; u < lev[l].size(); ++u) {
+        const int p = pos_of[lev[l][u]];
+        if (u > 0) {
+          const int pp = pos_of[lev[l][u - 1]];
+          if (b.stride[pp] != b.stride[p] * bt.dim(b, p)) return false;
+        }
+        d *= bt.dim(b, p);
+      }
+      const int64_t s = b.stride[pos_of[lev[l].back()]];
+      if (d > INT32_MAX || s > INT32_MAX) return false;
+      md[pad + l] = (int32_t)d;
+      st[pad + l] = (int32_t)s;
+    }
+    return true;
+  };
+  std::vector<int> opos_by_i(E.xfree.size());
+  for (size_t i = 0; i < E.xfree.size(); ++i) opos_by_i[i] = opos[i];
+  std::vector<int> xpos_by_i = E.xfree;
+  // S legs: contracted (in X's contracted order) and free (S order)
+  bool ok = true;
+  auto tab_of = [&](const BT& bt, const Block& b, const std::vector<int>& pos, int64_t* mx) {
+    TabRef t = make_table(pool, bt, b, pos, &ok);
+    if (mx) *mx = t.maxoff;
+    return t.id;
+  };
+  // output N legs, in S order, located in the output
+  std::vector<int> onpos;
+  for (int q : E.sfree) onpos.push_back(out.pos(S.names[q]));
+
+  // groups: output blocks with equal sectors on X's free legs
+  const std::vector<int>& xkey_pos = opos;   // output positions of X's free legs
+  std::map<std::vector<uint16_t>, std::vector<int>> gmap;
+  for (int ob = 0; ob < (int)out.blocks.size(); ++ob) {
+    std::vector<uint16_t> k;
+    for (int p : xkey_pos) k.push_back(out.blocks[ob].sect[p]);
+    gmap[k].push_back(ob);
+  }
+  std::vector<int> pstart(out.blocks.size() + 1, 0);
+  {
+    size_t t = 0;
+    for (size_t ob = 0; ob < out.blocks.size(); ++ob) {
+      pstart[ob] = (int)t;
+      while (t < trip.size() && trip[t].ob == (int)ob) ++t;
+    }
+    pstart[out.blocks.size()] = (int)trip.size();
+  }
+  int64_t tiles = 0;
+  for (auto& kv : gmap) {
+    const int ob0 = kv.second.front();
+    const Block& cb0 = out.blocks[ob0];
+    RtGroup g;
+    int32_t st_dummy[RT_MAXLEV];
+    if (!level_geom(out, cb0, opos_by_i, g.md, st_dummy)) {
+      err = "output block rows are not level-contiguous";
+      return false;
+    }
+    int64_t M = 1;
+    for (int l = 0; l < RT_MAXLEV; ++l) M *= g.md[l];
+    if (M > INT32_MAX) {
+      err = "layer step group too large";
+      return false;
+    }
+    g.M = (int32_t)M;
+    g.tile0 = (int32_t)tiles;
+    g.o0 = (int32_t)rt.outs.size();
+    for (int ob : kv.second) {
+      const Block& cb = out.blocks[ob];
+      RtOut base_o;
+      int32_t md2[RT_MAXLEV];
+      if (!level_geom(out, cb, opos_by_i, md2, base_o.ms)) {
+        err = "output block rows are not level-contiguous";
+        return false;
+      }
+      base_o.base = cb.base;
+      const int64_t Nb = prod_dims(out, cb, onpos);
+      // all N offsets of the block, then chunked
+      std::vector<int32_t> noff;
+      {
+        std::vector<int32_t> dims;
+        std::vector<int64_t> strides;
+        for (int p : onpos) {
+          dims.push_back(out.dim(cb, p));
+          strides.push_back(cb.stride[p]);
+        }
+        std::vector<int32_t> idx(dims.size(), 0);
+        int64_t off = 0;
+        for (int64_t e = 0; e < Nb; ++e) {
+          noff.push_back((int32_t)off);
+          for (int d = (int)dims.size() - 1; d >= 0; --d) {
+            if (++idx[d] < dims[d]) {
+              off += strides[d];
+              break;
+            }
+            off -= strides[d] * (int64_t)(dims[d] - 1);
+            idx[d] = 0;
+          }
+        }
+      }
+      int64_t rowmax = 0;
+      for (int l = 0; l < RT_MAXLEV; ++l) rowmax += (int64_t)(g.md[l] - 1) * base_o.ms[l];
+      int32_t nmax = 0;
+      for (int32_t v : noff) nmax = std::max(nmax, v);
+      rt.c_extent = std::max(rt.c_extent, cb.base + rowmax + nmax + 1);
+      for (int64_t n0 = 0; n0 < Nb; n0 += RT_NC) {
+        const int nc = (int)std::min<int64_t>(RT_NC, Nb - n0);
+        RtOut o = base_o;
+        o.nc = nc;
+        o.ntab = pool.add_raw(std::vector<int32_t>(noff.begin() + n0, noff.begin() + n0 + nc), &ok);
+        o.p0 = (int32_t)rt.pairs.size();
+        for (int pi = pstart[ob]; pi < pstart[ob + 1]; ++pi) {
+          const P3& t = trip[pi];
+          const Block& xb = X.blocks[t.xb];
+          const Block& sb = S.blocks[t.sb];
+          RtPair pr;
+          int32_t mdx[RT_MAXLEV];
+          if (!level_geom(X, xb, xpos_by_i, mdx, pr.xs)) {
+            err = "input block rows are not level-contiguous";
+            return false;
+          }
+          for (int l = 0; l < RT_MAXLEV; ++l)
+            if (mdx[l] != g.md[l]) {
+              err = "row levels differ between input and output block";
+              return false;
+            }
+          pr.xbase = xb.base;
+          const int64_t Kb = prod_dims(X, xb, E.xs);
+          pr.Kb = (int32_t)Kb;
+          int64_t kmax = 0;
+          pr.xktab = tab_of(X, xb, E.xs, &kmax);
+          int64_t xrow = 0;
+          for (int l = 0; l < RT_MAXLEV; ++l) xrow += (int64_t)(g.md[l] - 1) * pr.xs[l];
+          rt.x_extent = std::max(rt.x_extent, xb.base + xrow + kmax + 1);
+          pr.pk = rt.pack_size;
+          RtPack pk;
+          pk.dst = rt.pack_size;
+          pk.sbase = sb.base;
+          pk.Kb = pr.Kb;
+          pk.nc = nc;
+          int64_t skmax = 0;
+          pk.sktab = tab_of(S, sb, E.ss, &skmax);
+          // layer block N offsets of this chunk
+          {
+            std::vector<int32_t> dims;
+            std::vector<int64_t> strides;
+            for (int q : E.sfree) {
+              dims.push_back(S.dim(sb, q));
+              strides.push_back(sb.stride[q]);
+            }
+            std::vector<int32_t> all;
+            std::vector<int32_t> idx(dims.size(), 0);
+            int64_t off = 0;
+            for (int64_t e = 0; e < Nb; ++e) {
+              all.push_back((int32_t)off);
+              for (int d = (int)dims.size() - 1; d >= 0; --d) {
+                if (++idx[d] < dims[d]) {
+                  off += strides[d];
+                  break;
+                }
+                off -= strides[d] * (int64_t)(dims[d] - 1);
+                idx[d] = 0;
+              }
+            }
+            int32_t snmax = 0;
+            for (int64_t e = n0; e < n0 + nc; ++e) snmax = std::max(snmax, all[e]);
+            rt.s_extent = std::max(rt.s_extent, sb.base + skmax + snmax + 1);
+            pk.sntab = pool.add_raw(std::vector<int32_t>(all.begin() + n0, all.begin() + n0 + nc), &ok);
+          }
+          pk.alpha = trip_alpha(E, X, S, out, spec, sym, t);
+          rt.pack_size += Kb * nc;
+          rt.packs.push_back(pk);
+          rt.pairs.push_back(pr);
+          rt.flops += 2.0 * (double)M * (double)Kb * (double)nc;
+          rt.x_loads += (double)M * (double)Kb;
+        }
+        o.p1 = (int32_t)rt.pairs.size();
+        rt.outs.push_back(o);
+      }
+    }
+    g.o1 = (int32_t)rt.outs.size();
+    rt.groups.push_back(g);
+    tiles += (M + RT_ROWS - 1) / RT_ROWS;
+    if (tiles > INT32_MAX) {
+      err = "layer step has too many row tiles";
+      return false;
+    }
+  }
+  rt.ntiles = (int32_t)tiles;
+  {
+    std::vector<char> used(X.blocks.size(), 0);
+    for (const P3& t : trip) used[t.xb] = 1;
+    double xe = 0;
+    for (size_t b = 0; b < X.blocks.size(); ++b)
+      if (used[b]) xe += (double)X.block_elems(X.blocks[b]);
+    rt.bytes = 8.0 * (xe + (double)out.size);
+  }
+  if (!ok) {
+    err = "offset table overflow";
     return false;
   }
   return true;

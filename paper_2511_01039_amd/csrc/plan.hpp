@@ -106,6 +106,15 @@ struct TablePool {
   std::vector<int32_t> data;
   std::unordered_map<std::string, int32_t> index;
   int32_t add(const std::vector<int32_t>& dims, const std::vector<int64_t>& strides, bool* ok);
+  // a table given by its values
+  int32_t add_raw(const std::vector<int32_t>& v, bool* ok);
+};
+
+// Sum of the split parts of one output block into C (table addressed).
+struct ReduceTab {
+  int64_t c_off, p_off;
+  int32_t tcm, tcn;
+  int32_t M, N, nsplit, pad;
 };
 
 struct GemmPlan {
@@ -116,10 +125,19 @@ struct GemmPlan {
   int64_t b_extent = 0;
   int64_t c_extent = 0;
   int mt = 64, nt = 64;    // tile used for the jobs
+  double bytes = 0;        // algorithmic: distinct A, B blocks read once, C written once
+  // split-K: when partial_size > 0 every job writes a row-major part of its
+  // output block into a partial buffer of that many elements, and
+  // ``reduces`` sums the parts into C (fixed order, deterministic)
+  int64_t partial_size = 0;
+  int64_t max_red_mn = 0;
+  std::vector<ReduceTab> reduces;
 };
 
-// Tile shape choice for a list of output blocks (M, N) sizes.
-void choose_tile(const std::vector<std::pair<int64_t, int64_t>>& mn, int* mt, int* nt);
+// Tile shape choice for a list of output blocks: (M, N) sizes and the
+// contracted extent summed over each block's pairs.
+void choose_tile(const std::vector<std::pair<int64_t, int64_t>>& mn,
+                 const std::vector<int64_t>& ktot, int* mt, int* nt);
 
 // Per-pair scalar of a chain step: synthetic recoupling coefficient (SU(2))
 // times the parity sign. ``xlabs`` are the labels of the sketch-side
@@ -158,6 +176,64 @@ struct StepResult {
 
 bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sym,
                TablePool& pool, const BT* fixed_out, StepResult& res, std::string& err);
+
+// Row-thread form of a layer step (ket, PEPO or bra contracted into the
+// sketch-side intermediate; contracted and free legs of the layer tensor are
+// a few virtual/physical indices, the free legs of X span the environment
+// and sketch indices). Rows of the product are grouped by the sectors of X's
+// free legs; inside a group a row is addressed by its indices along up to
+// RT_MAXLEV "levels" (runs of legs contiguous in both X and the output), so
+// a row offset is a short dot product and no per-row tables exist. Each
+// output block is cut into column chunks of nc <= RT_NC columns; the layer
+// tensor's sub-block of every pair, scaled by the pair's scalar, is packed
+// row-major [Kb][nc] once per plan.
+constexpr int RT_MAXLEV = 4;
+constexpr int RT_NC = 16;
+constexpr int RT_ROWS = 256;   // rows per workgroup
+
+struct RtGroup {
+  int32_t tile0;               // first workgroup of the group
+  int32_t M;                   // rows
+  int32_t md[RT_MAXLEV];       // level dims, innermost last (unused levels 1)
+  int32_t o0, o1;              // output chunk range
+};
+struct RtOut {
+  int64_t base;                // output block element offset
+  int32_t ms[RT_MAXLEV];       // level strides in the output block
+  int32_t nc;                  // columns of this chunk
+  int32_t ntab;                // table of the nc column offsets
+  int32_t p0, p1;              // pair range
+};
+struct RtPair {
+  int64_t xbase;               // X block element offset
+  int64_t pk;                  // packed [Kb][nc] layer sub-block
+  int32_t xs[RT_MAXLEV];       // level strides in the X block
+  int32_t Kb;
+  int32_t xktab;               // table of the Kb contracted offsets in the X block
+};
+struct RtPack {
+  int64_t dst;                 // = RtPair::pk
+  int64_t sbase;               // layer block element offset
+  int32_t Kb, nc;
+  int32_t sktab, sntab;        // layer block offsets along K (Kb) and N (chunk, nc)
+  double alpha;
+};
+struct RtPlan {
+  std::vector<RtGroup> groups;
+  std::vector<RtOut> outs;
+  std::vector<RtPair> pairs;
+  std::vector<RtPack> packs;
+  int64_t pack_size = 0;       // doubles
+  int32_t ntiles = 0;
+  double flops = 0;
+  int64_t x_extent = 0, c_extent = 0, s_extent = 0;
+  // algorithmic HBM bytes: every input element read once, every output
+  // element written once; x_loads counts the element loads the rows issue
+  double bytes = 0, x_loads = 0;
+};
+
+bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sym,
+                  TablePool& pool, StepResult& res, RtPlan& rt, std::string& err);
 
 // Build the GEMM jobs of a plain dense product C = alpha op(A) op(B) where all
 // three are strided matrices (used by the factorisation steps).

@@ -15,12 +15,13 @@ const std::vector<int> ORDER_X[6] = {
     {N_c, N_dk, N_dw, N_db, N_j},
 };
 
-// storage orders of the intermediates (chosen for contiguous access of the
-// two large products, steps 1 and 5 and their transposes)
-static const std::vector<int> STORE_X1 = {N_a, N_tk, N_tw, N_tb, N_rk, N_rw, N_rb, N_j};
-static const std::vector<int> STORE_X2 = {N_a, N_tw, N_tb, N_rw, N_rb, N_j, N_p, N_lk, N_dk};
-static const std::vector<int> STORE_X3 = {N_a, N_tb, N_rb, N_j, N_lk, N_dk, N_q, N_lw, N_dw};
-static const std::vector<int> STORE_X4 = {N_a, N_lk, N_lw, N_lb, N_dk, N_dw, N_db, N_j};
+// storage orders of the intermediates: the sketch column index j is
+// innermost (stride 1) in all of them, and the free legs of each layer step
+// form at most three runs contiguous in both its input and its output
+static const std::vector<int> STORE_X1 = {N_a, N_tk, N_rk, N_tw, N_rw, N_tb, N_rb, N_j};
+static const std::vector<int> STORE_X2 = {N_a, N_p, N_tw, N_rw, N_lk, N_dk, N_tb, N_rb, N_j};
+static const std::vector<int> STORE_X3 = {N_a, N_q, N_lw, N_dw, N_lk, N_dk, N_tb, N_rb, N_j};
+static const std::vector<int> STORE_X4 = {N_a, N_lw, N_dw, N_lk, N_dk, N_lb, N_db, N_j};
 
 Status tensor_to_bt(const fpeps_tensor* t, const std::vector<int>& names, int nlab, BT& out,
                     bool flip_dirs) {
@@ -345,16 +346,26 @@ Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t bud
       sp.out_names = *store[s];
       sp.key_order = ORDER_X[s];
       StepResult r;
-      if (!plan_step(X, *S[s], sp, sym, out.ps.pool, s == 4 ? &rowL : nullptr, r, err))
-        return fail(FPEPS_ERR_SHAPE, "chain step " + std::to_string(s + 1) + ": " + err);
-      out.flops_fwd += r.plan.flops;
+      const bool layer = s >= 1 && s <= 3;
+      if (layer) {
+        RtPlan rp;
+        if (!plan_step_rt(X, *S[s], sp, sym, out.ps.pool, r, rp, err))
+          return fail(FPEPS_ERR_SHAPE, "chain step " + std::to_string(s + 1) + ": " + err);
+        out.flops_fwd += rp.flops;
+        sl.fwd[s] = out.ps.add_rt(std::move(rp));
+      } else {
+        if (!plan_step(X, *S[s], sp, sym, out.ps.pool, s == 4 ? &rowL : nullptr, r, err))
+          return fail(FPEPS_ERR_SHAPE, "chain step " + std::to_string(s + 1) + ": " + err);
+        out.flops_fwd += r.plan.flops;
+        sl.fwd[s] = out.ps.add(std::move(r.plan));
+      }
+      sl.fwd_rt[s] = layer;
       if (s < 4) {
         if (s % 2 == 0)
           sl.size1 = std::max(sl.size1, r.out.size);
         else
           sl.size2 = std::max(sl.size2, r.out.size);
       }
-      sl.fwd[s] = out.ps.add(std::move(r.plan));
       X = std::move(r.out);
     }
     if (with_bwd) {
@@ -370,17 +381,29 @@ Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t bud
         // sector (synthetic SU(2) scalars can reach others, which are dropped)
         sp.restrict_to_fixed = true;
         StepResult r;
-        if (!plan_step(Z, *S[bstep[s] - 1], sp, sym, out.ps.pool, s == 4 ? &colL : nullptr, r, err))
-          return fail(FPEPS_ERR_SHAPE,
-                      "transposed chain step " + std::to_string(bstep[s]) + ": " + err);
-        out.flops_bwd += r.plan.flops;
+        const bool layer = s >= 1 && s <= 3;
+        if (layer) {
+          RtPlan rp;
+          if (!plan_step_rt(Z, *S[bstep[s] - 1], sp, sym, out.ps.pool, r, rp, err))
+            return fail(FPEPS_ERR_SHAPE,
+                        "transposed chain step " + std::to_string(bstep[s]) + ": " + err);
+          out.flops_bwd += rp.flops;
+          sl.bwd[s] = out.ps.add_rt(std::move(rp));
+        } else {
+          if (!plan_step(Z, *S[bstep[s] - 1], sp, sym, out.ps.pool, s == 4 ? &colL : nullptr, r,
+                         err))
+            return fail(FPEPS_ERR_SHAPE,
+                        "transposed chain step " + std::to_string(bstep[s]) + ": " + err);
+          out.flops_bwd += r.plan.flops;
+          sl.bwd[s] = out.ps.add(std::move(r.plan));
+        }
+        sl.bwd_rt[s] = layer;
         if (s < 4) {
           if (s % 2 == 0)
             sl.size2 = std::max(sl.size2, r.out.size);
           else
             sl.size1 = std::max(sl.size1, r.out.size);
         }
-        sl.bwd[s] = out.ps.add(std::move(r.plan));
         Z = std::move(r.out);
       }
     } else {
@@ -391,6 +414,19 @@ Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t bud
     out.slices.push_back(sl);
   }
   FP_TRY(out.ps.upload(ctx, "site"));
+  // layer sub-blocks scaled by the per-pair scalars (the bra shares the
+  // ket's data)
+  for (const Slice& sl : out.slices)
+    for (int s = 0; s < 5; ++s) {
+      if (sl.fwd_rt[s]) {
+        const bool w = s == 2;
+        FP_TRY(out.ps.pack(ctx, sl.fwd[s], w ? dev.W : dev.A, w ? dev.W_size : dev.A_size));
+      }
+      if (sl.bwd[s] >= 0 && sl.bwd_rt[s]) {
+        const bool w = bstep[s] == 3;
+        FP_TRY(out.ps.pack(ctx, sl.bwd[s], w ? dev.W : dev.A, w ? dev.W_size : dev.A_size));
+      }
+    }
   ctx->peak_ws = std::max(ctx->peak_ws, (double)(out.ws1 + out.ws2) * sizeof(double));
   ctx->nslices = std::max(ctx->nslices, (int)out.slices.size());
   return Status::ok();
@@ -403,18 +439,18 @@ Status SiteOp::apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const do
   const int64_t s1 = std::max<int64_t>(pl.ws1, 1), s2 = std::max<int64_t>(pl.ws2, 1);
   for (const Slice& sl : pl.slices) {
     if (!transpose) {
-      FP_TRY(run_gemm(ctx, pl.ps, sl.fwd[0], dev.T, dev.T_size, x, pl.col_total, b1, s1, true));
-      FP_TRY(run_gemm(ctx, pl.ps, sl.fwd[1], b1, s1, dev.A, dev.A_size, b2, s2, true));
-      FP_TRY(run_gemm(ctx, pl.ps, sl.fwd[2], b2, s2, dev.W, dev.W_size, b1, s1, true));
-      FP_TRY(run_gemm(ctx, pl.ps, sl.fwd[3], b1, s1, dev.A, dev.A_size, b2, s2, true));
-      FP_TRY(run_gemm(ctx, pl.ps, sl.fwd[4], dev.R, dev.R_size, b2, s2, y, pl.row_total, true));
+      FP_TRY(run_gemm(ctx, pl.ps, sl.fwd[0], dev.T, dev.T_size, x, pl.col_total, b1, s1, true, 1));
+      FP_TRY(run_rt(ctx, pl.ps, sl.fwd[1], b1, s1, b2, s2, true, 2));
+      FP_TRY(run_rt(ctx, pl.ps, sl.fwd[2], b2, s2, b1, s1, true, 3));
+      FP_TRY(run_rt(ctx, pl.ps, sl.fwd[3], b1, s1, b2, s2, true, 4));
+      FP_TRY(run_gemm(ctx, pl.ps, sl.fwd[4], dev.R, dev.R_size, b2, s2, y, pl.row_total, true, 5));
     } else {
       if (sl.bwd[0] < 0) return fail(FPEPS_ERR_ARG, "transposed chain was not planned");
-      FP_TRY(run_gemm(ctx, pl.ps, sl.bwd[0], dev.R, dev.R_size, x, pl.row_total, b2, s2, true));
-      FP_TRY(run_gemm(ctx, pl.ps, sl.bwd[1], b2, s2, dev.A, dev.A_size, b1, s1, true));
-      FP_TRY(run_gemm(ctx, pl.ps, sl.bwd[2], b1, s1, dev.W, dev.W_size, b2, s2, true));
-      FP_TRY(run_gemm(ctx, pl.ps, sl.bwd[3], b2, s2, dev.A, dev.A_size, b1, s1, true));
-      FP_TRY(run_gemm(ctx, pl.ps, sl.bwd[4], dev.T, dev.T_size, b1, s1, y, pl.col_total, true));
+      FP_TRY(run_gemm(ctx, pl.ps, sl.bwd[0], dev.R, dev.R_size, x, pl.row_total, b2, s2, true, 15));
+      FP_TRY(run_rt(ctx, pl.ps, sl.bwd[1], b2, s2, b1, s1, true, 14));
+      FP_TRY(run_rt(ctx, pl.ps, sl.bwd[2], b1, s1, b2, s2, true, 13));
+      FP_TRY(run_rt(ctx, pl.ps, sl.bwd[3], b2, s2, b1, s1, true, 12));
+      FP_TRY(run_gemm(ctx, pl.ps, sl.bwd[4], dev.T, dev.T_size, b1, s1, y, pl.col_total, true, 11));
     }
   }
   return Status::ok();

@@ -54,7 +54,9 @@ class SiteOp {
   // the chain intermediates of one slice fit ``budget`` bytes.
   struct Slice {
     std::vector<SliceCol> cols;
-    int fwd[5], bwd[5];       // plan indices in the PlanSet
+    int fwd[5], bwd[5];       // plan indices in the PlanSet (GEMM or row-thread list)
+    bool fwd_rt[5] = {false, false, false, false, false};
+    bool bwd_rt[5] = {false, false, false, false, false};
     int64_t size1 = 0, size2 = 0;  // ping-pong intermediate buffer sizes (elements)
   };
   struct Plans {
