@@ -35,23 +35,20 @@ __device__ __forceinline__ void rt_chunk(const double* __restrict__ X,
     const int32_t* kt = tab + P.xktab;
     const double* bp = PK + P.pk;
     const int Kb = P.Kb;
-    int k = 0;
-    for (; k + 4 <= Kb; k += 4) {
-      const double a0 = xp[kt[k]], a1 = xp[kt[k + 1]], a2 = xp[kt[k + 2]], a3 = xp[kt[k + 3]];
-      const double* b = bp + k * NC;
+    // eight independent loads in flight per batch (Kb is wave-uniform, so
+    // the guards are scalar branches)
+    for (int k0 = 0; k0 < Kb; k0 += 8) {
+      double a[8];
 #pragma unroll
-      for (int n = 0; n < NC; ++n) {
-        acc[n] = fma(a0, b[n], acc[n]);
-        acc[n] = fma(a1, b[NC + n], acc[n]);
-        acc[n] = fma(a2, b[2 * NC + n], acc[n]);
-        acc[n] = fma(a3, b[3 * NC + n], acc[n]);
+      for (int u = 0; u < 8; ++u) a[u] = (k0 + u < Kb) ? xp[kt[k0 + u]] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (k0 + u < Kb) {
+          const double* b = bp + (k0 + u) * NC;
+#pragma unroll
+          for (int n = 0; n < NC; ++n) acc[n] = fma(a[u], b[n], acc[n]);
+        }
       }
-    }
-    for (; k < Kb; ++k) {
-      const double a = xp[kt[k]];
-      const double* b = bp + k * NC;
-#pragma unroll
-      for (int n = 0; n < NC; ++n) acc[n] = fma(a, b[n], acc[n]);
     }
   }
   if (live) {

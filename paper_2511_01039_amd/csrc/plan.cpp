@@ -416,15 +416,23 @@ bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sy
       ktot[ob] += prod_dims(A, spec.m_is_x ? X.blocks[trip[t].xb] : S.blocks[trip[t].sb], ak);
   choose_tile(mn, ktot, &plan.mt, &plan.nt);
   plan.pairs.reserve(trip.size());
+  // tables depend only on the block: built once per block
+  std::vector<TabRef> c_am(A.blocks.size(), TabRef{-1, 0}), c_ak(A.blocks.size(), TabRef{-1, 0});
+  std::vector<TabRef> c_bk(B.blocks.size(), TabRef{-1, 0}), c_bn(B.blocks.size(), TabRef{-1, 0});
+  auto cached = [&](std::vector<TabRef>& c, int i, const BT& bt, const std::vector<int>& pos) {
+    if (c[i].id < 0) c[i] = make_table(pool, bt, bt.blocks[i], pos, &ok);
+    return c[i];
+  };
   for (auto& t : trip) {
     const Block& xbk = X.blocks[t.xb];
     const Block& sbk = S.blocks[t.sb];
     const Block& abk = spec.m_is_x ? xbk : sbk;
     const Block& bbk = spec.m_is_x ? sbk : xbk;
-    TabRef tam = make_table(pool, A, abk, afree, &ok);
-    TabRef tak = make_table(pool, A, abk, ak, &ok);
-    TabRef tbk = make_table(pool, B, bbk, bk, &ok);
-    TabRef tbn = make_table(pool, B, bbk, bfree, &ok);
+    const int ai = spec.m_is_x ? t.xb : t.sb, bi = spec.m_is_x ? t.sb : t.xb;
+    TabRef tam = cached(c_am, ai, A, afree);
+    TabRef tak = cached(c_ak, ai, A, ak);
+    TabRef tbk = cached(c_bk, bi, B, bk);
+    TabRef tbn = cached(c_bn, bi, B, bfree);
     GemmPair gp;
     gp.a_off = abk.base;
     gp.b_off = bbk.base;
@@ -604,16 +612,15 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
     }
     return true;
   };
+  // per-block caches of the small tables
+  std::vector<TabRef> c_xk(X.blocks.size(), TabRef{-1, 0}), c_sk(S.blocks.size(), TabRef{-1, 0});
+  std::vector<std::vector<int32_t>> c_sn(S.blocks.size());
+  std::map<std::pair<int, int64_t>, int32_t> c_snt;
   std::vector<int> opos_by_i(E.xfree.size());
   for (size_t i = 0; i < E.xfree.size(); ++i) opos_by_i[i] = opos[i];
   std::vector<int> xpos_by_i = E.xfree;
   // S legs: contracted (in X's contracted order) and free (S order)
   bool ok = true;
-  auto tab_of = [&](const BT& bt, const Block& b, const std::vector<int>& pos, int64_t* mx) {
-    TabRef t = make_table(pool, bt, b, pos, &ok);
-    if (mx) *mx = t.maxoff;
-    return t.id;
-  };
   // output N legs, in S order, located in the output
   std::vector<int> onpos;
   for (int q : E.sfree) onpos.push_back(out.pos(S.names[q]));
@@ -692,8 +699,12 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
       int32_t nmax = 0;
       for (int32_t v : noff) nmax = std::max(nmax, v);
       rt.c_extent = std::max(rt.c_extent, cb.base + rowmax + nmax + 1);
-      for (int64_t n0 = 0; n0 < Nb; n0 += RT_NC) {
-        const int nc = (int)std::min<int64_t>(RT_NC, Nb - n0);
+      // equal chunks of at most RT_NC columns (18 -> 9 + 9, not 16 + 2):
+      // every chunk re-reads the row's inputs
+      const int64_t nchunks = (Nb + RT_NC - 1) / RT_NC;
+      const int64_t cw = (Nb + nchunks - 1) / nchunks;
+      for (int64_t n0 = 0; n0 < Nb; n0 += cw) {
+        const int nc = (int)std::min<int64_t>(cw, Nb - n0);
         RtOut o = base_o;
         o.nc = nc;
         o.ntab = pool.add_raw(std::vector<int32_t>(noff.begin() + n0, noff.begin() + n0 + nc), &ok);
@@ -716,8 +727,9 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
           pr.xbase = xb.base;
           const int64_t Kb = prod_dims(X, xb, E.xs);
           pr.Kb = (int32_t)Kb;
-          int64_t kmax = 0;
-          pr.xktab = tab_of(X, xb, E.xs, &kmax);
+          if (c_xk[t.xb].id < 0) c_xk[t.xb] = make_table(pool, X, xb, E.xs, &ok);
+          const int64_t kmax = c_xk[t.xb].maxoff;
+          pr.xktab = c_xk[t.xb].id;
           int64_t xrow = 0;
           for (int l = 0; l < RT_MAXLEV; ++l) xrow += (int64_t)(g.md[l] - 1) * pr.xs[l];
           rt.x_extent = std::max(rt.x_extent, xb.base + xrow + kmax + 1);
@@ -727,17 +739,18 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
           pk.sbase = sb.base;
           pk.Kb = pr.Kb;
           pk.nc = nc;
-          int64_t skmax = 0;
-          pk.sktab = tab_of(S, sb, E.ss, &skmax);
-          // layer block N offsets of this chunk
-          {
+          if (c_sk[t.sb].id < 0) c_sk[t.sb] = make_table(pool, S, sb, E.ss, &ok);
+          const int64_t skmax = c_sk[t.sb].maxoff;
+          pk.sktab = c_sk[t.sb].id;
+          // layer block N offsets (all Nb), then this chunk's table
+          std::vector<int32_t>& all = c_sn[t.sb];
+          if (all.empty()) {
             std::vector<int32_t> dims;
             std::vector<int64_t> strides;
             for (int q : E.sfree) {
               dims.push_back(S.dim(sb, q));
               strides.push_back(sb.stride[q]);
             }
-            std::vector<int32_t> all;
             std::vector<int32_t> idx(dims.size(), 0);
             int64_t off = 0;
             for (int64_t e = 0; e < Nb; ++e) {
@@ -751,11 +764,17 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
                 idx[d] = 0;
               }
             }
-            int32_t snmax = 0;
-            for (int64_t e = n0; e < n0 + nc; ++e) snmax = std::max(snmax, all[e]);
-            rt.s_extent = std::max(rt.s_extent, sb.base + skmax + snmax + 1);
-            pk.sntab = pool.add_raw(std::vector<int32_t>(all.begin() + n0, all.begin() + n0 + nc), &ok);
           }
+          int32_t snmax = 0;
+          for (int64_t e = n0; e < n0 + nc; ++e) snmax = std::max(snmax, all[e]);
+          rt.s_extent = std::max(rt.s_extent, sb.base + skmax + snmax + 1);
+          auto key = std::make_pair(t.sb, n0);
+          auto it = c_snt.find(key);
+          if (it == c_snt.end())
+            it = c_snt.emplace(key, pool.add_raw(std::vector<int32_t>(all.begin() + n0,
+                                                                        all.begin() + n0 + nc),
+                                                 &ok)).first;
+          pk.sntab = it->second;
           pk.alpha = trip_alpha(E, X, S, out, spec, sym, t);
           rt.pack_size += Kb * nc;
           rt.packs.push_back(pk);
