@@ -97,12 +97,26 @@ def main():
     ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 4 times (the known-size "
+                         "reference for HBM byte counters) and exit")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the row absorption runs on a single MI355X in this "
               "build; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import torch
+    if a.calibrate_copy:
+        n = 1 << 27                      # 2^27 doubles = 1 GiB
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy": {"bytes_read_per_copy": 8 * n,
+                                             "bytes_written_per_copy": 8 * n, "copies": 4}}))
+        return
     from paper_2511_01039_amd import Context, DeviceTensor, opts_for
     from paper_2511_01039_amd.binding import FLAG_TIME_KERNELS
     assert torch.cuda.is_available(), "bench.py needs a GPU"

@@ -109,23 +109,30 @@ Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
   // row-thread plans, concatenated with rebased ranges
   std::vector<RtGroup> rg;
   std::vector<RtOut> ro;
+  std::vector<RtKblk> rb;
+  std::vector<RtCol> rc;
   std::vector<RtPair> rp;
   std::vector<RtPack> rk;
   struct R4 {
-    size_t g, o, p, k;
+    size_t g, o, b, c, p, k;
   };
   std::vector<R4> rr;
   pack_off.clear();
   pack_total = 0;
   for (auto& r : rts) {
-    R4 b{rg.size(), ro.size(), rp.size(), rk.size()};
+    R4 b{rg.size(), ro.size(), rb.size(), rc.size(), rp.size(), rk.size()};
     rr.push_back(b);
     pack_off.push_back(pack_total);
     for (auto g : r.groups) {
       g.o0 += (int32_t)b.o;
       g.o1 += (int32_t)b.o;
+      g.k0 += (int32_t)b.b;
+      g.k1 += (int32_t)b.b;
+      g.c0 += (int32_t)b.c;
       rg.push_back(g);
     }
+    rb.insert(rb.end(), r.kblks.begin(), r.kblks.end());
+    rc.insert(rc.end(), r.cols.begin(), r.cols.end());
     for (auto o : r.outs) {
       o.p0 += (int32_t)b.p;
       o.p1 += (int32_t)b.p;
@@ -133,6 +140,7 @@ Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
     }
     for (auto p : r.pairs) {
       p.pk += pack_total;
+      p.kblk += (int32_t)b.b;
       rp.push_back(p);
     }
     for (auto k : r.packs) {
@@ -141,7 +149,8 @@ Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
     }
     pack_total += r.pack_size;
     if (ro.size() > (size_t)INT32_MAX || rp.size() > (size_t)INT32_MAX ||
-        rk.size() > (size_t)INT32_MAX)
+        rk.size() > (size_t)INT32_MAX || rb.size() > (size_t)INT32_MAX ||
+        rc.size() > (size_t)INT32_MAX)
       return fail(FPEPS_ERR_UNSUPPORTED, "layer plan too large");
   }
   void *dj = nullptr, *dp = nullptr, *dt = nullptr;
@@ -151,8 +160,11 @@ Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
   dtab = (int32_t*)dt;
   void* dr = nullptr;
   FP_TRY(ctx->upload(tag + "_red", reds.data(), reds.size() * sizeof(ReduceTab), &dr));
-  void *dg = nullptr, *dO = nullptr, *dP = nullptr, *dK = nullptr, *dpk = nullptr;
+  void *dg = nullptr, *dO = nullptr, *dP = nullptr, *dK = nullptr, *dpk = nullptr, *dB = nullptr;
   FP_TRY(ctx->upload(tag + "_rtg", rg.data(), rg.size() * sizeof(RtGroup), &dg));
+  FP_TRY(ctx->upload(tag + "_rtb", rb.data(), rb.size() * sizeof(RtKblk), &dB));
+  void* dC = nullptr;
+  FP_TRY(ctx->upload(tag + "_rtc", rc.data(), rc.size() * sizeof(RtCol), &dC));
   FP_TRY(ctx->upload(tag + "_rto", ro.data(), ro.size() * sizeof(RtOut), &dO));
   FP_TRY(ctx->upload(tag + "_rtp", rp.data(), rp.size() * sizeof(RtPair), &dP));
   FP_TRY(ctx->upload(tag + "_rtk", rk.data(), rk.size() * sizeof(RtPack), &dK));
@@ -164,7 +176,10 @@ Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
     DevRt d;
     d.groups = (const RtGroup*)dg + rr[i].g;
     d.outs = (const RtOut*)dO;
+    d.kblks = (const RtKblk*)dB;
+    d.cols = (const RtCol*)dC;
     d.pairs = (const RtPair*)dP;
+    d.lds_bytes = rts[i].lds_bytes;
     d.packs = (const RtPack*)dK + rr[i].k;
     d.ngroups = (int)rts[i].groups.size();
     d.ntiles = rts[i].ntiles;

@@ -27,9 +27,12 @@ hipError_t launch_gemm_f64(const DevGemm& g, const double* A, const double* B, d
 struct DevRt {
   const RtGroup* groups = nullptr;
   const RtOut* outs = nullptr;
+  const RtKblk* kblks = nullptr;
+  const RtCol* cols = nullptr;
   const RtPair* pairs = nullptr;
   const RtPack* packs = nullptr;
   int ngroups = 0, ntiles = 0, npacks = 0;
+  int lds_bytes = 0;
 };
 // Y[rows of every group] = X rows times the packed layer sub-blocks PK.
 hipError_t launch_rt_f64(const DevRt& r, const double* X, const double* PK, double* Y,

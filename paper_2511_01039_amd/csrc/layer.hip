@@ -3,51 +3,152 @@
 //
 // These products have a huge row count (environment x sketch indices) and
 // tiny contracted/column extents (a few virtual or physical indices), so
-// they are bound by HBM traffic, not by arithmetic. One thread owns one row
-// of one row group (fixed sectors on the free legs of X): it reads each of
-// its input values once per column chunk, multiplies them into NC
-// register accumulators against the packed, scalar-scaled layer sub-block
-// (wave-uniform addresses, served by the scalar data path), and writes
-// every output value once. Rows are numbered with the sketch column index
-// innermost, which is stride-1 in every intermediate, so loads and stores
-// of a wave are contiguous runs.
+// they are bound by HBM traffic, not by arithmetic. A workgroup takes 64,
+// 128 or 256 consecutive rows of one row group (fixed sectors on the free
+// legs of X). It first copies those rows of every X block of the group into
+// LDS, so each input element is read from HBM once (re-reading it from
+// global memory per output chunk thrashes L2); then each lane owns one row
+// and the four waves split the output chunks. A chunk's NC accumulators
+// are multiplied against the packed, scalar-scaled layer sub-block
+// (wave-uniform addresses, served by the scalar data path), and every
+// output value is written once. Rows are numbered with the sketch column
+// index innermost, which is stride-1 in every intermediate, so loads and
+// stores of a wave are contiguous runs. Groups whose X rows do not fit the
+// LDS budget read X directly.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
 
 namespace fp {
 
-template <int NC>
+// Plan data (groups, chunks, pairs, tables, packed layer blocks) is never
+// written by the kernel: reading it through the constant address space lets
+// wave-uniform loads use the scalar unit (s_load) even after the LDS barrier.
+#define FP_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const FP_CONST T* as_const(const T* p) {
+  return (const FP_CONST T*)p;
+}
+// field-wise copies out of the constant address space
+__device__ __forceinline__ RtGroup ld(const FP_CONST RtGroup* p) {
+  RtGroup g;
+  g.tile0 = p->tile0;
+  g.M = p->M;
+#pragma unroll
+  for (int l = 0; l < RT_MAXLEV; ++l) g.md[l] = p->md[l];
+  g.o0 = p->o0;
+  g.o1 = p->o1;
+  g.k0 = p->k0;
+  g.k1 = p->k1;
+  g.rows = p->rows;
+  g.staged = p->staged;
+  g.ktot = p->ktot;
+  g.c0 = p->c0;
+  return g;
+}
+__device__ __forceinline__ RtOut ld(const FP_CONST RtOut* p) {
+  RtOut o;
+  o.base = p->base;
+#pragma unroll
+  for (int l = 0; l < RT_MAXLEV; ++l) o.ms[l] = p->ms[l];
+  o.nc = p->nc;
+  o.ntab = p->ntab;
+  o.p0 = p->p0;
+  o.p1 = p->p1;
+  return o;
+}
+__device__ __forceinline__ RtKblk ld(const FP_CONST RtKblk* p) {
+  RtKblk k;
+  k.xbase = p->xbase;
+#pragma unroll
+  for (int l = 0; l < RT_MAXLEV; ++l) k.xs[l] = p->xs[l];
+  k.Kb = p->Kb;
+  k.xktab = p->xktab;
+  k.koff = p->koff;
+  k.pad = 0;
+  return k;
+}
+__device__ __forceinline__ RtCol ld(const FP_CONST RtCol* p) {
+  RtCol c;
+  c.xbase = p->xbase;
+#pragma unroll
+  for (int l = 0; l < RT_MAXLEV; ++l) c.xs[l] = p->xs[l];
+  return c;
+}
+__device__ __forceinline__ RtPair ld(const FP_CONST RtPair* p) {
+  RtPair r;
+  r.pk = p->pk;
+  r.kblk = p->kblk;
+  r.koff = p->koff;
+  r.Kb = p->Kb;
+  r.pad = 0;
+  return r;
+}
+
+// Accumulate one output chunk (NC columns) of row r of the tile and store it.
+// Staged groups read X from LDS (column-major: staged column c of tile row r
+// at lds[c * rows + r]); unstaged ones read it from X through the X block's
+// level strides and contracted-offset table.
+template <int NC, bool STAGED>
 __device__ __forceinline__ void rt_chunk(const double* __restrict__ X,
-                                         const double* __restrict__ PK, double* __restrict__ Y,
-                                         const RtOut& O, const RtPair* __restrict__ pairs,
-                                         const int32_t* __restrict__ tab,
+                                         const FP_CONST double* PK, double* __restrict__ Y,
+                                         const double* __restrict__ lds, int rows, int r,
+                                         const RtOut& O, const FP_CONST RtPair* pairs,
+                                         const FP_CONST RtKblk* kblks,
+                                         const FP_CONST int32_t* tab,
                                          const int32_t (&idx)[RT_MAXLEV], bool live) {
   double acc[NC];
 #pragma unroll
   for (int n = 0; n < NC; ++n) acc[n] = 0.0;
   for (int p = O.p0; p < O.p1; ++p) {
-    const RtPair P = pairs[p];
-    int32_t xo = 0;
-#pragma unroll
-    for (int l = 0; l < RT_MAXLEV; ++l) xo += idx[l] * P.xs[l];
-    const double* xp = X + P.xbase + xo;
-    const int32_t* kt = tab + P.xktab;
-    const double* bp = PK + P.pk;
+    const RtPair P = ld(pairs + p);
+    const FP_CONST double* bp = PK + P.pk;
     const int Kb = P.Kb;
-    // eight independent loads in flight per batch (Kb is wave-uniform, so
-    // the guards are scalar branches)
-    for (int k0 = 0; k0 < Kb; k0 += 8) {
-      double a[8];
+    if (STAGED) {
+      const double* lp = lds + (int64_t)P.koff * rows + r;
+      int k = 0;
+      for (; k + 4 <= Kb; k += 4) {
+        const double a0 = lp[(k + 0) * rows], a1 = lp[(k + 1) * rows];
+        const double a2 = lp[(k + 2) * rows], a3 = lp[(k + 3) * rows];
+        const FP_CONST double* b = bp + k * NC;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = (k0 + u < Kb) ? xp[kt[k0 + u]] : 0.0;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (k0 + u < Kb) {
-          const double* b = bp + (k0 + u) * NC;
-#pragma unroll
-          for (int n = 0; n < NC; ++n) acc[n] = fma(a[u], b[n], acc[n]);
+        for (int n = 0; n < NC; ++n) {
+          acc[n] = fma(a0, b[n], acc[n]);
+          acc[n] = fma(a1, b[NC + n], acc[n]);
+          acc[n] = fma(a2, b[2 * NC + n], acc[n]);
+          acc[n] = fma(a3, b[3 * NC + n], acc[n]);
         }
+      }
+      for (; k < Kb; ++k) {
+        const double a = lp[k * rows];
+        const FP_CONST double* b = bp + k * NC;
+#pragma unroll
+        for (int n = 0; n < NC; ++n) acc[n] = fma(a, b[n], acc[n]);
+      }
+    } else {
+      const RtKblk K = ld(kblks + P.kblk);
+      int32_t xo = 0;
+#pragma unroll
+      for (int l = 0; l < RT_MAXLEV; ++l) xo += idx[l] * K.xs[l];
+      const double* xp = X + K.xbase + xo;
+      const FP_CONST int32_t* kt = tab + K.xktab;
+      int k = 0;
+      for (; k + 4 <= Kb; k += 4) {
+        const double a0 = xp[kt[k]], a1 = xp[kt[k + 1]], a2 = xp[kt[k + 2]], a3 = xp[kt[k + 3]];
+        const FP_CONST double* b = bp + k * NC;
+#pragma unroll
+        for (int n = 0; n < NC; ++n) {
+          acc[n] = fma(a0, b[n], acc[n]);
+          acc[n] = fma(a1, b[NC + n], acc[n]);
+          acc[n] = fma(a2, b[2 * NC + n], acc[n]);
+          acc[n] = fma(a3, b[3 * NC + n], acc[n]);
+        }
+      }
+      for (; k < Kb; ++k) {
+        const double a = xp[kt[k]];
+        const FP_CONST double* b = bp + k * NC;
+#pragma unroll
+        for (int n = 0; n < NC; ++n) acc[n] = fma(a, b[n], acc[n]);
       }
     }
   }
@@ -56,46 +157,28 @@ __device__ __forceinline__ void rt_chunk(const double* __restrict__ X,
 #pragma unroll
     for (int l = 0; l < RT_MAXLEV; ++l) oo += idx[l] * O.ms[l];
     double* yp = Y + O.base + oo;
-    const int32_t* nt = tab + O.ntab;
+    const FP_CONST int32_t* nt = tab + O.ntab;
 #pragma unroll
     for (int n = 0; n < NC; ++n) yp[nt[n]] = acc[n];
   }
 }
 
-__global__ __launch_bounds__(RT_ROWS) void k_rt_f64(const double* __restrict__ X,
-                                                    const double* __restrict__ PK,
-                                                    double* __restrict__ Y,
-                                                    const RtGroup* __restrict__ groups,
-                                                    int ngroups, const RtOut* __restrict__ outs,
-                                                    const RtPair* __restrict__ pairs,
-                                                    const int32_t* __restrict__ tab) {
-  const int wg = blockIdx.x;
-  int lo = 0, hi = ngroups - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (groups[mid].tile0 <= wg)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const RtGroup G = groups[lo];
-  const int m = (wg - G.tile0) * RT_ROWS + (int)threadIdx.x;
-  const bool live = m < G.M;
-  // rows past the group end compute row M-1 (in bounds) and store nothing
-  int r = live ? m : G.M - 1;
-  int32_t idx[RT_MAXLEV];
-#pragma unroll
-  for (int l = RT_MAXLEV - 1; l >= 0; --l) {
-    const int d = G.md[l];
-    idx[l] = r % d;
-    r /= d;
-  }
-  for (int o = G.o0; o < G.o1; ++o) {
-    const RtOut O = outs[o];
+template <bool STAGED>
+__device__ __forceinline__ void rt_chunks(const double* __restrict__ X,
+                                          const FP_CONST double* PK, double* __restrict__ Y,
+                                          const double* __restrict__ lds, int rows, int r,
+                                          const RtGroup& G, int o_first, int o_step,
+                                          const FP_CONST RtOut* outs,
+                                          const FP_CONST RtPair* pairs,
+                                          const FP_CONST RtKblk* kblks,
+                                          const FP_CONST int32_t* tab,
+                                          const int32_t (&idx)[RT_MAXLEV], bool live) {
+  for (int o = G.o0 + o_first; o < G.o1; o += o_step) {
+    const RtOut O = ld(outs + o);
     switch (O.nc) {
-#define FP_RT_CASE(n) \
-  case n:             \
-    rt_chunk<n>(X, PK, Y, O, pairs, tab, idx, live); \
+#define FP_RT_CASE(n)                                                                    \
+  case n:                                                                                \
+    rt_chunk<n, STAGED>(X, PK, Y, lds, rows, r, O, pairs, kblks, tab, idx, live); \
     break;
       FP_RT_CASE(1) FP_RT_CASE(2) FP_RT_CASE(3) FP_RT_CASE(4) FP_RT_CASE(5) FP_RT_CASE(6)
       FP_RT_CASE(7) FP_RT_CASE(8) FP_RT_CASE(9) FP_RT_CASE(10) FP_RT_CASE(11) FP_RT_CASE(12)
@@ -105,6 +188,92 @@ __global__ __launch_bounds__(RT_ROWS) void k_rt_f64(const double* __restrict__ X
         break;
     }
   }
+}
+
+__device__ __forceinline__ void row_levels(const RtGroup& G, int m, int32_t (&idx)[RT_MAXLEV]) {
+#pragma unroll
+  for (int l = RT_MAXLEV - 1; l >= 0; --l) {
+    const int d = G.md[l];
+    idx[l] = m % d;
+    m /= d;
+  }
+}
+
+__global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
+    const double* __restrict__ X, const double* __restrict__ PK_, double* __restrict__ Y,
+    const RtGroup* __restrict__ groups_, int ngroups, const RtOut* __restrict__ outs_,
+    const RtKblk* __restrict__ kblks_, const RtCol* __restrict__ cols_,
+    const RtPair* __restrict__ pairs_, const int32_t* __restrict__ tab_) {
+  extern __shared__ double lds[];
+  const FP_CONST RtGroup* groups = as_const(groups_);
+  const FP_CONST RtOut* outs = as_const(outs_);
+  const FP_CONST RtKblk* kblks = as_const(kblks_);
+  const FP_CONST RtCol* cols = as_const(cols_);
+  const FP_CONST RtPair* pairs = as_const(pairs_);
+  const FP_CONST int32_t* tab = as_const(tab_);
+  const FP_CONST double* PK = as_const(PK_);
+  const int wg = blockIdx.x;
+  int lo = 0, hi = ngroups - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (groups[mid].tile0 <= wg)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const RtGroup G = ld(groups + lo);
+  const int rows = G.rows;                    // 64, 128 or 256
+  const int m0 = (wg - G.tile0) * rows;
+  const int tid = threadIdx.x;
+  if (G.staged) {
+    // stage: thread tid takes tile row tid % rows and the staged columns
+    // slot, slot + nslot, ... (slot = tid / rows is uniform per wave), eight
+    // loads in flight per batch; rows past the group end repeat row M-1 (in
+    // bounds, never stored)
+    const int sr = tid % rows, nslot = RT_THREADS / rows;
+    const int slot = __builtin_amdgcn_readfirstlane(tid / rows);
+    int32_t sidx[RT_MAXLEV];
+    row_levels(G, min(m0 + sr, G.M - 1), sidx);
+    const FP_CONST RtCol* gc = cols + G.c0;
+    for (int c0 = slot; c0 < G.ktot; c0 += 8 * nslot) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + u * nslot;
+        if (c < G.ktot) {
+          const RtCol C = ld(gc + c);
+          int32_t xo = 0;
+#pragma unroll
+          for (int l = 0; l < RT_MAXLEV; ++l) xo += sidx[l] * C.xs[l];
+          v[u] = X[C.xbase + xo];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + u * nslot;
+        if (c < G.ktot) lds[(int64_t)c * rows + sr] = v[u];
+      }
+    }
+    __syncthreads();
+  }
+  // compute: wave w owns tile rows (w % (rows/64)) * 64 + lane and the
+  // output chunks o0 + w / (rows/64), stepping by 4 / (rows/64)
+  // the wave index is uniform per wave; say so, so that the chunk loop and
+  // everything it loads stay scalar
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int rsub = rows >> 6;
+  const int r = (wave % rsub) * 64 + lane;
+  const int m = m0 + r;
+  const bool live = m < G.M;
+  int32_t idx[RT_MAXLEV];
+  row_levels(G, live ? m : G.M - 1, idx);
+  const int o_first = wave / rsub, o_step = 4 / rsub;
+  if (G.staged)
+    rt_chunks<true>(X, PK, Y, lds, rows, r, G, o_first, o_step, outs, pairs, kblks, tab, idx,
+                    live);
+  else
+    rt_chunks<false>(X, PK, Y, lds, rows, r, G, o_first, o_step, outs, pairs, kblks, tab, idx,
+                     live);
 }
 
 __global__ void k_rt_pack(const RtPack* __restrict__ packs, const double* __restrict__ S,
@@ -120,8 +289,9 @@ __global__ void k_rt_pack(const RtPack* __restrict__ packs, const double* __rest
 hipError_t launch_rt_f64(const DevRt& r, const double* X, const double* PK, double* Y,
                          const int32_t* tab, hipStream_t s) {
   if (r.ntiles <= 0 || r.ngroups <= 0) return hipSuccess;
-  k_rt_f64<<<dim3(r.ntiles), dim3(RT_ROWS), 0, s>>>(X, PK, Y, r.groups, r.ngroups, r.outs,
-                                                   r.pairs, tab);
+  if (r.lds_bytes < 0 || r.lds_bytes > RT_LDS_BYTES) return hipErrorInvalidValue;
+  k_rt_f64<<<dim3(r.ntiles), dim3(RT_THREADS), (size_t)r.lds_bytes, s>>>(
+      X, PK, Y, r.groups, r.ngroups, r.outs, r.kblks, r.cols, r.pairs, tab);
   return hipGetLastError();
 }
 

@@ -661,6 +661,47 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
     g.M = (int32_t)M;
     g.tile0 = (int32_t)tiles;
     g.o0 = (int32_t)rt.outs.size();
+    g.k0 = (int32_t)rt.kblks.size();
+    // the group's distinct X blocks, each with its staged column offset
+    std::map<int, int32_t> kmap;   // X block -> RtKblk index
+    int32_t ktot = 0;
+    for (int ob : kv.second)
+      for (int pi = pstart[ob]; pi < pstart[ob + 1]; ++pi) {
+        const int xbi = trip[pi].xb;
+        if (kmap.count(xbi)) continue;
+        const Block& xb = X.blocks[xbi];
+        RtKblk kb;
+        int32_t mdx[RT_MAXLEV];
+        if (!level_geom(X, xb, xpos_by_i, mdx, kb.xs)) {
+          err = "input block rows are not level-contiguous";
+          return false;
+        }
+        for (int l = 0; l < RT_MAXLEV; ++l)
+          if (mdx[l] != g.md[l]) {
+            err = "row levels differ between input and output block";
+            return false;
+          }
+        kb.xbase = xb.base;
+        const int64_t Kb = prod_dims(X, xb, E.xs);
+        if (Kb > INT32_MAX / 2) {
+          err = "contracted extent too large";
+          return false;
+        }
+        kb.Kb = (int32_t)Kb;
+        if (c_xk[xbi].id < 0) c_xk[xbi] = make_table(pool, X, xb, E.xs, &ok);
+        kb.xktab = c_xk[xbi].id;
+        int64_t xrow = 0;
+        for (int l = 0; l < RT_MAXLEV; ++l) xrow += (int64_t)(g.md[l] - 1) * kb.xs[l];
+        rt.x_extent = std::max(rt.x_extent, xb.base + xrow + c_xk[xbi].maxoff + 1);
+        kb.koff = ktot;
+        kb.pad = 0;
+        ktot += kb.Kb;
+        kmap.emplace(xbi, (int32_t)rt.kblks.size());
+        rt.kblks.push_back(kb);
+      }
+    g.k1 = (int32_t)rt.kblks.size();
+    g.ktot = ktot;
+    g.c0 = (int32_t)rt.cols.size();
     for (int ob : kv.second) {
       const Block& cb = out.blocks[ob];
       RtOut base_o;
@@ -714,25 +755,12 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
           const Block& xb = X.blocks[t.xb];
           const Block& sb = S.blocks[t.sb];
           RtPair pr;
-          int32_t mdx[RT_MAXLEV];
-          if (!level_geom(X, xb, xpos_by_i, mdx, pr.xs)) {
-            err = "input block rows are not level-contiguous";
-            return false;
-          }
-          for (int l = 0; l < RT_MAXLEV; ++l)
-            if (mdx[l] != g.md[l]) {
-              err = "row levels differ between input and output block";
-              return false;
-            }
-          pr.xbase = xb.base;
-          const int64_t Kb = prod_dims(X, xb, E.xs);
-          pr.Kb = (int32_t)Kb;
-          if (c_xk[t.xb].id < 0) c_xk[t.xb] = make_table(pool, X, xb, E.xs, &ok);
-          const int64_t kmax = c_xk[t.xb].maxoff;
-          pr.xktab = c_xk[t.xb].id;
-          int64_t xrow = 0;
-          for (int l = 0; l < RT_MAXLEV; ++l) xrow += (int64_t)(g.md[l] - 1) * pr.xs[l];
-          rt.x_extent = std::max(rt.x_extent, xb.base + xrow + kmax + 1);
+          const int32_t kbi = kmap.at(t.xb);
+          pr.kblk = kbi;
+          pr.koff = rt.kblks[kbi].koff;
+          pr.Kb = rt.kblks[kbi].Kb;
+          pr.pad = 0;
+          const int64_t Kb = pr.Kb;
           pr.pk = rt.pack_size;
           RtPack pk;
           pk.dst = rt.pack_size;
@@ -787,8 +815,29 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
       }
     }
     g.o1 = (int32_t)rt.outs.size();
+    // rows per workgroup: four waves share the chunks of 64 rows when there
+    // are enough chunks, else take 128 or 256 rows; staged when the X rows
+    // fit the LDS budget
+    const int nch = g.o1 - g.o0;
+    int rows = nch >= 4 ? 64 : (nch >= 2 ? 128 : 256);
+    while (rows > 64 && (int64_t)rows * ktot * 8 > RT_LDS_BYTES) rows /= 2;
+    g.rows = rows;
+    g.staged = (int64_t)rows * ktot * 8 <= RT_LDS_BYTES ? 1 : 0;
+    if (g.staged) {
+      for (int b = g.k0; b < g.k1; ++b) {
+        const RtKblk& K = rt.kblks[b];
+        const int32_t* kt = pool.data.data() + K.xktab;
+        for (int k = 0; k < K.Kb; ++k) {
+          RtCol c;
+          c.xbase = K.xbase + kt[k];
+          for (int l = 0; l < RT_MAXLEV; ++l) c.xs[l] = K.xs[l];
+          rt.cols.push_back(c);
+        }
+      }
+    }
+    if (g.staged) rt.lds_bytes = std::max<int32_t>(rt.lds_bytes, rows * ktot * 8);
     rt.groups.push_back(g);
-    tiles += (M + RT_ROWS - 1) / RT_ROWS;
+    tiles += (M + rows - 1) / rows;
     if (tiles > INT32_MAX) {
       err = "layer step has too many row tiles";
       return false;

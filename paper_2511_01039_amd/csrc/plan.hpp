@@ -186,16 +186,32 @@ bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sy
 // a row offset is a short dot product and no per-row tables exist. Each
 // output block is cut into column chunks of nc <= RT_NC columns; the layer
 // tensor's sub-block of every pair, scaled by the pair's scalar, is packed
-// row-major [Kb][nc] once per plan.
+// row-major [Kb][nc] once per plan. A workgroup takes ``rows`` consecutive
+// rows of one group; when the group's distinct X blocks fit, their values for
+// those rows are staged once in LDS (each X element leaves HBM once) and the
+// four waves split the output chunks.
 constexpr int RT_MAXLEV = 4;
 constexpr int RT_NC = 16;
-constexpr int RT_ROWS = 256;   // rows per workgroup
+constexpr int RT_THREADS = 256;
+constexpr int RT_LDS_BYTES = 64 * 1024;   // staging budget per workgroup
 
 struct RtGroup {
   int32_t tile0;               // first workgroup of the group
   int32_t M;                   // rows
   int32_t md[RT_MAXLEV];       // level dims, innermost last (unused levels 1)
   int32_t o0, o1;              // output chunk range
+  int32_t k0, k1;              // X block range (RtKblk)
+  int32_t rows;                // rows per workgroup: 64, 128 or 256
+  int32_t staged;              // 1: X rows staged in LDS (rows * ktot doubles)
+  int32_t ktot;                // sum of Kb over the group's X blocks
+  int32_t c0;                  // first staged column (RtCol), ktot of them
+};
+// One staged column of a group: X element of row (level indices i) at
+// xbase + sum_l i_l xs[l] (the X block base plus the column's contracted
+// offset, and the block's level strides).
+struct RtCol {
+  int64_t xbase;
+  int32_t xs[RT_MAXLEV];
 };
 struct RtOut {
   int64_t base;                // output block element offset
@@ -204,12 +220,21 @@ struct RtOut {
   int32_t ntab;                // table of the nc column offsets
   int32_t p0, p1;              // pair range
 };
-struct RtPair {
+// One X block of a group (contracted sector combination).
+struct RtKblk {
   int64_t xbase;               // X block element offset
-  int64_t pk;                  // packed [Kb][nc] layer sub-block
   int32_t xs[RT_MAXLEV];       // level strides in the X block
   int32_t Kb;
   int32_t xktab;               // table of the Kb contracted offsets in the X block
+  int32_t koff;                // first staged column of this block in LDS
+  int32_t pad;
+};
+struct RtPair {
+  int64_t pk;                  // packed [Kb][nc] layer sub-block
+  int32_t kblk;                // X block (RtKblk index)
+  int32_t koff;                // its staged column offset
+  int32_t Kb;
+  int32_t pad;
 };
 struct RtPack {
   int64_t dst;                 // = RtPair::pk
@@ -221,10 +246,13 @@ struct RtPack {
 struct RtPlan {
   std::vector<RtGroup> groups;
   std::vector<RtOut> outs;
+  std::vector<RtKblk> kblks;
+  std::vector<RtCol> cols;
   std::vector<RtPair> pairs;
   std::vector<RtPack> packs;
   int64_t pack_size = 0;       // doubles
   int32_t ntiles = 0;
+  int32_t lds_bytes = 0;       // dynamic LDS of the launch (largest staged group)
   double flops = 0;
   int64_t x_extent = 0, c_extent = 0, s_extent = 0;
   // algorithmic HBM bytes: every input element read once, every output
