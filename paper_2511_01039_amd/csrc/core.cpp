@@ -108,6 +108,8 @@ Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
     return fail(FPEPS_ERR_UNSUPPORTED, "plan too large");
   // row-thread plans, concatenated with rebased ranges
   std::vector<RtGroup> rg;
+  std::vector<int32_t> rtg;
+  std::vector<size_t> rtg0;
   std::vector<RtOut> ro;
   std::vector<RtKblk> rb;
   std::vector<RtCol> rc;
@@ -123,6 +125,8 @@ Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
     R4 b{rg.size(), ro.size(), rb.size(), rc.size(), rp.size(), rk.size()};
     rr.push_back(b);
     pack_off.push_back(pack_total);
+    rtg0.push_back(rtg.size());
+    for (int32_t t : r.tile_group) rtg.push_back(t + (int32_t)b.g);
     for (auto g : r.groups) {
       g.o0 += (int32_t)b.o;
       g.o1 += (int32_t)b.o;
@@ -162,6 +166,8 @@ Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
   FP_TRY(ctx->upload(tag + "_red", reds.data(), reds.size() * sizeof(ReduceTab), &dr));
   void *dg = nullptr, *dO = nullptr, *dP = nullptr, *dK = nullptr, *dpk = nullptr, *dB = nullptr;
   FP_TRY(ctx->upload(tag + "_rtg", rg.data(), rg.size() * sizeof(RtGroup), &dg));
+  void* dTG = nullptr;
+  FP_TRY(ctx->upload(tag + "_rttg", rtg.data(), rtg.size() * sizeof(int32_t), &dTG));
   FP_TRY(ctx->upload(tag + "_rtb", rb.data(), rb.size() * sizeof(RtKblk), &dB));
   void* dC = nullptr;
   FP_TRY(ctx->upload(tag + "_rtc", rc.data(), rc.size() * sizeof(RtCol), &dC));
@@ -174,7 +180,8 @@ Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
   drt.clear();
   for (size_t i = 0; i < rts.size(); ++i) {
     DevRt d;
-    d.groups = (const RtGroup*)dg + rr[i].g;
+    d.groups = (const RtGroup*)dg;
+    d.tile_group = (const int32_t*)dTG + rtg0[i];
     d.outs = (const RtOut*)dO;
     d.kblks = (const RtKblk*)dB;
     d.cols = (const RtCol*)dC;

@@ -26,6 +26,7 @@ hipError_t launch_gemm_f64(const DevGemm& g, const double* A, const double* B, d
 // A row-thread layer-step plan resident on the device.
 struct DevRt {
   const RtGroup* groups = nullptr;
+  const int32_t* tile_group = nullptr;
   const RtOut* outs = nullptr;
   const RtKblk* kblks = nullptr;
   const RtCol* cols = nullptr;

@@ -32,6 +32,8 @@ __device__ __forceinline__ const FP_CONST T* as_const(const T* p) {
 // field-wise copies out of the constant address space
 __device__ __forceinline__ RtGroup ld(const FP_CONST RtGroup* p) {
   RtGroup g;
+#pragma unroll
+  for (int l = 0; l < RT_MAXLEV; ++l) g.mg[l] = p->mg[l];
   g.tile0 = p->tile0;
   g.M = p->M;
 #pragma unroll
@@ -190,18 +192,26 @@ __device__ __forceinline__ void rt_chunks(const double* __restrict__ X,
   }
 }
 
+// Level indices of row m (m < 2^31): division by the level dims through
+// their multiply-high constants (no integer division instructions).
 __device__ __forceinline__ void row_levels(const RtGroup& G, int m, int32_t (&idx)[RT_MAXLEV]) {
+  uint32_t r = (uint32_t)m;
 #pragma unroll
   for (int l = RT_MAXLEV - 1; l >= 0; --l) {
-    const int d = G.md[l];
-    idx[l] = m % d;
-    m /= d;
+    if (G.md[l] == 1) {
+      idx[l] = 0;
+      continue;
+    }
+    const uint32_t q = (uint32_t)__umul64hi((uint64_t)r, G.mg[l]);
+    idx[l] = (int32_t)(r - q * (uint32_t)G.md[l]);
+    r = q;
   }
 }
 
 __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
     const double* __restrict__ X, const double* __restrict__ PK_, double* __restrict__ Y,
-    const RtGroup* __restrict__ groups_, int ngroups, const RtOut* __restrict__ outs_,
+    const RtGroup* __restrict__ groups_, const int32_t* __restrict__ tile_group,
+    const RtOut* __restrict__ outs_,
     const RtKblk* __restrict__ kblks_, const RtCol* __restrict__ cols_,
     const RtPair* __restrict__ pairs_, const int32_t* __restrict__ tab_) {
   extern __shared__ double lds[];
@@ -213,27 +223,24 @@ __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
   const FP_CONST int32_t* tab = as_const(tab_);
   const FP_CONST double* PK = as_const(PK_);
   const int wg = blockIdx.x;
-  int lo = 0, hi = ngroups - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (groups[mid].tile0 <= wg)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const RtGroup G = ld(groups + lo);
+  const RtGroup G = ld(groups + as_const(tile_group)[wg]);
   const int rows = G.rows;                    // 64, 128 or 256
   const int m0 = (wg - G.tile0) * rows;
   const int tid = threadIdx.x;
+  // thread tid stages and computes the same tile row r = tid % rows
+  // (= (wave % (rows/64)) * 64 + lane); rows past the group end repeat row
+  // M-1 (in bounds, never stored)
+  const int lrows = 31 - __builtin_clz(rows);  // rows is a power of two
+  const int r = tid & (rows - 1);
+  const int m = m0 + r;
+  const bool live = m < G.M;
+  int32_t idx[RT_MAXLEV];
+  row_levels(G, live ? m : G.M - 1, idx);
   if (G.staged) {
-    // stage: thread tid takes tile row tid % rows and the staged columns
-    // slot, slot + nslot, ... (slot = tid / rows is uniform per wave), eight
-    // loads in flight per batch; rows past the group end repeat row M-1 (in
-    // bounds, never stored)
-    const int sr = tid % rows, nslot = RT_THREADS / rows;
-    const int slot = __builtin_amdgcn_readfirstlane(tid / rows);
-    int32_t sidx[RT_MAXLEV];
-    row_levels(G, min(m0 + sr, G.M - 1), sidx);
+    // stage the staged columns slot, slot + nslot, ... (slot = tid / rows
+    // is uniform per wave), eight loads in flight per batch
+    const int nslot = RT_THREADS >> lrows;
+    const int slot = __builtin_amdgcn_readfirstlane(tid >> lrows);
     const FP_CONST RtCol* gc = cols + G.c0;
     for (int c0 = slot; c0 < G.ktot; c0 += 8 * nslot) {
       double v[8];
@@ -244,30 +251,25 @@ __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
           const RtCol C = ld(gc + c);
           int32_t xo = 0;
 #pragma unroll
-          for (int l = 0; l < RT_MAXLEV; ++l) xo += sidx[l] * C.xs[l];
+          for (int l = 0; l < RT_MAXLEV; ++l) xo += idx[l] * C.xs[l];
           v[u] = X[C.xbase + xo];
         }
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int c = c0 + u * nslot;
-        if (c < G.ktot) lds[(int64_t)c * rows + sr] = v[u];
+        if (c < G.ktot) lds[c * rows + r] = v[u];
       }
     }
     __syncthreads();
   }
   // compute: wave w owns tile rows (w % (rows/64)) * 64 + lane and the
-  // output chunks o0 + w / (rows/64), stepping by 4 / (rows/64)
-  // the wave index is uniform per wave; say so, so that the chunk loop and
+  // output chunks o0 + w / (rows/64), stepping by 4 / (rows/64); the wave
+  // index is uniform per wave: say so, so that the chunk loop and
   // everything it loads stay scalar
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int rsub = rows >> 6;
-  const int r = (wave % rsub) * 64 + lane;
-  const int m = m0 + r;
-  const bool live = m < G.M;
-  int32_t idx[RT_MAXLEV];
-  row_levels(G, live ? m : G.M - 1, idx);
-  const int o_first = wave / rsub, o_step = 4 / rsub;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lsub = lrows - 6;                  // log2(rows / 64)
+  const int o_first = wave >> lsub, o_step = 4 >> lsub;
   if (G.staged)
     rt_chunks<true>(X, PK, Y, lds, rows, r, G, o_first, o_step, outs, pairs, kblks, tab, idx,
                     live);
@@ -291,7 +293,7 @@ hipError_t launch_rt_f64(const DevRt& r, const double* X, const double* PK, doub
   if (r.ntiles <= 0 || r.ngroups <= 0) return hipSuccess;
   if (r.lds_bytes < 0 || r.lds_bytes > RT_LDS_BYTES) return hipErrorInvalidValue;
   k_rt_f64<<<dim3(r.ntiles), dim3(RT_THREADS), (size_t)r.lds_bytes, s>>>(
-      X, PK, Y, r.groups, r.ngroups, r.outs, r.kblks, r.cols, r.pairs, tab);
+      X, PK, Y, r.groups, r.tile_group, r.outs, r.kblks, r.cols, r.pairs, tab);
   return hipGetLastError();
 }
 

@@ -659,6 +659,8 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
       return false;
     }
     g.M = (int32_t)M;
+    for (int l = 0; l < RT_MAXLEV; ++l)
+      g.mg[l] = g.md[l] > 1 ? UINT64_MAX / (uint64_t)g.md[l] + 1 : 0;
     g.tile0 = (int32_t)tiles;
     g.o0 = (int32_t)rt.outs.size();
     g.k0 = (int32_t)rt.kblks.size();
@@ -838,6 +840,8 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
     if (g.staged) rt.lds_bytes = std::max<int32_t>(rt.lds_bytes, rows * ktot * 8);
     rt.groups.push_back(g);
     tiles += (M + rows - 1) / rows;
+    if (tiles <= INT32_MAX)
+      rt.tile_group.resize((size_t)tiles, (int32_t)rt.groups.size() - 1);
     if (tiles > INT32_MAX) {
       err = "layer step has too many row tiles";
       return false;

@@ -196,6 +196,8 @@ constexpr int RT_THREADS = 256;
 constexpr int RT_LDS_BYTES = 64 * 1024;   // staging budget per workgroup
 
 struct RtGroup {
+  uint64_t mg[RT_MAXLEV];      // floor((2^64 - 1) / md) + 1: n / md = umulhi64(n, mg) for
+                               // n < 2^31 (md = 1 levels are skipped)
   int32_t tile0;               // first workgroup of the group
   int32_t M;                   // rows
   int32_t md[RT_MAXLEV];       // level dims, innermost last (unused levels 1)
@@ -250,6 +252,7 @@ struct RtPlan {
   std::vector<RtCol> cols;
   std::vector<RtPair> pairs;
   std::vector<RtPack> packs;
+  std::vector<int32_t> tile_group;   // group of every workgroup
   int64_t pack_size = 0;       // doubles
   int32_t ntiles = 0;
   int32_t lds_bytes = 0;       // dynamic LDS of the launch (largest staged group)
