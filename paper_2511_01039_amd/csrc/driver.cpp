@@ -683,16 +683,20 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
         nt += op.sect[J].n;
       }
       double xl = 0, pk = 0;
-      for (const RtPlan& r : pl.ps.rts) {
-        xl += r.x_loads;
-        pk += (double)r.pack_size;
+      size_t tabs = 0;
+      for (const auto& sl : pl.slices) {
+        for (const RtPlan& r : sl.ps->rts) {
+          xl += r.x_loads;
+          pk += (double)r.pack_size;
+        }
+        tabs += sl.ps->pool.data.size();
       }
       std::fprintf(stderr,
                    "[fpeps] site %d: sectors %d m %lld n %lld analyse %.3fs rsvd %.3fs (plan %.3fs) "
                    "chain flops/app %.3e slices %zu ws %.2f GB table entries %zu layer loads "
                    "%.3e pack %.3e\n",
                    x, ns, (long long)mt, (long long)nt, tw1 - tw0, wall() - tw1, t_plan, pl.flops_fwd,
-                   pl.slices.size(), (pl.ws1 + pl.ws2) * 8e-9, pl.ps.pool.data.size(), xl, pk);
+                   pl.slices.size(), (pl.ws1 + pl.ws2) * 8e-9, tabs, xl, pk);
     }
     // outputs: environment site (U) and the next remainder (R)
     std::vector<int> sel;

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <map>
+#include <thread>
 
 namespace fp {
 
@@ -326,109 +327,132 @@ Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t bud
   }
   if (!cur.empty()) slices.push_back(cur);
 
+  out.slices.resize(slices.size());
+  for (size_t i = 0; i < slices.size(); ++i) out.slices[i].cols = slices[i];
+  // slices are independent: plan them on host threads
+  std::vector<Status> st(slices.size());
+  {
+    const unsigned hc = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>(slices.size(), std::min(16u, hc));
+    auto work = [&](size_t t) {
+      for (size_t i = t; i < slices.size(); i += nt) st[i] = plan_slice(k, out, out.slices[i], with_bwd);
+    };
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < nt; ++t) th.emplace_back(work, t);
+    if (nt > 0) work(0);
+    for (auto& x : th) x.join();
+  }
+  for (auto& e : st) FP_TRY(e);
+  for (size_t i = 0; i < out.slices.size(); ++i) {
+    Slice& sl = out.slices[i];
+    out.flops_fwd += sl.flops_fwd;
+    out.flops_bwd += sl.flops_bwd;
+    out.ws1 = std::max(out.ws1, sl.size1);
+    out.ws2 = std::max(out.ws2, sl.size2);
+    FP_TRY(sl.ps->upload(ctx, "site" + std::to_string(i)));
+    // layer sub-blocks scaled by the per-pair scalars (the bra shares the
+    // ket's data)
+    for (int s = 0; s < 5; ++s) {
+      if (sl.fwd_rt[s]) {
+        const bool w = s == 2;
+        FP_TRY(sl.ps->pack(ctx, sl.fwd[s], w ? dev.W : dev.A, w ? dev.W_size : dev.A_size));
+      }
+      if (sl.bwd[s] >= 0 && sl.bwd_rt[s]) {
+        const bool w = s == 2;   // bwd order: T5, T4, T3, T2, T1
+        FP_TRY(sl.ps->pack(ctx, sl.bwd[s], w ? dev.W : dev.A, w ? dev.W_size : dev.A_size));
+      }
+    }
+  }
+  ctx->peak_ws = std::max(ctx->peak_ws, (double)(out.ws1 + out.ws2) * sizeof(double));
+  ctx->nslices = std::max(ctx->nslices, (int)out.slices.size());
+  return Status::ok();
+}
+
+Status SiteOp::plan_slice(const std::vector<int32_t>& k, const Plans& pl, Slice& sl,
+                          bool with_bwd) const {
+  sl.ps = std::make_shared<PlanSet>();
+  PlanSet& ps = *sl.ps;
+  const std::vector<SliceCol>& sc = sl.cols;
   std::string err;
   const std::vector<int>* store[5] = {&STORE_X1, &STORE_X2, &STORE_X3, &STORE_X4, &ORDER_X[5]};
   const BT* S[5] = {&T, &ket, &W, &bra, &R};
   const bool mx[5] = {false, true, true, true, false};
   const std::vector<int>* bstore[5] = {&STORE_X4, &STORE_X3, &STORE_X2, &STORE_X1, &ORDER_X[0]};
   const int bstep[5] = {5, 4, 3, 2, 1};
-  for (auto& sc : slices) {
-    Slice sl;
-    sl.cols = sc;
-    BT colL = omega_layout(sc, k, out.col_off, out.col_total, false);
-    BT rowL = omega_layout(sc, k, out.row_off, out.row_total, true);
-    BT X = colL;
+  BT colL = omega_layout(sc, k, pl.col_off, pl.col_total, false);
+  BT rowL = omega_layout(sc, k, pl.row_off, pl.row_total, true);
+  BT X = colL;
+  for (int s = 0; s < 5; ++s) {
+    StepSpec sp;
+    sp.step = s + 1;
+    sp.m_is_x = mx[s];
+    sp.key_side = 0;
+    sp.out_names = *store[s];
+    sp.key_order = ORDER_X[s];
+    StepResult r;
+    const bool layer = s >= 1 && s <= 3;
+    if (layer) {
+      RtPlan rp;
+      if (!plan_step_rt(X, *S[s], sp, sym, ps.pool, r, rp, err))
+        return fail(FPEPS_ERR_SHAPE, "chain step " + std::to_string(s + 1) + ": " + err);
+      sl.flops_fwd += rp.flops;
+      sl.fwd[s] = ps.add_rt(std::move(rp));
+    } else {
+      if (!plan_step(X, *S[s], sp, sym, ps.pool, s == 4 ? &rowL : nullptr, r, err))
+        return fail(FPEPS_ERR_SHAPE, "chain step " + std::to_string(s + 1) + ": " + err);
+      sl.flops_fwd += r.plan.flops;
+      sl.fwd[s] = ps.add(std::move(r.plan));
+    }
+    sl.fwd_rt[s] = layer;
+    if (s < 4) {
+      if (s % 2 == 0)
+        sl.size1 = std::max(sl.size1, r.out.size);
+      else
+        sl.size2 = std::max(sl.size2, r.out.size);
+    }
+    X = std::move(r.out);
+  }
+  if (with_bwd) {
+    BT Z = rowL;
     for (int s = 0; s < 5; ++s) {
       StepSpec sp;
-      sp.step = s + 1;
-      sp.m_is_x = mx[s];
-      sp.key_side = 0;
-      sp.out_names = *store[s];
-      sp.key_order = ORDER_X[s];
+      sp.step = bstep[s];
+      sp.m_is_x = mx[bstep[s] - 1];
+      sp.key_side = 1;
+      sp.out_names = *bstore[s];
+      sp.key_order = ORDER_X[bstep[s] - 1];
+      // M^T is the transpose of M on M's domain: the column tuples of each
+      // sector (synthetic SU(2) scalars can reach others, which are dropped)
+      sp.restrict_to_fixed = true;
       StepResult r;
       const bool layer = s >= 1 && s <= 3;
       if (layer) {
         RtPlan rp;
-        if (!plan_step_rt(X, *S[s], sp, sym, out.ps.pool, r, rp, err))
-          return fail(FPEPS_ERR_SHAPE, "chain step " + std::to_string(s + 1) + ": " + err);
-        out.flops_fwd += rp.flops;
-        sl.fwd[s] = out.ps.add_rt(std::move(rp));
+        if (!plan_step_rt(Z, *S[bstep[s] - 1], sp, sym, ps.pool, r, rp, err))
+          return fail(FPEPS_ERR_SHAPE,
+                      "transposed chain step " + std::to_string(bstep[s]) + ": " + err);
+        sl.flops_bwd += rp.flops;
+        sl.bwd[s] = ps.add_rt(std::move(rp));
       } else {
-        if (!plan_step(X, *S[s], sp, sym, out.ps.pool, s == 4 ? &rowL : nullptr, r, err))
-          return fail(FPEPS_ERR_SHAPE, "chain step " + std::to_string(s + 1) + ": " + err);
-        out.flops_fwd += r.plan.flops;
-        sl.fwd[s] = out.ps.add(std::move(r.plan));
+        if (!plan_step(Z, *S[bstep[s] - 1], sp, sym, ps.pool, s == 4 ? &colL : nullptr, r,
+                       err))
+          return fail(FPEPS_ERR_SHAPE,
+                      "transposed chain step " + std::to_string(bstep[s]) + ": " + err);
+        sl.flops_bwd += r.plan.flops;
+        sl.bwd[s] = ps.add(std::move(r.plan));
       }
-      sl.fwd_rt[s] = layer;
+      sl.bwd_rt[s] = layer;
       if (s < 4) {
         if (s % 2 == 0)
-          sl.size1 = std::max(sl.size1, r.out.size);
-        else
           sl.size2 = std::max(sl.size2, r.out.size);
+        else
+          sl.size1 = std::max(sl.size1, r.out.size);
       }
-      X = std::move(r.out);
+      Z = std::move(r.out);
     }
-    if (with_bwd) {
-      BT Z = rowL;
-      for (int s = 0; s < 5; ++s) {
-        StepSpec sp;
-        sp.step = bstep[s];
-        sp.m_is_x = mx[bstep[s] - 1];
-        sp.key_side = 1;
-        sp.out_names = *bstore[s];
-        sp.key_order = ORDER_X[bstep[s] - 1];
-        // M^T is the transpose of M on M's domain: the column tuples of each
-        // sector (synthetic SU(2) scalars can reach others, which are dropped)
-        sp.restrict_to_fixed = true;
-        StepResult r;
-        const bool layer = s >= 1 && s <= 3;
-        if (layer) {
-          RtPlan rp;
-          if (!plan_step_rt(Z, *S[bstep[s] - 1], sp, sym, out.ps.pool, r, rp, err))
-            return fail(FPEPS_ERR_SHAPE,
-                        "transposed chain step " + std::to_string(bstep[s]) + ": " + err);
-          out.flops_bwd += rp.flops;
-          sl.bwd[s] = out.ps.add_rt(std::move(rp));
-        } else {
-          if (!plan_step(Z, *S[bstep[s] - 1], sp, sym, out.ps.pool, s == 4 ? &colL : nullptr, r,
-                         err))
-            return fail(FPEPS_ERR_SHAPE,
-                        "transposed chain step " + std::to_string(bstep[s]) + ": " + err);
-          out.flops_bwd += r.plan.flops;
-          sl.bwd[s] = out.ps.add(std::move(r.plan));
-        }
-        sl.bwd_rt[s] = layer;
-        if (s < 4) {
-          if (s % 2 == 0)
-            sl.size2 = std::max(sl.size2, r.out.size);
-          else
-            sl.size1 = std::max(sl.size1, r.out.size);
-        }
-        Z = std::move(r.out);
-      }
-    } else {
-      for (int s = 0; s < 5; ++s) sl.bwd[s] = -1;
-    }
-    out.ws1 = std::max(out.ws1, sl.size1);
-    out.ws2 = std::max(out.ws2, sl.size2);
-    out.slices.push_back(sl);
+  } else {
+    for (int s = 0; s < 5; ++s) sl.bwd[s] = -1;
   }
-  FP_TRY(out.ps.upload(ctx, "site"));
-  // layer sub-blocks scaled by the per-pair scalars (the bra shares the
-  // ket's data)
-  for (const Slice& sl : out.slices)
-    for (int s = 0; s < 5; ++s) {
-      if (sl.fwd_rt[s]) {
-        const bool w = s == 2;
-        FP_TRY(out.ps.pack(ctx, sl.fwd[s], w ? dev.W : dev.A, w ? dev.W_size : dev.A_size));
-      }
-      if (sl.bwd[s] >= 0 && sl.bwd_rt[s]) {
-        const bool w = bstep[s] == 3;
-        FP_TRY(out.ps.pack(ctx, sl.bwd[s], w ? dev.W : dev.A, w ? dev.W_size : dev.A_size));
-      }
-    }
-  ctx->peak_ws = std::max(ctx->peak_ws, (double)(out.ws1 + out.ws2) * sizeof(double));
-  ctx->nslices = std::max(ctx->nslices, (int)out.slices.size());
   return Status::ok();
 }
 
@@ -439,18 +463,18 @@ Status SiteOp::apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const do
   const int64_t s1 = std::max<int64_t>(pl.ws1, 1), s2 = std::max<int64_t>(pl.ws2, 1);
   for (const Slice& sl : pl.slices) {
     if (!transpose) {
-      FP_TRY(run_gemm(ctx, pl.ps, sl.fwd[0], dev.T, dev.T_size, x, pl.col_total, b1, s1, true, 1));
-      FP_TRY(run_rt(ctx, pl.ps, sl.fwd[1], b1, s1, b2, s2, true, 2));
-      FP_TRY(run_rt(ctx, pl.ps, sl.fwd[2], b2, s2, b1, s1, true, 3));
-      FP_TRY(run_rt(ctx, pl.ps, sl.fwd[3], b1, s1, b2, s2, true, 4));
-      FP_TRY(run_gemm(ctx, pl.ps, sl.fwd[4], dev.R, dev.R_size, b2, s2, y, pl.row_total, true, 5));
+      FP_TRY(run_gemm(ctx, *sl.ps, sl.fwd[0], dev.T, dev.T_size, x, pl.col_total, b1, s1, true, 1));
+      FP_TRY(run_rt(ctx, *sl.ps, sl.fwd[1], b1, s1, b2, s2, true, 2));
+      FP_TRY(run_rt(ctx, *sl.ps, sl.fwd[2], b2, s2, b1, s1, true, 3));
+      FP_TRY(run_rt(ctx, *sl.ps, sl.fwd[3], b1, s1, b2, s2, true, 4));
+      FP_TRY(run_gemm(ctx, *sl.ps, sl.fwd[4], dev.R, dev.R_size, b2, s2, y, pl.row_total, true, 5));
     } else {
       if (sl.bwd[0] < 0) return fail(FPEPS_ERR_ARG, "transposed chain was not planned");
-      FP_TRY(run_gemm(ctx, pl.ps, sl.bwd[0], dev.R, dev.R_size, x, pl.row_total, b2, s2, true, 15));
-      FP_TRY(run_rt(ctx, pl.ps, sl.bwd[1], b2, s2, b1, s1, true, 14));
-      FP_TRY(run_rt(ctx, pl.ps, sl.bwd[2], b1, s1, b2, s2, true, 13));
-      FP_TRY(run_rt(ctx, pl.ps, sl.bwd[3], b2, s2, b1, s1, true, 12));
-      FP_TRY(run_gemm(ctx, pl.ps, sl.bwd[4], dev.T, dev.T_size, b1, s1, y, pl.col_total, true, 11));
+      FP_TRY(run_gemm(ctx, *sl.ps, sl.bwd[0], dev.R, dev.R_size, x, pl.row_total, b2, s2, true, 15));
+      FP_TRY(run_rt(ctx, *sl.ps, sl.bwd[1], b2, s2, b1, s1, true, 14));
+      FP_TRY(run_rt(ctx, *sl.ps, sl.bwd[2], b1, s1, b2, s2, true, 13));
+      FP_TRY(run_rt(ctx, *sl.ps, sl.bwd[3], b2, s2, b1, s1, true, 12));
+      FP_TRY(run_gemm(ctx, *sl.ps, sl.bwd[4], dev.T, dev.T_size, b1, s1, y, pl.col_total, true, 11));
     }
   }
   return Status::ok();

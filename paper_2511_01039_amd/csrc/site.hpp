@@ -4,6 +4,7 @@
 #pragma once
 
 #include <array>
+#include <memory>
 #include <vector>
 
 #include "core.hpp"
@@ -53,6 +54,8 @@ class SiteOp {
   // Plans of M (fwd) and M^T (bwd) for per-sector widths k, sliced so that
   // the chain intermediates of one slice fit ``budget`` bytes.
   struct Slice {
+    std::shared_ptr<PlanSet> ps;   // this slice's plans (planned independently)
+    double flops_fwd = 0, flops_bwd = 0;
     std::vector<SliceCol> cols;
     int fwd[5], bwd[5];       // plan indices in the PlanSet (GEMM or row-thread list)
     bool fwd_rt[5] = {false, false, false, false, false};
@@ -60,7 +63,6 @@ class SiteOp {
     int64_t size1 = 0, size2 = 0;  // ping-pong intermediate buffer sizes (elements)
   };
   struct Plans {
-    PlanSet ps;
     std::vector<Slice> slices;
     std::vector<int64_t> col_off, row_off;   // per sector offsets for width k
     int64_t col_total = 0, row_total = 0;
@@ -76,6 +78,8 @@ class SiteOp {
  private:
   BT omega_layout(const std::vector<SliceCol>& cols, const std::vector<int32_t>& k,
                   const std::vector<int64_t>& off, int64_t total, bool rows) const;
+  // forward and transposed chain plans of one slice (host only, thread safe)
+  Status plan_slice(const std::vector<int32_t>& k, const Plans& pl, Slice& sl, bool with_bwd) const;
 };
 
 // Convert an fpeps_tensor into a planner BT with the given leg names.
