@@ -49,26 +49,38 @@ __device__ __forceinline__ void load_tile(const double* __restrict__ A,
   const int32_t* tbn = tab + pr.tbn;
   r.akf = pr.flags & 1;
   r.bnf = pr.flags & 2;
+  // branch-free: indices are clamped into the block (always a valid
+  // address), every table and data load of the tile is issued before any is
+  // used, and out-of-range elements are zeroed afterwards
+  constexpr int NA = (MT * KT) / 256, NB = (NT * KT) / 256;
+  int32_t oa[NA], ob[NB];
+  bool va[NA], vb[NB];
 #pragma unroll
-  for (int i = 0; i < (MT * KT) / 256; ++i) {
+  for (int i = 0; i < NA; ++i) {
     const int e = tid + i * 256;
     const int mm = r.akf ? e / KT : e % MT;
     const int kk = r.akf ? e % KT : e / MT;
     const int m = job.m0 + mm, k = t.kb + kk;
-    double v = 0.0;
-    if (m < job.M && k < kend) v = Ab[(int64_t)tam[m] + tak[k]] * pr.alpha;
-    r.a[i] = v;
+    va[i] = m < job.M && k < kend;
+    oa[i] = tam[min(m, job.M - 1)] + tak[min(k, kend - 1)];
   }
 #pragma unroll
-  for (int i = 0; i < (NT * KT) / 256; ++i) {
+  for (int i = 0; i < NB; ++i) {
     const int e = tid + i * 256;
     const int nn = r.bnf ? e % NT : e / KT;
     const int kk = r.bnf ? e / NT : e % KT;
     const int n = job.n0 + nn, k = t.kb + kk;
-    double v = 0.0;
-    if (n < job.N && k < kend) v = Bb[(int64_t)tbk[k] + tbn[n]];
-    r.b[i] = v;
+    vb[i] = n < job.N && k < kend;
+    ob[i] = tbk[min(k, kend - 1)] + tbn[min(n, job.N - 1)];
   }
+#pragma unroll
+  for (int i = 0; i < NA; ++i) r.a[i] = Ab[oa[i]];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) r.b[i] = Bb[ob[i]];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) r.a[i] = va[i] ? r.a[i] * pr.alpha : 0.0;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) r.b[i] = vb[i] ? r.b[i] : 0.0;
 }
 
 template <int MT, int NT, int KT>
@@ -108,7 +120,7 @@ __device__ __forceinline__ bool next_tile(const GemmPair* __restrict__ pairs, co
 // prefetched into registers while the previous tile is multiplied out of
 // LDS (double-buffered, one barrier per tile).
 template <int MT, int NT, int WM, int WN>
-__global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ A,
+__global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ A,
                                                   const double* __restrict__ B,
                                                   double* __restrict__ C,
                                                   const GemmJob* __restrict__ jobs,
@@ -176,8 +188,24 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ A,
     }
   }
 
+  // epilogue: the thread's FM*4 row offsets and FN column offsets are
+  // loaded once (clamped, branch-free); the stores are predicated
   const int32_t* tcm = tab + job.tcm;
   const int32_t* tcn = tab + job.tcn;
+  int32_t om[FM][4], on[FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = job.m0 + wm * WTM + i * 16 + 4 * r + lk;
+      om[i][r] = tcm[min(m, job.M - 1)];
+    }
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int n = job.n0 + wn * WTN + j * 16 + lrow;
+    on[j] = tcn[min(n, job.N - 1)];
+  }
+  double* Cb = C + job.c_off;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -186,7 +214,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const double* __restrict__ A,
       for (int r = 0; r < 4; ++r) {
         const int m = job.m0 + wm * WTM + i * 16 + 4 * r + lk;
         const int n = job.n0 + wn * WTN + j * 16 + lrow;
-        if (m < job.M && n < job.N) C[job.c_off + (int64_t)tcm[m] + tcn[n]] = acc[i][j][r];
+        if (m < job.M && n < job.N) Cb[(int64_t)om[i][r] + on[j]] = acc[i][j][r];
       }
 }
 
