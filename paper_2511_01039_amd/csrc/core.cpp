@@ -187,6 +187,12 @@ Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
     d.cols = (const RtCol*)dC;
     d.pairs = (const RtPair*)dP;
     d.lds_bytes = rts[i].lds_bytes;
+    d.nlaunch = rts[i].nlaunch;
+    for (int c = 0; c < RT_NCLASS; ++c) {
+      d.l_tile0[c] = rts[i].l_tile0[c];
+      d.l_ntiles[c] = rts[i].l_ntiles[c];
+      d.l_lds[c] = rts[i].l_lds[c];
+    }
     d.packs = (const RtPack*)dK + rr[i].k;
     d.ngroups = (int)rts[i].groups.size();
     d.ntiles = rts[i].ntiles;

@@ -34,6 +34,8 @@ struct DevRt {
   const RtPack* packs = nullptr;
   int ngroups = 0, ntiles = 0, npacks = 0;
   int lds_bytes = 0;
+  int nlaunch = 0;                     // one launch per LDS class
+  int l_tile0[RT_NCLASS] = {0}, l_ntiles[RT_NCLASS] = {0}, l_lds[RT_NCLASS] = {0};
 };
 // Y[rows of every group] = X rows times the packed layer sub-blocks PK.
 hipError_t launch_rt_f64(const DevRt& r, const double* X, const double* PK, double* Y,

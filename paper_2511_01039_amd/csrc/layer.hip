@@ -88,9 +88,12 @@ __device__ __forceinline__ RtPair ld(const FP_CONST RtPair* p) {
 }
 
 // Accumulate one output chunk (NC columns) of row r of the tile and store it.
-// Staged groups read X from LDS (column-major: staged column c of tile row r
-// at lds[c * rows + r]); unstaged ones read it from X through the X block's
-// level strides and contracted-offset table.
+// Staged groups read X from LDS: the tile's rows are split into 64-row
+// sub-blocks, and staged column c of row r is at
+// lds[((r / 64) * ktot + c) * 64 + r % 64], so a wave reads 64 consecutive
+// doubles per column and successive columns sit at fixed byte offsets
+// (immediate offsets of ds_read). Unstaged groups read X from global memory
+// through the X block's level strides and contracted-offset table.
 template <int NC, bool STAGED>
 __device__ __forceinline__ void rt_chunk(const double* __restrict__ X,
                                          const FP_CONST double* PK, double* __restrict__ Y,
@@ -107,11 +110,11 @@ __device__ __forceinline__ void rt_chunk(const double* __restrict__ X,
     const FP_CONST double* bp = PK + P.pk;
     const int Kb = P.Kb;
     if (STAGED) {
-      const double* lp = lds + (int64_t)P.koff * rows + r;
+      const double* lp = lds + P.koff * 64;
       int k = 0;
       for (; k + 4 <= Kb; k += 4) {
-        const double a0 = lp[(k + 0) * rows], a1 = lp[(k + 1) * rows];
-        const double a2 = lp[(k + 2) * rows], a3 = lp[(k + 3) * rows];
+        const double a0 = lp[(k + 0) * 64], a1 = lp[(k + 1) * 64];
+        const double a2 = lp[(k + 2) * 64], a3 = lp[(k + 3) * 64];
         const FP_CONST double* b = bp + k * NC;
 #pragma unroll
         for (int n = 0; n < NC; ++n) {
@@ -122,7 +125,7 @@ __device__ __forceinline__ void rt_chunk(const double* __restrict__ X,
         }
       }
       for (; k < Kb; ++k) {
-        const double a = lp[k * rows];
+        const double a = lp[k * 64];
         const FP_CONST double* b = bp + k * NC;
 #pragma unroll
         for (int n = 0; n < NC; ++n) acc[n] = fma(a, b[n], acc[n]);
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
     const RtGroup* __restrict__ groups_, const int32_t* __restrict__ tile_group,
     const RtOut* __restrict__ outs_,
     const RtKblk* __restrict__ kblks_, const RtCol* __restrict__ cols_,
-    const RtPair* __restrict__ pairs_, const int32_t* __restrict__ tab_) {
+    const RtPair* __restrict__ pairs_, const int32_t* __restrict__ tab_, int tile_base) {
   extern __shared__ double lds[];
   const FP_CONST RtGroup* groups = as_const(groups_);
   const FP_CONST RtOut* outs = as_const(outs_);
@@ -222,7 +225,7 @@ __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
   const FP_CONST RtPair* pairs = as_const(pairs_);
   const FP_CONST int32_t* tab = as_const(tab_);
   const FP_CONST double* PK = as_const(PK_);
-  const int wg = blockIdx.x;
+  const int wg = tile_base + (int)blockIdx.x;
   const RtGroup G = ld(groups + as_const(tile_group)[wg]);
   const int rows = G.rows;                    // 64, 128 or 256
   const int m0 = (wg - G.tile0) * rows;
@@ -242,23 +245,25 @@ __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
     const int nslot = RT_THREADS >> lrows;
     const int slot = __builtin_amdgcn_readfirstlane(tid >> lrows);
     const FP_CONST RtCol* gc = cols + G.c0;
+    double* lst = lds + (r >> 6) * G.ktot * 64 + (r & 63);
     for (int c0 = slot; c0 < G.ktot; c0 += 8 * nslot) {
+      // descriptors of the batch first (clamped: always valid), then the
+      // eight loads, then the LDS writes
+      RtCol C[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) C[u] = ld(gc + min(c0 + u * nslot, G.ktot - 1));
       double v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int c = c0 + u * nslot;
-        if (c < G.ktot) {
-          const RtCol C = ld(gc + c);
-          int32_t xo = 0;
+        int32_t xo = 0;
 #pragma unroll
-          for (int l = 0; l < RT_MAXLEV; ++l) xo += idx[l] * C.xs[l];
-          v[u] = X[C.xbase + xo];
-        }
+        for (int l = 0; l < RT_MAXLEV; ++l) xo += idx[l] * C[u].xs[l];
+        v[u] = X[C[u].xbase + xo];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int c = c0 + u * nslot;
-        if (c < G.ktot) lds[c * rows + r] = v[u];
+        if (c < G.ktot) lst[c * 64] = v[u];
       }
     }
     __syncthreads();
@@ -270,11 +275,13 @@ __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lsub = lrows - 6;                  // log2(rows / 64)
   const int o_first = wave >> lsub, o_step = 4 >> lsub;
+  // this lane's row inside the staged tile: sub-block r / 64, lane r % 64
+  const double* lrow = lds + (r >> 6) * G.ktot * 64 + (r & 63);
   if (G.staged)
-    rt_chunks<true>(X, PK, Y, lds, rows, r, G, o_first, o_step, outs, pairs, kblks, tab, idx,
+    rt_chunks<true>(X, PK, Y, lrow, rows, r, G, o_first, o_step, outs, pairs, kblks, tab, idx,
                     live);
   else
-    rt_chunks<false>(X, PK, Y, lds, rows, r, G, o_first, o_step, outs, pairs, kblks, tab, idx,
+    rt_chunks<false>(X, PK, Y, lrow, rows, r, G, o_first, o_step, outs, pairs, kblks, tab, idx,
                      live);
 }
 
@@ -291,9 +298,11 @@ __global__ void k_rt_pack(const RtPack* __restrict__ packs, const double* __rest
 hipError_t launch_rt_f64(const DevRt& r, const double* X, const double* PK, double* Y,
                          const int32_t* tab, hipStream_t s) {
   if (r.ntiles <= 0 || r.ngroups <= 0) return hipSuccess;
-  if (r.lds_bytes < 0 || r.lds_bytes > RT_LDS_BYTES) return hipErrorInvalidValue;
-  k_rt_f64<<<dim3(r.ntiles), dim3(RT_THREADS), (size_t)r.lds_bytes, s>>>(
-      X, PK, Y, r.groups, r.tile_group, r.outs, r.kblks, r.cols, r.pairs, tab);
+  for (int c = 0; c < r.nlaunch; ++c) {
+    if (r.l_lds[c] < 0 || r.l_lds[c] > RT_LDS_BYTES || r.l_ntiles[c] <= 0) return hipErrorInvalidValue;
+    k_rt_f64<<<dim3(r.l_ntiles[c]), dim3(RT_THREADS), (size_t)r.l_lds[c], s>>>(
+        X, PK, Y, r.groups, r.tile_group, r.outs, r.kblks, r.cols, r.pairs, tab, r.l_tile0[c]);
+  }
   return hipGetLastError();
 }
 

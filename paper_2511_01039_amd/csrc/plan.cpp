@@ -840,10 +840,49 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
     if (g.staged) rt.lds_bytes = std::max<int32_t>(rt.lds_bytes, rows * ktot * 8);
     rt.groups.push_back(g);
     tiles += (M + rows - 1) / rows;
-    if (tiles <= INT32_MAX)
-      rt.tile_group.resize((size_t)tiles, (int32_t)rt.groups.size() - 1);
     if (tiles > INT32_MAX) {
       err = "layer step has too many row tiles";
+      return false;
+    }
+  }
+  // order the groups by LDS class and renumber their tiles; every class is
+  // one launch
+  {
+    auto cls = [](const RtGroup& g) {
+      if (!g.staged) return 0;
+      const int64_t b = (int64_t)g.rows * g.ktot * 8;
+      return b <= 16 * 1024 ? 1 : (b <= 32 * 1024 ? 2 : 3);
+    };
+    std::vector<RtGroup> sorted;
+    sorted.reserve(rt.groups.size());
+    for (int c = 0; c < RT_NCLASS; ++c)
+      for (const RtGroup& g : rt.groups)
+        if (cls(g) == c) sorted.push_back(g);
+    rt.groups.swap(sorted);
+    rt.tile_group.clear();
+    int64_t t = 0;
+    rt.nlaunch = 0;
+    for (int c = 0; c < RT_NCLASS; ++c) {
+      const int64_t t0 = t;
+      int32_t lds = 0;
+      for (size_t gi = 0; gi < rt.groups.size(); ++gi) {
+        RtGroup& g = rt.groups[gi];
+        if (cls(g) != c) continue;
+        g.tile0 = (int32_t)t;
+        const int64_t nt = ((int64_t)g.M + g.rows - 1) / g.rows;
+        rt.tile_group.insert(rt.tile_group.end(), (size_t)nt, (int32_t)gi);
+        t += nt;
+        if (g.staged) lds = std::max<int32_t>(lds, g.rows * g.ktot * 8);
+      }
+      if (t > t0) {
+        rt.l_tile0[rt.nlaunch] = (int32_t)t0;
+        rt.l_ntiles[rt.nlaunch] = (int32_t)(t - t0);
+        rt.l_lds[rt.nlaunch] = lds;
+        ++rt.nlaunch;
+      }
+    }
+    if (t != tiles) {
+      err = "layer step tile count mismatch";
       return false;
     }
   }

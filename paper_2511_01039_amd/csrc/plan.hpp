@@ -194,6 +194,7 @@ constexpr int RT_MAXLEV = 4;
 constexpr int RT_NC = 16;
 constexpr int RT_THREADS = 256;
 constexpr int RT_LDS_BYTES = 64 * 1024;   // staging budget per workgroup
+constexpr int RT_NCLASS = 4;              // LDS classes: 0 (unstaged), <=16K, <=32K, <=64K
 
 struct RtGroup {
   uint64_t mg[RT_MAXLEV];      // floor((2^64 - 1) / md) + 1: n / md = umulhi64(n, mg) for
@@ -255,7 +256,12 @@ struct RtPlan {
   std::vector<int32_t> tile_group;   // group of every workgroup
   int64_t pack_size = 0;       // doubles
   int32_t ntiles = 0;
-  int32_t lds_bytes = 0;       // dynamic LDS of the launch (largest staged group)
+  int32_t lds_bytes = 0;       // largest staged group
+  // groups are ordered by LDS class so that each class is one launch with
+  // its own dynamic LDS size (a launch reserves its largest group's LDS for
+  // every workgroup, which would cap the occupancy of small groups)
+  int32_t nlaunch = 0;
+  int32_t l_tile0[RT_NCLASS] = {0}, l_ntiles[RT_NCLASS] = {0}, l_lds[RT_NCLASS] = {0};
   double flops = 0;
   int64_t x_extent = 0, c_extent = 0, s_extent = 0;
   // algorithmic HBM bytes: every input element read once, every output
