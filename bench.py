@@ -47,6 +47,31 @@ def workload(cfg):
     return row, desc, bond
 
 
+def profiled_traffic(kernel, precision="fp64"):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, calibrated against a plain
+    copy), or None when there is none or the kernel source has changed since
+    the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_config4_{precision}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    src = fields.get("kernel_source")
+    if not src or "traffic_bytes_per_launch" not in fields:
+        return None
+    src_path = os.path.join(ROOT, src)
+    if not os.path.exists(src_path):
+        return None
+    if hashlib.sha256(open(src_path, "rb").read()).hexdigest() != fields.get("kernel_source_sha256"):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(row, budget_s=20.0):
     """The FP64 oracle on a bounded sample of the same workload: the chain
     product M_x X at the first interior site (x = 1, remainder from the
@@ -163,7 +188,7 @@ def main():
     if lay_s >= gem_s:
         nl = max(cls["layer_launches"], 1)
         roof = {"bound": "hbm", "achieved": layer_gbs, "peak": HBM_PEAK, "unit": "GB/s",
-                "frac": layer_gbs / HBM_PEAK, "traffic": None,
+                "frac": layer_gbs / HBM_PEAK, "traffic": profiled_traffic("k_rt_f64", a.precision),
                 "kernel": "k_rt_f64 (ket/PEPO/bra layer steps and transposes)",
                 "launches_per_step": cls["layer_launches"] / a.steps,
                 "avg_launch_ms": 1e3 * lay_s / nl,
@@ -171,7 +196,7 @@ def main():
     else:
         ng = max(cls["gemm_launches"], 1)
         roof = {"bound": "mfma", "achieved": gemm_tfs, "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                "frac": gemm_tfs / PEAK["fp64"], "traffic": None,
+                "frac": gemm_tfs / PEAK["fp64"], "traffic": profiled_traffic("k_gemm_f64", a.precision),
                 "kernel": "k_gemm_f64 (environment/remainder contractions)",
                 "launches_per_step": cls["gemm_launches"] / a.steps,
                 "avg_launch_ms": 1e3 * gem_s / ng,

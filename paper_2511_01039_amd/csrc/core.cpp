@@ -234,18 +234,21 @@ Status run_rt(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* X, int
                                      ", y " + std::to_string(p.c_extent) + "/" +
                                      std::to_string(y_size) + ")");
   if (!X || !Y) return fail(FPEPS_ERR_ARG, "null operand buffer");
-  if (timed && ctx->time_kernels) {
-    hipEvent_t a, b;
-    FP_TRY(ctx->timed_events(&a, &b));
-    ctx->evflops.push_back(p.flops);
-    ctx->evlabel.push_back(label);
-    ctx->evbytes.push_back(p.bytes);
-    FP_HIP(hipEventRecord(a, ctx->stream));
-    FP_HIP(launch_rt_f64(ps.drt[idx], X, ps.dpack, Y, ps.dtab, ctx->stream));
-    FP_HIP(hipEventRecord(b, ctx->stream));
-    return Status::ok();
+  const DevRt& d = ps.drt[idx];
+  for (int c = 0; c < d.nlaunch; ++c) {
+    if (timed && ctx->time_kernels) {
+      hipEvent_t a, b;
+      FP_TRY(ctx->timed_events(&a, &b));
+      ctx->evflops.push_back(p.l_flops[c]);
+      ctx->evlabel.push_back(label);
+      ctx->evbytes.push_back(p.l_bytes[c]);
+      FP_HIP(hipEventRecord(a, ctx->stream));
+      FP_HIP(launch_rt_f64(d, c, X, ps.dpack, Y, ps.dtab, ctx->stream));
+      FP_HIP(hipEventRecord(b, ctx->stream));
+    } else {
+      FP_HIP(launch_rt_f64(d, c, X, ps.dpack, Y, ps.dtab, ctx->stream));
+    }
   }
-  FP_HIP(launch_rt_f64(ps.drt[idx], X, ps.dpack, Y, ps.dtab, ctx->stream));
   return Status::ok();
 }
 

@@ -37,8 +37,9 @@ struct DevRt {
   int nlaunch = 0;                     // one launch per LDS class
   int l_tile0[RT_NCLASS] = {0}, l_ntiles[RT_NCLASS] = {0}, l_lds[RT_NCLASS] = {0};
 };
-// Y[rows of every group] = X rows times the packed layer sub-blocks PK.
-hipError_t launch_rt_f64(const DevRt& r, const double* X, const double* PK, double* Y,
+// Y[rows of the groups of LDS class launch c] = X rows times the packed
+// layer sub-blocks PK (one launch of the plan's nlaunch).
+hipError_t launch_rt_f64(const DevRt& r, int c, const double* X, const double* PK, double* Y,
                          const int32_t* tab, hipStream_t s);
 // PK[dst + k nc + c] = alpha S[sbase + sk[k] + sn[c]] for every pack entry.
 hipError_t launch_rt_pack(const DevRt& r, const double* S, const int32_t* tab, double* PK,

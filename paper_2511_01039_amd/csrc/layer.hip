@@ -295,14 +295,12 @@ __global__ void k_rt_pack(const RtPack* __restrict__ packs, const double* __rest
   }
 }
 
-hipError_t launch_rt_f64(const DevRt& r, const double* X, const double* PK, double* Y,
+hipError_t launch_rt_f64(const DevRt& r, int c, const double* X, const double* PK, double* Y,
                          const int32_t* tab, hipStream_t s) {
-  if (r.ntiles <= 0 || r.ngroups <= 0) return hipSuccess;
-  for (int c = 0; c < r.nlaunch; ++c) {
-    if (r.l_lds[c] < 0 || r.l_lds[c] > RT_LDS_BYTES || r.l_ntiles[c] <= 0) return hipErrorInvalidValue;
-    k_rt_f64<<<dim3(r.l_ntiles[c]), dim3(RT_THREADS), (size_t)r.l_lds[c], s>>>(
-        X, PK, Y, r.groups, r.tile_group, r.outs, r.kblks, r.cols, r.pairs, tab, r.l_tile0[c]);
-  }
+  if (c < 0 || c >= r.nlaunch || r.ngroups <= 0) return hipErrorInvalidValue;
+  if (r.l_lds[c] < 0 || r.l_lds[c] > RT_LDS_BYTES || r.l_ntiles[c] <= 0) return hipErrorInvalidValue;
+  k_rt_f64<<<dim3(r.l_ntiles[c]), dim3(RT_THREADS), (size_t)r.l_lds[c], s>>>(
+      X, PK, Y, r.groups, r.tile_group, r.outs, r.kblks, r.cols, r.pairs, tab, r.l_tile0[c]);
   return hipGetLastError();
 }
 

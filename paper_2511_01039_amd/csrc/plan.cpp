@@ -865,9 +865,18 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
     for (int c = 0; c < RT_NCLASS; ++c) {
       const int64_t t0 = t;
       int32_t lds = 0;
+      double lf = 0, lb = 0;
       for (size_t gi = 0; gi < rt.groups.size(); ++gi) {
         RtGroup& g = rt.groups[gi];
         if (cls(g) != c) continue;
+        // algorithmic work of the group: its rows of every X block read
+        // once, its output chunks written once, 2 M Kb nc per pair
+        for (int b = g.k0; b < g.k1; ++b) lb += 8.0 * g.M * rt.kblks[b].Kb;
+        for (int o = g.o0; o < g.o1; ++o) {
+          lb += 8.0 * g.M * rt.outs[o].nc;
+          for (int p = rt.outs[o].p0; p < rt.outs[o].p1; ++p)
+            lf += 2.0 * g.M * rt.pairs[p].Kb * rt.outs[o].nc;
+        }
         g.tile0 = (int32_t)t;
         const int64_t nt = ((int64_t)g.M + g.rows - 1) / g.rows;
         rt.tile_group.insert(rt.tile_group.end(), (size_t)nt, (int32_t)gi);
@@ -878,6 +887,8 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
         rt.l_tile0[rt.nlaunch] = (int32_t)t0;
         rt.l_ntiles[rt.nlaunch] = (int32_t)(t - t0);
         rt.l_lds[rt.nlaunch] = lds;
+        rt.l_flops[rt.nlaunch] = lf;
+        rt.l_bytes[rt.nlaunch] = lb;
         ++rt.nlaunch;
       }
     }

@@ -262,6 +262,7 @@ struct RtPlan {
   // every workgroup, which would cap the occupancy of small groups)
   int32_t nlaunch = 0;
   int32_t l_tile0[RT_NCLASS] = {0}, l_ntiles[RT_NCLASS] = {0}, l_lds[RT_NCLASS] = {0};
+  double l_flops[RT_NCLASS] = {0}, l_bytes[RT_NCLASS] = {0};   // per launch
   double flops = 0;
   int64_t x_extent = 0, c_extent = 0, s_extent = 0;
   // algorithmic HBM bytes: every input element read once, every output
