@@ -120,7 +120,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=4)
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 4 times (the known-size "
@@ -208,7 +208,9 @@ def main():
                        "frac_fp64_mfma": gemm_tfs / PEAK["fp64"]}}
     line = {"metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": a.steps,
             "warmup": a.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if a.precision == "fp64" else "f32-storage/f64-arith",
+            "data": "synthetic",
             "config": {"workload": desc, "lattice": "8x8", "chi": row.chi,
                        "precision": a.precision, "alg_flops_per_step": flops / a.steps,
                        "device_seconds_per_step": dev_s / a.steps},

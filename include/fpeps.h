@@ -71,9 +71,18 @@ typedef enum {
 } fpeps_status;
 
 typedef enum {
-  FPEPS_FP64 = 0,     /* every product in double precision */
-  FPEPS_FP32 = 1,     /* bulk chain products on FP32 MFMA, FP32 accumulate */
-  FPEPS_BF16X3 = 2    /* bulk chain products as three BF16 MFMA passes */
+  FPEPS_FP64 = 0,     /* every product and intermediate in double precision */
+  FPEPS_FP32 = 1,     /* mixed: the chain intermediates (X1..X4 and their
+                         transposes) of the range finder's sketch and power
+                         iterations, except its last product, are stored in
+                         FP32, halving the HBM traffic of the layer steps;
+                         every product still accumulates in FP64, and the
+                         last range-finder product, the projection
+                         B = Q^T M, orthonormalisation, core factorisation,
+                         cut and norms are FP64. Available in
+                         fpeps_env_absorb and fpeps_site_apply (which applies
+                         the chain with FP32 intermediates). */
+  FPEPS_BF16X3 = 2    /* reserved (FPEPS_ERR_UNSUPPORTED) */
 } fpeps_precision;
 
 typedef enum {

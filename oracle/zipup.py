@@ -21,19 +21,22 @@ from .chain import (SiteOperator, ORDERS, R_NAMES, trivial_remainder, sketch_arr
 from .rsvd import sketch_widths, global_cut, orth, SV_CUT
 
 
-SIGN_TIE = 1e-10
+SIGN_TIE = 1e-5
 
 
 def fix_signs(U, R):
     """Canonical gauge of a truncated factorisation U R: every column of U is
     flipped (with the matching row of R) so that its leading entry is
     positive, the leading entry being the first (in row order) whose
-    magnitude is within a relative 1e-10 of the column's largest. The
+    magnitude is within a relative 1e-5 of the column's largest. The
     singular vectors of an SVD are unique only up to these signs; fixing them
     makes the environment, and with it the sketch of the next row,
     independent of the SVD routine. The tolerance matters when a symmetry
     (the ket-bra exchange of <psi|W|psi> with a symmetric W) makes entries
-    of equal magnitude."""
+    of equal magnitude: it must exceed the rounding of the computation that
+    produced U (FP32 storage of the chain intermediates perturbs such ties at
+    the 1e-7 level), so that every path picks the same entry of a tied
+    pair."""
     U, R = U.copy(), R.copy()
     for c in range(U.shape[1]):
         a = np.abs(U[:, c])

@@ -131,8 +131,8 @@ fpeps_status fpeps_site_apply(fpeps_ctx ctx, const fpeps_tensor* R, const fpeps_
                               const double* x_in, double* y_out, fpeps_report* report) {
   return guarded(ctx, [&]() -> fp::Status {
     if (!k || !x_in || !y_out) return fp::fail(FPEPS_ERR_ARG, "null argument");
-    if (opts->precision != FPEPS_FP64)
-      return fp::fail(FPEPS_ERR_UNSUPPORTED, "only FPEPS_FP64 is available in this build");
+    if (opts->precision != FPEPS_FP64 && opts->precision != FPEPS_FP32)
+      return fp::fail(FPEPS_ERR_UNSUPPORTED, "precision: FPEPS_FP64 or FPEPS_FP32");
     if (report) std::memset(report, 0, sizeof(*report));
     fp::SiteOp op;
     FP_TRY(fp::make_site(ctx, R, T, A, W, opts, op));
@@ -143,12 +143,12 @@ fpeps_status fpeps_site_apply(fpeps_ctx ctx, const fpeps_tensor* R, const fpeps_
     const int64_t budget = opts->slice_budget > 0 ? opts->slice_budget : ((int64_t)24 << 30);
     ctx->peak_ws = 0;
     ctx->nslices = 0;
-    FP_TRY(op.plan(ctx, kk, budget, pl, transpose != 0));
+    FP_TRY(op.plan(ctx, kk, budget, pl, transpose != 0, opts->precision == FPEPS_FP32));
     hipEvent_t e0, e1;
     FP_HIP(hipEventCreate(&e0));
     FP_HIP(hipEventCreate(&e1));
     FP_HIP(hipEventRecord(e0, ctx->stream));
-    FP_TRY(op.apply(ctx, pl, transpose != 0, x_in, y_out));
+    FP_TRY(op.apply(ctx, pl, transpose != 0, x_in, y_out, opts->precision == FPEPS_FP32));
     FP_HIP(hipEventRecord(e1, ctx->stream));
     FP_HIP(hipEventSynchronize(e1));
     float ms = 0;

@@ -224,8 +224,8 @@ Status PlanSet::pack(fpeps_ctx_s* ctx, int idx, const double* S, int64_t s_size)
   return Status::ok();
 }
 
-Status run_rt(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* X, int64_t x_size,
-              double* Y, int64_t y_size, bool timed, int label) {
+Status run_rt(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const void* X, int64_t x_size,
+              void* Y, int64_t y_size, bool f32, bool timed, int label) {
   const RtPlan& p = ps.rts[idx];
   if (p.ntiles == 0) return Status::ok();
   if (p.x_extent > x_size || p.c_extent > y_size)
@@ -241,12 +241,12 @@ Status run_rt(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* X, int
       FP_TRY(ctx->timed_events(&a, &b));
       ctx->evflops.push_back(p.l_flops[c]);
       ctx->evlabel.push_back(label);
-      ctx->evbytes.push_back(p.l_bytes[c]);
+      ctx->evbytes.push_back(f32 ? 0.5 * p.l_bytes[c] : p.l_bytes[c]);
       FP_HIP(hipEventRecord(a, ctx->stream));
-      FP_HIP(launch_rt_f64(d, c, X, ps.dpack, Y, ps.dtab, ctx->stream));
+      FP_HIP(launch_rt_f64(d, c, X, f32, ps.dpack, Y, ps.dtab, ctx->stream));
       FP_HIP(hipEventRecord(b, ctx->stream));
     } else {
-      FP_HIP(launch_rt_f64(d, c, X, ps.dpack, Y, ps.dtab, ctx->stream));
+      FP_HIP(launch_rt_f64(d, c, X, f32, ps.dpack, Y, ps.dtab, ctx->stream));
     }
   }
   return Status::ok();
@@ -255,6 +255,12 @@ Status run_rt(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* X, int
 Status run_gemm(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A, int64_t a_size,
                 const double* B, int64_t b_size, double* C, int64_t c_size, bool timed,
                 int label) {
+  return run_gemm_mixed(ctx, ps, idx, A, a_size, B, false, b_size, C, false, c_size, timed, label);
+}
+
+Status run_gemm_mixed(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A,
+                      int64_t a_size, const void* B, bool b_f32, int64_t b_size, void* C,
+                      bool c_f32, int64_t c_size, bool timed, int label) {
   const GemmPlan& p = ps.plans[idx];
   if (p.jobs.empty()) return Status::ok();
   // every table-addressed access must stay inside its buffer
@@ -265,8 +271,10 @@ Status run_gemm(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A, i
                                      ", c " + std::to_string(p.c_extent) + "/" +
                                      std::to_string(c_size) + ")");
   if (!A || !B || !C) return fail(FPEPS_ERR_ARG, "null operand buffer");
-  double* target = C;
-  if (p.partial_size > 0) FP_TRY(ctx->bufT("gemm_part", (size_t)p.partial_size, &target));
+  if (b_f32 && c_f32) return fail(FPEPS_ERR_UNSUPPORTED, "GEMM with both B and C in FP32");
+  // split-K parts are summed in FP64 and rounded once into C
+  double* part = nullptr;
+  if (p.partial_size > 0) FP_TRY(ctx->bufT("gemm_part", (size_t)p.partial_size, &part));
   hipEvent_t ea = nullptr, eb = nullptr;
   const bool tk = timed && ctx->time_kernels;
   if (tk) {
@@ -276,10 +284,13 @@ Status run_gemm(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A, i
     ctx->evbytes.push_back(p.bytes);
     FP_HIP(hipEventRecord(ea, ctx->stream));
   }
-  FP_HIP(launch_gemm_f64(ps.dev[idx], A, B, target, ps.dtab, ctx->stream));
-  if (p.partial_size > 0)
-    FP_HIP(launch_reduce_tab(ps.dev[idx].reduces, ps.dev[idx].nred, p.max_red_mn, C, target,
+  if (part) {
+    FP_HIP(launch_gemm_mixed(ps.dev[idx], A, B, b_f32, part, false, ps.dtab, ctx->stream));
+    FP_HIP(launch_reduce_tab(ps.dev[idx].reduces, ps.dev[idx].nred, p.max_red_mn, C, c_f32, part,
                              ps.dtab, ctx->stream));
+  } else {
+    FP_HIP(launch_gemm_mixed(ps.dev[idx], A, B, b_f32, C, c_f32, ps.dtab, ctx->stream));
+  }
   if (tk) FP_HIP(hipEventRecord(eb, ctx->stream));
   return Status::ok();
 }

@@ -126,7 +126,11 @@ struct PlanSet {
 Status run_gemm(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A, int64_t a_size,
                 const double* B, int64_t b_size, double* C, int64_t c_size, bool timed = false,
                 int label = 0);
-Status run_rt(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* X, int64_t x_size,
-              double* Y, int64_t y_size, bool timed = false, int label = 0);
+// B or C in FP32 (sizes in elements; see launch_gemm_mixed)
+Status run_gemm_mixed(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A,
+                      int64_t a_size, const void* B, bool b_f32, int64_t b_size, void* C,
+                      bool c_f32, int64_t c_size, bool timed = false, int label = 0);
+Status run_rt(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const void* X, int64_t x_size,
+              void* Y, int64_t y_size, bool f32, bool timed = false, int label = 0);
 
 }  // namespace fp

@@ -266,21 +266,23 @@ Status rsvd_run(fpeps_ctx_s* ctx, RsvdIO& io, int chi, int p, int q, uint64_t se
   FP_TRY(ctx->upload("rs_gauss", gd.data(), gd.size() * sizeof(GaussDesc), (void**)&dgd));
   FP_HIP(launch_gaussian(dgd, (int)gd.size(), maxe, c0, seed, ctx->stream));
   // stage A
-  FP_TRY(io.apply(false, c0, r0));
+  // the last product of the range finder (it fixes Q) and the projection
+  // are "final": FP64 intermediates in mixed precision
+  FP_TRY(io.apply(false, q == 0, c0, r0));
   double* Q = nullptr;
   FP_TRY(orth(ctx, dp, 0, RL, r0, r1, &Q, &out.fallbacks));
   for (int it = 0; it < q; ++it) {
-    FP_TRY(io.apply(true, Q, c0));
+    FP_TRY(io.apply(true, false, Q, c0));
     double* Qz = nullptr;
     FP_TRY(orth(ctx, dp, 1, CL, c0, c1, &Qz, &out.fallbacks));
     double* Yb = (Q == r0) ? r1 : r0;
-    FP_TRY(io.apply(false, Qz, Yb));
+    FP_TRY(io.apply(false, it == q - 1, Qz, Yb));
     double* other = (Yb == r0) ? r1 : r0;
     FP_TRY(orth(ctx, dp, 0, RL, Yb, other, &Q, &out.fallbacks));
   }
   // stage B: B^T = M^T Q, core factorisation of B B^T
   double* Bt = c0;
-  FP_TRY(io.apply(true, Q, Bt));
+  FP_TRY(io.apply(true, true, Q, Bt));
   out.Q = Q;
   out.Bt = Bt;
   double *part = nullptr, *small = nullptr;
@@ -492,8 +494,9 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
                   double* log_norm, fpeps_report* rep) {
   if (L < 1 || !env_in || !ket || !pepo || !o || !env_out || !log_norm)
     return fail(FPEPS_ERR_ARG, "null argument or L < 1");
-  if (o->precision != FPEPS_FP64)
-    return fail(FPEPS_ERR_UNSUPPORTED, "only FPEPS_FP64 is available in this build");
+  if (o->precision != FPEPS_FP64 && o->precision != FPEPS_FP32)
+    return fail(FPEPS_ERR_UNSUPPORTED, "precision: FPEPS_FP64 or FPEPS_FP32");
+  const bool f32 = o->precision == FPEPS_FP32;
   if (o->cbe_extra != 0)
     return fail(FPEPS_ERR_UNSUPPORTED, "bond expansion inside the absorption is not available");
   if (o->chi < 1 || o->oversample < 0 || o->power_iters < 0)
@@ -609,14 +612,14 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
       std::vector<int32_t> k(ns, 0);
       k[J1] = 1;
       SiteOp::Plans pl;
-      FP_TRY(op.plan(ctx, k, budget, pl, false));
+      FP_TRY(op.plan(ctx, k, budget, pl, false, f32));
       double *xin = nullptr, *y = nullptr, *part = nullptr, *nrm = nullptr;
       FP_TRY(ctx->bufT("last_x", 1, &xin));
       FP_TRY(ctx->bufT("last_y", (size_t)std::max<int64_t>(pl.row_total, 1), &y));
       FP_TRY(ctx->bufT("nrm_part", 512, &part));
       FP_TRY(ctx->bufT("nrm_out", 1, &nrm));
       FP_HIP(launch_fill(xin, 1, 1.0, ctx->stream));
-      FP_TRY(op.apply(ctx, pl, false, xin, y));
+      FP_TRY(op.apply(ctx, pl, false, xin, y, false));
       FP_HIP(launch_sumsq(y, pl.row_total, part, nrm, ctx->stream));
       double h = 0;
       FP_HIP(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -664,11 +667,13 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     double t_plan = 0;
     io.prepare = [&](const std::vector<int32_t>& k) {
       const double t0 = wall();
-      Status st = op.plan(ctx, k, budget, pl, true);
+      Status st = op.plan(ctx, k, budget, pl, true, f32);
       t_plan += wall() - t0;
       return st;
     };
-    io.apply = [&](bool t, const double* xi, double* yo) { return op.apply(ctx, pl, t, xi, yo); };
+    io.apply = [&](bool t, bool fin, const double* xi, double* yo) {
+      return op.apply(ctx, pl, t, xi, yo, f32 && !fin);
+    };
     RsvdOut rs;
     const double tw1 = wall();
     {
@@ -1079,7 +1084,7 @@ Status explicit_rsvd(fpeps_ctx_s* ctx, int nmat, const int64_t* m, const int64_t
   io.width_m = mm;
   io.width_n = nn;
   io.prepare = [&](const std::vector<int32_t>& k) { return explicit_prepare(ctx, e, k); };
-  io.apply = [&](bool t, const double* x, double* y) -> Status {
+  io.apply = [&](bool t, bool, const double* x, double* y) -> Status {
     if (!t) {
       double* xc = const_cast<double*>(x);
       if (cbe) FP_TRY(project(ctx, e, false, xc, e.col_total));

@@ -20,7 +20,12 @@ struct RsvdIO {
   std::vector<uint32_t> c1;                // sketch counter word per sector
   uint32_t c2 = 0, c3 = 0;
   std::function<Status(const std::vector<int32_t>&)> prepare;
-  std::function<Status(bool, const double*, double*)> apply;
+  // apply(transpose, final, x, y): y = M x or M^T x; ``final`` marks the
+  // last range-finder product (it fixes Q) and the projection B^T = M^T Q
+  // (FP64 intermediates in mixed precision; the earlier range-finder
+  // products tolerate FP32 intermediates, their rounding being damped by
+  // the later multiplications)
+  std::function<Status(bool, bool, const double*, double*)> apply;
 };
 
 struct RsvdOut {

@@ -32,9 +32,9 @@ struct TileRegs {
   bool akf, bnf;
 };
 
-template <int MT, int NT, int KT>
+template <int MT, int NT, int KT, class TB>
 __device__ __forceinline__ void load_tile(const double* __restrict__ A,
-                                          const double* __restrict__ B,
+                                          const TB* __restrict__ B,
                                           const GemmPair* __restrict__ pairs,
                                           const int32_t* __restrict__ tab, const GemmJob& job,
                                           const TileCursor& t, int tid,
@@ -42,7 +42,7 @@ __device__ __forceinline__ void load_tile(const double* __restrict__ A,
   const GemmPair pr = pairs[t.p];
   const int kend = job.k1 < pr.K ? job.k1 : pr.K;
   const double* Ab = A + pr.a_off;
-  const double* Bb = B + pr.b_off;
+  const TB* Bb = B + pr.b_off;
   const int32_t* tam = tab + pr.tam;
   const int32_t* tak = tab + pr.tak;
   const int32_t* tbk = tab + pr.tbk;
@@ -76,7 +76,7 @@ __device__ __forceinline__ void load_tile(const double* __restrict__ A,
 #pragma unroll
   for (int i = 0; i < NA; ++i) r.a[i] = Ab[oa[i]];
 #pragma unroll
-  for (int i = 0; i < NB; ++i) r.b[i] = Bb[ob[i]];
+  for (int i = 0; i < NB; ++i) r.b[i] = (double)Bb[ob[i]];
 #pragma unroll
   for (int i = 0; i < NA; ++i) r.a[i] = va[i] ? r.a[i] * pr.alpha : 0.0;
 #pragma unroll
@@ -119,10 +119,10 @@ __device__ __forceinline__ bool next_tile(const GemmPair* __restrict__ pairs, co
 // One workgroup (four waves, WM x WN) per output tile; K tiles are
 // prefetched into registers while the previous tile is multiplied out of
 // LDS (double-buffered, one barrier per tile).
-template <int MT, int NT, int WM, int WN>
+template <int MT, int NT, int WM, int WN, class TB, class TC>
 __global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ A,
-                                                  const double* __restrict__ B,
-                                                  double* __restrict__ C,
+                                                  const TB* __restrict__ B,
+                                                  TC* __restrict__ C,
                                                   const GemmJob* __restrict__ jobs,
                                                   const GemmPair* __restrict__ pairs,
                                                   const int32_t* __restrict__ tab) {
@@ -161,13 +161,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ 
   }
   if (have) {
     TileRegs<MT, NT, KT> regs;
-    load_tile<MT, NT, KT>(A, B, pairs, tab, job, cur, tid, regs);
+    load_tile<MT, NT, KT, TB>(A, B, pairs, tab, job, cur, tid, regs);
     store_tile<MT, NT, KT>(sA[0], sB[0], tid, regs);
     __syncthreads();
     int buf = 0;
     while (true) {
       const bool more = next_tile(pairs, job, cur, KT);
-      if (more) load_tile<MT, NT, KT>(A, B, pairs, tab, job, cur, tid, regs);
+      if (more) load_tile<MT, NT, KT, TB>(A, B, pairs, tab, job, cur, tid, regs);
 #pragma unroll
       for (int kk = 0; kk < KT; kk += 4) {
         double a[FM], b[FN];
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ 
     const int n = job.n0 + wn * WTN + j * 16 + lrow;
     on[j] = tcn[min(n, job.N - 1)];
   }
-  double* Cb = C + job.c_off;
+  TC* Cb = C + job.c_off;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -214,18 +214,19 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ 
       for (int r = 0; r < 4; ++r) {
         const int m = job.m0 + wm * WTM + i * 16 + 4 * r + lk;
         const int n = job.n0 + wn * WTN + j * 16 + lrow;
-        if (m < job.M && n < job.N) Cb[(int64_t)om[i][r] + on[j]] = acc[i][j][r];
+        if (m < job.M && n < job.N) Cb[(int64_t)om[i][r] + on[j]] = (TC)acc[i][j][r];
       }
 }
 
-hipError_t launch_gemm_f64(const DevGemm& g, const double* A, const double* B, double* C,
-                           const int32_t* tables, hipStream_t s) {
-  if (g.njobs <= 0) return hipSuccess;
+template <class TB, class TC>
+static hipError_t launch_typed(const DevGemm& g, const double* A, const TB* B, TC* C,
+                               const int32_t* tables, hipStream_t s) {
   dim3 grid(g.njobs), block(256);
-#define FP_GEMM_TILE(mt_, nt_, wm_, wn_)                                                  \
-  if (g.mt == mt_ && g.nt == nt_) {                                                       \
-    k_gemm_f64<mt_, nt_, wm_, wn_><<<grid, block, 0, s>>>(A, B, C, g.jobs, g.pairs, tables); \
-    return hipGetLastError();                                                             \
+#define FP_GEMM_TILE(mt_, nt_, wm_, wn_)                                                 \
+  if (g.mt == mt_ && g.nt == nt_) {                                                      \
+    k_gemm_f64<mt_, nt_, wm_, wn_, TB, TC>                                               \
+        <<<grid, block, 0, s>>>(A, B, C, g.jobs, g.pairs, tables);                       \
+    return hipGetLastError();                                                            \
   }
   FP_GEMM_TILE(128, 128, 2, 2)
   FP_GEMM_TILE(128, 64, 2, 2)
@@ -239,9 +240,28 @@ hipError_t launch_gemm_f64(const DevGemm& g, const double* A, const double* B, d
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_gemm_f64(const DevGemm& g, const double* A, const double* B, double* C,
+                           const int32_t* tables, hipStream_t s) {
+  if (g.njobs <= 0) return hipSuccess;
+  return launch_typed<double, double>(g, A, B, C, tables, s);
+}
+
+hipError_t launch_gemm_mixed(const DevGemm& g, const double* A, const void* B, bool b_f32,
+                             void* C, bool c_f32, const int32_t* tables, hipStream_t s) {
+  if (g.njobs <= 0) return hipSuccess;
+  if (!b_f32 && !c_f32)
+    return launch_typed<double, double>(g, A, (const double*)B, (double*)C, tables, s);
+  if (!b_f32 && c_f32)
+    return launch_typed<double, float>(g, A, (const double*)B, (float*)C, tables, s);
+  if (b_f32 && !c_f32)
+    return launch_typed<float, double>(g, A, (const float*)B, (double*)C, tables, s);
+  return hipErrorInvalidValue;
+}
+
 // Sum of the split parts of table-addressed output blocks:
 // C[c_off + tcm[m] + tcn[n]] = sum_q P[p_off + q M N + m N + n].
-__global__ void k_reduce_tab(const ReduceTab* __restrict__ d, double* __restrict__ C,
+template <class TC>
+__global__ void k_reduce_tab(const ReduceTab* __restrict__ d, TC* __restrict__ C,
                              const double* __restrict__ P, const int32_t* __restrict__ tab) {
   const ReduceTab r = d[blockIdx.y];
   const int64_t mn = (int64_t)r.M * r.N;
@@ -252,17 +272,20 @@ __global__ void k_reduce_tab(const ReduceTab* __restrict__ d, double* __restrict
     double s = 0.0;
     for (int q = 0; q < r.nsplit; ++q) s += P[r.p_off + (int64_t)q * mn + e];
     const int m = (int)(e / r.N), n = (int)(e % r.N);
-    C[r.c_off + (int64_t)tcm[m] + tcn[n]] = s;
+    C[r.c_off + (int64_t)tcm[m] + tcn[n]] = (TC)s;
   }
 }
 
-hipError_t launch_reduce_tab(const ReduceTab* d, int nd, int64_t max_mn, double* C,
+hipError_t launch_reduce_tab(const ReduceTab* d, int nd, int64_t max_mn, void* C, bool c_f32,
                              const double* P, const int32_t* tab, hipStream_t s) {
   if (nd <= 0) return hipSuccess;
   int64_t bx = (max_mn + 255) / 256;
   if (bx > 256) bx = 256;
   if (bx < 1) bx = 1;
-  k_reduce_tab<<<dim3((unsigned)bx, nd), 256, 0, s>>>(d, C, P, tab);
+  if (c_f32)
+    k_reduce_tab<float><<<dim3((unsigned)bx, nd), 256, 0, s>>>(d, (float*)C, P, tab);
+  else
+    k_reduce_tab<double><<<dim3((unsigned)bx, nd), 256, 0, s>>>(d, (double*)C, P, tab);
   return hipGetLastError();
 }
 

@@ -39,14 +39,20 @@ struct DevRt {
 };
 // Y[rows of the groups of LDS class launch c] = X rows times the packed
 // layer sub-blocks PK (one launch of the plan's nlaunch).
-hipError_t launch_rt_f64(const DevRt& r, int c, const double* X, const double* PK, double* Y,
-                         const int32_t* tab, hipStream_t s);
+// X and Y are double, or float when ``f32`` (FP32 storage, FP64 arithmetic).
+hipError_t launch_rt_f64(const DevRt& r, int c, const void* X, bool f32, const double* PK,
+                         void* Y, const int32_t* tab, hipStream_t s);
 // PK[dst + k nc + c] = alpha S[sbase + sk[k] + sn[c]] for every pack entry.
 hipError_t launch_rt_pack(const DevRt& r, const double* S, const int32_t* tab, double* PK,
                           hipStream_t s);
 
+// The same with FP32 storage of B or C (loads widen to FP64, stores round
+// the FP64 accumulators once): (B f64, C f32) or (B f32, C f64).
+hipError_t launch_gemm_mixed(const DevGemm& g, const double* A, const void* B, bool b_f32,
+                             void* C, bool c_f32, const int32_t* tables, hipStream_t s);
+
 // Sum of the split parts of table-addressed output blocks (see GemmPlan).
-hipError_t launch_reduce_tab(const ReduceTab* d, int nd, int64_t max_mn, double* C,
+hipError_t launch_reduce_tab(const ReduceTab* d, int nd, int64_t max_mn, void* C, bool c_f32,
                              const double* P, const int32_t* tab, hipStream_t s);
 
 // Sum of split-K partials: C(m, n) = sum_s P[p_off + s*M*N + m*N + n].
@@ -100,7 +106,7 @@ hipError_t launch_svqb_scale(const SmallDesc* d, int nd, double* buf, double tau
 // Canonical signs of a truncated factorisation: column c of U (m x ncol,
 // row-major at u_off) is flipped together with row c of R (ncol x n at
 // r_off) so that the column's leading entry is positive: the first row whose
-// magnitude is within a relative 1e-10 of the column's largest. One
+// magnitude is within a relative 1e-5 of the column's largest. One
 // workgroup per (matrix, column).
 struct SignDesc {
   int64_t u_off, r_off;

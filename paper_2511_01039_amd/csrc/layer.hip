@@ -1,5 +1,6 @@
 // Layer steps of the chain (ket, PEPO and bra contracted into the
-// sketch-side intermediate, and their transposes), FP64.
+// sketch-side intermediate, and their transposes). Intermediates are stored
+// in FP64 or FP32; every product and sum is FP64.
 //
 // These products have a huge row count (environment x sketch indices) and
 // tiny contracted/column extents (a few virtual or physical indices), so
@@ -94,10 +95,10 @@ __device__ __forceinline__ RtPair ld(const FP_CONST RtPair* p) {
 // doubles per column and successive columns sit at fixed byte offsets
 // (immediate offsets of ds_read). Unstaged groups read X from global memory
 // through the X block's level strides and contracted-offset table.
-template <int NC, bool STAGED>
-__device__ __forceinline__ void rt_chunk(const double* __restrict__ X,
-                                         const FP_CONST double* PK, double* __restrict__ Y,
-                                         const double* __restrict__ lds, int rows, int r,
+template <int NC, bool STAGED, class T>
+__device__ __forceinline__ void rt_chunk(const T* __restrict__ X,
+                                         const FP_CONST double* PK, T* __restrict__ Y,
+                                         const T* __restrict__ lds, int rows, int r,
                                          const RtOut& O, const FP_CONST RtPair* pairs,
                                          const FP_CONST RtKblk* kblks,
                                          const FP_CONST int32_t* tab,
@@ -110,11 +111,11 @@ __device__ __forceinline__ void rt_chunk(const double* __restrict__ X,
     const FP_CONST double* bp = PK + P.pk;
     const int Kb = P.Kb;
     if (STAGED) {
-      const double* lp = lds + P.koff * 64;
+      const T* lp = lds + P.koff * 64;
       int k = 0;
       for (; k + 4 <= Kb; k += 4) {
-        const double a0 = lp[(k + 0) * 64], a1 = lp[(k + 1) * 64];
-        const double a2 = lp[(k + 2) * 64], a3 = lp[(k + 3) * 64];
+        const double a0 = (double)lp[(k + 0) * 64], a1 = (double)lp[(k + 1) * 64];
+        const double a2 = (double)lp[(k + 2) * 64], a3 = (double)lp[(k + 3) * 64];
         const FP_CONST double* b = bp + k * NC;
 #pragma unroll
         for (int n = 0; n < NC; ++n) {
@@ -125,7 +126,7 @@ __device__ __forceinline__ void rt_chunk(const double* __restrict__ X,
         }
       }
       for (; k < Kb; ++k) {
-        const double a = lp[k * 64];
+        const double a = (double)lp[k * 64];
         const FP_CONST double* b = bp + k * NC;
 #pragma unroll
         for (int n = 0; n < NC; ++n) acc[n] = fma(a, b[n], acc[n]);
@@ -135,11 +136,12 @@ __device__ __forceinline__ void rt_chunk(const double* __restrict__ X,
       int32_t xo = 0;
 #pragma unroll
       for (int l = 0; l < RT_MAXLEV; ++l) xo += idx[l] * K.xs[l];
-      const double* xp = X + K.xbase + xo;
+      const T* xp = X + K.xbase + xo;
       const FP_CONST int32_t* kt = tab + K.xktab;
       int k = 0;
       for (; k + 4 <= Kb; k += 4) {
-        const double a0 = xp[kt[k]], a1 = xp[kt[k + 1]], a2 = xp[kt[k + 2]], a3 = xp[kt[k + 3]];
+        const double a0 = (double)xp[kt[k]], a1 = (double)xp[kt[k + 1]];
+        const double a2 = (double)xp[kt[k + 2]], a3 = (double)xp[kt[k + 3]];
         const FP_CONST double* b = bp + k * NC;
 #pragma unroll
         for (int n = 0; n < NC; ++n) {
@@ -150,7 +152,7 @@ __device__ __forceinline__ void rt_chunk(const double* __restrict__ X,
         }
       }
       for (; k < Kb; ++k) {
-        const double a = xp[kt[k]];
+        const double a = (double)xp[kt[k]];
         const FP_CONST double* b = bp + k * NC;
 #pragma unroll
         for (int n = 0; n < NC; ++n) acc[n] = fma(a, b[n], acc[n]);
@@ -161,17 +163,17 @@ __device__ __forceinline__ void rt_chunk(const double* __restrict__ X,
     int32_t oo = 0;
 #pragma unroll
     for (int l = 0; l < RT_MAXLEV; ++l) oo += idx[l] * O.ms[l];
-    double* yp = Y + O.base + oo;
+    T* yp = Y + O.base + oo;
     const FP_CONST int32_t* nt = tab + O.ntab;
 #pragma unroll
-    for (int n = 0; n < NC; ++n) yp[nt[n]] = acc[n];
+    for (int n = 0; n < NC; ++n) yp[nt[n]] = (T)acc[n];
   }
 }
 
-template <bool STAGED>
-__device__ __forceinline__ void rt_chunks(const double* __restrict__ X,
-                                          const FP_CONST double* PK, double* __restrict__ Y,
-                                          const double* __restrict__ lds, int rows, int r,
+template <bool STAGED, class T>
+__device__ __forceinline__ void rt_chunks(const T* __restrict__ X,
+                                          const FP_CONST double* PK, T* __restrict__ Y,
+                                          const T* __restrict__ lds, int rows, int r,
                                           const RtGroup& G, int o_first, int o_step,
                                           const FP_CONST RtOut* outs,
                                           const FP_CONST RtPair* pairs,
@@ -183,7 +185,7 @@ __device__ __forceinline__ void rt_chunks(const double* __restrict__ X,
     switch (O.nc) {
 #define FP_RT_CASE(n)                                                                    \
   case n:                                                                                \
-    rt_chunk<n, STAGED>(X, PK, Y, lds, rows, r, O, pairs, kblks, tab, idx, live); \
+    rt_chunk<n, STAGED, T>(X, PK, Y, lds, rows, r, O, pairs, kblks, tab, idx, live); \
     break;
       FP_RT_CASE(1) FP_RT_CASE(2) FP_RT_CASE(3) FP_RT_CASE(4) FP_RT_CASE(5) FP_RT_CASE(6)
       FP_RT_CASE(7) FP_RT_CASE(8) FP_RT_CASE(9) FP_RT_CASE(10) FP_RT_CASE(11) FP_RT_CASE(12)
@@ -211,13 +213,15 @@ __device__ __forceinline__ void row_levels(const RtGroup& G, int m, int32_t (&id
   }
 }
 
+template <class T>
 __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
-    const double* __restrict__ X, const double* __restrict__ PK_, double* __restrict__ Y,
+    const T* __restrict__ X, const double* __restrict__ PK_, T* __restrict__ Y,
     const RtGroup* __restrict__ groups_, const int32_t* __restrict__ tile_group,
     const RtOut* __restrict__ outs_,
     const RtKblk* __restrict__ kblks_, const RtCol* __restrict__ cols_,
     const RtPair* __restrict__ pairs_, const int32_t* __restrict__ tab_, int tile_base) {
-  extern __shared__ double lds[];
+  extern __shared__ double lds_raw[];
+  T* lds = (T*)lds_raw;
   const FP_CONST RtGroup* groups = as_const(groups_);
   const FP_CONST RtOut* outs = as_const(outs_);
   const FP_CONST RtKblk* kblks = as_const(kblks_);
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
     const int nslot = RT_THREADS >> lrows;
     const int slot = __builtin_amdgcn_readfirstlane(tid >> lrows);
     const FP_CONST RtCol* gc = cols + G.c0;
-    double* lst = lds + (r >> 6) * G.ktot * 64 + (r & 63);
+    T* lst = lds + (r >> 6) * G.ktot * 64 + (r & 63);
     for (int c0 = slot; c0 < G.ktot; c0 += 8 * nslot) {
       // descriptors of the batch first (clamped: always valid), then the
       // eight loads, then the LDS writes
@@ -258,12 +262,12 @@ __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
         int32_t xo = 0;
 #pragma unroll
         for (int l = 0; l < RT_MAXLEV; ++l) xo += idx[l] * C[u].xs[l];
-        v[u] = X[C[u].xbase + xo];
+        v[u] = (double)X[C[u].xbase + xo];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int c = c0 + u * nslot;
-        if (c < G.ktot) lst[c * 64] = v[u];
+        if (c < G.ktot) lst[c * 64] = (T)v[u];
       }
     }
     __syncthreads();
@@ -276,12 +280,12 @@ __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
   const int lsub = lrows - 6;                  // log2(rows / 64)
   const int o_first = wave >> lsub, o_step = 4 >> lsub;
   // this lane's row inside the staged tile: sub-block r / 64, lane r % 64
-  const double* lrow = lds + (r >> 6) * G.ktot * 64 + (r & 63);
+  const T* lrow = lds + (r >> 6) * G.ktot * 64 + (r & 63);
   if (G.staged)
-    rt_chunks<true>(X, PK, Y, lrow, rows, r, G, o_first, o_step, outs, pairs, kblks, tab, idx,
+    rt_chunks<true, T>(X, PK, Y, lrow, rows, r, G, o_first, o_step, outs, pairs, kblks, tab, idx,
                     live);
   else
-    rt_chunks<false>(X, PK, Y, lrow, rows, r, G, o_first, o_step, outs, pairs, kblks, tab, idx,
+    rt_chunks<false, T>(X, PK, Y, lrow, rows, r, G, o_first, o_step, outs, pairs, kblks, tab, idx,
                      live);
 }
 
@@ -295,12 +299,19 @@ __global__ void k_rt_pack(const RtPack* __restrict__ packs, const double* __rest
   }
 }
 
-hipError_t launch_rt_f64(const DevRt& r, int c, const double* X, const double* PK, double* Y,
-                         const int32_t* tab, hipStream_t s) {
+hipError_t launch_rt_f64(const DevRt& r, int c, const void* X, bool f32, const double* PK,
+                         void* Y, const int32_t* tab, hipStream_t s) {
   if (c < 0 || c >= r.nlaunch || r.ngroups <= 0) return hipErrorInvalidValue;
   if (r.l_lds[c] < 0 || r.l_lds[c] > RT_LDS_BYTES || r.l_ntiles[c] <= 0) return hipErrorInvalidValue;
-  k_rt_f64<<<dim3(r.l_ntiles[c]), dim3(RT_THREADS), (size_t)r.l_lds[c], s>>>(
-      X, PK, Y, r.groups, r.tile_group, r.outs, r.kblks, r.cols, r.pairs, tab, r.l_tile0[c]);
+  // the plan sizes LDS for double; FP32 staging takes half
+  if (f32)
+    k_rt_f64<float><<<dim3(r.l_ntiles[c]), dim3(RT_THREADS), (size_t)r.l_lds[c] / 2, s>>>(
+        (const float*)X, PK, (float*)Y, r.groups, r.tile_group, r.outs, r.kblks, r.cols, r.pairs,
+        tab, r.l_tile0[c]);
+  else
+    k_rt_f64<double><<<dim3(r.l_ntiles[c]), dim3(RT_THREADS), (size_t)r.l_lds[c], s>>>(
+        (const double*)X, PK, (double*)Y, r.groups, r.tile_group, r.outs, r.kblks, r.cols,
+        r.pairs, tab, r.l_tile0[c]);
   return hipGetLastError();
 }
 

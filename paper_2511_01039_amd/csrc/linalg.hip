@@ -405,7 +405,7 @@ __global__ __launch_bounds__(256) void k_sign_fix(const SignDesc* __restrict__ d
     if ((int)threadIdx.x < w) bv[threadIdx.x] = fmax(bv[threadIdx.x], bv[threadIdx.x + w]);
     __syncthreads();
   }
-  const double thr = bv[0] * (1.0 - 1e-10);
+  const double thr = bv[0] * (1.0 - 1e-5);
   // pass 2: first row whose magnitude reaches the threshold
   int first = 0x7fffffff;
   for (int i = threadIdx.x; i < g.m; i += blockDim.x)

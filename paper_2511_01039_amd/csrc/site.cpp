@@ -280,10 +280,11 @@ BT SiteOp::omega_layout(const std::vector<SliceCol>& cols, const std::vector<int
 }
 
 Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t budget, Plans& out,
-                    bool with_bwd) {
+                    bool with_bwd, bool f32) {
   const int ns = (int)sect.size();
   if ((int)k.size() != ns) return fail(FPEPS_ERR_ARG, "width list does not match the sectors");
   out = Plans();
+  out.f32 = f32;
   out.col_off.resize(ns);
   out.row_off.resize(ns);
   for (int J = 0; J < ns; ++J) {
@@ -294,7 +295,7 @@ Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t bud
   }
   // slices: whole sectors packed greedily; a sector larger than the budget
   // is split into column ranges
-  const double elem_budget = (double)budget / sizeof(double);
+  const double elem_budget = (double)budget / (f32 ? sizeof(float) : sizeof(double));
   std::vector<std::vector<SliceCol>> slices;
   std::vector<SliceCol> cur;
   double used = 0;
@@ -363,7 +364,8 @@ Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t bud
       }
     }
   }
-  ctx->peak_ws = std::max(ctx->peak_ws, (double)(out.ws1 + out.ws2) * sizeof(double));
+  ctx->peak_ws = std::max(ctx->peak_ws,
+                          (double)(out.ws1 + out.ws2) * (f32 ? sizeof(float) : sizeof(double)));
   ctx->nslices = std::max(ctx->nslices, (int)out.slices.size());
   return Status::ok();
 }
@@ -456,25 +458,33 @@ Status SiteOp::plan_slice(const std::vector<int32_t>& k, const Plans& pl, Slice&
   return Status::ok();
 }
 
-Status SiteOp::apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const double* x, double* y) {
-  double *b1 = nullptr, *b2 = nullptr;
-  FP_TRY(ctx->bufT("chain1", (size_t)std::max<int64_t>(pl.ws1, 1), &b1));
-  FP_TRY(ctx->bufT("chain2", (size_t)std::max<int64_t>(pl.ws2, 1), &b2));
+Status SiteOp::apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const double* x, double* y,
+                     bool f32) {
+  const size_t es = f32 ? sizeof(float) : sizeof(double);
+  void *b1 = nullptr, *b2 = nullptr;
+  FP_TRY(ctx->buf("chain1", (size_t)std::max<int64_t>(pl.ws1, 1) * es + 256, &b1));
+  FP_TRY(ctx->buf("chain2", (size_t)std::max<int64_t>(pl.ws2, 1) * es + 256, &b2));
   const int64_t s1 = std::max<int64_t>(pl.ws1, 1), s2 = std::max<int64_t>(pl.ws2, 1);
+  const bool f = f32;
   for (const Slice& sl : pl.slices) {
+    const PlanSet& ps = *sl.ps;
     if (!transpose) {
-      FP_TRY(run_gemm(ctx, *sl.ps, sl.fwd[0], dev.T, dev.T_size, x, pl.col_total, b1, s1, true, 1));
-      FP_TRY(run_rt(ctx, *sl.ps, sl.fwd[1], b1, s1, b2, s2, true, 2));
-      FP_TRY(run_rt(ctx, *sl.ps, sl.fwd[2], b2, s2, b1, s1, true, 3));
-      FP_TRY(run_rt(ctx, *sl.ps, sl.fwd[3], b1, s1, b2, s2, true, 4));
-      FP_TRY(run_gemm(ctx, *sl.ps, sl.fwd[4], dev.R, dev.R_size, b2, s2, y, pl.row_total, true, 5));
+      FP_TRY(run_gemm_mixed(ctx, ps, sl.fwd[0], dev.T, dev.T_size, x, false, pl.col_total, b1, f,
+                            s1, true, 1));
+      FP_TRY(run_rt(ctx, ps, sl.fwd[1], b1, s1, b2, s2, f, true, 2));
+      FP_TRY(run_rt(ctx, ps, sl.fwd[2], b2, s2, b1, s1, f, true, 3));
+      FP_TRY(run_rt(ctx, ps, sl.fwd[3], b1, s1, b2, s2, f, true, 4));
+      FP_TRY(run_gemm_mixed(ctx, ps, sl.fwd[4], dev.R, dev.R_size, b2, f, s2, y, false,
+                            pl.row_total, true, 5));
     } else {
       if (sl.bwd[0] < 0) return fail(FPEPS_ERR_ARG, "transposed chain was not planned");
-      FP_TRY(run_gemm(ctx, *sl.ps, sl.bwd[0], dev.R, dev.R_size, x, pl.row_total, b2, s2, true, 15));
-      FP_TRY(run_rt(ctx, *sl.ps, sl.bwd[1], b2, s2, b1, s1, true, 14));
-      FP_TRY(run_rt(ctx, *sl.ps, sl.bwd[2], b1, s1, b2, s2, true, 13));
-      FP_TRY(run_rt(ctx, *sl.ps, sl.bwd[3], b2, s2, b1, s1, true, 12));
-      FP_TRY(run_gemm(ctx, *sl.ps, sl.bwd[4], dev.T, dev.T_size, b1, s1, y, pl.col_total, true, 11));
+      FP_TRY(run_gemm_mixed(ctx, ps, sl.bwd[0], dev.R, dev.R_size, x, false, pl.row_total, b2, f,
+                            s2, true, 15));
+      FP_TRY(run_rt(ctx, ps, sl.bwd[1], b2, s2, b1, s1, f, true, 14));
+      FP_TRY(run_rt(ctx, ps, sl.bwd[2], b1, s1, b2, s2, f, true, 13));
+      FP_TRY(run_rt(ctx, ps, sl.bwd[3], b2, s2, b1, s1, f, true, 12));
+      FP_TRY(run_gemm_mixed(ctx, ps, sl.bwd[4], dev.T, dev.T_size, b1, f, s1, y, false,
+                            pl.col_total, true, 11));
     }
   }
   return Status::ok();

@@ -66,14 +66,17 @@ class SiteOp {
     std::vector<Slice> slices;
     std::vector<int64_t> col_off, row_off;   // per sector offsets for width k
     int64_t col_total = 0, row_total = 0;
-    int64_t ws1 = 0, ws2 = 0;
+    int64_t ws1 = 0, ws2 = 0;   // elements of the two ping-pong intermediates
     double flops_fwd = 0, flops_bwd = 0;
+    bool f32 = false;           // intermediates stored in FP32 (arithmetic stays FP64)
   };
   Status plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t budget, Plans& out,
-              bool with_bwd = true);
+              bool with_bwd = true, bool f32 = false);
   // y = M x (transpose = false) or M^T x, per-sector matrices at the offsets
-  // of ``pl`` (x: col layout for M, row layout for M^T).
-  Status apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const double* x, double* y);
+  // of ``pl`` (x: col layout for M, row layout for M^T). ``f32`` stores the
+  // chain intermediates of this application in FP32 (arithmetic stays FP64).
+  Status apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const double* x, double* y,
+               bool f32);
 
  private:
   BT omega_layout(const std::vector<SliceCol>& cols, const std::vector<int32_t>& k,

@@ -1,0 +1,165 @@
+"""Mixed precision (FPEPS_FP32) against the FP64 oracle (needs a GPU).
+
+In this mode the chain intermediates are stored in FP32 while every product
+accumulates in FP64 and the factorisations stay FP64. The target bound for
+the network value is 1e-6 relative to the FP64 result; the chain itself is
+checked norm-wise per sector (elements near zero carry the FP32 rounding of
+their larger neighbours). Each case also checks that the error is above the
+FP64 level, i.e. that the FP32 storage is really in use.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from workloads.tensor import Leg
+
+pytestmark = pytest.mark.gpu
+
+MIXED_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_01039_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def dev(t):
+    from paper_2511_01039_amd import DeviceTensor
+    return DeviceTensor.from_host(t)
+
+
+def devs(ts):
+    return [dev(t) for t in ts]
+
+
+def normwise(a, b):
+    a, b = np.asarray(a, dtype=float), np.asarray(b, dtype=float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+CASES = [
+    ("none", dict(kind="none", L=3, d=2, D=3, w=2, chi=9)),
+    ("u1u1", dict(kind="u1u1", L=3, env_scale=3, virt_scale=2)),
+    ("su2", dict(kind="su2", L=3, env_scale=4, virt_scale=2)),
+]
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
+def test_site_chain_mixed_matches_oracle(ctx, name, kw):
+    """a3 in mixed precision: M_x X and M_x^T Y per sector within 1e-6
+    (norm-wise) of the FP64 oracle."""
+    import torch
+    from oracle.blocks import BT
+    from oracle.chain import SiteOperator
+    from oracle.zipup import SiteProblem
+    from paper_2511_01039_amd import opts_for
+    row = wl.small_row(seed=5, **kw)
+    rng = np.random.default_rng(11)
+    x = 1
+    T, A, W = row.T[x], row.A[x], row.W[x]
+    cat = row.meta["cat"]["env"]
+    legs = [cat, T.legs[0].flipped(), A.legs[1].flipped(), W.legs[2].flipped(), A.legs[1]]
+    legs = [Leg(l.labels, l.dims, d) for l, d in zip(legs, (1, -1, -1, -1, 1))]
+    Rt = wl.random_tensor(row.sym, legs, rng)
+    names = ["c", "a", "lk", "lw", "lb"]
+    sp = SiteProblem(SiteOperator(row.sym, BT(names, dict(zip(names, Rt.legs)), Rt.to_dict()),
+                                  T, A, W))
+    opts = opts_for(row.sym, precision="fp32")
+    widths = [1, 5, 37]
+    k = [widths[i % 3] for i in range(len(sp.sect))]
+    errs = []
+    for transpose in (False, True):
+        rows_in = sp.m if transpose else sp.n
+        rows_out = sp.n if transpose else sp.m
+        Xs = [rng.standard_normal((r, kk)) for r, kk in zip(rows_in, k)]
+        want = sp.apply_mt(Xs) if transpose else sp.apply_m(Xs)
+        xin = torch.from_numpy(np.concatenate([a.ravel() for a in Xs])).cuda()
+        tot = sum(r * kk for r, kk in zip(rows_out, k))
+        y, _ = ctx.site_apply(dev(Rt), dev(T), dev(A), dev(W), opts, k, xin,
+                              transpose=transpose, out_elems=tot)
+        y = y[:tot].cpu().numpy()
+        p = 0
+        for r, kk, w in zip(rows_out, k, want):
+            g = y[p:p + r * kk].reshape(r, kk)
+            p += r * kk
+            if w.size:
+                errs.append(normwise(g, w))
+    err = max(errs)
+    print(f"{name}: mixed chain norm-wise rel err {err:.2e}")
+    assert err < MIXED_TOL
+    assert err > 1e-13   # FP32 storage in use
+
+
+ROWS = [
+    ("none", dict(kind="none", L=4, d=2, D=3, w=2, chi=9), 12),
+    ("u1u1", dict(kind="u1u1", L=4, env_scale=2, virt_scale=2), 14),
+    ("su2", dict(kind="su2", L=4, env_scale=3, virt_scale=2), 10),
+]
+
+
+@pytest.mark.parametrize("name,kw,chi", ROWS, ids=[r[0] for r in ROWS])
+def test_absorb_row_mixed_matches_oracle(ctx, name, kw, chi):
+    """a1-a8 in mixed precision: one row absorbed with rSVD truncation. The
+    network value against a fixed random bottom environment and the
+    log-norm within 1e-6 of the FP64 oracle; singular values norm-wise
+    within 1e-6 per site."""
+    from oracle.zipup import absorb_row
+    from oracle.expect import overlap
+    from paper_2511_01039_amd import opts_for
+    row = wl.small_row(seed=3, oversample=4, power_iters=1, **kw)
+    env, lg, info = absorb_row(row.sym, row.T, row.A, row.W, chi, 4, 1, 17, row=row.row)
+    out, glg, rep = ctx.env_absorb(devs(row.T), devs(row.A), devs(row.W),
+                                   opts_for(row.sym, chi=chi, oversample=4, power_iters=1, seed=17,
+                                            row=row.row, precision="fp32"))
+    for x in range(len(env) - 1):
+        sig, sec, kept = ctx.absorb_diag(x)
+        want = np.concatenate([np.asarray(s) for s in info["sigma"][x]])
+        assert normwise(sig, want) < MIXED_TOL
+    bot = wl.random_bottom_env(row.sym, env, row.meta["cat"]["env"], np.random.default_rng(5))
+    v_or = overlap(env, bot) * math.exp(lg)
+    v_gpu = ctx.expect(out, devs(bot)) * math.exp(glg)
+    rel = abs(v_gpu - v_or) / abs(v_or)
+    print(f"{name}: mixed s_row oracle {v_or:.15e} gpu {v_gpu:.15e} rel {rel:.2e} "
+          f"log_norm diff {abs(glg - lg):.2e} gap {rep['min_rel_gap']:.2e}")
+    assert abs(glg - lg) < MIXED_TOL * max(1.0, abs(lg))
+    assert rel < MIXED_TOL
+    assert rel > 1e-15   # FP32 storage in use
+
+
+def test_config1_network_value_mixed(ctx):
+    """Config 1 (4x4, chi = 32, p = 8, q = 1): <W> = Z_W / Z_1 in mixed
+    precision within 1e-6 of the FP64 oracle."""
+    from oracle.expect import network_value, ratio, closing_env
+    from paper_2511_01039_amd import opts_for
+    lat = wl.config1_lattice()
+    prm = wl.config1_params()
+    ident = wl.identity_pepo(lat.sym, 4, 4, lat.A[0][0].legs[0])
+
+    def gpu_value(W):
+        env = devs(wl.trivial_env(lat.sym, 4))
+        lg = 0.0
+        for y in range(4):
+            env, lg, _ = ctx.env_absorb(env, devs(lat.A[y]), devs(W[y]),
+                                        opts_for(lat.sym, chi=prm["chi"], oversample=prm["oversample"],
+                                                 power_iters=prm["power_iters"], seed=prm["seed"],
+                                                 row=y, precision="fp32"),
+                                        log_norm=lg)
+        v = ctx.expect(env, devs(closing_env([t.to_host() for t in env])))
+        return (1 if v > 0 else -1), lg + math.log(abs(v))
+
+    got = ratio(gpu_value(lat.W), gpu_value(ident))
+    want = ratio(network_value(lat.sym, lat.A, lat.W, prm["chi"], prm["oversample"],
+                               prm["power_iters"], prm["seed"]),
+                 network_value(lat.sym, lat.A, ident, prm["chi"], prm["oversample"],
+                               prm["power_iters"], prm["seed"]))
+    rel = abs(got - want) / abs(want)
+    print(f"config1 mixed <W>: oracle {want:.15e} gpu {got:.15e} rel {rel:.2e}")
+    assert rel < MIXED_TOL

@@ -265,3 +265,49 @@ def test_config1_network_value(ctx):
     got, want = ratio(gw, g1), ratio(ow, o1)
     print(f"config1 <W>: oracle {want:.15e} gpu {got:.15e} rel {abs(got - want) / abs(want):.2e}")
     assert abs(got - want) < 1e-11 * abs(want)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_config4_site_chain_full_size(ctx, precision, tol):
+    """a3 at the full size of the headline workload: the interior site x = 1 of
+    the 8x8 SU(2)-synthetic chi = 500 row (12 sectors, 432000 x 155348), with
+    a random remainder of the row's structure and one or two sketch columns
+    per sector (so that the oracle finishes in seconds). M_x X and M_x^T Y
+    against the oracle, element by element in FP64 and norm-wise per sector
+    in mixed precision."""
+    import torch
+    from oracle.blocks import BT
+    from oracle.chain import SiteOperator
+    from oracle.zipup import SiteProblem
+    from paper_2511_01039_amd import opts_for
+    row = wl.config4_row()
+    rng = np.random.default_rng(21)
+    x = 1
+    T, A, W = row.T[x], row.A[x], row.W[x]
+    Rt = remainder_tensor(row.sym, row, x, wl.legs_su2(500)["env"], rng)
+    names = ["c", "a", "lk", "lw", "lb"]
+    sp = SiteProblem(SiteOperator(row.sym, BT(names, dict(zip(names, Rt.legs)), Rt.to_dict()),
+                                  T, A, W))
+    assert len(sp.sect) == 12 and sum(sp.m) == 432000 and sum(sp.n) == 155348
+    opts = opts_for(row.sym, precision=precision)
+    k = [1 + (i % 2) for i in range(len(sp.sect))]
+    for transpose in (False, True):
+        rows_in = sp.m if transpose else sp.n
+        rows_out = sp.n if transpose else sp.m
+        Xs = [rng.standard_normal((r, kk)) for r, kk in zip(rows_in, k)]
+        want = sp.apply_mt(Xs) if transpose else sp.apply_m(Xs)
+        xin = torch.from_numpy(np.concatenate([a.ravel() for a in Xs])).cuda()
+        tot = sum(r * kk for r, kk in zip(rows_out, k))
+        y, _ = ctx.site_apply(dev(Rt), dev(T), dev(A), dev(W), opts, k, xin,
+                              transpose=transpose, out_elems=tot)
+        y = y[:tot].cpu().numpy()
+        p, errs = 0, []
+        for r, kk, w in zip(rows_out, k, want):
+            g = y[p:p + r * kk].reshape(r, kk)
+            p += r * kk
+            if w.size:
+                errs.append(rel_err(g, w) if precision == "fp64" else
+                            float(np.linalg.norm(g - w) / np.linalg.norm(w)))
+        print(f"config4 site chain {precision} {'bwd' if transpose else 'fwd'}: "
+              f"max rel err {max(errs):.2e}")
+        assert max(errs) < tol
