@@ -267,28 +267,41 @@ def test_config1_network_value(ctx):
     assert abs(got - want) < 1e-11 * abs(want)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
-def test_config4_site_chain_full_size(ctx, precision, tol):
-    """a3 at the full size of the headline workload: the interior site x = 1 of
-    the 8x8 SU(2)-synthetic chi = 500 row (12 sectors, 432000 x 155348), with
-    a random remainder of the row's structure and one or two sketch columns
-    per sector (so that the oracle finishes in seconds). M_x X and M_x^T Y
-    against the oracle, element by element in FP64 and norm-wise per sector
-    in mixed precision."""
+FULL = [
+    # (config, precision, tolerance): FP64 element by element, mixed norm-wise
+    (4, "fp64", 1e-12), (4, "fp32", 1e-6),
+    (2, "fp64", 1e-12), (2, "fp32", 1e-6),
+]
+
+
+@pytest.mark.parametrize("cfg,precision,tol", FULL,
+                         ids=[f"config{c}-{p}" for c, p, _ in FULL])
+def test_site_chain_full_size(ctx, cfg, precision, tol):
+    """a3 at the full size of the benchmark workloads: the interior site x = 1
+    of the 8x8 SU(2)-synthetic chi = 500 row (config 4: 12 sectors,
+    432000 x 155348) and of the dense Hubbard-comb chi = 128 row (config 2),
+    with a random remainder of the row's structure and one or two sketch
+    columns per sector (so that the oracle finishes in seconds). M_x X and
+    M_x^T Y against the oracle, element by element in FP64 and norm-wise per
+    sector in mixed precision."""
     import torch
     from oracle.blocks import BT
     from oracle.chain import SiteOperator
     from oracle.zipup import SiteProblem
     from paper_2511_01039_amd import opts_for
-    row = wl.config4_row()
+    if cfg == 4:
+        row, env = wl.config4_row(), wl.legs_su2(500)["env"]
+    else:
+        row, env = wl.config2_row(), wl.legs_dense(4, 6, 6, 128)["env"]
     rng = np.random.default_rng(21)
     x = 1
     T, A, W = row.T[x], row.A[x], row.W[x]
-    Rt = remainder_tensor(row.sym, row, x, wl.legs_su2(500)["env"], rng)
+    Rt = remainder_tensor(row.sym, row, x, env, rng)
     names = ["c", "a", "lk", "lw", "lb"]
     sp = SiteProblem(SiteOperator(row.sym, BT(names, dict(zip(names, Rt.legs)), Rt.to_dict()),
                                   T, A, W))
-    assert len(sp.sect) == 12 and sum(sp.m) == 432000 and sum(sp.n) == 155348
+    if cfg == 4:
+        assert len(sp.sect) == 12 and sum(sp.m) == 432000 and sum(sp.n) == 155348
     opts = opts_for(row.sym, precision=precision)
     k = [1 + (i % 2) for i in range(len(sp.sect))]
     for transpose in (False, True):
@@ -308,6 +321,6 @@ def test_config4_site_chain_full_size(ctx, precision, tol):
             if w.size:
                 errs.append(rel_err(g, w) if precision == "fp64" else
                             float(np.linalg.norm(g - w) / np.linalg.norm(w)))
-        print(f"config4 site chain {precision} {'bwd' if transpose else 'fwd'}: "
-              f"max rel err {max(errs):.2e}")
+        print(f"config{cfg} site chain {precision} {'bwd' if transpose else 'fwd'}: "
+              f"sectors {len(sp.sect)} m {sum(sp.m)} n {sum(sp.n)} max rel err {max(errs):.2e}")
         assert max(errs) < tol
