@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ 
                                                   TC* __restrict__ C,
                                                   const GemmJob* __restrict__ jobs,
                                                   const GemmPair* __restrict__ pairs,
-                                                  const int32_t* __restrict__ tab) {
+                                                  const int32_t* __restrict__ tab, int swz) {
   constexpr int KT = 16;
   constexpr int WTM = MT / WM, WTN = NT / WN;
   constexpr int FM = WTM / 16, FN = WTN / 16;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ 
   __shared__ double sA[2][KT][MT + 1];
   __shared__ double sB[2][KT][NT + 1];
 
-  const GemmJob job = jobs[blockIdx.x];
+  const GemmJob job = jobs[xcd_swizzle((int)blockIdx.x, (int)gridDim.x, swz)];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -218,6 +218,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ 
       }
 }
 
+// Runs of 4 consecutive jobs per XCD: larger runs (or one contiguous range
+// per XCD) leave long-K split blocks on a few XCDs and unbalance the launch.
+constexpr int GEMM_XCD_RUN = 4;
+
 template <class TB, class TC>
 static hipError_t launch_typed(const DevGemm& g, const double* A, const TB* B, TC* C,
                                const int32_t* tables, hipStream_t s) {
@@ -225,7 +229,7 @@ static hipError_t launch_typed(const DevGemm& g, const double* A, const TB* B, T
 #define FP_GEMM_TILE(mt_, nt_, wm_, wn_)                                                 \
   if (g.mt == mt_ && g.nt == nt_) {                                                      \
     k_gemm_f64<mt_, nt_, wm_, wn_, TB, TC>                                               \
-        <<<grid, block, 0, s>>>(A, B, C, g.jobs, g.pairs, tables);                       \
+        <<<grid, block, 0, s>>>(A, B, C, g.jobs, g.pairs, tables, GEMM_XCD_RUN); \
     return hipGetLastError();                                                            \
   }
   FP_GEMM_TILE(128, 128, 2, 2)

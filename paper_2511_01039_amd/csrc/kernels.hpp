@@ -9,6 +9,24 @@
 
 namespace fp {
 
+// Workgroups of a launch are dispatched round-robin over the 8 XCDs, each
+// with its own L2. Block b runs job xcd_swizzle(b, n, c): runs of c
+// consecutive jobs (which share operand panels) go to one XCD, and the runs
+// are dealt round-robin over the XCDs (c = 0: one contiguous range per XCD).
+// Bijective on [0, n): the first whole rounds are permuted, the tail is
+// unchanged.
+__device__ __forceinline__ int xcd_swizzle(int b, int n, int c) {
+  if (c <= 0) {
+    const int per = n >> 3;
+    if (b >= (per << 3)) return b;
+    return (b & 7) * per + (b >> 3);
+  }
+  const int round = 8 * c;
+  if (b >= (n / round) * round) return b;
+  const int slot = b >> 3;   // position of b in its XCD's sequence
+  return (slot / c) * round + (b & 7) * c + (slot % c);
+}
+
 // A GEMM plan resident on the device.
 struct DevGemm {
   const GemmJob* jobs = nullptr;

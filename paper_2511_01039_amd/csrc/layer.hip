@@ -219,7 +219,7 @@ __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
     const RtGroup* __restrict__ groups_, const int32_t* __restrict__ tile_group,
     const RtOut* __restrict__ outs_,
     const RtKblk* __restrict__ kblks_, const RtCol* __restrict__ cols_,
-    const RtPair* __restrict__ pairs_, const int32_t* __restrict__ tab_, int tile_base) {
+    const RtPair* __restrict__ pairs_, const int32_t* __restrict__ tab_, int tile_base, int swz) {
   extern __shared__ double lds_raw[];
   T* lds = (T*)lds_raw;
   const FP_CONST RtGroup* groups = as_const(groups_);
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
   const FP_CONST RtPair* pairs = as_const(pairs_);
   const FP_CONST int32_t* tab = as_const(tab_);
   const FP_CONST double* PK = as_const(PK_);
-  const int wg = tile_base + (int)blockIdx.x;
+  const int wg = tile_base + xcd_swizzle((int)blockIdx.x, (int)gridDim.x, swz);
   const RtGroup G = ld(groups + as_const(tile_group)[wg]);
   const int rows = G.rows;                    // 64, 128 or 256
   const int m0 = (wg - G.tile0) * rows;
@@ -299,6 +299,10 @@ __global__ void k_rt_pack(const RtPack* __restrict__ packs, const double* __rest
   }
 }
 
+// One contiguous range of tiles per XCD: neighbouring tiles of a row group
+// share its plan data and packed layer blocks in that XCD's L2.
+constexpr int LAYER_XCD_RUN = 0;
+
 hipError_t launch_rt_f64(const DevRt& r, int c, const void* X, bool f32, const double* PK,
                          void* Y, const int32_t* tab, hipStream_t s) {
   if (c < 0 || c >= r.nlaunch || r.ngroups <= 0) return hipErrorInvalidValue;
@@ -307,11 +311,11 @@ hipError_t launch_rt_f64(const DevRt& r, int c, const void* X, bool f32, const d
   if (f32)
     k_rt_f64<float><<<dim3(r.l_ntiles[c]), dim3(RT_THREADS), (size_t)r.l_lds[c] / 2, s>>>(
         (const float*)X, PK, (float*)Y, r.groups, r.tile_group, r.outs, r.kblks, r.cols, r.pairs,
-        tab, r.l_tile0[c]);
+        tab, r.l_tile0[c], LAYER_XCD_RUN);
   else
     k_rt_f64<double><<<dim3(r.l_ntiles[c]), dim3(RT_THREADS), (size_t)r.l_lds[c], s>>>(
         (const double*)X, PK, (double*)Y, r.groups, r.tile_group, r.outs, r.kblks, r.cols,
-        r.pairs, tab, r.l_tile0[c]);
+        r.pairs, tab, r.l_tile0[c], LAYER_XCD_RUN);
   return hipGetLastError();
 }
 
