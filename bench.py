@@ -48,6 +48,84 @@ def workload(cfg):
     return row, desc, bond
 
 
+def bench_config5(a):
+    """Batched bond expansion over one row of config 3: for each interior site
+    of the U(1)xU(1) chi = 256 row, the per-sector shapes of its site operator
+    (from the library) are filled with seeded explicit matrices of decaying
+    spectrum; a step is, for every site, one rSVD truncation of all its
+    sectors (chi = 256, p = 8, q = 1, one cut over the sectors) and one
+    controlled bond expansion by ceil(0.1 chi) = 26 directions orthogonal to
+    the kept left and right spaces (q = 0)."""
+    import torch
+    import numpy as np
+    import workloads as wl
+    from workloads.tensor import Leg
+    from paper_2511_01039_amd import Context, DeviceTensor, opts_for, make_opts
+    cfg = wl.CONFIG5
+    row = wl.config3_row()
+    env = wl.legs_u1u1(256)["env"]
+    ctx = Context(0)
+    rng = np.random.default_rng(0)
+    dev = DeviceTensor.from_host
+    sites = []
+    for x in range(1, len(row.T) - 1):
+        T, A, W = row.T[x], row.A[x], row.W[x]
+        legs = [env, T.legs[0].flipped(), A.legs[1].flipped(), W.legs[2].flipped(), A.legs[1]]
+        legs = [Leg(l.labels, l.dims, d) for l, d in zip(legs, (1, -1, -1, -1, 1))]
+        Rt = wl.random_tensor(row.sym, legs, rng)
+        _, m, n = ctx.site_shape(dev(Rt), dev(T), dev(A), dev(W), opts_for(row.sym))
+        g = torch.Generator(device="cuda").manual_seed(1000 + x)
+        mats = []
+        for mi, ni in zip(m, n):
+            r = int(min(mi, ni))
+            s = torch.exp(-torch.arange(r, device="cuda", dtype=torch.float64) / cfg["decay"])
+            Am = torch.randn(int(mi), r, generator=g, device="cuda", dtype=torch.float64) / math.sqrt(mi)
+            Bm = torch.randn(r, int(ni), generator=g, device="cuda", dtype=torch.float64) / math.sqrt(ni)
+            mats.append(((Am * s) @ Bm).contiguous())
+        sites.append(mats)
+    ropts = make_opts(chi=cfg["chi"], oversample=cfg["oversample"], power_iters=cfg["power_iters"],
+                      seed=0, tag=0)
+    copts = make_opts(cbe_extra=cfg["cbe_extra"], oversample=cfg["cbe_oversample"], seed=0, tag=1)
+
+    def step():
+        flops = 0.0
+        for mats in sites:
+            U, R, sig, kept, rep = ctx.rsvd_truncate(mats, ropts)
+            flops += rep["alg_flops"]
+            # kept right space V (rows orthonormal): R = S V^T
+            Us, Vs = [], []
+            for u, rr, sg, k in zip(U, R, sig, kept):
+                sg_t = torch.as_tensor(np.asarray(sg[:k]), device="cuda", dtype=torch.float64)
+                Us.append(u)
+                Vs.append((rr / sg_t[:, None]).contiguous() if k > 0 else rr)
+            Q, csig, ckept, crep = ctx.cbe_expand(mats, Us, Vs, copts)
+            flops += crep["alg_flops"]
+        return flops
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    flops = 0.0
+    for _ in range(a.steps):
+        flops += step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / a.steps
+    nmat = sum(len(s) for s in sites)
+    sides = [int(min(t.shape)) for s in sites for t in s]
+    line = {"metric": "batched rSVD truncation + bond expansion of one row, per-row latency",
+            "value": 1e3 * sec, "unit": "ms", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": 1e3 * sec, "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "config 5: bond expansion over the interior sites of the 8x8 "
+                                   "U(1)xU(1) chi=256 row; per site all sector matrices "
+                                   f"({nmat} matrices, sides {min(sides)}-{max(sides)}), "
+                                   "rSVD chi=256 p=8 q=1 then CBE 26 directions p=8 q=0",
+                       "alg_flops_per_step": flops / a.steps,
+                       "tflops": flops / a.steps / sec / 1e12}}
+    print(json.dumps(line), flush=True)
+
+
 def profiled_traffic(kernel, precision="fp64"):
     """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE runs, calibrated against a plain
@@ -145,9 +223,12 @@ def main():
         print(json.dumps({"calibrate_copy": {"bytes_read_per_copy": 8 * n,
                                              "bytes_written_per_copy": 8 * n, "copies": 4}}))
         return
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.config == 5:
+        bench_config5(a)
+        return
     from paper_2511_01039_amd import Context, DeviceTensor, opts_for
     from paper_2511_01039_amd.binding import FLAG_TIME_KERNELS
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     import numpy as np
     import workloads as wl
     row, desc, bond = workload(a.config)

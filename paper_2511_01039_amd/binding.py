@@ -68,6 +68,14 @@ class CReport(C.Structure):
 _lib = None
 
 
+def _check_dense(ts):
+    """The library reads matrices as contiguous row-major float64 on the GPU."""
+    import torch
+    for t in ts:
+        if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+            raise FpepsError(-1, "expected contiguous float64 CUDA tensors")
+
+
 def load():
     """Load libfpeps.so (raises if it is missing: there is no other path)."""
     global _lib
@@ -292,6 +300,7 @@ class Context:
     def site_apply(self, R, T, A, W, opts, k, x, transpose=False, out_elems=None):
         """x: torch float64 device tensor (per-sector matrices); returns y."""
         import torch
+        _check_dense([x])
         keep = []
         kk = _i32(k)
         cts = [t.ctensor(keep) for t in (R, T, A, W)]
@@ -306,6 +315,7 @@ class Context:
     def rsvd_truncate(self, mats, opts):
         """mats: list of 2-D torch float64 device tensors. Returns U, R, sigma, kept, report."""
         import torch
+        _check_dense(mats)
         nm = len(mats)
         m = np.array([a.shape[0] for a in mats], np.int64)
         n = np.array([a.shape[1] for a in mats], np.int64)
@@ -332,13 +342,18 @@ class Context:
 
     def cbe_expand(self, mats, U, V, opts):
         import torch
+        _check_dense(mats)
         nm = len(mats)
         m = np.array([a.shape[0] for a in mats], np.int64)
         n = np.array([a.shape[1] for a in mats], np.int64)
         r = np.array([u.shape[1] for u in U], np.int32)
         A = (C.c_void_p * nm)(*[a.data_ptr() for a in mats])
-        Up = (C.c_void_p * nm)(*[u.contiguous().data_ptr() for u in U])
-        Vp = (C.c_void_p * nm)(*[v.contiguous().data_ptr() for v in V])
+        # contiguous copies held until the call returns (a temporary's
+        # data_ptr would dangle)
+        Uc = [u.contiguous() for u in U]
+        Vc = [v.contiguous() for v in V]
+        Up = (C.c_void_p * nm)(*[u.data_ptr() for u in Uc])
+        Vp = (C.c_void_p * nm)(*[v.data_ptr() for v in Vc])
         Q = [torch.empty(max(int(mi * min(mi, ni)), 1), dtype=torch.float64, device=mats[0].device)
              for mi, ni in zip(m, n)]
         Qp = (C.c_void_p * nm)(*[q.data_ptr() for q in Q])

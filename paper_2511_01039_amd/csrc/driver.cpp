@@ -1137,6 +1137,21 @@ Status explicit_rsvd(fpeps_ctx_s* ctx, int nmat, const int64_t* m, const int64_t
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
   if (rep) {
+    // algorithmic flops, counted as for a site of the absorption: (2 + 2q)
+    // dense products (plus the projector splits of the expansion),
+    // orthonormalisation, core factorisation and the output factors
+    const int qq = cbe ? 0 : o->power_iters;
+    double fl = 0;
+    for (int i = 0; i < nmat; ++i) {
+      const double mi = (double)e.m[i], ni = (double)e.n[i], k = rs.k[i], c = rs.kept[i];
+      if (k <= 0) continue;
+      fl += (2 + 2 * qq) * 2.0 * mi * ni * k;
+      if (cbe) fl += (2 + 2 * qq) * 4.0 * (rr ? rr[i] : 0) * k * (mi + ni);
+      fl += (qq + 1) * (2 * mi * k * k - 2 * k * k * k / 3.0) + qq * (2 * ni * k * k - 2 * k * k * k / 3.0);
+      fl += 2 * ni * k * k + 12 * k * k * k;
+      fl += 2 * mi * k * c + (cbe ? 0.0 : 2 * k * c * ni);
+    }
+    rep->alg_flops = fl;
     rep->seconds = ms * 1e-3;
     rep->fallbacks = rs.fallbacks;
     int tot = 0;

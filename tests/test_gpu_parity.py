@@ -324,3 +324,61 @@ def test_site_chain_full_size(ctx, cfg, precision, tol):
         print(f"config{cfg} site chain {precision} {'bwd' if transpose else 'fwd'}: "
               f"sectors {len(sp.sect)} m {sum(sp.m)} n {sum(sp.n)} max rel err {max(errs):.2e}")
         assert max(errs) < tol
+
+
+def test_config5_bond_expansion_site_matches_oracle(ctx):
+    """a7 at the sizes of the bond-expansion workload (config 5): the largest
+    sector matrices of interior site 1 of the U(1)xU(1) chi = 256 row (shapes
+    from the site operator), seeded explicit matrices of decaying spectrum;
+    one rSVD truncation over the sectors (chi = 256, p = 8, q = 1) and one
+    bond expansion by 26 directions (p = 8, q = 0) against the oracle: kept
+    counts, singular values, projectors; Q orthogonal to U and orthonormal."""
+    import torch
+    from oracle.blocks import BT
+    from oracle.chain import SiteOperator
+    from oracle.zipup import SiteProblem
+    from oracle.rsvd import rsvd_explicit
+    from oracle.cbe import cbe_explicit
+    from paper_2511_01039_amd import make_opts
+    cfg = wl.CONFIG5
+    row = wl.config3_row()
+    rng = np.random.default_rng(3)
+    x = 1
+    Rt = remainder_tensor(row.sym, row, x, wl.legs_u1u1(256)["env"], rng)
+    names = ["c", "a", "lk", "lw", "lb"]
+    sp = SiteOperator(row.sym, BT(names, dict(zip(names, Rt.legs)), Rt.to_dict()),
+                      row.T[x], row.A[x], row.W[x])
+    prob = SiteProblem(sp)
+    shapes = sorted(zip(prob.m, prob.n), key=lambda t: -min(t))[:6]
+    assert min(shapes[0]) >= 500
+    mats = [wl.decaying_matrix(m, n, rng, cfg["decay"]) for m, n in shapes]
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    want = rsvd_explicit(mats, chi=cfg["chi"], p=cfg["oversample"], q=cfg["power_iters"],
+                         seed=0, tag=0)
+    U, R, sig, kept, _ = ctx.rsvd_truncate([t(a) for a in mats],
+                                           make_opts(chi=cfg["chi"], oversample=cfg["oversample"],
+                                                     power_iters=cfg["power_iters"], seed=0, tag=0))
+    assert list(kept) == list(want["kept"])
+    Uh, Vh = [], []
+    for i in range(len(mats)):
+        u = U[i].cpu().numpy()
+        assert rel_err(sig[i], want["sigma"][i]) < 1e-11
+        assert np.abs(u @ u.T - want["U"][i] @ want["U"][i].T).max() < 1e-10
+        Uh.append(want["U"][i])
+        Vh.append(want["R"][i] / np.asarray(want["sigma"][i])[:, None])
+    cw = cbe_explicit(mats, Uh, Vh, chi_extra=cfg["cbe_extra"], p=cfg["cbe_oversample"], seed=0,
+                      tag=1)
+    Q, csig, ckept, _ = ctx.cbe_expand([t(a) for a in mats], [t(u) for u in Uh],
+                                       [t(v) for v in Vh],
+                                       make_opts(cbe_extra=cfg["cbe_extra"],
+                                                 oversample=cfg["cbe_oversample"], seed=0, tag=1))
+    assert list(ckept) == list(cw["kept"])
+    for i in range(len(mats)):
+        if ckept[i] == 0:
+            continue
+        q = Q[i].cpu().numpy()
+        assert np.abs(q.T @ Uh[i]).max() < 1e-12
+        assert np.abs(q.T @ q - np.eye(q.shape[1])).max() < 1e-12
+        assert np.abs(q @ q.T - cw["Q"][i] @ cw["Q"][i].T).max() < 1e-10
+        assert rel_err(csig[i], cw["sigma"][i]) < 1e-11
+    print(f"config5 site: shapes {shapes} kept {list(kept)} cbe kept {list(ckept)}")

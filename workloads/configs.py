@@ -462,3 +462,18 @@ def random_bottom_env(sym, top_env, bond_leg, rng):
                [Leg(b.labels, b.dims, 1)]
         out.append(random_tensor(sym, legs, rng))
     return out
+
+
+def decaying_matrix(m, n, rng, decay=32.0):
+    """An m x n matrix A diag(s) B with Gaussian A (m x r), B (r x n),
+    r = min(m, n) and s_i = exp(-i / decay): a decaying spectrum of the kind
+    a truncation acts on (stand-in for the explicit per-sector matrices of a
+    bond-expansion step)."""
+    r = min(m, n)
+    s = np.exp(-np.arange(r) / decay)
+    A = rng.standard_normal((m, r)) / math.sqrt(m)
+    B = rng.standard_normal((r, n)) / math.sqrt(n)
+    return (A * s) @ B
+
+
+CONFIG5 = dict(chi=256, oversample=8, power_iters=1, cbe_extra=26, cbe_oversample=8, decay=32.0)
