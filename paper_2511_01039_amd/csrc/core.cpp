@@ -5,10 +5,18 @@
 #include <cstring>
 
 fpeps_ctx_s::~fpeps_ctx_s() {
-  if (!bufs.empty() || !evpool.empty()) (void)hipDeviceSynchronize();
+  if (!bufs.empty() || !evpool.empty() || stage) (void)hipDeviceSynchronize();
   for (auto e : evpool) (void)hipEventDestroy(e);
   for (auto& kv : bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
+  if (stage) (void)hipHostFree(stage);
+}
+
+fp::Status fpeps_ctx_s::stage_begin() {
+  FP_HIP(hipStreamSynchronize(stream));
+  stage_used = 0;
+  stage_async = true;
+  return fp::Status::ok();
 }
 
 fp::Status fpeps_ctx_s::buf(const std::string& name, size_t bytes, void** out) {
@@ -37,6 +45,29 @@ fp::Status fpeps_ctx_s::buf(const std::string& name, size_t bytes, void** out) {
 fp::Status fpeps_ctx_s::upload(const std::string& name, const void* host, size_t bytes,
                                void** dev) {
   FP_TRY(buf(name, bytes, dev));
+  if (stage_async && bytes) {
+    const size_t need = (bytes + 255) / 256 * 256;
+    if (stage_used + need > stage_cap) {
+      // every copy issued from the arena so far must finish before it is
+      // replaced
+      FP_HIP(hipStreamSynchronize(stream));
+      const size_t cap = std::max({2 * stage_cap, need, (size_t)64 << 20});
+      if (stage) FP_HIP(hipHostFree(stage));
+      stage = nullptr;
+      stage_cap = 0;
+      if (hipHostMalloc((void**)&stage, cap, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        stage = nullptr;
+        return fp::fail(FPEPS_ERR_NOMEM, "pinned staging allocation failed");
+      }
+      stage_cap = cap;
+      stage_used = 0;
+    }
+    std::memcpy(stage + stage_used, host, bytes);
+    FP_HIP(hipMemcpyAsync(*dev, stage + stage_used, bytes, hipMemcpyHostToDevice, stream));
+    stage_used += need;
+    return fp::Status::ok();
+  }
   if (bytes) {
     // the previous contents may still be read by queued kernels
     FP_HIP(hipStreamSynchronize(stream));

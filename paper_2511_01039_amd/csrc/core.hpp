@@ -77,6 +77,14 @@ struct fpeps_ctx_s {
   double kt_seconds = 0, kt_flops = 0;
   long kt_launches = 0;
   bool verbose = false;
+  // pinned staging arena for plan uploads (asynchronous host-to-device
+  // copies between stage_begin and stage_end; stage_begin waits for the
+  // stream, so the arena is never overwritten while a copy reads it)
+  char* stage = nullptr;
+  size_t stage_cap = 0, stage_used = 0;
+  bool stage_async = false;
+  fp::Status stage_begin();
+  void stage_end() { stage_async = false; }
 
   ~fpeps_ctx_s();
   // device buffer ``name`` of at least ``bytes`` (grown, contents lost on growth)

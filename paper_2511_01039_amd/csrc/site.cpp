@@ -331,12 +331,17 @@ Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t bud
   out.slices.resize(slices.size());
   for (size_t i = 0; i < slices.size(); ++i) out.slices[i].cols = slices[i];
   // slices are independent: plan them on host threads
-  std::vector<Status> st(slices.size());
+  // tasks: the forward and the transposed chain of every slice
+  const size_t ntask = slices.size() * (with_bwd ? 2 : 1);
+  std::vector<Status> st(ntask);
+  for (auto& sl : out.slices)
+    for (int s = 0; s < 5; ++s) sl.bwd[s] = -1;
   {
     const unsigned hc = std::max(1u, std::thread::hardware_concurrency());
-    const size_t nt = std::min<size_t>(slices.size(), std::min(16u, hc));
+    const size_t nt = std::min<size_t>(ntask, std::min(16u, hc));
     auto work = [&](size_t t) {
-      for (size_t i = t; i < slices.size(); i += nt) st[i] = plan_slice(k, out, out.slices[i], with_bwd);
+      for (size_t i = t; i < ntask; i += nt)
+        st[i] = plan_slice(k, out, out.slices[i % slices.size()], i >= slices.size());
     };
     std::vector<std::thread> th;
     for (size_t t = 1; t < nt; ++t) th.emplace_back(work, t);
@@ -344,13 +349,16 @@ Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t bud
     for (auto& x : th) x.join();
   }
   for (auto& e : st) FP_TRY(e);
+  // uploads through the pinned arena, asynchronous on the stream
+  FP_TRY(ctx->stage_begin());
   for (size_t i = 0; i < out.slices.size(); ++i) {
     Slice& sl = out.slices[i];
     out.flops_fwd += sl.flops_fwd;
     out.flops_bwd += sl.flops_bwd;
-    out.ws1 = std::max(out.ws1, sl.size1);
-    out.ws2 = std::max(out.ws2, sl.size2);
-    FP_TRY(sl.ps->upload(ctx, "site" + std::to_string(i)));
+    out.ws1 = std::max(out.ws1, std::max(sl.size1, sl.bsize1));
+    out.ws2 = std::max(out.ws2, std::max(sl.size2, sl.bsize2));
+    FP_TRY(sl.ps->upload(ctx, "site" + std::to_string(i) + "f"));
+    if (sl.psb) FP_TRY(sl.psb->upload(ctx, "site" + std::to_string(i) + "b"));
     // layer sub-blocks scaled by the per-pair scalars (the bra shares the
     // ket's data)
     for (int s = 0; s < 5; ++s) {
@@ -358,12 +366,13 @@ Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t bud
         const bool w = s == 2;
         FP_TRY(sl.ps->pack(ctx, sl.fwd[s], w ? dev.W : dev.A, w ? dev.W_size : dev.A_size));
       }
-      if (sl.bwd[s] >= 0 && sl.bwd_rt[s]) {
+      if (sl.psb && sl.bwd[s] >= 0 && sl.bwd_rt[s]) {
         const bool w = s == 2;   // bwd order: T5, T4, T3, T2, T1
-        FP_TRY(sl.ps->pack(ctx, sl.bwd[s], w ? dev.W : dev.A, w ? dev.W_size : dev.A_size));
+        FP_TRY(sl.psb->pack(ctx, sl.bwd[s], w ? dev.W : dev.A, w ? dev.W_size : dev.A_size));
       }
     }
   }
+  ctx->stage_end();
   ctx->peak_ws = std::max(ctx->peak_ws,
                           (double)(out.ws1 + out.ws2) * (f32 ? sizeof(float) : sizeof(double)));
   ctx->nslices = std::max(ctx->nslices, (int)out.slices.size());
@@ -371,9 +380,13 @@ Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t bud
 }
 
 Status SiteOp::plan_slice(const std::vector<int32_t>& k, const Plans& pl, Slice& sl,
-                          bool with_bwd) const {
-  sl.ps = std::make_shared<PlanSet>();
-  PlanSet& ps = *sl.ps;
+                          bool bwd) const {
+  std::shared_ptr<PlanSet> own = std::make_shared<PlanSet>();
+  if (bwd)
+    sl.psb = own;
+  else
+    sl.ps = own;
+  PlanSet& ps = *own;
   const std::vector<SliceCol>& sc = sl.cols;
   std::string err;
   const std::vector<int>* store[5] = {&STORE_X1, &STORE_X2, &STORE_X3, &STORE_X4, &ORDER_X[5]};
@@ -384,7 +397,7 @@ Status SiteOp::plan_slice(const std::vector<int32_t>& k, const Plans& pl, Slice&
   BT colL = omega_layout(sc, k, pl.col_off, pl.col_total, false);
   BT rowL = omega_layout(sc, k, pl.row_off, pl.row_total, true);
   BT X = colL;
-  for (int s = 0; s < 5; ++s) {
+  for (int s = 0; s < 5 && !bwd; ++s) {
     StepSpec sp;
     sp.step = s + 1;
     sp.m_is_x = mx[s];
@@ -414,7 +427,7 @@ Status SiteOp::plan_slice(const std::vector<int32_t>& k, const Plans& pl, Slice&
     }
     X = std::move(r.out);
   }
-  if (with_bwd) {
+  if (bwd) {
     BT Z = rowL;
     for (int s = 0; s < 5; ++s) {
       StepSpec sp;
@@ -452,8 +465,6 @@ Status SiteOp::plan_slice(const std::vector<int32_t>& k, const Plans& pl, Slice&
       }
       Z = std::move(r.out);
     }
-  } else {
-    for (int s = 0; s < 5; ++s) sl.bwd[s] = -1;
   }
   return Status::ok();
 }
@@ -477,13 +488,14 @@ Status SiteOp::apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const do
       FP_TRY(run_gemm_mixed(ctx, ps, sl.fwd[4], dev.R, dev.R_size, b2, f, s2, y, false,
                             pl.row_total, true, 5));
     } else {
-      if (sl.bwd[0] < 0) return fail(FPEPS_ERR_ARG, "transposed chain was not planned");
-      FP_TRY(run_gemm_mixed(ctx, ps, sl.bwd[0], dev.R, dev.R_size, x, false, pl.row_total, b2, f,
+      if (sl.bwd[0] < 0 || !sl.psb) return fail(FPEPS_ERR_ARG, "transposed chain was not planned");
+      const PlanSet& psb = *sl.psb;
+      FP_TRY(run_gemm_mixed(ctx, psb, sl.bwd[0], dev.R, dev.R_size, x, false, pl.row_total, b2, f,
                             s2, true, 15));
-      FP_TRY(run_rt(ctx, ps, sl.bwd[1], b2, s2, b1, s1, f, true, 14));
-      FP_TRY(run_rt(ctx, ps, sl.bwd[2], b1, s1, b2, s2, f, true, 13));
-      FP_TRY(run_rt(ctx, ps, sl.bwd[3], b2, s2, b1, s1, f, true, 12));
-      FP_TRY(run_gemm_mixed(ctx, ps, sl.bwd[4], dev.T, dev.T_size, b1, f, s1, y, false,
+      FP_TRY(run_rt(ctx, psb, sl.bwd[1], b2, s2, b1, s1, f, true, 14));
+      FP_TRY(run_rt(ctx, psb, sl.bwd[2], b1, s1, b2, s2, f, true, 13));
+      FP_TRY(run_rt(ctx, psb, sl.bwd[3], b2, s2, b1, s1, f, true, 12));
+      FP_TRY(run_gemm_mixed(ctx, psb, sl.bwd[4], dev.T, dev.T_size, b1, f, s1, y, false,
                             pl.col_total, true, 11));
     }
   }

@@ -54,13 +54,15 @@ class SiteOp {
   // Plans of M (fwd) and M^T (bwd) for per-sector widths k, sliced so that
   // the chain intermediates of one slice fit ``budget`` bytes.
   struct Slice {
-    std::shared_ptr<PlanSet> ps;   // this slice's plans (planned independently)
+    std::shared_ptr<PlanSet> ps;   // this slice's forward plans (planned independently)
+    std::shared_ptr<PlanSet> psb;  // and its transposed-chain plans
     double flops_fwd = 0, flops_bwd = 0;
     std::vector<SliceCol> cols;
     int fwd[5], bwd[5];       // plan indices in the PlanSet (GEMM or row-thread list)
     bool fwd_rt[5] = {false, false, false, false, false};
     bool bwd_rt[5] = {false, false, false, false, false};
-    int64_t size1 = 0, size2 = 0;  // ping-pong intermediate buffer sizes (elements)
+    int64_t size1 = 0, size2 = 0;    // ping-pong intermediate sizes (elements), forward
+    int64_t bsize1 = 0, bsize2 = 0;  // and transposed chain
   };
   struct Plans {
     std::vector<Slice> slices;
@@ -81,8 +83,9 @@ class SiteOp {
  private:
   BT omega_layout(const std::vector<SliceCol>& cols, const std::vector<int32_t>& k,
                   const std::vector<int64_t>& off, int64_t total, bool rows) const;
-  // forward and transposed chain plans of one slice (host only, thread safe)
-  Status plan_slice(const std::vector<int32_t>& k, const Plans& pl, Slice& sl, bool with_bwd) const;
+  // forward (bwd = false) or transposed chain plans of one slice (host only,
+  // thread safe; the two directions write different fields of the slice)
+  Status plan_slice(const std::vector<int32_t>& k, const Plans& pl, Slice& sl, bool bwd) const;
 };
 
 // Convert an fpeps_tensor into a planner BT with the given leg names.
