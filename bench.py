@@ -126,6 +126,65 @@ def bench_config5(a):
     print(json.dumps(line), flush=True)
 
 
+def bench_lattice(a):
+    """<W> = Z_W / Z_1 of the full 8x8 SU(2)-synthetic lattice at the shapes of
+    the headline row (reduced D = 6, w = 4, d = 3; chi = 500, p = 20, q = 2):
+    every row absorbed top to bottom, then closed. W is a near-identity PEPO
+    (1 + 0.5 R per site), so that <W> is of order one; with a purely random W
+    the value is exponentially small and dominated by cancellation. Run once
+    in FP64 and once in mixed precision; prints both values, their relative
+    difference, the log-norms and the times."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2511_01039_amd import Context, DeviceTensor, opts_for
+    lat = wl.config4_lattice()
+    W = wl.near_identity_pepo(lat.sym, wl.legs_su2(500), lat.Lx, lat.Ly, np.random.default_rng(1))
+    ident = wl.identity_pepo(lat.sym, lat.Lx, lat.Ly, lat.A[0][0].legs[0])
+    ctx = Context(0)
+    dev = lambda ts: [DeviceTensor.from_host(t) for t in ts]
+    A = [dev(r) for r in lat.A]
+
+    def value(W, precision):
+        Wd = [dev(r) for r in W]
+        env = dev(wl.trivial_env(lat.sym, lat.Lx))
+        lg, flops = 0.0, 0.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for y in range(lat.Ly):
+            env, lg, rep = ctx.env_absorb(env, A[y], Wd[y],
+                                          opts_for(lat.sym, chi=500, oversample=20, power_iters=2,
+                                                   seed=0, row=y, precision=precision),
+                                          log_norm=lg)
+            flops += rep["alg_flops"]
+            print(f"{precision} row {y}: {rep['seconds']:.3f} s", file=sys.stderr, flush=True)
+        v = ctx.expect(env, dev(wl.bottom_closing(env)))
+        torch.cuda.synchronize()
+        return (1 if v > 0 else -1), lg + math.log(abs(v)), time.perf_counter() - t0, flops
+
+    res = {}
+    for prec in ("fp64", "fp32"):
+        zw, z1 = value(W, prec), value(ident, prec)
+        res[prec] = dict(W=zw[0] * z1[0] * math.exp(zw[1] - z1[1]), seconds=zw[2] + z1[2],
+                         flops=zw[3] + z1[3], log_zw=zw[1], log_z1=z1[1])
+    rel = abs(res["fp32"]["W"] - res["fp64"]["W"]) / abs(res["fp64"]["W"])
+    line = {"metric": "<W> of the 8x8 SU(2)-synthetic lattice, chi=500: mixed vs FP64",
+            "value": res["fp64"]["seconds"] / res["fp32"]["seconds"], "unit": "speedup",
+            "n_gpus": 1, "steps": 1, "warmup": 0, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "full 8x8 SU(2)-synthetic lattice (reduced D=6, w=4, d=3, "
+                                   "fermionic signs), near-identity W, Z_W and Z_1 top to "
+                                   "bottom, chi=500 p=20 q=2"},
+            "W_fp64": res["fp64"]["W"], "W_mixed": res["fp32"]["W"], "rel_err": rel,
+            "log_zw_diff": abs(res["fp32"]["log_zw"] - res["fp64"]["log_zw"]),
+            "log_z1_diff": abs(res["fp32"]["log_z1"] - res["fp64"]["log_z1"]),
+            "log_z1_fp64": res["fp64"]["log_z1"],
+            "seconds_fp64": res["fp64"]["seconds"], "seconds_mixed": res["fp32"]["seconds"],
+            "tflops_fp64": res["fp64"]["flops"] / res["fp64"]["seconds"] / 1e12,
+            "tflops_mixed": res["fp32"]["flops"] / res["fp32"]["seconds"] / 1e12}
+    print(json.dumps(line), flush=True)
+
+
 def profiled_traffic(kernel, precision="fp64"):
     """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE runs, calibrated against a plain
@@ -203,6 +262,8 @@ def main():
                     help="mixed-vs-fp64 (default): time both paths on the same row and report the "
                          "mixed one if its network value is within 1e-6 of FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lattice", action="store_true",
+                    help="<W> of the full 8x8 lattice at the headline shapes, FP64 and mixed")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 4 times (the known-size "
                          "reference for HBM byte counters) and exit")
@@ -226,6 +287,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.config == 5:
         bench_config5(a)
+        return
+    if a.lattice:
+        bench_lattice(a)
         return
     from paper_2511_01039_amd import Context, DeviceTensor, opts_for
     from paper_2511_01039_amd.binding import FLAG_TIME_KERNELS

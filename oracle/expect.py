@@ -40,19 +40,9 @@ def overlap(top, bottom):
 
 def closing_env(env):
     """An environment of dim-1 legs matching the open (dim-1) bundle legs of
-    ``env``: used below the last row."""
-    out = []
-    for t in env:
-        legs = []
-        for i, l in enumerate(t.legs):
-            if i in (0, 4):
-                legs.append(Leg(np.zeros((1, l.labels.shape[1]), dtype=np.int32),
-                                np.ones(1, dtype=np.int32), -l.dir))
-            else:
-                assert l.total == 1, "bundle legs must be closed (dim 1)"
-                legs.append(Leg(l.labels.copy(), l.dims.copy(), -l.dir))
-        out.append(Tensor.from_blocks(legs, [(0,) * 5], [np.ones((1,) * 5)]))
-    return out
+    ``env``: used below the last row (built by the shared input module)."""
+    from workloads.configs import bottom_closing
+    return bottom_closing(env)
 
 
 def network_value(sym, lattice_A, lattice_W, chi, p, q, seed, exact_svd=False, bra=None,

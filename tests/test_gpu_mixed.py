@@ -163,3 +163,19 @@ def test_config1_network_value_mixed(ctx):
     rel = abs(got - want) / abs(want)
     print(f"config1 mixed <W>: oracle {want:.15e} gpu {got:.15e} rel {rel:.2e}")
     assert rel < MIXED_TOL
+
+
+def test_su2_lattice_network_value_mixed(ctx):
+    """The 3x3 SU(2)-synthetic lattice of the FP64 test in mixed precision:
+    <W> within 1e-6 of the FP64 oracle."""
+    from oracle.expect import network_value, ratio
+    from test_gpu_parity import lattice_value
+    lat = wl.su2_lattice(3, 3, wl.legs_su2_mini(env_scale=2, virt_scale=1), seed=4)
+    ident = wl.identity_pepo(lat.sym, 3, 3, lat.A[0][0].legs[0])
+    got = ratio(lattice_value(ctx, lat, lat.W, 12, 4, 1, 7, "fp32"),
+                lattice_value(ctx, lat, ident, 12, 4, 1, 7, "fp32"))
+    want = ratio(network_value(lat.sym, lat.A, lat.W, 12, 4, 1, 7)[:2],
+                 network_value(lat.sym, lat.A, ident, 12, 4, 1, 7)[:2])
+    rel = abs(got - want) / abs(want)
+    print(f"su2 3x3 mixed <W>: oracle {want:.15e} gpu {got:.15e} rel {rel:.2e}")
+    assert rel < MIXED_TOL

@@ -382,3 +382,34 @@ def test_config5_bond_expansion_site_matches_oracle(ctx):
         assert np.abs(q @ q.T - cw["Q"][i] @ cw["Q"][i].T).max() < 1e-10
         assert rel_err(csig[i], cw["sigma"][i]) < 1e-11
     print(f"config5 site: shapes {shapes} kept {list(kept)} cbe kept {list(ckept)}")
+
+
+def lattice_value(ctx, lat, W, chi, p, q, seed, precision="fp64"):
+    """<top|closing> after absorbing every row top to bottom on the device:
+    (sign, log |Z|)."""
+    from oracle.expect import closing_env
+    from paper_2511_01039_amd import opts_for
+    Ly, Lx = len(lat.A), len(lat.A[0])
+    env = devs(wl.trivial_env(lat.sym, Lx))
+    lg = 0.0
+    for y in range(Ly):
+        env, lg, _ = ctx.env_absorb(env, devs(lat.A[y]), devs(W[y]),
+                                    opts_for(lat.sym, chi=chi, oversample=p, power_iters=q,
+                                             seed=seed, row=y, precision=precision),
+                                    log_norm=lg)
+    v = ctx.expect(env, devs(closing_env([t.to_host() for t in env])))
+    return (1 if v > 0 else -1), lg + math.log(abs(v))
+
+
+def test_su2_lattice_network_value(ctx):
+    """a1-a8 on a whole SU(2)-synthetic lattice (3x3, fermionic signs, random
+    PEPO): <W> = Z_W / Z_1 top to bottom with chi = 12, rSVD p = 4, q = 1,
+    FP64 device path vs the oracle within 1e-11."""
+    from oracle.expect import network_value, ratio
+    lat = wl.su2_lattice(3, 3, wl.legs_su2_mini(env_scale=2, virt_scale=1), seed=4)
+    ident = wl.identity_pepo(lat.sym, 3, 3, lat.A[0][0].legs[0])
+    got = ratio(lattice_value(ctx, lat, lat.W, 12, 4, 1, 7), lattice_value(ctx, lat, ident, 12, 4, 1, 7))
+    want = ratio(network_value(lat.sym, lat.A, lat.W, 12, 4, 1, 7)[:2],
+                 network_value(lat.sym, lat.A, ident, 12, 4, 1, 7)[:2])
+    print(f"su2 3x3 <W>: oracle {want:.15e} gpu {got:.15e} rel {abs(got - want) / abs(want):.2e}")
+    assert abs(got - want) < 1e-11 * abs(want)

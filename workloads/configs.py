@@ -322,6 +322,31 @@ def random_symmetric_pepo(cat, Lx, Ly, rng):
     return out
 
 
+def near_identity_pepo(sym, cat, Lx, Ly, rng, eps=0.5):
+    """W = 1 + eps * R per site: R a random tensor on the PEPO legs of the
+    catalogue, 1 = delta_{qp} on the first index of the trivial sector of
+    every virtual leg. Such an operator (the shape of a short imaginary-time
+    step) gives <W> of order one, so its relative error measures the
+    contraction rather than a cancellation in a vanishing value."""
+    out = []
+    for y in range(Ly):
+        row = []
+        for x in range(Lx):
+            legs = pepo_site_legs(cat, x, y, Lx, Ly)
+            t = random_tensor(sym, legs, rng)
+            t.data *= eps
+            z = [int(np.flatnonzero((l.labels == np.asarray(sym.zero_label())).all(axis=1))[0])
+                 for l in legs[2:]]
+            for s in range(legs[0].nsect):
+                i = t.find((s, s) + tuple(z))
+                assert i is not None, "identity block must be allowed"
+                b = t.block(i)
+                b[:, :, 0, 0, 0, 0] += np.eye(int(legs[0].dims[s]))
+            row.append(t)
+        out.append(row)
+    return out
+
+
 def identity_pepo(sym, Lx, Ly, d_leg, scale=1.0):
     """W = delta_{qp} with trivial (dim-1) virtual legs; ``scale`` multiplies
     the (0, 0) site only."""
@@ -356,6 +381,23 @@ def random_top_env(sym, cat, A_row, W_row, rng):
                                              x == L - 1), rng) for x in range(L)]
 
 
+def bottom_closing(env):
+    """The environment below the last row: ones on dim-1 legs facing the
+    open (dim-1) bundle legs of ``env`` (anything with ``.legs``)."""
+    out = []
+    for t in env:
+        legs = []
+        for i, l in enumerate(t.legs):
+            if i in (0, 4):
+                legs.append(Leg(np.zeros((1, l.labels.shape[1]), dtype=np.int32),
+                                np.ones(1, dtype=np.int32), -l.dir))
+            else:
+                assert l.total == 1, "bundle legs must be closed (dim 1)"
+                legs.append(Leg(l.labels.copy(), l.dims.copy(), -l.dir))
+        out.append(Tensor.from_blocks(legs, [(0,) * 5], [np.ones((1,) * 5)]))
+    return out
+
+
 def trivial_env(sym, L):
     """The environment above the top row: every leg one dim-1 sector."""
     bnd = Leg.make([(sym.zero_label(), 1)])
@@ -377,6 +419,24 @@ def config1_lattice(Lx=4, Ly=4, d=2, D=3, w=2, seed=0):
     A = random_peps(sym, cat, Lx, Ly, rng)
     W = random_symmetric_pepo(cat, Lx, Ly, rng)
     return Lattice(sym, A, W, Lx, Ly)
+
+
+def su2_lattice(Lx, Ly, cat, seed=0, fermionic=True):
+    """SU(2)-synthetic lattice: random PEPS and random PEPO blocks on the
+    multiplet catalogue ``cat`` (N(0,1)/sqrt(numel) per block)."""
+    sym = Sym("su2", coef_seed=seed, fermionic=fermionic)
+    rng = np.random.default_rng(seed)
+    A = random_peps(sym, cat, Lx, Ly, rng)
+    W = [[random_tensor(sym, pepo_site_legs(cat, x, y, Lx, Ly), rng) for x in range(Lx)]
+         for y in range(Ly)]
+    return Lattice(sym, A, W, Lx, Ly)
+
+
+def config4_lattice(Lx=8, Ly=8, seed=0):
+    """The full 8x8 lattice at the shapes of the headline row: reduced
+    D = 6 (multiplicities 3, 2, 1), w = 4, d = 3; absorbed with chi = 500,
+    p = 20, q = 2."""
+    return su2_lattice(Lx, Ly, legs_su2(500), seed=seed)
 
 
 def config1_params():
