@@ -131,9 +131,10 @@ def bench_lattice(a):
     the headline row (reduced D = 6, w = 4, d = 3; chi = 500, p = 20, q = 2):
     every row absorbed top to bottom, then closed. W is a near-identity PEPO
     (1 + 0.5 R per site), so that <W> is of order one; with a purely random W
-    the value is exponentially small and dominated by cancellation. Run once
-    in FP64 and once in mixed precision; prints both values, their relative
-    difference, the log-norms and the times."""
+    the value is exponentially small and dominated by cancellation. Runs in
+    FP64 and in mixed precision with sketch seed 0, and in FP64 with seed 1
+    (the spread of the randomized method itself); prints the values, their
+    relative differences, the log-norms and the times."""
     import numpy as np
     import torch
     import workloads as wl
@@ -145,7 +146,7 @@ def bench_lattice(a):
     dev = lambda ts: [DeviceTensor.from_host(t) for t in ts]
     A = [dev(r) for r in lat.A]
 
-    def value(W, precision):
+    def value(W, precision, seed=0):
         Wd = [dev(r) for r in W]
         env = dev(wl.trivial_env(lat.sym, lat.Lx))
         lg, flops = 0.0, 0.0
@@ -154,20 +155,23 @@ def bench_lattice(a):
         for y in range(lat.Ly):
             env, lg, rep = ctx.env_absorb(env, A[y], Wd[y],
                                           opts_for(lat.sym, chi=500, oversample=20, power_iters=2,
-                                                   seed=0, row=y, precision=precision),
+                                                   seed=seed, row=y, precision=precision),
                                           log_norm=lg)
             flops += rep["alg_flops"]
-            print(f"{precision} row {y}: {rep['seconds']:.3f} s", file=sys.stderr, flush=True)
+            print(f"{precision} seed {seed} row {y}: {rep['seconds']:.3f} s", file=sys.stderr,
+                  flush=True)
         v = ctx.expect(env, dev(wl.bottom_closing(env)))
         torch.cuda.synchronize()
         return (1 if v > 0 else -1), lg + math.log(abs(v)), time.perf_counter() - t0, flops
 
     res = {}
-    for prec in ("fp64", "fp32"):
-        zw, z1 = value(W, prec), value(ident, prec)
-        res[prec] = dict(W=zw[0] * z1[0] * math.exp(zw[1] - z1[1]), seconds=zw[2] + z1[2],
-                         flops=zw[3] + z1[3], log_zw=zw[1], log_z1=z1[1])
+    for key, prec, seed in (("fp64", "fp64", 0), ("fp32", "fp32", 0), ("seed1", "fp64", 1)):
+        zw, z1 = value(W, prec, seed), value(ident, prec, seed)
+        res[key] = dict(W=zw[0] * z1[0] * math.exp(zw[1] - z1[1]), seconds=zw[2] + z1[2],
+                        flops=zw[3] + z1[3], log_zw=zw[1], log_z1=z1[1])
     rel = abs(res["fp32"]["W"] - res["fp64"]["W"]) / abs(res["fp64"]["W"])
+    # the method's own spread: FP64 with another sketch seed
+    seed_rel = abs(res["seed1"]["W"] - res["fp64"]["W"]) / abs(res["fp64"]["W"])
     line = {"metric": "<W> of the 8x8 SU(2)-synthetic lattice, chi=500: mixed vs FP64",
             "value": res["fp64"]["seconds"] / res["fp32"]["seconds"], "unit": "speedup",
             "n_gpus": 1, "steps": 1, "warmup": 0, "higher_is_better": True,
@@ -179,6 +183,8 @@ def bench_lattice(a):
             "log_zw_diff": abs(res["fp32"]["log_zw"] - res["fp64"]["log_zw"]),
             "log_z1_diff": abs(res["fp32"]["log_z1"] - res["fp64"]["log_z1"]),
             "log_z1_fp64": res["fp64"]["log_z1"],
+            "W_fp64_seed1": res["seed1"]["W"], "seed_rel": seed_rel,
+            "log_z1_seed_diff": abs(res["seed1"]["log_z1"] - res["fp64"]["log_z1"]),
             "seconds_fp64": res["fp64"]["seconds"], "seconds_mixed": res["fp32"]["seconds"],
             "tflops_fp64": res["fp64"]["flops"] / res["fp64"]["seconds"] / 1e12,
             "tflops_mixed": res["fp32"]["flops"] / res["fp32"]["seconds"] / 1e12}

@@ -106,11 +106,14 @@ fp::Status fpeps_ctx_s::harvest_timing() {
     b[1] += evflops[i / 2];
     b[2] += 1;
     b[3] += evbytes[i / 2];
+    b[4] += evshape[i / 2][0];
+    b[5] += evshape[i / 2][1];
   }
   evused = 0;
   evflops.clear();
   evlabel.clear();
   evbytes.clear();
+  evshape.clear();
   return fp::Status::ok();
 }
 
@@ -271,8 +274,10 @@ Status run_rt(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const void* X, int64
       hipEvent_t a, b;
       FP_TRY(ctx->timed_events(&a, &b));
       ctx->evflops.push_back(p.l_flops[c]);
-      ctx->evlabel.push_back(label);
+      // at verbose level 2 every launch class of a step is kept apart
+      ctx->evlabel.push_back(ctx->verbose >= 2 ? label + 100 * (c + 1) : label);
       ctx->evbytes.push_back(f32 ? 0.5 * p.l_bytes[c] : p.l_bytes[c]);
+      ctx->evshape.push_back({(double)p.l_ntiles[c], (double)p.l_lds[c]});
       FP_HIP(hipEventRecord(a, ctx->stream));
       FP_HIP(launch_rt_f64(d, c, X, f32, ps.dpack, Y, ps.dtab, ctx->stream));
       FP_HIP(hipEventRecord(b, ctx->stream));
@@ -313,6 +318,7 @@ Status run_gemm_mixed(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double
     ctx->evflops.push_back(p.flops);
     ctx->evlabel.push_back(label);
     ctx->evbytes.push_back(p.bytes);
+    ctx->evshape.push_back({0.0, 0.0});
     FP_HIP(hipEventRecord(ea, ctx->stream));
   }
   if (part) {

@@ -72,11 +72,12 @@ struct fpeps_ctx_s {
   std::vector<double> evflops;
   std::vector<int> evlabel;
   std::vector<double> evbytes;
-  // label -> {seconds, flops, launches, algorithmic bytes}
-  std::map<int, std::array<double, 4>> kt_by_label;
+  std::vector<std::array<double, 2>> evshape;  // layer launches: tiles, LDS bytes
+  // label -> {seconds, flops, launches, algorithmic bytes, tiles, LDS bytes}
+  std::map<int, std::array<double, 6>> kt_by_label;
   double kt_seconds = 0, kt_flops = 0;
   long kt_launches = 0;
-  bool verbose = false;
+  int verbose = 0;  // FPEPS_VERBOSE: 1 per site and step, 2 also per layer launch class
   // pinned staging arena for plan uploads (asynchronous host-to-device
   // copies between stage_begin and stage_end; stage_begin waits for the
   // stream, so the arena is never overwritten while a copy reads it)

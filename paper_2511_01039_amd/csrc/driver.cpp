@@ -518,8 +518,12 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
   ctx->evflops.clear();
   ctx->evlabel.clear();
   ctx->evbytes.clear();
+  ctx->evshape.clear();
   ctx->kt_by_label.clear();
-  ctx->verbose = std::getenv("FPEPS_VERBOSE") != nullptr;
+  {
+    const char* v = std::getenv("FPEPS_VERBOSE");
+    ctx->verbose = v ? std::max(1, std::atoi(v)) : 0;
+  }
   auto wall = [] { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
   hipEvent_t ev0, ev1;
   FP_HIP(hipEventCreate(&ev0));
@@ -846,13 +850,19 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     }
   }
   if (ctx->verbose && ctx->time_kernels) {
-    for (auto& kv : ctx->kt_by_label)
+    for (auto& kv : ctx->kt_by_label) {
+      const int base = kv.first % 100, cls = kv.first / 100 - 1;
+      const auto& v = kv.second;
       std::fprintf(stderr,
                    "[fpeps] chain step %s%d: %6.0f launches %9.3f s %10.3e flops %7.2f TFLOP/s "
-                   "%9.1f GB %7.2f TB/s\n",
-                   kv.first >= 10 ? "T" : "", kv.first >= 10 ? kv.first - 10 : kv.first,
-                   kv.second[2], kv.second[0], kv.second[1], kv.second[1] / kv.second[0] * 1e-12,
-                   kv.second[3] * 1e-9, kv.second[3] / kv.second[0] * 1e-12);
+                   "%9.1f GB %7.2f TB/s",
+                   base >= 10 ? "T" : "", base >= 10 ? base - 10 : base, v[2], v[0], v[1],
+                   v[1] / v[0] * 1e-12, v[3] * 1e-9, v[3] / v[0] * 1e-12);
+      if (cls >= 0)
+        std::fprintf(stderr, "  class %d: %.0f tiles/launch, %.1f KiB LDS", cls, v[4] / v[2],
+                     v[5] / v[2] / 1024.0);
+      std::fprintf(stderr, "\n");
+    }
   }
   ctx->time_kernels = false;
   return Status::ok();
