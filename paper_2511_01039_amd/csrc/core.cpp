@@ -42,38 +42,52 @@ fp::Status fpeps_ctx_s::buf(const std::string& name, size_t bytes, void** out) {
   return fp::Status::ok();
 }
 
-fp::Status fpeps_ctx_s::upload(const std::string& name, const void* host, size_t bytes,
-                               void** dev) {
-  FP_TRY(buf(name, bytes, dev));
-  if (stage_async && bytes) {
-    const size_t need = (bytes + 255) / 256 * 256;
-    if (stage_used + need > stage_cap) {
-      // every copy issued from the arena so far must finish before it is
-      // replaced
-      FP_HIP(hipStreamSynchronize(stream));
-      const size_t cap = std::max({2 * stage_cap, need, (size_t)64 << 20});
-      if (stage) FP_HIP(hipHostFree(stage));
+fp::Status fpeps_ctx_s::stage_alloc(size_t bytes, char** host) {
+  const size_t need = (bytes + 255) / 256 * 256;
+  if (stage_used + need > stage_cap) {
+    // every copy issued from the arena so far must finish before it is
+    // replaced
+    FP_HIP(hipStreamSynchronize(stream));
+    const size_t cap = std::max({2 * stage_cap, need, (size_t)64 << 20});
+    if (stage) FP_HIP(hipHostFree(stage));
+    stage = nullptr;
+    stage_cap = 0;
+    if (hipHostMalloc((void**)&stage, cap, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
       stage = nullptr;
-      stage_cap = 0;
-      if (hipHostMalloc((void**)&stage, cap, hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        stage = nullptr;
-        return fp::fail(FPEPS_ERR_NOMEM, "pinned staging allocation failed");
-      }
-      stage_cap = cap;
-      stage_used = 0;
+      return fp::fail(FPEPS_ERR_NOMEM, "pinned staging allocation failed");
     }
-    std::memcpy(stage + stage_used, host, bytes);
-    FP_HIP(hipMemcpyAsync(*dev, stage + stage_used, bytes, hipMemcpyHostToDevice, stream));
-    stage_used += need;
-    return fp::Status::ok();
+    stage_cap = cap;
+    stage_used = 0;
   }
-  if (bytes) {
+  *host = stage + stage_used;
+  stage_used += need;
+  return fp::Status::ok();
+}
+
+fp::Status fpeps_ctx_s::upload_region(const std::string& name, const char* host, size_t bytes,
+                                      void** dev) {
+  FP_TRY(buf(name, bytes, dev));
+  if (!bytes) return fp::Status::ok();
+  if (stage_async) {
+    FP_HIP(hipMemcpyAsync(*dev, host, bytes, hipMemcpyHostToDevice, stream));
+  } else {
     // the previous contents may still be read by queued kernels
     FP_HIP(hipStreamSynchronize(stream));
     FP_HIP(hipMemcpy(*dev, host, bytes, hipMemcpyHostToDevice));
   }
   return fp::Status::ok();
+}
+
+fp::Status fpeps_ctx_s::upload(const std::string& name, const void* host, size_t bytes,
+                               void** dev) {
+  if (stage_async && bytes) {
+    char* h = nullptr;
+    FP_TRY(stage_alloc(bytes, &h));
+    std::memcpy(h, host, bytes);
+    return upload_region(name, h, bytes, dev);
+  }
+  return upload_region(name, (const char*)host, bytes, dev);
 }
 
 fp::Status fpeps_ctx_s::sync() {
@@ -119,95 +133,144 @@ fp::Status fpeps_ctx_s::harvest_timing() {
 
 namespace fp {
 
-Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
-  std::vector<GemmJob> jobs;
-  std::vector<GemmPair> pairs;
-  std::vector<ReduceTab> reds;
-  std::vector<size_t> red0;
-  std::vector<std::pair<size_t, size_t>> range;
+Status PlanSet::serialize() {
+  Image m;
   for (auto& p : plans) {
-    red0.push_back(reds.size());
-    reds.insert(reds.end(), p.reduces.begin(), p.reduces.end());
-    const int32_t base = (int32_t)pairs.size();
-    const size_t j0 = jobs.size();
+    m.red0.push_back(m.reds.size());
+    m.reds.insert(m.reds.end(), p.reduces.begin(), p.reduces.end());
+    const int32_t base = (int32_t)m.pairs.size();
+    const size_t j0 = m.jobs.size();
     for (auto j : p.jobs) {
       j.p0 += base;
       j.p1 += base;
-      jobs.push_back(j);
+      m.jobs.push_back(j);
     }
-    pairs.insert(pairs.end(), p.pairs.begin(), p.pairs.end());
-    range.emplace_back(j0, p.jobs.size());
+    m.pairs.insert(m.pairs.end(), p.pairs.begin(), p.pairs.end());
+    m.range.emplace_back(j0, p.jobs.size());
   }
-  if (pairs.size() > (size_t)INT32_MAX || jobs.size() > (size_t)INT32_MAX)
+  if (m.pairs.size() > (size_t)INT32_MAX || m.jobs.size() > (size_t)INT32_MAX)
     return fail(FPEPS_ERR_UNSUPPORTED, "plan too large");
   // row-thread plans, concatenated with rebased ranges
-  std::vector<RtGroup> rg;
-  std::vector<int32_t> rtg;
-  std::vector<size_t> rtg0;
-  std::vector<RtOut> ro;
-  std::vector<RtKblk> rb;
-  std::vector<RtCol> rc;
-  std::vector<RtPair> rp;
-  std::vector<RtPack> rk;
-  struct R4 {
-    size_t g, o, b, c, p, k;
-  };
-  std::vector<R4> rr;
   pack_off.clear();
   pack_total = 0;
   for (auto& r : rts) {
-    R4 b{rg.size(), ro.size(), rb.size(), rc.size(), rp.size(), rk.size()};
-    rr.push_back(b);
+    const size_t g0 = m.rg.size(), o0 = m.ro.size(), b0 = m.rb.size(), c0 = m.rc.size(),
+                 p0 = m.rp.size();
+    m.rk0.push_back(m.rk.size());
     pack_off.push_back(pack_total);
-    rtg0.push_back(rtg.size());
-    for (int32_t t : r.tile_group) rtg.push_back(t + (int32_t)b.g);
+    m.rg0.push_back(g0);
+    m.rtg0.push_back(m.ntiles);
+    m.ntiles += (size_t)r.ntiles;
     for (auto g : r.groups) {
-      g.o0 += (int32_t)b.o;
-      g.o1 += (int32_t)b.o;
-      g.k0 += (int32_t)b.b;
-      g.k1 += (int32_t)b.b;
-      g.c0 += (int32_t)b.c;
-      rg.push_back(g);
+      g.o0 += (int32_t)o0;
+      g.o1 += (int32_t)o0;
+      g.k0 += (int32_t)b0;
+      g.k1 += (int32_t)b0;
+      g.c0 += (int32_t)c0;
+      m.rg.push_back(g);
     }
-    rb.insert(rb.end(), r.kblks.begin(), r.kblks.end());
-    rc.insert(rc.end(), r.cols.begin(), r.cols.end());
+    m.rb.insert(m.rb.end(), r.kblks.begin(), r.kblks.end());
+    m.rc.insert(m.rc.end(), r.cols.begin(), r.cols.end());
     for (auto o : r.outs) {
-      o.p0 += (int32_t)b.p;
-      o.p1 += (int32_t)b.p;
-      ro.push_back(o);
+      o.p0 += (int32_t)p0;
+      o.p1 += (int32_t)p0;
+      m.ro.push_back(o);
     }
-    for (auto p : r.pairs) {
-      p.pk += pack_total;
-      p.kblk += (int32_t)b.b;
-      rp.push_back(p);
+    for (auto pr : r.pairs) {
+      pr.pk += pack_total;
+      pr.kblk += (int32_t)b0;
+      m.rp.push_back(pr);
     }
     for (auto k : r.packs) {
       k.dst += pack_total;
-      rk.push_back(k);
+      m.rk.push_back(k);
     }
     pack_total += r.pack_size;
-    if (ro.size() > (size_t)INT32_MAX || rp.size() > (size_t)INT32_MAX ||
-        rk.size() > (size_t)INT32_MAX || rb.size() > (size_t)INT32_MAX ||
-        rc.size() > (size_t)INT32_MAX)
+    if (m.rg.size() > (size_t)INT32_MAX || m.ro.size() > (size_t)INT32_MAX ||
+        m.rp.size() > (size_t)INT32_MAX ||
+        m.rk.size() > (size_t)INT32_MAX || m.rb.size() > (size_t)INT32_MAX ||
+        m.rc.size() > (size_t)INT32_MAX)
       return fail(FPEPS_ERR_UNSUPPORTED, "layer plan too large");
   }
-  void *dj = nullptr, *dp = nullptr, *dt = nullptr;
-  FP_TRY(ctx->upload(tag + "_jobs", jobs.data(), jobs.size() * sizeof(GemmJob), &dj));
-  FP_TRY(ctx->upload(tag + "_pairs", pairs.data(), pairs.size() * sizeof(GemmPair), &dp));
-  FP_TRY(ctx->upload(tag + "_tab", pool.data.data(), pool.data.size() * sizeof(int32_t), &dt));
-  dtab = (int32_t*)dt;
-  void* dr = nullptr;
-  FP_TRY(ctx->upload(tag + "_red", reds.data(), reds.size() * sizeof(ReduceTab), &dr));
-  void *dg = nullptr, *dO = nullptr, *dP = nullptr, *dK = nullptr, *dpk = nullptr, *dB = nullptr;
-  FP_TRY(ctx->upload(tag + "_rtg", rg.data(), rg.size() * sizeof(RtGroup), &dg));
+  // one device image: every array 256-byte aligned
+  const size_t sz[10] = {m.jobs.size() * sizeof(GemmJob),   m.pairs.size() * sizeof(GemmPair),
+                         pool.data.size() * sizeof(int32_t), m.reds.size() * sizeof(ReduceTab),
+                         m.rg.size() * sizeof(RtGroup),      m.rb.size() * sizeof(RtKblk),
+                         m.rc.size() * sizeof(RtCol),        m.ro.size() * sizeof(RtOut),
+                         m.rp.size() * sizeof(RtPair),       m.rk.size() * sizeof(RtPack)};
+  size_t o = 0;
+  for (int i = 0; i < 10; ++i) {
+    m.off[i] = o;
+    o += (sz[i] + 255) / 256 * 256;
+  }
+  m.bytes = o;
+  m.ready = true;
+  img = std::move(m);
+  return Status::ok();
+}
+
+void PlanSet::write_image(char* dst) const {
+  const Image& m = img;
+  const void* src[10] = {m.jobs.data(), m.pairs.data(), pool.data.data(), m.reds.data(),
+                         m.rg.data(),   m.rb.data(),    m.rc.data(),       m.ro.data(),
+                         m.rp.data(),   m.rk.data()};
+  for (int i = 0; i < 10; ++i) {
+    const size_t n = (i + 1 < 10 ? m.off[i + 1] : m.bytes) - m.off[i];
+    if (n == 0) continue;
+    // the array's own size; the rest of its aligned slot is padding
+    size_t len = 0;
+    switch (i) {
+      case 0: len = m.jobs.size() * sizeof(GemmJob); break;
+      case 1: len = m.pairs.size() * sizeof(GemmPair); break;
+      case 2: len = pool.data.size() * sizeof(int32_t); break;
+      case 3: len = m.reds.size() * sizeof(ReduceTab); break;
+      case 4: len = m.rg.size() * sizeof(RtGroup); break;
+      case 5: len = m.rb.size() * sizeof(RtKblk); break;
+      case 6: len = m.rc.size() * sizeof(RtCol); break;
+      case 7: len = m.ro.size() * sizeof(RtOut); break;
+      case 8: len = m.rp.size() * sizeof(RtPair); break;
+      default: len = m.rk.size() * sizeof(RtPack); break;
+    }
+    if (len) std::memcpy(dst + m.off[i], src[i], len);
+  }
+}
+
+Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
+  if (!img.ready) FP_TRY(serialize());
+  if (ctx->stage_async) {
+    char* h = nullptr;
+    FP_TRY(ctx->stage_alloc(img.bytes, &h));
+    write_image(h);
+    return bind(ctx, tag, h);
+  }
+  std::vector<char> h(std::max<size_t>(img.bytes, 1));
+  write_image(h.data());
+  return bind(ctx, tag, h.data());
+}
+
+Status PlanSet::bind(fpeps_ctx_s* ctx, const std::string& tag, const char* host) {
+  if (!img.ready) return fail(FPEPS_ERR_ARG, "plan image was not built");
+  const Image& m = img;
+  void* dimg = nullptr;
+  FP_TRY(ctx->upload_region(tag + "_img", host, m.bytes, &dimg));
+  char* base = (char*)dimg;
+  void* dj = base + m.off[0];
+  void* dp = base + m.off[1];
+  dtab = (int32_t*)(base + m.off[2]);
+  void* dr = base + m.off[3];
+  void* dg = base + m.off[4];
+  void* dB = base + m.off[5];
+  void* dC = base + m.off[6];
+  void* dO = base + m.off[7];
+  void* dP = base + m.off[8];
+  void* dK = base + m.off[9];
+  void* dpk = nullptr;
+  // the group of every workgroup: written on the device from the groups
   void* dTG = nullptr;
-  FP_TRY(ctx->upload(tag + "_rttg", rtg.data(), rtg.size() * sizeof(int32_t), &dTG));
-  FP_TRY(ctx->upload(tag + "_rtb", rb.data(), rb.size() * sizeof(RtKblk), &dB));
-  void* dC = nullptr;
-  FP_TRY(ctx->upload(tag + "_rtc", rc.data(), rc.size() * sizeof(RtCol), &dC));
-  FP_TRY(ctx->upload(tag + "_rto", ro.data(), ro.size() * sizeof(RtOut), &dO));
-  FP_TRY(ctx->upload(tag + "_rtp", rp.data(), rp.size() * sizeof(RtPair), &dP));
-  FP_TRY(ctx->upload(tag + "_rtk", rk.data(), rk.size() * sizeof(RtPack), &dK));
+  FP_TRY(ctx->buf(tag + "_rttg", std::max<size_t>(m.ntiles, 1) * sizeof(int32_t), &dTG));
+  for (size_t i = 0; i < rts.size(); ++i)
+    FP_HIP(launch_tile_group((const RtGroup*)dg, (int)m.rg0[i], (int)rts[i].groups.size(),
+                             (int32_t*)dTG + m.rtg0[i], ctx->stream));
   FP_TRY(ctx->buf(tag + "_pack", (size_t)std::max<int64_t>(pack_total, 1) * sizeof(double), &dpk));
   dpack = (double*)dpk;
   this->tag = tag;
@@ -215,7 +278,7 @@ Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
   for (size_t i = 0; i < rts.size(); ++i) {
     DevRt d;
     d.groups = (const RtGroup*)dg;
-    d.tile_group = (const int32_t*)dTG + rtg0[i];
+    d.tile_group = (const int32_t*)dTG + m.rtg0[i];
     d.outs = (const RtOut*)dO;
     d.kblks = (const RtKblk*)dB;
     d.cols = (const RtCol*)dC;
@@ -227,7 +290,7 @@ Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
       d.l_ntiles[c] = rts[i].l_ntiles[c];
       d.l_lds[c] = rts[i].l_lds[c];
     }
-    d.packs = (const RtPack*)dK + rr[i].k;
+    d.packs = (const RtPack*)dK + m.rk0[i];
     d.ngroups = (int)rts[i].groups.size();
     d.ntiles = rts[i].ntiles;
     d.npacks = (int)rts[i].packs.size();
@@ -236,15 +299,17 @@ Status PlanSet::upload(fpeps_ctx_s* ctx, const std::string& tag) {
   dev.clear();
   for (size_t i = 0; i < plans.size(); ++i) {
     DevGemm g;
-    g.jobs = (const GemmJob*)dj + range[i].first;
+    g.jobs = (const GemmJob*)dj + m.range[i].first;
     g.pairs = (const GemmPair*)dp;
-    g.njobs = (int)range[i].second;
+    g.njobs = (int)m.range[i].second;
     g.mt = plans[i].mt;
     g.nt = plans[i].nt;
-    g.reduces = (const ReduceTab*)dr + red0[i];
+    g.reduces = (const ReduceTab*)dr + m.red0[i];
     g.nred = (int)plans[i].reduces.size();
     dev.push_back(g);
   }
+  // the arena holds its own copy of every image: release the host image
+  img = Image();
   return Status::ok();
 }
 

@@ -83,9 +83,16 @@ struct fpeps_ctx_s {
   // stream, so the arena is never overwritten while a copy reads it)
   char* stage = nullptr;
   size_t stage_cap = 0, stage_used = 0;
+  double plan_up_bytes = 0, plan_up_seconds = 0;   // last plan upload (diagnostics)
   bool stage_async = false;
   fp::Status stage_begin();
   void stage_end() { stage_async = false; }
+  // ``bytes`` of the arena for the caller to fill (grows it, after waiting
+  // for every copy issued from it, when it is too small)
+  fp::Status stage_alloc(size_t bytes, char** host);
+  // device buffer ``name`` filled from ``host`` (an arena region: an
+  // asynchronous copy between stage_begin and stage_end, else a blocking one)
+  fp::Status upload_region(const std::string& name, const char* host, size_t bytes, void** dev);
 
   ~fpeps_ctx_s();
   // device buffer ``name`` of at least ``bytes`` (grown, contents lost on growth)
@@ -119,6 +126,36 @@ struct PlanSet {
   double* dpack = nullptr;
   int32_t* dtab = nullptr;
   std::string tag;
+  // Host image of all plans of the set, concatenated with rebased ranges.
+  // serialize() builds it (host only, safe on a planning thread); upload()
+  // copies it to the device (building it first if needed) and releases it.
+  struct Image {
+    std::vector<GemmJob> jobs;
+    std::vector<GemmPair> pairs;
+    std::vector<ReduceTab> reds;
+    std::vector<size_t> red0;
+    std::vector<std::pair<size_t, size_t>> range;
+    std::vector<RtGroup> rg;
+    std::vector<size_t> rg0;     // first group of every row-thread plan
+    std::vector<size_t> rtg0;    // first tile of every row-thread plan
+    size_t ntiles = 0;
+    std::vector<RtOut> ro;
+    std::vector<RtKblk> rb;
+    std::vector<RtCol> rc;
+    std::vector<RtPair> rp;
+    std::vector<RtPack> rk;
+    std::vector<size_t> rk0;
+    // byte offsets of the arrays in the single device image, and its size
+    size_t off[10] = {0};
+    size_t bytes = 0;
+    bool ready = false;
+  } img;
+  Status serialize();
+  // host half of the upload: the image (serialize() first), written at dst
+  // (img.bytes bytes); safe on any thread
+  void write_image(char* dst) const;
+  // device half: copies the image from ``host`` and sets the device views
+  Status bind(fpeps_ctx_s* ctx, const std::string& tag, const char* host);
   Status upload(fpeps_ctx_s* ctx, const std::string& tag);
   int add(GemmPlan&& p) {
     plans.push_back(std::move(p));

@@ -703,9 +703,10 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
       std::fprintf(stderr,
                    "[fpeps] site %d: sectors %d m %lld n %lld analyse %.3fs rsvd %.3fs (plan %.3fs) "
                    "chain flops/app %.3e slices %zu ws %.2f GB table entries %zu layer loads "
-                   "%.3e pack %.3e\n",
+                   "%.3e pack %.3e upload %.1f MB %.3fs\n",
                    x, ns, (long long)mt, (long long)nt, tw1 - tw0, wall() - tw1, t_plan, pl.flops_fwd,
-                   pl.slices.size(), (pl.ws1 + pl.ws2) * 8e-9, tabs, xl, pk);
+                   pl.slices.size(), (pl.ws1 + pl.ws2) * 8e-9, tabs, xl, pk,
+                   ctx->plan_up_bytes * 1e-6, ctx->plan_up_seconds);
     }
     // outputs: environment site (U) and the next remainder (R)
     std::vector<int> sel;

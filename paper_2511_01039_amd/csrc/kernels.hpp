@@ -44,7 +44,7 @@ hipError_t launch_gemm_f64(const DevGemm& g, const double* A, const double* B, d
 // A row-thread layer-step plan resident on the device.
 struct DevRt {
   const RtGroup* groups = nullptr;
-  const int32_t* tile_group = nullptr;
+  const int32_t* tile_group = nullptr;   // group of every workgroup (filled on the device)
   const RtOut* outs = nullptr;
   const RtKblk* kblks = nullptr;
   const RtCol* cols = nullptr;
@@ -61,6 +61,11 @@ struct DevRt {
 hipError_t launch_rt_f64(const DevRt& r, int c, const void* X, bool f32, const double* PK,
                          void* Y, const int32_t* tab, hipStream_t s);
 // PK[dst + k nc + c] = alpha S[sbase + sk[k] + sn[c]] for every pack entry.
+// tile_group[tile0 + i] = g_first + g for every group g of groups[g_first ..
+// g_first + ngroups) and its tiles i < ceil(M / rows): the group of every
+// workgroup, written on the device instead of being uploaded.
+hipError_t launch_tile_group(const RtGroup* groups, int g_first, int ngroups, int32_t* tile_group,
+                             hipStream_t s);
 hipError_t launch_rt_pack(const DevRt& r, const double* S, const int32_t* tab, double* PK,
                           hipStream_t s);
 

@@ -289,6 +289,21 @@ __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
                      live);
 }
 
+__global__ void k_tile_group(const RtGroup* __restrict__ groups, int g_first,
+                             int32_t* __restrict__ tile_group) {
+  const int g = g_first + (int)blockIdx.x;
+  const RtGroup G = groups[g];
+  const int nt = (G.M + G.rows - 1) / G.rows;
+  for (int i = threadIdx.x; i < nt; i += blockDim.x) tile_group[G.tile0 + i] = g;
+}
+
+hipError_t launch_tile_group(const RtGroup* groups, int g_first, int ngroups, int32_t* tile_group,
+                             hipStream_t s) {
+  if (ngroups <= 0) return hipSuccess;
+  k_tile_group<<<dim3(ngroups), dim3(256), 0, s>>>(groups, g_first, tile_group);
+  return hipGetLastError();
+}
+
 __global__ void k_rt_pack(const RtPack* __restrict__ packs, const double* __restrict__ S,
                           const int32_t* __restrict__ tab, double* __restrict__ PK) {
   const RtPack P = packs[blockIdx.x];

@@ -859,7 +859,6 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
       for (const RtGroup& g : rt.groups)
         if (cls(g) == c) sorted.push_back(g);
     rt.groups.swap(sorted);
-    rt.tile_group.clear();
     int64_t t = 0;
     rt.nlaunch = 0;
     for (int c = 0; c < RT_NCLASS; ++c) {
@@ -879,7 +878,6 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
         }
         g.tile0 = (int32_t)t;
         const int64_t nt = ((int64_t)g.M + g.rows - 1) / g.rows;
-        rt.tile_group.insert(rt.tile_group.end(), (size_t)nt, (int32_t)gi);
         t += nt;
         if (g.staged) lds = std::max<int32_t>(lds, g.rows * g.ktot * 8);
       }

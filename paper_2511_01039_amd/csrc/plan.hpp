@@ -253,7 +253,6 @@ struct RtPlan {
   std::vector<RtCol> cols;
   std::vector<RtPair> pairs;
   std::vector<RtPack> packs;
-  std::vector<int32_t> tile_group;   // group of every workgroup
   int64_t pack_size = 0;       // doubles
   int32_t ntiles = 0;
   int32_t lds_bytes = 0;       // largest staged group

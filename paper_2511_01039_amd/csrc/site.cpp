@@ -2,6 +2,7 @@
 #include "site.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <thread>
 
@@ -350,15 +351,44 @@ Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t bud
   }
   for (auto& e : st) FP_TRY(e);
   // uploads through the pinned arena, asynchronous on the stream
+  const auto up0 = std::chrono::steady_clock::now();
   FP_TRY(ctx->stage_begin());
+  // one arena region per plan set, written on host threads, then one copy each
+  std::vector<PlanSet*> sets;
+  std::vector<std::string> tags;
+  for (size_t i = 0; i < out.slices.size(); ++i) {
+    sets.push_back(out.slices[i].ps.get());
+    tags.push_back("site" + std::to_string(i) + "f");
+    if (out.slices[i].psb) {
+      sets.push_back(out.slices[i].psb.get());
+      tags.push_back("site" + std::to_string(i) + "b");
+    }
+  }
+  std::vector<size_t> region(sets.size() + 1, 0);
+  for (size_t i = 0; i < sets.size(); ++i) {
+    if (!sets[i]->img.ready) FP_TRY(sets[i]->serialize());
+    region[i + 1] = region[i] + (sets[i]->img.bytes + 255) / 256 * 256;
+  }
+  char* arena = nullptr;
+  FP_TRY(ctx->stage_alloc(std::max<size_t>(region.back(), 1), &arena));
+  {
+    const unsigned hc = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>(sets.size(), std::min(16u, hc));
+    auto work = [&](size_t t) {
+      for (size_t i = t; i < sets.size(); i += nt) sets[i]->write_image(arena + region[i]);
+    };
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < nt; ++t) th.emplace_back(work, t);
+    if (nt > 0) work(0);
+    for (auto& x : th) x.join();
+  }
+  for (size_t i = 0; i < sets.size(); ++i) FP_TRY(sets[i]->bind(ctx, tags[i], arena + region[i]));
   for (size_t i = 0; i < out.slices.size(); ++i) {
     Slice& sl = out.slices[i];
     out.flops_fwd += sl.flops_fwd;
     out.flops_bwd += sl.flops_bwd;
     out.ws1 = std::max(out.ws1, std::max(sl.size1, sl.bsize1));
     out.ws2 = std::max(out.ws2, std::max(sl.size2, sl.bsize2));
-    FP_TRY(sl.ps->upload(ctx, "site" + std::to_string(i) + "f"));
-    if (sl.psb) FP_TRY(sl.psb->upload(ctx, "site" + std::to_string(i) + "b"));
     // layer sub-blocks scaled by the per-pair scalars (the bra shares the
     // ket's data)
     for (int s = 0; s < 5; ++s) {
@@ -372,7 +402,10 @@ Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t bud
       }
     }
   }
+  ctx->plan_up_bytes = (double)ctx->stage_used;
   ctx->stage_end();
+  ctx->plan_up_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - up0).count();
   ctx->peak_ws = std::max(ctx->peak_ws,
                           (double)(out.ws1 + out.ws2) * (f32 ? sizeof(float) : sizeof(double)));
   ctx->nslices = std::max(ctx->nslices, (int)out.slices.size());
@@ -466,7 +499,8 @@ Status SiteOp::plan_slice(const std::vector<int32_t>& k, const Plans& pl, Slice&
       Z = std::move(r.out);
     }
   }
-  return Status::ok();
+  // the device image of this slice's plans, built here on the planning thread
+  return own->serialize();
 }
 
 Status SiteOp::apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const double* x, double* y,
