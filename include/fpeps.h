@@ -164,6 +164,10 @@ typedef struct {
   double gemm_seconds;
   double gemm_flops;
   double gemm_bytes;
+  /* fpeps_env_absorb: sites whose analysis and plans were those of the
+     previous site (equal block structure of T, A, W and the remainder, equal
+     sketch widths); they are uploaded again with the site's own layer data. */
+  int32_t plan_reuses;
 } fpeps_report;
 
 /* Context: one per host thread. ``stream`` is a hipStream_t (NULL: default

@@ -59,7 +59,8 @@ class CReport(C.Structure):
                 ("layer_launches", C.c_int32), ("layer_seconds", C.c_double),
                 ("layer_flops", C.c_double), ("layer_bytes", C.c_double),
                 ("gemm_launches", C.c_int32), ("gemm_seconds", C.c_double),
-                ("gemm_flops", C.c_double), ("gemm_bytes", C.c_double)]
+                ("gemm_flops", C.c_double), ("gemm_bytes", C.c_double),
+                ("plan_reuses", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -308,8 +308,6 @@ Status PlanSet::bind(fpeps_ctx_s* ctx, const std::string& tag, const char* host)
     g.nred = (int)plans[i].reduces.size();
     dev.push_back(g);
   }
-  // the arena holds its own copy of every image: release the host image
-  img = Image();
   return Status::ok();
 }
 

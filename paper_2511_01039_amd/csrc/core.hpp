@@ -128,7 +128,8 @@ struct PlanSet {
   std::string tag;
   // Host image of all plans of the set, concatenated with rebased ranges.
   // serialize() builds it (host only, safe on a planning thread); upload()
-  // copies it to the device (building it first if needed) and releases it.
+  // copies it to the device (building it first if needed). It is kept, so
+  // the same plans can be uploaded again for another site.
   struct Image {
     std::vector<GemmJob> jobs;
     std::vector<GemmPair> pairs;

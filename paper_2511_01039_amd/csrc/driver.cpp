@@ -567,6 +567,17 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     R.size = 1;
   }
   int rcur = 0;
+  // The previous site's analysis and plans: a site whose structure key,
+  // widths, budget and precision are equal reuses them (interior sites of a
+  // row often share their block structure) and only uploads them again.
+  struct PlanCache {
+    std::string key;
+    std::vector<Sector> sect;
+    std::vector<std::vector<int64_t>> unit_size;
+    std::shared_ptr<SiteOp::Plans> pl;
+    std::vector<int32_t> k;
+  } cache;
+  int cache_hits = 0;
   for (int x = 0; x < L; ++x) {
     BT T, K, W;
     FP_TRY(tensor_to_bt(&env_in[x], {N_a, N_tk, N_tw, N_tb, N_b}, nlab, T));
@@ -596,7 +607,14 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     const double tw0 = wall();
     SiteOp op;
     FP_TRY(op.init(sym, nlab, std::move(T), std::move(K), std::move(W), std::move(R), d));
-    FP_TRY(op.analyse());
+    std::string key = op.structure_key();
+    const bool same = !cache.key.empty() && key == cache.key;
+    if (same) {
+      op.sect = cache.sect;
+      op.unit_size = cache.unit_size;
+    } else {
+      FP_TRY(op.analyse());
+    }
     const int ns = (int)op.sect.size();
     SiteDiag& dg = ctx->diag[x];
     for (auto& s : op.sect) {
@@ -660,7 +678,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     }
     // randomized SVD of M_x
     RsvdIO io;
-    SiteOp::Plans pl;
+    std::shared_ptr<SiteOp::Plans> plp;
     for (int J = 0; J < ns; ++J) {
       io.m.push_back(op.sect[J].m);
       io.n.push_back(op.sect[J].n);
@@ -671,12 +689,21 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     double t_plan = 0;
     io.prepare = [&](const std::vector<int32_t>& k) {
       const double t0 = wall();
-      Status st = op.plan(ctx, k, budget, pl, true, f32);
+      Status st = Status::ok();
+      if (same && cache.pl && cache.k == k && cache.pl->f32 == f32) {
+        plp = cache.pl;
+        st = op.upload(ctx, *plp);
+        ++cache_hits;
+      } else {
+        plp = std::make_shared<SiteOp::Plans>();
+        st = op.plan_host(k, budget, *plp, true, f32);
+        if (st.good()) st = op.upload(ctx, *plp);
+      }
       t_plan += wall() - t0;
       return st;
     };
     io.apply = [&](bool t, bool fin, const double* xi, double* yo) {
-      return op.apply(ctx, pl, t, xi, yo, f32 && !fin);
+      return op.apply(ctx, *plp, t, xi, yo, f32 && !fin);
     };
     RsvdOut rs;
     const double tw1 = wall();
@@ -693,7 +720,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
       }
       double xl = 0, pk = 0;
       size_t tabs = 0;
-      for (const auto& sl : pl.slices) {
+      for (const auto& sl : plp->slices) {
         for (const RtPlan& r : sl.ps->rts) {
           xl += r.x_loads;
           pk += (double)r.pack_size;
@@ -701,12 +728,17 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
         tabs += sl.ps->pool.data.size();
       }
       std::fprintf(stderr,
-                   "[fpeps] site %d: sectors %d m %lld n %lld analyse %.3fs rsvd %.3fs (plan %.3fs) "
+                   "[fpeps] site %d%s: sectors %d m %lld n %lld analyse %.3fs rsvd %.3fs (plan %.3fs) "
                    "chain flops/app %.3e slices %zu ws %.2f GB table entries %zu layer loads "
                    "%.3e pack %.3e upload %.1f MB %.3fs\n",
-                   x, ns, (long long)mt, (long long)nt, tw1 - tw0, wall() - tw1, t_plan, pl.flops_fwd,
-                   pl.slices.size(), (pl.ws1 + pl.ws2) * 8e-9, tabs, xl, pk,
+                   x, same ? " (plans reused)" : "", ns, (long long)mt, (long long)nt, tw1 - tw0, wall() - tw1, t_plan, plp->flops_fwd,
+                   plp->slices.size(), (plp->ws1 + plp->ws2) * 8e-9, tabs, xl, pk,
                    ctx->plan_up_bytes * 1e-6, ctx->plan_up_seconds);
+    }
+    if (ctx->verbose >= 2) {
+      std::fprintf(stderr, "[fpeps] site %d kept", x);
+      for (int v : rs.kept) std::fprintf(stderr, " %d", v);
+      std::fprintf(stderr, "\n");
     }
     // outputs: environment site (U) and the next remainder (R)
     std::vector<int> sel;
@@ -793,6 +825,11 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     Rdev = Rbuf[rn];
     R_size = std::max<int64_t>(rt, 1);
     rcur = rn;
+    cache.key = std::move(key);
+    cache.sect = op.sect;
+    cache.unit_size = op.unit_size;
+    cache.pl = plp;
+    cache.k = rs.k;
     // diagnostics and report
     dg.k = rs.k;
     dg.kept = rs.kept;
@@ -802,7 +839,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
         dg.sigma.push_back(l > 0 ? std::sqrt(l) : 0.0);
         dg.sector.push_back(J);
       }
-    double site_flops = pl.flops_fwd * (2 + 2 * o->power_iters);
+    double site_flops = plp->flops_fwd * (2 + 2 * o->power_iters);
     for (int J = 0; J < ns; ++J) {
       const double m = (double)op.sect[J].m, n = (double)op.sect[J].n, k = rs.k[J],
                    c = rs.kept[J];
@@ -838,6 +875,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     rep->kept_total = kept_total;
     rep->nslices = ctx->nslices;
     rep->fallbacks = fallbacks;
+    rep->plan_reuses = cache_hits;
     rep->kernel_launches = (int32_t)ctx->kt_launches;
     rep->kernel_seconds = ctx->kt_seconds;
     rep->kernel_flops = ctx->kt_flops;

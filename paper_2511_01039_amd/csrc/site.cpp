@@ -282,6 +282,42 @@ BT SiteOp::omega_layout(const std::vector<SliceCol>& cols, const std::vector<int
 
 Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t budget, Plans& out,
                     bool with_bwd, bool f32) {
+  FP_TRY(plan_host(k, budget, out, with_bwd, f32));
+  return upload(ctx, out);
+}
+
+namespace {
+void key_put(std::string& s, const void* p, size_t n) { s.append((const char*)p, n); }
+void key_bt(std::string& s, const BT& bt) {
+  const int64_t nn = (int64_t)bt.names.size(), nb = (int64_t)bt.blocks.size();
+  key_put(s, &nn, sizeof nn);
+  key_put(s, bt.names.data(), bt.names.size() * sizeof(int));
+  for (const LegP& l : bt.cat) {
+    const int64_t h[3] = {l->nlab, l->dir, (int64_t)l->dim.size()};
+    key_put(s, h, sizeof h);
+    key_put(s, l->lab.data(), l->lab.size() * sizeof(int32_t));
+    key_put(s, l->dim.data(), l->dim.size() * sizeof(int32_t));
+  }
+  key_put(s, &nb, sizeof nb);
+  for (const Block& b : bt.blocks) {
+    key_put(s, b.sect.data(), nn * sizeof(uint16_t));
+    key_put(s, &b.base, sizeof b.base);
+    key_put(s, b.stride.data(), nn * sizeof(int64_t));
+  }
+  key_put(s, &bt.size, sizeof bt.size);
+}
+}  // namespace
+
+std::string SiteOp::structure_key() const {
+  std::string s;
+  const int64_t h[4] = {sym.kind, sym.fermionic ? 1 : 0, (int64_t)sym.coef_seed, nlab};
+  key_put(s, h, sizeof h);
+  for (const BT* b : {&T, &ket, &W, &bra, &R}) key_bt(s, *b);
+  return s;
+}
+
+Status SiteOp::plan_host(const std::vector<int32_t>& k, int64_t budget, Plans& out,
+                         bool with_bwd, bool f32) const {
   const int ns = (int)sect.size();
   if ((int)k.size() != ns) return fail(FPEPS_ERR_ARG, "width list does not match the sectors");
   out = Plans();
@@ -350,6 +386,17 @@ Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t bud
     for (auto& x : th) x.join();
   }
   for (auto& e : st) FP_TRY(e);
+  for (const Slice& sl : out.slices) {
+    out.flops_fwd += sl.flops_fwd;
+    out.flops_bwd += sl.flops_bwd;
+    out.ws1 = std::max(out.ws1, std::max(sl.size1, sl.bsize1));
+    out.ws2 = std::max(out.ws2, std::max(sl.size2, sl.bsize2));
+  }
+  return Status::ok();
+}
+
+Status SiteOp::upload(fpeps_ctx_s* ctx, Plans& out) const {
+  const bool f32 = out.f32;
   // uploads through the pinned arena, asynchronous on the stream
   const auto up0 = std::chrono::steady_clock::now();
   FP_TRY(ctx->stage_begin());
@@ -385,10 +432,6 @@ Status SiteOp::plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t bud
   for (size_t i = 0; i < sets.size(); ++i) FP_TRY(sets[i]->bind(ctx, tags[i], arena + region[i]));
   for (size_t i = 0; i < out.slices.size(); ++i) {
     Slice& sl = out.slices[i];
-    out.flops_fwd += sl.flops_fwd;
-    out.flops_bwd += sl.flops_bwd;
-    out.ws1 = std::max(out.ws1, std::max(sl.size1, sl.bsize1));
-    out.ws2 = std::max(out.ws2, std::max(sl.size2, sl.bsize2));
     // layer sub-blocks scaled by the per-pair scalars (the bra shares the
     // ket's data)
     for (int s = 0; s < 5; ++s) {

@@ -50,6 +50,11 @@ class SiteOp {
               const SiteData& d);
   // Sector structure (columns, rows via a structure-only forward pass).
   Status analyse();
+  // Everything the analysis and the plans depend on, serialised: symmetry,
+  // and the legs, block sectors, offsets and strides of T, ket, W, bra and
+  // R (not their data). Two sites with equal keys have equal sectors, and
+  // equal plans for equal widths.
+  std::string structure_key() const;
 
   // Plans of M (fwd) and M^T (bwd) for per-sector widths k, sliced so that
   // the chain intermediates of one slice fit ``budget`` bytes.
@@ -74,6 +79,12 @@ class SiteOp {
   };
   Status plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t budget, Plans& out,
               bool with_bwd = true, bool f32 = false);
+  // the two halves of plan(): host planning (no device work), and the upload
+  // of the plans with this site's packed layer blocks (plans of another site
+  // with the same structure key can be uploaded for this one)
+  Status plan_host(const std::vector<int32_t>& k, int64_t budget, Plans& out, bool with_bwd,
+                   bool f32) const;
+  Status upload(fpeps_ctx_s* ctx, Plans& pl) const;
   // y = M x (transpose = false) or M^T x, per-sector matrices at the offsets
   // of ``pl`` (x: col layout for M, row layout for M^T). ``f32`` stores the
   // chain intermediates of this application in FP32 (arithmetic stays FP64).

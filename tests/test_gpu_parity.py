@@ -239,6 +239,34 @@ def test_absorb_row_matches_oracle(ctx, name, kw, chi):
     assert abs(v_gpu - v_or) < 1e-11 * abs(v_or)
 
 
+def test_absorb_row_reuses_plans(ctx):
+    """A dense 6-site row whose interior sites share their block structure
+    (12 kept at every site): sites after the first interior one reuse the
+    previous site's analysis and plans with their own layer data. Kept
+    counts, singular values, log-norm and s_row still agree with the oracle."""
+    from oracle.zipup import absorb_row
+    from oracle.expect import overlap
+    from paper_2511_01039_amd import opts_for
+    row = wl.small_row(seed=3, oversample=4, power_iters=1, kind="none", L=6, d=2, D=3, w=2,
+                       chi=9)
+    env, lg, info = absorb_row(row.sym, row.T, row.A, row.W, 12, 4, 1, 17, row=row.row)
+    out, glg, rep = ctx.env_absorb(devs(row.T), devs(row.A), devs(row.W),
+                                   opts_for(row.sym, chi=12, oversample=4, power_iters=1, seed=17,
+                                            row=row.row))
+    print(f"plan reuses {rep['plan_reuses']}")
+    assert rep["plan_reuses"] >= 2
+    for x in range(len(env) - 1):
+        sig, sec, kept = ctx.absorb_diag(x)
+        assert list(kept) == list(info["kept"][x]), (x, kept, info["kept"][x])
+        want = np.concatenate([np.asarray(s) for s in info["sigma"][x]])
+        assert rel_err(sig, want) < 1e-11
+    bot = wl.random_bottom_env(row.sym, env, row.meta["cat"]["env"], np.random.default_rng(5))
+    v_or = overlap(env, bot) * math.exp(lg)
+    v_gpu = ctx.expect(out, devs(bot)) * math.exp(glg)
+    assert abs(glg - lg) < 1e-11 * max(1.0, abs(lg))
+    assert abs(v_gpu - v_or) < 1e-11 * abs(v_or)
+
+
 def test_config1_network_value(ctx):
     """Config 1: 4x4 dense lattice, <W> = Z_W / Z_1 top to bottom with chi = 32,
     rSVD (p = 8, q = 1): FP64 device path vs the oracle within 1e-11."""
