@@ -6,10 +6,14 @@ randomized-SVD truncation at every bond.
 
 A step is one full row absorption (8 sites: sketch, chain applications,
 orthonormalisation, projection, core factorisation, cut, new environment and
-remainder) on inputs resident in HBM. Prints one JSON line.
+remainder) on inputs resident in HBM. The timed steps run the library as a
+caller would (slices of a site alternate between two streams); the per-kernel
+figures of the roofline come from one more step on one stream with every
+launch timed by HIP events. Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--config 4]
-                    [--precision mixed-vs-fp64|fp64|fp32]
+                    [--precision mixed-vs-fp64|fp64|fp32] [--one-stream]
+                    [--lattice] [--config 5] [--calibrate-copy]
 """
 from __future__ import annotations
 
@@ -268,6 +272,8 @@ def main():
                     help="mixed-vs-fp64 (default): time both paths on the same row and report the "
                          "mixed one if its network value is within 1e-6 of FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="run every slice on one stream (no overlap of slices)")
     ap.add_argument("--lattice", action="store_true",
                     help="<W> of the full 8x8 lattice at the headline shapes, FP64 and mixed")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -298,7 +304,7 @@ def main():
         bench_lattice(a)
         return
     from paper_2511_01039_amd import Context, DeviceTensor, opts_for
-    from paper_2511_01039_amd.binding import FLAG_TIME_KERNELS
+    from paper_2511_01039_amd.binding import FLAG_TIME_KERNELS, FLAG_ONE_STREAM
     import numpy as np
     import workloads as wl
     row, desc, bond = workload(a.config)
@@ -310,8 +316,13 @@ def main():
         """W untimed + K timed absorptions of the row; device-resident inputs."""
         kw = dict(chi=row.chi, oversample=row.oversample, power_iters=row.power_iters, seed=0,
                   row=row.row, precision=precision)
-        opts = opts_for(row.sym, **kw)
-        topts = opts_for(row.sym, flags=FLAG_TIME_KERNELS, **kw)
+        # timed steps: the library's default two streams (slices overlap);
+        # kernel figures: one more step on one stream with every launch timed
+        # by HIP events (overlapping launches would stretch each other's
+        # durations)
+        base = FLAG_ONE_STREAM if a.one_stream else 0
+        opts = opts_for(row.sym, flags=base, **kw)
+        kopts = opts_for(row.sym, flags=FLAG_ONE_STREAM | FLAG_TIME_KERNELS, **kw)
         caps = None
         for i in range(a.warmup):
             out, lg, rep = ctx.env_absorb(T, A, W, opts, caps=caps)
@@ -325,16 +336,20 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(a.steps):
-            out, lg, rep = ctx.env_absorb(T, A, W, topts, caps=caps)
+            out, lg, rep = ctx.env_absorb(T, A, W, opts, caps=caps)
             r["flops"] += rep["alg_flops"]
             r["dev_s"] += rep["seconds"]
-            for k in cls:
-                cls[k] += rep[k]
             print(f"{precision} step {i}: {rep['seconds']:.3f} s device", file=sys.stderr,
                   flush=True)
         torch.cuda.synchronize()
         r["sec"] = (time.perf_counter() - t0) / a.steps
         r["value"] = r["flops"] / a.steps / r["sec"] / 1e12
+        _, _, krep = ctx.env_absorb(T, A, W, kopts, caps=caps)
+        for k in cls:
+            cls[k] = krep[k]
+        r["kernel_step_s"] = krep["seconds"]
+        print(f"{precision} kernel-timing step (one stream): {krep['seconds']:.3f} s device",
+              file=sys.stderr, flush=True)
         r["cls"], r["out"], r["lg"] = cls, out, lg
         return r
 
@@ -370,7 +385,7 @@ def main():
         roof = {"bound": "hbm", "achieved": layer_gbs, "peak": HBM_PEAK, "unit": "GB/s",
                 "frac": layer_gbs / HBM_PEAK, "traffic": profiled_traffic("k_rt_f64", rep_prec),
                 "kernel": "k_rt_f64 (ket/PEPO/bra layer steps and transposes)",
-                "launches_per_step": cls["layer_launches"] / a.steps,
+                "launches_per_step": cls["layer_launches"],
                 "avg_launch_ms": 1e3 * lay_s / nl,
                 "bytes_per_launch": cls["layer_bytes"] / nl}
     else:
@@ -378,14 +393,17 @@ def main():
         roof = {"bound": "mfma", "achieved": gemm_tfs, "peak": PEAK["fp64"], "unit": "TFLOP/s",
                 "frac": gemm_tfs / PEAK["fp64"], "traffic": profiled_traffic("k_gemm_f64", rep_prec),
                 "kernel": "k_gemm_f64 (environment/remainder contractions)",
-                "launches_per_step": cls["gemm_launches"] / a.steps,
+                "launches_per_step": cls["gemm_launches"],
                 "avg_launch_ms": 1e3 * gem_s / ng,
                 "flops_per_launch": cls["gemm_flops"] / ng}
     roof["kernels"] = {
-        "k_rt_f64": {"seconds_per_step": lay_s / a.steps, "GB/s": layer_gbs,
+        "k_rt_f64": {"seconds_per_step": lay_s, "GB/s": layer_gbs,
                      "frac_hbm": layer_gbs / HBM_PEAK},
-        "k_gemm_f64": {"seconds_per_step": gem_s / a.steps, "TFLOP/s": gemm_tfs,
+        "k_gemm_f64": {"seconds_per_step": gem_s, "TFLOP/s": gemm_tfs,
                        "frac_fp64_mfma": gemm_tfs / PEAK["fp64"]}}
+    roof["timing"] = ("HIP events around every launch, one extra step of the same row on one "
+                      "stream (launches do not overlap); the timed steps run slices on two "
+                      "streams")
     line = {"metric": METRIC, "value": R["value"], "unit": "TFLOP/s", "n_gpus": 1,
             "steps": a.steps, "warmup": a.warmup, "ms_per_step": R["sec"] * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

@@ -125,7 +125,9 @@ typedef struct {
   int32_t symmetry;       /* fpeps_symmetry */
   int32_t fermionic;      /* 1: parity sign on every contracted block pair */
   uint64_t coef_seed;     /* SU(2): key of the synthetic recoupling scalars */
-  int64_t slice_budget;   /* bytes for chain intermediates per slice (0: automatic) */
+  int64_t slice_budget;   /* bytes for chain intermediates per slice (0: automatic). The
+                             slices of a site alternate between two streams, so two
+                             slices' intermediates are live (see FPEPS_FLAG_ONE_STREAM) */
   uint32_t flags;         /* FPEPS_FLAG_* */
   int32_t tag;            /* explicit-matrix calls: counter word c2 of the sketch */
   double sv_cut;          /* singular values <= sv_cut * largest are never kept
@@ -135,6 +137,8 @@ typedef struct {
 #define FPEPS_FLAG_NO_GRAPH 1u      /* do not capture per-site launch sequences */
 #define FPEPS_FLAG_CHECK_FINITE 2u  /* scan inputs for NaN/Inf first */
 #define FPEPS_FLAG_TIME_KERNELS 4u  /* time every chain launch with HIP events */
+#define FPEPS_FLAG_ONE_STREAM 8u    /* run every slice on the context's stream (one set of
+                                       chain intermediates; no overlap of slices) */
 
 typedef struct {
   double alg_flops;        /* algorithmic flop count (block-pair GEMMs + factorisations) */

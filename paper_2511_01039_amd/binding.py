@@ -22,7 +22,7 @@ STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_SYMMETRY", -4: "ERR_
           -9: "ERR_NODEVICE"}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 SYM = {"none": 0, "u1u1": 1, "su2": 2}
-FLAG_NO_GRAPH, FLAG_CHECK_FINITE, FLAG_TIME_KERNELS = 1, 2, 4
+FLAG_NO_GRAPH, FLAG_CHECK_FINITE, FLAG_TIME_KERNELS, FLAG_ONE_STREAM = 1, 2, 4, 8
 
 
 class FpepsError(RuntimeError):

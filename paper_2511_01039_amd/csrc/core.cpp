@@ -5,11 +5,21 @@
 #include <cstring>
 
 fpeps_ctx_s::~fpeps_ctx_s() {
-  if (!bufs.empty() || !evpool.empty() || stage) (void)hipDeviceSynchronize();
+  if (!bufs.empty() || !evpool.empty() || stage || stream2) (void)hipDeviceSynchronize();
   for (auto e : evpool) (void)hipEventDestroy(e);
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  if (stream2) (void)hipStreamDestroy(stream2);
   for (auto& kv : bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (stage) (void)hipHostFree(stage);
+}
+
+fp::Status fpeps_ctx_s::ensure_stream2() {
+  if (!stream2) FP_HIP(hipStreamCreateWithFlags(&stream2, hipStreamNonBlocking));
+  if (!ev_fork) FP_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+  if (!ev_join) FP_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  return fp::Status::ok();
 }
 
 fp::Status fpeps_ctx_s::stage_begin() {
@@ -373,7 +383,10 @@ Status run_gemm_mixed(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double
   if (b_f32 && c_f32) return fail(FPEPS_ERR_UNSUPPORTED, "GEMM with both B and C in FP32");
   // split-K parts are summed in FP64 and rounded once into C
   double* part = nullptr;
-  if (p.partial_size > 0) FP_TRY(ctx->bufT("gemm_part", (size_t)p.partial_size, &part));
+  // each stream has its own partial buffer (slices on two streams overlap)
+  if (p.partial_size > 0)
+    FP_TRY(ctx->bufT(ctx->stream2 && ctx->stream == ctx->stream2 ? "gemm_part2" : "gemm_part",
+                     (size_t)p.partial_size, &part));
   hipEvent_t ea = nullptr, eb = nullptr;
   const bool tk = timed && ctx->time_kernels;
   if (tk) {

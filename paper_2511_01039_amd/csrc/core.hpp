@@ -60,6 +60,12 @@ struct SiteDiag {
 struct fpeps_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
+  // second stream for alternate slices of a site (default priority; created
+  // on first use), with the fork and join events between the two
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool two_streams = true;   // cleared by FPEPS_FLAG_ONE_STREAM
+  fp::Status ensure_stream2();
   std::string err;
   std::map<std::string, fp::DevBuf> bufs;
   std::vector<fp::SiteDiag> diag;

@@ -512,6 +512,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
   ctx->peak_ws = 0;
   ctx->nslices = 0;
   ctx->time_kernels = (o->flags & FPEPS_FLAG_TIME_KERNELS) != 0;
+  ctx->two_streams = (o->flags & FPEPS_FLAG_ONE_STREAM) == 0;
   ctx->kt_seconds = ctx->kt_flops = 0;
   ctx->kt_launches = 0;
   ctx->evused = 0;
@@ -739,6 +740,39 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
       std::fprintf(stderr, "[fpeps] site %d kept", x);
       for (int v : rs.kept) std::fprintf(stderr, " %d", v);
       std::fprintf(stderr, "\n");
+      // GEMM steps: jobs, 16-deep K tiles per job, tile shapes
+      const int steps[4] = {1, 5, 11, 15};
+      for (int st : steps) {
+        double jobs = 0, tiles = 0, small = 0, mts = 0, nts = 0, nplan = 0;
+        for (const auto& sl : plp->slices) {
+          const bool bwd = st > 10;
+          const int idx = bwd ? sl.bwd[st == 15 ? 0 : 4] : sl.fwd[st == 1 ? 0 : 4];
+          const PlanSet* ps = bwd ? sl.psb.get() : sl.ps.get();
+          if (!ps || idx < 0) continue;
+          const GemmPlan& g = ps->plans[idx];
+          for (const GemmJob& j : g.jobs) {
+            int64_t t = 0;
+            for (int q = j.p0; q < j.p1; ++q) {
+              const int64_t k0 = std::max(j.k0, 0), k1 = std::min<int64_t>(j.k1, g.pairs[q].K);
+              if (k1 > k0) t += (k1 - k0 + 15) / 16;
+            }
+            jobs += 1;
+            tiles += (double)t;
+            if (t <= 4) small += 1;
+          }
+          if (!g.jobs.empty()) {
+            mts += g.mt;
+            nts += g.nt;
+            nplan += 1;
+          }
+        }
+        std::fprintf(stderr,
+                     "[fpeps] site %d gemm step %s%d: %.0f jobs, %.1f K tiles per job, %.0f%% of "
+                     "jobs with <= 4 tiles, mean tile %.0fx%.0f\n",
+                     x, st > 10 ? "T" : "", st > 10 ? st - 10 : st, jobs,
+                     jobs > 0 ? tiles / jobs : 0.0, jobs > 0 ? 100.0 * small / jobs : 0.0,
+                     mts / std::max(nplan, 1.0), nts / std::max(nplan, 1.0));
+      }
     }
     // outputs: environment site (U) and the next remainder (R)
     std::vector<int> sel;

@@ -29,6 +29,8 @@ template <int MT, int NT, int KT>
 struct TileRegs {
   double a[(MT * KT) / 256];
   double b[(NT * KT) / 256];
+  double alpha;
+  uint32_t valid;   // bit i: a[i] in range; bit NA + i: b[i] in range
   bool akf, bnf;
 };
 
@@ -51,17 +53,19 @@ __device__ __forceinline__ void load_tile(const double* __restrict__ A,
   r.bnf = pr.flags & 2;
   // branch-free: indices are clamped into the block (always a valid
   // address), every table and data load of the tile is issued before any is
-  // used, and out-of-range elements are zeroed afterwards
+  // used, and out-of-range elements are zeroed when the tile is stored to LDS
+  // (after the current tile's products, so the loads stay in flight meanwhile)
   constexpr int NA = (MT * KT) / 256, NB = (NT * KT) / 256;
+  static_assert(NA + NB <= 32, "validity mask");
   int32_t oa[NA], ob[NB];
-  bool va[NA], vb[NB];
+  uint32_t valid = 0;
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
     const int e = tid + i * 256;
     const int mm = r.akf ? e / KT : e % MT;
     const int kk = r.akf ? e % KT : e / MT;
     const int m = job.m0 + mm, k = t.kb + kk;
-    va[i] = m < job.M && k < kend;
+    valid |= (m < job.M && k < kend) ? (1u << i) : 0u;
     oa[i] = tam[min(m, job.M - 1)] + tak[min(k, kend - 1)];
   }
 #pragma unroll
@@ -70,35 +74,34 @@ __device__ __forceinline__ void load_tile(const double* __restrict__ A,
     const int nn = r.bnf ? e % NT : e / KT;
     const int kk = r.bnf ? e / NT : e % KT;
     const int n = job.n0 + nn, k = t.kb + kk;
-    vb[i] = n < job.N && k < kend;
+    valid |= (n < job.N && k < kend) ? (1u << (NA + i)) : 0u;
     ob[i] = tbk[min(k, kend - 1)] + tbn[min(n, job.N - 1)];
   }
 #pragma unroll
   for (int i = 0; i < NA; ++i) r.a[i] = Ab[oa[i]];
 #pragma unroll
   for (int i = 0; i < NB; ++i) r.b[i] = (double)Bb[ob[i]];
-#pragma unroll
-  for (int i = 0; i < NA; ++i) r.a[i] = va[i] ? r.a[i] * pr.alpha : 0.0;
-#pragma unroll
-  for (int i = 0; i < NB; ++i) r.b[i] = vb[i] ? r.b[i] : 0.0;
+  r.alpha = pr.alpha;
+  r.valid = valid;
 }
 
 template <int MT, int NT, int KT>
 __device__ __forceinline__ void store_tile(double (*sA)[MT + 1], double (*sB)[NT + 1], int tid,
                                            const TileRegs<MT, NT, KT>& r) {
+  constexpr int NA = (MT * KT) / 256;
 #pragma unroll
-  for (int i = 0; i < (MT * KT) / 256; ++i) {
+  for (int i = 0; i < NA; ++i) {
     const int e = tid + i * 256;
     const int mm = r.akf ? e / KT : e % MT;
     const int kk = r.akf ? e % KT : e / MT;
-    sA[kk][mm] = r.a[i];
+    sA[kk][mm] = (r.valid >> i) & 1u ? r.a[i] * r.alpha : 0.0;
   }
 #pragma unroll
   for (int i = 0; i < (NT * KT) / 256; ++i) {
     const int e = tid + i * 256;
     const int nn = r.bnf ? e % NT : e / KT;
     const int kk = r.bnf ? e / NT : e % KT;
-    sB[kk][nn] = r.b[i];
+    sB[kk][nn] = (r.valid >> (NA + i)) & 1u ? r.b[i] : 0.0;
   }
 }
 

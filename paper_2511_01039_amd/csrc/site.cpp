@@ -549,34 +549,62 @@ Status SiteOp::plan_slice(const std::vector<int32_t>& k, const Plans& pl, Slice&
 Status SiteOp::apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const double* x, double* y,
                      bool f32) {
   const size_t es = f32 ? sizeof(float) : sizeof(double);
-  void *b1 = nullptr, *b2 = nullptr;
-  FP_TRY(ctx->buf("chain1", (size_t)std::max<int64_t>(pl.ws1, 1) * es + 256, &b1));
-  FP_TRY(ctx->buf("chain2", (size_t)std::max<int64_t>(pl.ws2, 1) * es + 256, &b2));
   const int64_t s1 = std::max<int64_t>(pl.ws1, 1), s2 = std::max<int64_t>(pl.ws2, 1);
+  // Slices are independent (disjoint sketch columns, disjoint outputs): they
+  // alternate between the context's stream and a second one, each with its
+  // own ping-pong intermediates, so the GEMM steps of one slice can run
+  // beside the layer steps of the next.
+  const bool two = ctx->two_streams && pl.slices.size() > 1;
+  void* b[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  FP_TRY(ctx->buf("chain1", (size_t)s1 * es + 256, &b[0][0]));
+  FP_TRY(ctx->buf("chain2", (size_t)s2 * es + 256, &b[0][1]));
+  hipStream_t s0 = ctx->stream;
+  if (two) {
+    FP_TRY(ctx->ensure_stream2());
+    FP_TRY(ctx->buf("chain1b", (size_t)s1 * es + 256, &b[1][0]));
+    FP_TRY(ctx->buf("chain2b", (size_t)s2 * es + 256, &b[1][1]));
+    // the second stream starts after everything queued so far (x is ready)
+    FP_HIP(hipEventRecord(ctx->ev_fork, s0));
+    FP_HIP(hipStreamWaitEvent(ctx->stream2, ctx->ev_fork, 0));
+  }
+  ctx->peak_ws = std::max(ctx->peak_ws, (double)(s1 + s2) * (double)es * (two ? 2.0 : 1.0));
   const bool f = f32;
-  for (const Slice& sl : pl.slices) {
-    const PlanSet& ps = *sl.ps;
+  auto run_slice = [&](const Slice& sl, void* c1, void* c2) -> Status {
     if (!transpose) {
-      FP_TRY(run_gemm_mixed(ctx, ps, sl.fwd[0], dev.T, dev.T_size, x, false, pl.col_total, b1, f,
+      const PlanSet& ps = *sl.ps;
+      FP_TRY(run_gemm_mixed(ctx, ps, sl.fwd[0], dev.T, dev.T_size, x, false, pl.col_total, c1, f,
                             s1, true, 1));
-      FP_TRY(run_rt(ctx, ps, sl.fwd[1], b1, s1, b2, s2, f, true, 2));
-      FP_TRY(run_rt(ctx, ps, sl.fwd[2], b2, s2, b1, s1, f, true, 3));
-      FP_TRY(run_rt(ctx, ps, sl.fwd[3], b1, s1, b2, s2, f, true, 4));
-      FP_TRY(run_gemm_mixed(ctx, ps, sl.fwd[4], dev.R, dev.R_size, b2, f, s2, y, false,
+      FP_TRY(run_rt(ctx, ps, sl.fwd[1], c1, s1, c2, s2, f, true, 2));
+      FP_TRY(run_rt(ctx, ps, sl.fwd[2], c2, s2, c1, s1, f, true, 3));
+      FP_TRY(run_rt(ctx, ps, sl.fwd[3], c1, s1, c2, s2, f, true, 4));
+      FP_TRY(run_gemm_mixed(ctx, ps, sl.fwd[4], dev.R, dev.R_size, c2, f, s2, y, false,
                             pl.row_total, true, 5));
     } else {
       if (sl.bwd[0] < 0 || !sl.psb) return fail(FPEPS_ERR_ARG, "transposed chain was not planned");
       const PlanSet& psb = *sl.psb;
-      FP_TRY(run_gemm_mixed(ctx, psb, sl.bwd[0], dev.R, dev.R_size, x, false, pl.row_total, b2, f,
+      FP_TRY(run_gemm_mixed(ctx, psb, sl.bwd[0], dev.R, dev.R_size, x, false, pl.row_total, c2, f,
                             s2, true, 15));
-      FP_TRY(run_rt(ctx, psb, sl.bwd[1], b2, s2, b1, s1, f, true, 14));
-      FP_TRY(run_rt(ctx, psb, sl.bwd[2], b1, s1, b2, s2, f, true, 13));
-      FP_TRY(run_rt(ctx, psb, sl.bwd[3], b2, s2, b1, s1, f, true, 12));
-      FP_TRY(run_gemm_mixed(ctx, psb, sl.bwd[4], dev.T, dev.T_size, b1, f, s1, y, false,
+      FP_TRY(run_rt(ctx, psb, sl.bwd[1], c2, s2, c1, s1, f, true, 14));
+      FP_TRY(run_rt(ctx, psb, sl.bwd[2], c1, s1, c2, s2, f, true, 13));
+      FP_TRY(run_rt(ctx, psb, sl.bwd[3], c2, s2, c1, s1, f, true, 12));
+      FP_TRY(run_gemm_mixed(ctx, psb, sl.bwd[4], dev.T, dev.T_size, c1, f, s1, y, false,
                             pl.col_total, true, 11));
     }
+    return Status::ok();
+  };
+  Status st = Status::ok();
+  for (size_t i = 0; i < pl.slices.size() && st.good(); ++i) {
+    const int q = two ? (int)(i & 1) : 0;
+    ctx->stream = q ? ctx->stream2 : s0;
+    st = run_slice(pl.slices[i], b[q][0], b[q][1]);
   }
-  return Status::ok();
+  ctx->stream = s0;
+  if (two) {
+    // the context's stream continues after both
+    FP_HIP(hipEventRecord(ctx->ev_join, ctx->stream2));
+    FP_HIP(hipStreamWaitEvent(s0, ctx->ev_join, 0));
+  }
+  return st;
 }
 
 }  // namespace fp
