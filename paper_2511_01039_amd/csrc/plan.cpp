@@ -798,7 +798,9 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
           int32_t snmax = 0;
           for (int64_t e = n0; e < n0 + nc; ++e) snmax = std::max(snmax, all[e]);
           rt.s_extent = std::max(rt.s_extent, sb.base + skmax + snmax + 1);
-          auto key = std::make_pair(t.sb, n0);
+          // keyed by the chunk's first column and its width (a block may be
+          // chunked differently in another group)
+          auto key = std::make_pair(t.sb, n0 * (RT_NC + 1) + nc);
           auto it = c_snt.find(key);
           if (it == c_snt.end())
             it = c_snt.emplace(key, pool.add_raw(std::vector<int32_t>(all.begin() + n0,

@@ -133,6 +133,33 @@ def test_site_chain_slicing_is_invariant(ctx):
     assert torch.equal(y0[:tot], y1[:tot])
 
 
+def test_two_streams_match_one_stream(ctx):
+    """Slices alternate between two streams by default; the products are the
+    same bit for bit as with every slice on one stream, forward and
+    transposed."""
+    import torch
+    from paper_2511_01039_amd import opts_for
+    from paper_2511_01039_amd.binding import FLAG_ONE_STREAM
+    row = wl.small_row("u1u1", L=3, seed=2, env_scale=3, virt_scale=2)
+    rng = np.random.default_rng(3)
+    Rt = remainder_tensor(row.sym, row, 1, row.meta["cat"]["env"], rng)
+    o = opts_for(row.sym)
+    lab, m, n = ctx.site_shape(dev(Rt), dev(row.T[1]), dev(row.A[1]), dev(row.W[1]), o)
+    k = [5] * len(m)
+    for transpose in (False, True):
+        rows_in, rows_out = (m, n) if transpose else (n, m)
+        X = torch.from_numpy(rng.standard_normal(int(sum(rows_in)) * 5)).cuda()
+        tot = int(sum(rows_out)) * 5
+        ys = []
+        for flags in (0, FLAG_ONE_STREAM):
+            o2 = opts_for(row.sym, slice_budget=20000, flags=flags)
+            y, r = ctx.site_apply(dev(Rt), dev(row.T[1]), dev(row.A[1]), dev(row.W[1]), o2, k, X,
+                                  transpose=transpose, out_elems=tot)
+            assert r["nslices"] > 2
+            ys.append(y[:tot].clone())
+        assert torch.equal(ys[0], ys[1])
+
+
 def prescribed(m, n, sig, seed):
     rng = np.random.default_rng(seed)
     r = len(sig)
