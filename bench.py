@@ -59,7 +59,9 @@ def bench_config5(a):
     spectrum; a step is, for every site, one rSVD truncation of all its
     sectors (chi = 256, p = 8, q = 1, one cut over the sectors) and one
     controlled bond expansion by ceil(0.1 chi) = 26 directions orthogonal to
-    the kept left and right spaces (q = 0)."""
+    the kept left and right spaces (q = 0). All sites go in one grouped
+    truncation call and one grouped expansion call (each site its own
+    problem); ``--per-site`` makes one call of each per site instead."""
     import torch
     import numpy as np
     import workloads as wl
@@ -91,20 +93,24 @@ def bench_config5(a):
                       seed=0, tag=0)
     copts = make_opts(cbe_extra=cfg["cbe_extra"], oversample=cfg["cbe_oversample"], seed=0, tag=1)
 
+    def truncate_expand(mats, group):
+        U, R, sig, kept, rep = ctx.rsvd_truncate(mats, ropts, group=group)
+        # kept right space V (rows orthonormal): R = S V^T
+        Us, Vs = [], []
+        for u, rr, sg, k in zip(U, R, sig, kept):
+            sg_t = torch.as_tensor(np.asarray(sg[:k]), device="cuda", dtype=torch.float64)
+            Us.append(u)
+            Vs.append((rr / sg_t[:, None]).contiguous() if k > 0 else rr)
+        Q, csig, ckept, crep = ctx.cbe_expand(mats, Us, Vs, copts, group=group)
+        return rep["alg_flops"] + crep["alg_flops"]
+
+    all_mats = [a for mats in sites for a in mats]
+    all_group = [g for g, mats in enumerate(sites) for _ in mats]
+
     def step():
-        flops = 0.0
-        for mats in sites:
-            U, R, sig, kept, rep = ctx.rsvd_truncate(mats, ropts)
-            flops += rep["alg_flops"]
-            # kept right space V (rows orthonormal): R = S V^T
-            Us, Vs = [], []
-            for u, rr, sg, k in zip(U, R, sig, kept):
-                sg_t = torch.as_tensor(np.asarray(sg[:k]), device="cuda", dtype=torch.float64)
-                Us.append(u)
-                Vs.append((rr / sg_t[:, None]).contiguous() if k > 0 else rr)
-            Q, csig, ckept, crep = ctx.cbe_expand(mats, Us, Vs, copts)
-            flops += crep["alg_flops"]
-        return flops
+        if a.per_site:
+            return sum(truncate_expand(mats, None) for mats in sites)
+        return truncate_expand(all_mats, all_group)
 
     for _ in range(a.warmup):
         step()
@@ -125,6 +131,7 @@ def bench_config5(a):
                                    "U(1)xU(1) chi=256 row; per site all sector matrices "
                                    f"({nmat} matrices, sides {min(sides)}-{max(sides)}), "
                                    "rSVD chi=256 p=8 q=1 then CBE 26 directions p=8 q=0",
+                       "calls": "one per site" if a.per_site else "one grouped call per kind",
                        "alg_flops_per_step": flops / a.steps,
                        "tflops": flops / a.steps / sec / 1e12}}
     print(json.dumps(line), flush=True)
@@ -272,6 +279,8 @@ def main():
                     help="mixed-vs-fp64 (default): time both paths on the same row and report the "
                          "mixed one if its network value is within 1e-6 of FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--per-site", action="store_true",
+                    help="config 5: one truncation and one expansion call per site")
     ap.add_argument("--one-stream", action="store_true",
                     help="run every slice on one stream (no overlap of slices)")
     ap.add_argument("--lattice", action="store_true",

@@ -235,6 +235,22 @@ fpeps_status fpeps_rsvd_truncate(fpeps_ctx ctx, int32_t nmat, const int64_t* m,
                                  double* const* R_out, int32_t* kept, double* sigma,
                                  fpeps_report* report);
 
+/* The same for several independent truncation problems in one call (for
+ * instance the per-site truncations of a row, Sec. 4; the batching of all of
+ * a row's truncations into grouped launches): matrix i belongs to problem
+ * group[i] (host array, values 0 .. nmat-1). Each group has its own sketch
+ * widths and its own cut to opts->chi; its sketch counters are
+ * (element/2, ordinal of the matrix inside its group, opts->tag + group[i], 0).
+ * A grouped call therefore returns what one fpeps_rsvd_truncate call per
+ * group (matrices in the same order, tag + g) returns, up to rounding order.
+ * The report gives the smallest relative gap and the largest discarded
+ * weight over the groups. */
+fpeps_status fpeps_rsvd_truncate_grouped(fpeps_ctx ctx, int32_t nmat, const int64_t* m,
+                                         const int64_t* n, const double* const* A,
+                                         const int32_t* group, const fpeps_opts* opts,
+                                         double* const* U_out, double* const* R_out,
+                                         int32_t* kept, double* sigma, fpeps_report* report);
+
 /* Controlled bond expansion of explicit matrices: for each A_i (m_i x n_i)
  * with kept left space U_i (m_i x r_i, orthonormal columns) and kept right
  * space V_i (r_i x n_i, orthonormal rows), the opts->cbe_extra most weighty
@@ -247,6 +263,17 @@ fpeps_status fpeps_cbe_expand(fpeps_ctx ctx, int32_t nmat, const int64_t* m, con
                               const double* const* U, const double* const* V,
                               const fpeps_opts* opts, double* const* Q_out, int32_t* kept,
                               double* sigma, fpeps_report* report);
+
+/* Bond expansion of several independent problems in one call: group[i] as in
+ * fpeps_rsvd_truncate_grouped; opts->cbe_extra directions per group, sketch
+ * counters (element/2, ordinal inside the group, opts->tag + group[i],
+ * 1 << 16). */
+fpeps_status fpeps_cbe_expand_grouped(fpeps_ctx ctx, int32_t nmat, const int64_t* m,
+                                      const int64_t* n, const double* const* A,
+                                      const int32_t* group, const int32_t* r,
+                                      const double* const* U, const double* const* V,
+                                      const fpeps_opts* opts, double* const* Q_out,
+                                      int32_t* kept, double* sigma, fpeps_report* report);
 
 /* Network value of a top environment (L sites) and a bottom environment
  * whose bundle legs (k, w, b') match the top's: the contraction of all

@@ -108,6 +108,14 @@ def load():
                               P(C.c_void_p), P(C.c_int32), P(C.c_void_p), P(C.c_void_p),
                               P(COpts), P(C.c_void_p), P(C.c_int32), P(C.c_double),
                               P(CReport)], C.c_int),
+        "fpeps_rsvd_truncate_grouped": ([C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_int64),
+                                         P(C.c_void_p), P(C.c_int32), P(COpts), P(C.c_void_p),
+                                         P(C.c_void_p), P(C.c_int32), P(C.c_double), P(CReport)],
+                                        C.c_int),
+        "fpeps_cbe_expand_grouped": ([C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_int64),
+                                      P(C.c_void_p), P(C.c_int32), P(C.c_int32), P(C.c_void_p),
+                                      P(C.c_void_p), P(COpts), P(C.c_void_p), P(C.c_int32),
+                                      P(C.c_double), P(CReport)], C.c_int),
         "fpeps_expect": ([C.c_void_p, C.c_int32, T, T, P(C.c_double)], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -121,7 +129,8 @@ def load():
 def exported_symbols():
     return ["fpeps_version", "fpeps_create", "fpeps_destroy", "fpeps_set_stream",
             "fpeps_last_error", "fpeps_env_absorb", "fpeps_absorb_diag", "fpeps_site_shape",
-            "fpeps_site_apply", "fpeps_rsvd_truncate", "fpeps_cbe_expand", "fpeps_expect"]
+            "fpeps_site_apply", "fpeps_rsvd_truncate", "fpeps_rsvd_truncate_grouped",
+            "fpeps_cbe_expand", "fpeps_cbe_expand_grouped", "fpeps_expect"]
 
 
 def _i32(a):
@@ -313,8 +322,10 @@ class Context:
                                              C.byref(rep)))
         return y, rep.as_dict()
 
-    def rsvd_truncate(self, mats, opts):
-        """mats: list of 2-D torch float64 device tensors. Returns U, R, sigma, kept, report."""
+    def rsvd_truncate(self, mats, opts, group=None):
+        """mats: list of 2-D torch float64 device tensors; group (optional): the
+        truncation problem of every matrix (fpeps_rsvd_truncate_grouped).
+        Returns U, R, sigma, kept, report."""
         import torch
         _check_dense(mats)
         nm = len(mats)
@@ -330,9 +341,18 @@ class Context:
         kept = np.zeros(nm, np.int32)
         sig = np.zeros(int(sum(min(a, b) for a, b in zip(m, n))) + 1)
         rep = CReport()
-        self.check(self.lib.fpeps_rsvd_truncate(self.h, nm, _ptr(m, C.c_int64), _ptr(n, C.c_int64), A,
-                                                C.byref(opts), Up, Rp, _ptr(kept, C.c_int32),
-                                                _ptr(sig, C.c_double), C.byref(rep)))
+        if group is None:
+            self.check(self.lib.fpeps_rsvd_truncate(self.h, nm, _ptr(m, C.c_int64),
+                                                    _ptr(n, C.c_int64), A, C.byref(opts), Up, Rp,
+                                                    _ptr(kept, C.c_int32), _ptr(sig, C.c_double),
+                                                    C.byref(rep)))
+        else:
+            g = _i32(group)
+            self.check(self.lib.fpeps_rsvd_truncate_grouped(self.h, nm, _ptr(m, C.c_int64),
+                                                            _ptr(n, C.c_int64), A,
+                                                            _ptr(g, C.c_int32), C.byref(opts), Up,
+                                                            Rp, _ptr(kept, C.c_int32),
+                                                            _ptr(sig, C.c_double), C.byref(rep)))
         Us = [U[i][:int(m[i] * kept[i])].reshape(int(m[i]), int(kept[i])) for i in range(nm)]
         Rs = [R[i][:int(n[i] * kept[i])].reshape(int(kept[i]), int(n[i])) for i in range(nm)]
         sigs, p = [], 0
@@ -341,7 +361,9 @@ class Context:
             p += kept[i]
         return Us, Rs, sigs, kept, rep.as_dict()
 
-    def cbe_expand(self, mats, U, V, opts):
+    def cbe_expand(self, mats, U, V, opts, group=None):
+        """Bond expansion directions orthogonal to U and V (group as in
+        rsvd_truncate). Returns Q, sigma, kept, report."""
         import torch
         _check_dense(mats)
         nm = len(mats)
@@ -361,10 +383,18 @@ class Context:
         kept = np.zeros(nm, np.int32)
         sig = np.zeros(int(sum(min(a, b) for a, b in zip(m, n))) + 1)
         rep = CReport()
-        self.check(self.lib.fpeps_cbe_expand(self.h, nm, _ptr(m, C.c_int64), _ptr(n, C.c_int64), A,
-                                             _ptr(r, C.c_int32), Up, Vp, C.byref(opts), Qp,
-                                             _ptr(kept, C.c_int32), _ptr(sig, C.c_double),
-                                             C.byref(rep)))
+        if group is None:
+            self.check(self.lib.fpeps_cbe_expand(self.h, nm, _ptr(m, C.c_int64),
+                                                 _ptr(n, C.c_int64), A, _ptr(r, C.c_int32), Up, Vp,
+                                                 C.byref(opts), Qp, _ptr(kept, C.c_int32),
+                                                 _ptr(sig, C.c_double), C.byref(rep)))
+        else:
+            g = _i32(group)
+            self.check(self.lib.fpeps_cbe_expand_grouped(self.h, nm, _ptr(m, C.c_int64),
+                                                         _ptr(n, C.c_int64), A, _ptr(g, C.c_int32),
+                                                         _ptr(r, C.c_int32), Up, Vp, C.byref(opts),
+                                                         Qp, _ptr(kept, C.c_int32),
+                                                         _ptr(sig, C.c_double), C.byref(rep)))
         Qs = [Q[i][:int(m[i] * kept[i])].reshape(int(m[i]), int(kept[i])) for i in range(nm)]
         sigs, p = [], 0
         for i in range(nm):

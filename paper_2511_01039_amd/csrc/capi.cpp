@@ -177,6 +177,33 @@ fpeps_status fpeps_rsvd_truncate(fpeps_ctx ctx, int32_t nmat, const int64_t* m, 
   });
 }
 
+fpeps_status fpeps_rsvd_truncate_grouped(fpeps_ctx ctx, int32_t nmat, const int64_t* m,
+                                         const int64_t* n, const double* const* A,
+                                         const int32_t* group, const fpeps_opts* opts,
+                                         double* const* U_out, double* const* R_out,
+                                         int32_t* kept, double* sigma, fpeps_report* report) {
+  return guarded(ctx, [&] {
+    if (report) std::memset(report, 0, sizeof(*report));
+    if (!group) return fp::fail(FPEPS_ERR_ARG, "null group list");
+    return fp::explicit_rsvd(ctx, nmat, m, n, A, opts, U_out, R_out, kept, sigma, report,
+                             nullptr, nullptr, nullptr, false, group);
+  });
+}
+
+fpeps_status fpeps_cbe_expand_grouped(fpeps_ctx ctx, int32_t nmat, const int64_t* m,
+                                      const int64_t* n, const double* const* A,
+                                      const int32_t* group, const int32_t* r,
+                                      const double* const* U, const double* const* V,
+                                      const fpeps_opts* opts, double* const* Q_out,
+                                      int32_t* kept, double* sigma, fpeps_report* report) {
+  return guarded(ctx, [&] {
+    if (report) std::memset(report, 0, sizeof(*report));
+    if (!group) return fp::fail(FPEPS_ERR_ARG, "null group list");
+    return fp::explicit_rsvd(ctx, nmat, m, n, A, opts, Q_out, nullptr, kept, sigma, report, r,
+                             U, V, true, group);
+  });
+}
+
 fpeps_status fpeps_cbe_expand(fpeps_ctx ctx, int32_t nmat, const int64_t* m, const int64_t* n,
                               const double* const* A, const int32_t* r, const double* const* U,
                               const double* const* V, const fpeps_opts* opts,

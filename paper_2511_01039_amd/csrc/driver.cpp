@@ -221,15 +221,25 @@ Status rsvd_run(fpeps_ctx_s* ctx, RsvdIO& io, int chi, int p, int q, uint64_t se
                 RsvdOut& out, double sv_cut) {
   if (!(sv_cut > 0.0)) sv_cut = 1e-7;
   const int ns = (int)io.m.size();
-  // sketch widths k_J = min(m_J, n_J, ceil(chi m_J / sum m) + p)
+  // sketch widths k_J = min(m_J, n_J, ceil(chi m_J / sum m) + p), the sum
+  // over the sector's group
   const std::vector<int64_t>& wm = io.width_m.empty() ? io.m : io.width_m;
   const std::vector<int64_t>& wn = io.width_n.empty() ? io.n : io.width_n;
-  int64_t msum = 0;
-  for (auto v : wm) msum += std::max<int64_t>(v, 0);
+  if (!io.grp.empty() && (int)io.grp.size() != ns) return fail(FPEPS_ERR_ARG, "group list size");
+  if (!io.c2v.empty() && (int)io.c2v.size() != ns) return fail(FPEPS_ERR_ARG, "tag list size");
+  int ngrp = 1;
+  for (int g : io.grp) {
+    if (g < 0) return fail(FPEPS_ERR_ARG, "negative group");
+    ngrp = std::max(ngrp, g + 1);
+  }
+  auto grp_of = [&](int J) { return io.grp.empty() ? 0 : io.grp[J]; };
+  std::vector<int64_t> msum(ngrp, 0);
+  for (int J = 0; J < ns; ++J) msum[grp_of(J)] += std::max<int64_t>(wm[J], 0);
   out.k.assign(ns, 0);
   for (int J = 0; J < ns; ++J) {
-    if (wm[J] <= 0 || wn[J] <= 0 || msum <= 0) continue;
-    const int64_t want = ((int64_t)chi * wm[J] + msum - 1) / msum + p;
+    const int64_t ms = msum[grp_of(J)];
+    if (wm[J] <= 0 || wn[J] <= 0 || ms <= 0) continue;
+    const int64_t want = ((int64_t)chi * wm[J] + ms - 1) / ms + p;
     out.k[J] = (int32_t)std::min({wm[J], wn[J], want});
   }
   FP_TRY(io.prepare(out.k));
@@ -257,7 +267,7 @@ Status rsvd_run(fpeps_ctx_s* ctx, RsvdIO& io, int chi, int p, int q, uint64_t se
     g.off = CL.off[J];
     g.nelem = io.n[J] * (int64_t)out.k[J];
     g.c1 = io.c1[J];
-    g.c2 = io.c2;
+    g.c2 = io.c2v.empty() ? io.c2 : io.c2v[J];
     g.c3 = io.c3;
     gd.push_back(g);
     maxe = std::max(maxe, g.nelem);
@@ -311,41 +321,53 @@ Status rsvd_run(fpeps_ctx_s* ctx, RsvdIO& io, int chi, int p, int q, uint64_t se
   FP_TRY(ctx->upload("rs_jac", jd.data(), jd.size() * sizeof(SmallDesc), (void**)&djd));
   FP_HIP(hipMemsetAsync(status, 0, sizeof(int), ctx->stream));
   FP_HIP(launch_jacobi_eig(djd, (int)jd.size(), dp.max_k, small, status, ctx->stream));
-  // global cut
+  // global cut of every group (sectors listed group by group)
   std::vector<int64_t> loff;
   std::vector<int32_t> kk;
   std::vector<int> sidx;
-  int total = 0;
-  for (int J = 0; J < ns; ++J) {
-    if (out.k[J] <= 0) continue;
-    loff.push_back(2 * dp.S + dp.lam_off[J]);
-    kk.push_back(out.k[J]);
-    sidx.push_back(J);
-    total += out.k[J];
+  std::vector<CutGroup> cg(ngrp, CutGroup{0, 0, 0, 0});
+  int max_ns = 0, max_total = 0;
+  for (int g = 0; g < ngrp; ++g) {
+    cg[g].s0 = (int32_t)kk.size();
+    for (int J = 0; J < ns; ++J) {
+      if (out.k[J] <= 0 || grp_of(J) != g) continue;
+      loff.push_back(2 * dp.S + dp.lam_off[J]);
+      kk.push_back(out.k[J]);
+      sidx.push_back(J);
+      cg[g].total += out.k[J];
+    }
+    cg[g].ns = (int32_t)kk.size() - cg[g].s0;
+    max_ns = std::max(max_ns, (int)cg[g].ns);
+    max_total = std::max(max_total, (int)cg[g].total);
   }
   int64_t* dloff = nullptr;
   int32_t* dkk = nullptr;
   int32_t* dkept = nullptr;
   CutOut* dcut = nullptr;
+  CutGroup* dcg = nullptr;
   FP_TRY(ctx->upload("rs_loff", loff.data(), loff.size() * sizeof(int64_t), (void**)&dloff));
   FP_TRY(ctx->upload("rs_kk", kk.data(), kk.size() * sizeof(int32_t), (void**)&dkk));
+  FP_TRY(ctx->upload("rs_cg", cg.data(), cg.size() * sizeof(CutGroup), (void**)&dcg));
   FP_TRY(ctx->bufT("rs_kept", kk.size() + 1, &dkept));
-  FP_TRY(ctx->bufT("rs_cut", 1, &dcut));
-  if (total > 6144 || (int)kk.size() > 1024)
+  FP_TRY(ctx->bufT("rs_cut", (size_t)ngrp, &dcut));
+  if (max_total > 6144 || max_ns > 1024)
     return fail(FPEPS_ERR_UNSUPPORTED, "too many singular values for the on-chip cut");
-  FP_HIP(launch_cut(dloff, dkk, (int)kk.size(), chi, total, sv_cut, small, dkept, dcut,
+  FP_HIP(launch_cut(dcg, ngrp, max_ns, max_total, dloff, dkk, chi, sv_cut, small, dkept, dcut,
                     ctx->stream));
   std::vector<int32_t> kept_c(kk.size());
   int hs = 0;
+  out.cuts.assign(ngrp, CutOut{});
   FP_HIP(hipMemcpyAsync(kept_c.data(), dkept, kk.size() * sizeof(int32_t),
                         hipMemcpyDeviceToHost, ctx->stream));
-  FP_HIP(hipMemcpyAsync(&out.cut, dcut, sizeof(CutOut), hipMemcpyDeviceToHost, ctx->stream));
+  FP_HIP(hipMemcpyAsync(out.cuts.data(), dcut, ngrp * sizeof(CutOut), hipMemcpyDeviceToHost,
+                        ctx->stream));
   FP_HIP(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   out.lam.assign(dp.lam_total, 0.0);
   if (dp.lam_total)
     FP_HIP(hipMemcpyAsync(out.lam.data(), small + 2 * dp.S, dp.lam_total * sizeof(double),
                           hipMemcpyDeviceToHost, ctx->stream));
   FP_TRY(ctx->sync());
+  out.cut = out.cuts[0];
   if (hs & 4) out.fallbacks |= 2u;
   out.kept.assign(ns, 0);
   for (size_t i = 0; i < sidx.size(); ++i) out.kept[sidx[i]] = kept_c[i];
@@ -1110,8 +1132,11 @@ Status explicit_rsvd(fpeps_ctx_s* ctx, int nmat, const int64_t* m, const int64_t
                      const double* const* A, const fpeps_opts* o, double* const* U_out,
                      double* const* R_out, int32_t* kept, double* sigma, fpeps_report* rep,
                      const int32_t* rr, const double* const* Uin, const double* const* Vin,
-                     bool cbe) {
+                     bool cbe, const int32_t* group) {
   if (nmat < 1 || !m || !n || !A || !o || !kept) return fail(FPEPS_ERR_ARG, "null argument");
+  if (group)
+    for (int i = 0; i < nmat; ++i)
+      if (group[i] < 0 || group[i] >= nmat) return fail(FPEPS_ERR_ARG, "group ids must be 0 .. nmat-1");
   if (o->precision != FPEPS_FP64)
     return fail(FPEPS_ERR_UNSUPPORTED, "only FPEPS_FP64 is available in this build");
   hipEvent_t ev0, ev1;
@@ -1159,8 +1184,19 @@ Status explicit_rsvd(fpeps_ctx_s* ctx, int nmat, const int64_t* m, const int64_t
   RsvdIO io;
   io.m = e.m;
   io.n = e.n;
-  for (int i = 0; i < nmat; ++i) io.c1.push_back((uint32_t)i);
-  io.c2 = (uint32_t)o->tag;
+  if (!group) {
+    for (int i = 0; i < nmat; ++i) io.c1.push_back((uint32_t)i);
+    io.c2 = (uint32_t)o->tag;
+  } else {
+    // every group is the problem of its own call: sketch counters (ordinal
+    // inside the group, tag + group), widths and cut per group
+    std::vector<uint32_t> ord(nmat, 0);
+    for (int i = 0; i < nmat; ++i) {
+      io.c1.push_back(ord[group[i]]++);
+      io.c2v.push_back((uint32_t)(o->tag + group[i]));
+      io.grp.push_back(group[i]);
+    }
+  }
   io.c3 = cbe ? (1u << 16) : 0u;
   // widths follow the (residual) sizes: k_i = min(m_i', n_i', ceil(chi m_i'/sum m') + p)
   const int chi = cbe ? o->cbe_extra : o->chi;
@@ -1240,10 +1276,14 @@ Status explicit_rsvd(fpeps_ctx_s* ctx, int nmat, const int64_t* m, const int64_t
     int tot = 0;
     for (int v : rs.kept) tot += v;
     rep->kept_total = tot;
-    rep->min_rel_gap = (rs.cut.s_next >= 0 && rs.cut.s_last > 0)
-                           ? (rs.cut.s_last - rs.cut.s_next) / rs.cut.s_last
-                           : -1.0;
-    rep->discarded_weight = rs.cut.total2 > 0 ? 1.0 - rs.cut.kept2 / rs.cut.total2 : 0.0;
+    // over the groups: the smallest relative gap and the largest discarded weight
+    double gap = INFINITY, disc = 0.0;
+    for (const CutOut& c : rs.cuts) {
+      if (c.s_next >= 0 && c.s_last > 0) gap = std::min(gap, (c.s_last - c.s_next) / c.s_last);
+      if (c.total2 > 0) disc = std::max(disc, 1.0 - c.kept2 / c.total2);
+    }
+    rep->min_rel_gap = std::isfinite(gap) ? gap : -1.0;
+    rep->discarded_weight = disc;
   }
   return Status::ok();
 }

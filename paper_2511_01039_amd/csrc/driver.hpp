@@ -19,6 +19,11 @@ struct RsvdIO {
   std::vector<int64_t> width_m, width_n;   // sizes deciding the widths (default m, n)
   std::vector<uint32_t> c1;                // sketch counter word per sector
   uint32_t c2 = 0, c3 = 0;
+  // independent truncation problems in one batch: group of every sector
+  // (empty: one group), its own widths and cut; c2v (if set) replaces c2 per
+  // sector
+  std::vector<int32_t> grp;
+  std::vector<uint32_t> c2v;
   std::function<Status(const std::vector<int32_t>&)> prepare;
   // apply(transpose, final, x, y): y = M x or M^T x; ``final`` marks the
   // last range-finder product (it fixes Q) and the projection B^T = M^T Q
@@ -36,7 +41,8 @@ struct RsvdOut {
   double* Bt = nullptr;      // column layout, B^T = M^T Q
   double* small = nullptr;   // [G | eigenvectors | eigenvalues]
   std::vector<double> lam;   // eigenvalues of B B^T, per sector descending
-  CutOut cut{};
+  CutOut cut{};                // group 0 (the only one of a single problem)
+  std::vector<CutOut> cuts;    // every group
   uint32_t fallbacks = 0;
 };
 
@@ -53,7 +59,8 @@ Status make_site(fpeps_ctx_s* ctx, const fpeps_tensor* R, const fpeps_tensor* T,
 Status explicit_rsvd(fpeps_ctx_s* ctx, int nmat, const int64_t* m, const int64_t* n,
                      const double* const* A, const fpeps_opts* o, double* const* U_out,
                      double* const* R_out, int32_t* kept, double* sigma, fpeps_report* rep,
-                     const int32_t* r, const double* const* U, const double* const* V, bool cbe);
+                     const int32_t* r, const double* const* U, const double* const* V, bool cbe,
+                     const int32_t* group = nullptr);
 Status overlap(fpeps_ctx_s* ctx, int L, const fpeps_tensor* top, const fpeps_tensor* bot,
                double* value);
 Status axpy_inplace(fpeps_ctx_s* ctx, double* x, const double* y, int64_t n);

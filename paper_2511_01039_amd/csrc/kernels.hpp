@@ -119,8 +119,15 @@ struct CutOut {
   double s_last;      // smallest kept s
   double s_next;      // largest cut s (or -1)
 };
-hipError_t launch_cut(const int64_t* lam_off, const int32_t* k, int nsect, int chi, int total,
-                      double sv_cut, const double* buf, int32_t* kept, CutOut* out, hipStream_t s);
+// One cut per group: group g ranks the values of sectors [s0, s0 + ns) of
+// the lists (lam_off, k), ``total`` values in all, keeps ranks < chi, and
+// writes kept[s0 ..] and out[g]. One workgroup per group.
+struct CutGroup {
+  int32_t s0, ns, total, pad;
+};
+hipError_t launch_cut(const CutGroup* groups, int ngroups, int max_ns, int max_total,
+                      const int64_t* lam_off, const int32_t* k, int chi, double sv_cut,
+                      const double* buf, int32_t* kept, CutOut* out, hipStream_t s);
 // SVQB scaling: column i of the k x k eigenvector matrix at b_off is
 // multiplied by 1/sqrt(lambda_i) (eigenvalues at c_off, descending), or set to
 // zero when lambda_i <= tau * lambda_0 (numerically null direction).

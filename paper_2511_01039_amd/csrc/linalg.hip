@@ -276,16 +276,23 @@ hipError_t launch_jacobi_eig(const SmallDesc* d, int nd, int max_k, double* buf,
 }
 
 // ---------------------------------------------------------------------------
-// Global cut: rank every sqrt(lambda) among all sectors (descending, ties by
-// sector then position) and keep ranks < chi.
+// Global cut of one group (one workgroup each): rank every sqrt(lambda) among
+// the group's sectors (descending, ties by sector then position) and keep
+// ranks < chi.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_cut(const int64_t* __restrict__ lam_off,
-                                              const int32_t* __restrict__ kk, int nsect, int chi,
-                                              int total, double sv_cut,
-                                              const double* __restrict__ buf,
-                                              int32_t* __restrict__ kept,
-                                              CutOut* __restrict__ out) {
+__global__ __launch_bounds__(1024) void k_cut(const CutGroup* __restrict__ groups,
+                                              const int64_t* __restrict__ lam_off_all,
+                                              const int32_t* __restrict__ kk_all, int chi,
+                                              double sv_cut, const double* __restrict__ buf,
+                                              int32_t* __restrict__ kept_all,
+                                              CutOut* __restrict__ outs) {
   extern __shared__ double sm[];
+  const CutGroup G = groups[blockIdx.x];
+  const int64_t* lam_off = lam_off_all + G.s0;
+  const int32_t* kk = kk_all + G.s0;
+  int32_t* kept = kept_all + G.s0;
+  CutOut* out = outs + blockIdx.x;
+  const int nsect = G.ns, total = G.total;
   double* sig = sm;                               // [total]
   int* sec = (int*)(sm + total);                  // [total]
   int* pos = sec + total;                         // [total]
@@ -357,12 +364,14 @@ __global__ __launch_bounds__(1024) void k_cut(const int64_t* __restrict__ lam_of
   }
 }
 
-hipError_t launch_cut(const int64_t* lam_off, const int32_t* k, int nsect, int chi, int total,
-                      double sv_cut, const double* buf, int32_t* kept, CutOut* out, hipStream_t s) {
-  if (nsect > 1024) return hipErrorInvalidValue;
-  const size_t shm = (size_t)total * (sizeof(double) + 2 * sizeof(int));
+hipError_t launch_cut(const CutGroup* groups, int ngroups, int max_ns, int max_total,
+                      const int64_t* lam_off, const int32_t* k, int chi, double sv_cut,
+                      const double* buf, int32_t* kept, CutOut* out, hipStream_t s) {
+  if (ngroups <= 0) return hipSuccess;
+  if (max_ns > 1024) return hipErrorInvalidValue;
+  const size_t shm = (size_t)max_total * (sizeof(double) + 2 * sizeof(int));
   if (shm > 96 * 1024) return hipErrorInvalidValue;
-  k_cut<<<1, 1024, shm, s>>>(lam_off, k, nsect, chi, total, sv_cut, buf, kept, out);
+  k_cut<<<dim3(ngroups), 1024, shm, s>>>(groups, lam_off, k, chi, sv_cut, buf, kept, out);
   return hipGetLastError();
 }
 

@@ -439,6 +439,59 @@ def test_config5_bond_expansion_site_matches_oracle(ctx):
     print(f"config5 site: shapes {shapes} kept {list(kept)} cbe kept {list(ckept)}")
 
 
+def test_grouped_truncations_match_oracle_per_group(ctx):
+    """a9: several independent truncation problems (the per-site truncations
+    of a row) in one grouped call. Each group has its own widths and cut and
+    the sketch counters of its own call (tag + group), so every group agrees
+    with the oracle run on that group alone: kept counts, singular values and
+    projectors; then the grouped bond expansion likewise."""
+    import torch
+    from oracle.rsvd import rsvd_explicit
+    from oracle.cbe import cbe_explicit
+    from paper_2511_01039_amd import make_opts
+    rng = np.random.default_rng(11)
+    shapes = [[(300, 250), (120, 200), (80, 80)], [(400, 150), (60, 90)], [(200, 220)]]
+    mats, group = [], []
+    for g, sh in enumerate(shapes):
+        for m, n in sh:
+            mats.append(wl.decaying_matrix(m, n, rng, 20.0))
+            group.append(g)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    chi, p, q = 40, 8, 1
+    U, R, sig, kept, rep = ctx.rsvd_truncate([t(a) for a in mats],
+                                             make_opts(chi=chi, oversample=p, power_iters=q,
+                                                       seed=0, tag=5), group=group)
+    Uh, Vh = [None] * len(mats), [None] * len(mats)
+    for g in range(len(shapes)):
+        idx = [i for i in range(len(mats)) if group[i] == g]
+        want = rsvd_explicit([mats[i] for i in idx], chi=chi, p=p, q=q, seed=0, tag=5 + g)
+        assert [int(kept[i]) for i in idx] == list(want["kept"]), g
+        assert sum(int(kept[i]) for i in idx) <= chi
+        for j, i in enumerate(idx):
+            u = U[i].cpu().numpy()
+            assert rel_err(sig[i], want["sigma"][j]) < 1e-11
+            assert np.abs(u @ u.T - want["U"][j] @ want["U"][j].T).max() < 1e-10
+            Uh[i] = want["U"][j]
+            Vh[i] = want["R"][j] / np.asarray(want["sigma"][j])[:, None]
+    Q, csig, ckept, _ = ctx.cbe_expand([t(a) for a in mats], [t(u) for u in Uh],
+                                       [t(v) for v in Vh],
+                                       make_opts(cbe_extra=6, oversample=4, seed=0, tag=7),
+                                       group=group)
+    for g in range(len(shapes)):
+        idx = [i for i in range(len(mats)) if group[i] == g]
+        cw = cbe_explicit([mats[i] for i in idx], [Uh[i] for i in idx], [Vh[i] for i in idx],
+                          chi_extra=6, p=4, seed=0, tag=7 + g)
+        assert [int(ckept[i]) for i in idx] == list(cw["kept"]), g
+        for j, i in enumerate(idx):
+            if ckept[i] == 0:
+                continue
+            qq = Q[i].cpu().numpy()
+            assert np.abs(qq.T @ Uh[i]).max() < 1e-12
+            assert np.abs(qq @ qq.T - cw["Q"][j] @ cw["Q"][j].T).max() < 1e-10
+            assert rel_err(csig[i], cw["sigma"][j]) < 1e-11
+    print(f"grouped: kept {list(kept)} cbe kept {list(ckept)}")
+
+
 def lattice_value(ctx, lat, W, chi, p, q, seed, precision="fp64"):
     """<top|closing> after absorbing every row top to bottom on the device:
     (sign, log |Z|)."""
