@@ -290,8 +290,8 @@ def main():
                          "reference for HBM byte counters) and exit")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the row absorption runs on a single MI355X in this "
-              "build; --gpus must be 1", file=sys.stderr)
+        print("bench.py measures one GPU: the row absorption runs on a single MI355X; "
+              "--gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import torch
     if a.calibrate_copy:

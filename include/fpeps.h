@@ -66,7 +66,7 @@ typedef enum {
   FPEPS_ERR_HIP = -5,         /* a HIP runtime call failed */
   FPEPS_ERR_NUMERIC = -6,     /* NaN / Inf met, or a factorisation broke down */
   FPEPS_ERR_CAPACITY = -7,    /* an output buffer is too small; see report */
-  FPEPS_ERR_UNSUPPORTED = -8, /* valid request this build does not do */
+  FPEPS_ERR_UNSUPPORTED = -8, /* valid request the library does not implement */
   FPEPS_ERR_NODEVICE = -9     /* no usable gfx950 device */
 } fpeps_status;
 

@@ -1138,7 +1138,7 @@ Status explicit_rsvd(fpeps_ctx_s* ctx, int nmat, const int64_t* m, const int64_t
     for (int i = 0; i < nmat; ++i)
       if (group[i] < 0 || group[i] >= nmat) return fail(FPEPS_ERR_ARG, "group ids must be 0 .. nmat-1");
   if (o->precision != FPEPS_FP64)
-    return fail(FPEPS_ERR_UNSUPPORTED, "only FPEPS_FP64 is available in this build");
+    return fail(FPEPS_ERR_UNSUPPORTED, "explicit matrices: only FPEPS_FP64 is available");
   hipEvent_t ev0, ev1;
   FP_HIP(hipEventCreate(&ev0));
   FP_HIP(hipEventCreate(&ev1));
