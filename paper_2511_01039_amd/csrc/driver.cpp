@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <map>
 
 namespace fp {
 
@@ -762,6 +763,32 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
       std::fprintf(stderr, "[fpeps] site %d kept", x);
       for (int v : rs.kept) std::fprintf(stderr, " %d", v);
       std::fprintf(stderr, "\n");
+      // layer steps: tiles by (rows per tile, staged columns, chunks) over all
+      // slices
+      for (int st = 1; st <= 3; ++st)
+        for (int bwd = 0; bwd < 2; ++bwd) {
+          std::map<std::array<int, 3>, double> hist;
+          double all = 0;
+          for (const auto& sl : plp->slices) {
+            const PlanSet* ps = bwd ? sl.psb.get() : sl.ps.get();
+            const int idx = bwd ? sl.bwd[st] : sl.fwd[st];
+            const bool rt = bwd ? sl.bwd_rt[st] : sl.fwd_rt[st];
+            if (!ps || idx < 0 || !rt) continue;
+            for (const RtGroup& g : ps->rts[idx].groups) {
+              const double nt = (double)((g.M + g.rows - 1) / g.rows);
+              const int kb = g.ktot <= 8 ? 8 : g.ktot <= 16 ? 16 : g.ktot <= 32 ? 32 : g.ktot <= 64 ? 64 : 999;
+              hist[{g.rows, kb, std::min(g.o1 - g.o0, 9)}] += nt;
+              all += nt;
+            }
+          }
+          std::fprintf(stderr, "[fpeps] site %d layer step %s%d tiles:", x, bwd ? "T" : "",
+                       bwd ? 5 - st : st + 1);
+          for (auto& kv : hist)
+            if (kv.second >= 0.02 * all)
+              std::fprintf(stderr, " rows%d/k<=%d/nch%d:%.0f%%", kv.first[0], kv.first[1],
+                           kv.first[2], 100.0 * kv.second / all);
+          std::fprintf(stderr, "\n");
+        }
       // GEMM steps: jobs, 16-deep K tiles per job, tile shapes
       const int steps[4] = {1, 5, 11, 15};
       for (int st : steps) {
