@@ -281,6 +281,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-site", action="store_true",
                     help="config 5: one truncation and one expansion call per site")
+    ap.add_argument("--slice-budget-gib", type=float, default=0.0,
+                    help="workspace per slice set in GiB (0: the library's default)")
     ap.add_argument("--one-stream", action="store_true",
                     help="run every slice on one stream (no overlap of slices)")
     ap.add_argument("--lattice", action="store_true",
@@ -324,7 +326,7 @@ def main():
     def run(precision):
         """W untimed + K timed absorptions of the row; device-resident inputs."""
         kw = dict(chi=row.chi, oversample=row.oversample, power_iters=row.power_iters, seed=0,
-                  row=row.row, precision=precision)
+                  row=row.row, precision=precision, slice_budget=int(a.slice_budget_gib * 2**30))
         # timed steps: the library's default two streams (slices overlap);
         # kernel figures: one more step on one stream with every launch timed
         # by HIP events (overlapping launches would stretch each other's
