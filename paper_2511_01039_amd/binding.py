@@ -348,6 +348,8 @@ class Context:
                                                     C.byref(rep)))
         else:
             g = _i32(group)
+            if g.shape != (nm,):
+                raise FpepsError(-1, "group must list one problem id per matrix")
             self.check(self.lib.fpeps_rsvd_truncate_grouped(self.h, nm, _ptr(m, C.c_int64),
                                                             _ptr(n, C.c_int64), A,
                                                             _ptr(g, C.c_int32), C.byref(opts), Up,
@@ -390,6 +392,8 @@ class Context:
                                                  _ptr(sig, C.c_double), C.byref(rep)))
         else:
             g = _i32(group)
+            if g.shape != (nm,):
+                raise FpepsError(-1, "group must list one problem id per matrix")
             self.check(self.lib.fpeps_cbe_expand_grouped(self.h, nm, _ptr(m, C.c_int64),
                                                          _ptr(n, C.c_int64), A, _ptr(g, C.c_int32),
                                                          _ptr(r, C.c_int32), Up, Vp, C.byref(opts),
