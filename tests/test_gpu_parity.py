@@ -490,6 +490,19 @@ def test_grouped_truncations_match_oracle_per_group(ctx):
             assert np.abs(qq @ qq.T - cw["Q"][j] @ cw["Q"][j].T).max() < 1e-10
             assert rel_err(csig[i], cw["sigma"][j]) < 1e-11
     print(f"grouped: kept {list(kept)} cbe kept {list(ckept)}")
+    # one group holding every matrix is the ungrouped call, bit for bit; an
+    # empty group id in between changes nothing for the others
+    sub = [t(a) for a in mats[:3]]
+    o = make_opts(chi=chi, oversample=p, power_iters=q, seed=0, tag=5)
+    U0, _, _, k0, _ = ctx.rsvd_truncate(sub, o)
+    U1, _, _, k1, _ = ctx.rsvd_truncate(sub, o, group=[0, 0, 0])
+    assert list(k0) == list(k1)
+    for a, b in zip(U0, U1):
+        assert torch.equal(a, b)
+    U2, _, _, k2, _ = ctx.rsvd_truncate(sub, o, group=[0, 2, 2])
+    want0 = rsvd_explicit(mats[:1], chi=chi, p=p, q=q, seed=0, tag=5)
+    want2 = rsvd_explicit(mats[1:3], chi=chi, p=p, q=q, seed=0, tag=7)
+    assert [int(v) for v in k2] == list(want0["kept"]) + list(want2["kept"])
 
 
 def lattice_value(ctx, lat, W, chi, p, q, seed, precision="fp64"):
