@@ -197,6 +197,73 @@ __device__ __forceinline__ void rt_chunks(const T* __restrict__ X,
   }
 }
 
+// One chunk (NC <= RT_NC2 columns) for the two rows of a lane in a two-row
+// tile: row a in sub-block 0 and row b = a + 64 in sub-block 1; every packed
+// layer value feeds both products.
+template <int NC, class T>
+__device__ __forceinline__ void rt_chunk2(const FP_CONST double* PK, T* __restrict__ Y,
+                                          const T* __restrict__ la, const T* __restrict__ lb,
+                                          const RtOut& O, const FP_CONST RtPair* pairs,
+                                          const FP_CONST int32_t* tab,
+                                          const int32_t (&ia)[RT_MAXLEV],
+                                          const int32_t (&ib)[RT_MAXLEV], bool live_a,
+                                          bool live_b) {
+  double acc_a[NC], acc_b[NC];
+#pragma unroll
+  for (int n = 0; n < NC; ++n) acc_a[n] = acc_b[n] = 0.0;
+  for (int p = O.p0; p < O.p1; ++p) {
+    const RtPair P = ld(pairs + p);
+    const FP_CONST double* bp = PK + P.pk;
+    const int Kb = P.Kb;
+    const T* pa = la + P.koff * 64;
+    const T* pb = lb + P.koff * 64;
+    constexpr int KU = NC > 4 ? 4 : 8;
+    int k = 0;
+    for (; k + KU <= Kb; k += KU) {
+      double xa[KU], xb[KU];
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        xa[u] = (double)pa[(k + u) * 64];
+        xb[u] = (double)pb[(k + u) * 64];
+      }
+      const FP_CONST double* b = bp + k * NC;
+#pragma unroll
+      for (int u = 0; u < KU; ++u)
+#pragma unroll
+        for (int n = 0; n < NC; ++n) {
+          acc_a[n] = fma(xa[u], b[u * NC + n], acc_a[n]);
+          acc_b[n] = fma(xb[u], b[u * NC + n], acc_b[n]);
+        }
+    }
+    for (; k < Kb; ++k) {
+      const double xa = (double)pa[k * 64], xb = (double)pb[k * 64];
+      const FP_CONST double* b = bp + k * NC;
+#pragma unroll
+      for (int n = 0; n < NC; ++n) {
+        acc_a[n] = fma(xa, b[n], acc_a[n]);
+        acc_b[n] = fma(xb, b[n], acc_b[n]);
+      }
+    }
+  }
+  const FP_CONST int32_t* nt = tab + O.ntab;
+  if (live_a) {
+    int32_t oo = 0;
+#pragma unroll
+    for (int l = 0; l < RT_MAXLEV; ++l) oo += ia[l] * O.ms[l];
+    T* yp = Y + O.base + oo;
+#pragma unroll
+    for (int n = 0; n < NC; ++n) yp[nt[n]] = (T)acc_a[n];
+  }
+  if (live_b) {
+    int32_t oo = 0;
+#pragma unroll
+    for (int l = 0; l < RT_MAXLEV; ++l) oo += ib[l] * O.ms[l];
+    T* yp = Y + O.base + oo;
+#pragma unroll
+    for (int n = 0; n < NC; ++n) yp[nt[n]] = (T)acc_b[n];
+  }
+}
+
 // Level indices of row m (m < 2^31): division by the level dims through
 // their multiply-high constants (no integer division instructions).
 __device__ __forceinline__ void row_levels(const RtGroup& G, int m, int32_t (&idx)[RT_MAXLEV]) {
@@ -277,6 +344,34 @@ __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
   // index is uniform per wave: say so, so that the chunk loop and
   // everything it loads stay scalar
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  if (G.staged == 2) {
+    // two-row tile (128 rows): lane rows m0 + lane and m0 + 64 + lane (rows
+    // past the group end repeat row M - 1, never stored); wave w takes
+    // chunks o0 + w, o0 + w + 4, ...
+    const int lane = tid & 63;
+    const int ma = m0 + lane, mb = m0 + 64 + lane;
+    const bool live_a = ma < G.M, live_b = mb < G.M;
+    int32_t ia[RT_MAXLEV], ib[RT_MAXLEV];
+    row_levels(G, live_a ? ma : G.M - 1, ia);
+    row_levels(G, live_b ? mb : G.M - 1, ib);
+    const T* la = lds + lane;
+    const T* lb = lds + G.ktot * 64 + lane;
+    for (int o = G.o0 + wave; o < G.o1; o += 4) {
+      const RtOut O = ld(outs + o);
+      switch (O.nc) {
+#define FP_RT2_CASE(n)                                                                   \
+  case n:                                                                                \
+    rt_chunk2<n, T>(PK, Y, la, lb, O, pairs, tab, ia, ib, live_a, live_b);               \
+    break;
+        FP_RT2_CASE(1) FP_RT2_CASE(2) FP_RT2_CASE(3) FP_RT2_CASE(4) FP_RT2_CASE(5)
+        FP_RT2_CASE(6) FP_RT2_CASE(7) FP_RT2_CASE(8)
+#undef FP_RT2_CASE
+        default:
+          break;
+      }
+    }
+    return;
+  }
   const int lsub = lrows - 6;                  // log2(rows / 64)
   const int o_first = wave >> lsub, o_step = 4 >> lsub;
   // this lane's row inside the staged tile: sub-block r / 64, lane r % 64

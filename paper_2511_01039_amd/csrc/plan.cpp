@@ -704,6 +704,15 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
     g.k1 = (int32_t)rt.kblks.size();
     g.ktot = ktot;
     g.c0 = (int32_t)rt.cols.size();
+    // two rows per lane (see RT_PAIR_LDS) when the chunks at RT_NC columns
+    // already fill the four waves
+    bool pair_rows = false;
+    {
+      int64_t have = 0;
+      for (int ob : kv.second) have += (prod_dims(out, out.blocks[ob], onpos) + RT_NC - 1) / RT_NC;
+      pair_rows = have >= 4 && M >= 128 && (int64_t)128 * ktot * 8 <= RT_PAIR_LDS;
+    }
+    const int ncmax = pair_rows ? RT_NC2 : RT_NC;
     for (int ob : kv.second) {
       const Block& cb = out.blocks[ob];
       RtOut base_o;
@@ -744,7 +753,7 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
       rt.c_extent = std::max(rt.c_extent, cb.base + rowmax + nmax + 1);
       // equal chunks of at most RT_NC columns (18 -> 9 + 9, not 16 + 2):
       // every chunk re-reads the row's inputs
-      const int64_t nchunks = (Nb + RT_NC - 1) / RT_NC;
+      const int64_t nchunks = (Nb + ncmax - 1) / ncmax;
       const int64_t cw = (Nb + nchunks - 1) / nchunks;
       for (int64_t n0 = 0; n0 < Nb; n0 += cw) {
         const int nc = (int)std::min<int64_t>(cw, Nb - n0);
@@ -825,8 +834,9 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
     const int nch = g.o1 - g.o0;
     int rows = nch >= 4 ? 64 : (nch >= 2 ? 128 : 256);
     while (rows > 64 && (int64_t)rows * ktot * 8 > RT_LDS_BYTES) rows /= 2;
+    if (pair_rows) rows = 128;
     g.rows = rows;
-    g.staged = (int64_t)rows * ktot * 8 <= RT_LDS_BYTES ? 1 : 0;
+    g.staged = (int64_t)rows * ktot * 8 <= RT_LDS_BYTES ? (pair_rows ? 2 : 1) : 0;
     if (g.staged) {
       for (int b = g.k0; b < g.k1; ++b) {
         const RtKblk& K = rt.kblks[b];

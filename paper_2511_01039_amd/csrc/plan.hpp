@@ -192,6 +192,12 @@ bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sy
 // four waves split the output chunks.
 constexpr int RT_MAXLEV = 4;
 constexpr int RT_NC = 16;
+// Groups whose output needs four or more chunks (the four waves share the
+// chunks of the tile) and whose 128 staged rows fit RT_PAIR_LDS take 128-row
+// tiles with two rows per lane and chunks of at most RT_NC2 columns: each
+// packed layer value loaded by a wave then feeds two products.
+constexpr int RT_NC2 = 8;
+constexpr int RT_PAIR_LDS = 32 * 1024;
 constexpr int RT_THREADS = 256;
 constexpr int RT_LDS_BYTES = 64 * 1024;   // staging budget per workgroup
 constexpr int RT_NCLASS = 4;              // LDS classes: 0 (unstaged), <=16K, <=32K, <=64K
@@ -205,7 +211,8 @@ struct RtGroup {
   int32_t o0, o1;              // output chunk range
   int32_t k0, k1;              // X block range (RtKblk)
   int32_t rows;                // rows per workgroup: 64, 128 or 256
-  int32_t staged;              // 1: X rows staged in LDS (rows * ktot doubles)
+  int32_t staged;              // 1: X rows staged in LDS (rows * ktot doubles); 2: also two
+                               // rows per lane (rows = 128, chunks of <= RT_NC2 columns)
   int32_t ktot;                // sum of Kb over the group's X blocks
   int32_t c0;                  // first staged column (RtCol), ktot of them
 };
