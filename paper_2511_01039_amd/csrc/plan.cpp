@@ -29,30 +29,52 @@ static inline int label_parity(int kind, const int32_t* lab) {
   return 0;
 }
 
-double pair_alpha(const SymInfo& sym, int step, const std::vector<const int32_t*>& xlabs,
-                  const std::vector<const int32_t*>& tlabs, const std::vector<bool>& xshared,
-                  const std::vector<bool>& tshared, int nlab) {
-  double a = 1.0;
+// The scalar is split in two halves: the sketch-side half (the hash state
+// after the step and the X labels, and the parity of X's free legs) depends
+// only on the keyed block, so a plan computes it once per block.
+struct AlphaHead {
+  uint64_t h;
+  int px;
+};
+
+static AlphaHead alpha_head(const SymInfo& sym, int step, const int32_t* const* xlabs, int nx,
+                            const char* xshared, int nlab) {
+  AlphaHead a{sym.coef_seed, 0};
   if (sym.kind == SYM_SU2) {
-    const uint64_t golden = 0x9E3779B97F4A7C15ull;
-    uint64_t h = sym.coef_seed;
-    auto fold = [&](int64_t w) { h = splitmix64_mix(h + golden + (uint64_t)w); };
-    fold(step);
-    for (auto* l : xlabs)
-      for (int i = 0; i < nlab; ++i) fold(l[i]);
-    for (auto* l : tlabs)
-      for (int i = 0; i < nlab; ++i) fold(l[i]);
-    a = 2.0 * ((double)(h >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+    a.h = splitmix64_mix(a.h + 0x9E3779B97F4A7C15ull + (uint64_t)(int64_t)step);
+    for (int j = 0; j < nx; ++j)
+      for (int i = 0; i < nlab; ++i)
+        a.h = splitmix64_mix(a.h + 0x9E3779B97F4A7C15ull + (uint64_t)(int64_t)xlabs[j][i]);
+  }
+  if (sym.fermionic)
+    for (int i = 0; i < nx; ++i)
+      if (!xshared[i]) a.px += label_parity(sym.kind, xlabs[i]);
+  return a;
+}
+
+static double alpha_tail(const SymInfo& sym, AlphaHead a, const int32_t* const* tlabs, int nt,
+                         const char* tshared, int nlab) {
+  double v = 1.0;
+  if (sym.kind == SYM_SU2) {
+    uint64_t h = a.h;
+    for (int j = 0; j < nt; ++j)
+      for (int i = 0; i < nlab; ++i)
+        h = splitmix64_mix(h + 0x9E3779B97F4A7C15ull + (uint64_t)(int64_t)tlabs[j][i]);
+    v = 2.0 * ((double)(h >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
   }
   if (sym.fermionic) {
-    int px = 0, pt = 0;
-    for (size_t i = 0; i < xlabs.size(); ++i)
-      if (!xshared[i]) px += label_parity(sym.kind, xlabs[i]);
-    for (size_t i = 0; i < tlabs.size(); ++i)
+    int pt = 0;
+    for (int i = 0; i < nt; ++i)
       if (tshared[i]) pt += label_parity(sym.kind, tlabs[i]);
-    if ((px * pt) & 1) a = -a;
+    if ((a.px * pt) & 1) v = -v;
   }
-  return a;
+  return v;
+}
+
+double pair_alpha(const SymInfo& sym, int step, const int32_t* const* xlabs, int nx,
+                  const int32_t* const* tlabs, int nt, const char* xshared, const char* tshared,
+                  int nlab) {
+  return alpha_tail(sym, alpha_head(sym, step, xlabs, nx, xshared, nlab), tlabs, nt, tshared, nlab);
 }
 
 int32_t TablePool::add(const std::vector<int32_t>& dims, const std::vector<int64_t>& strides,
@@ -217,8 +239,11 @@ struct StepEnum {
   std::vector<P3> trip;
   // per-pair scalar keys
   std::vector<int> kpos;
-  std::vector<bool> kshared, sshared;
+  std::vector<char> kshared, sshared;
   int nlab = 1;
+  // sketch-side halves of the pair scalar, per keyed block (filled lazily)
+  std::vector<AlphaHead> head;
+  std::vector<char> head_set;
 };
 
 bool enumerate_step(const BT& X, const BT& S, const StepSpec& spec, const BT* fixed_out, BT& out,
@@ -291,59 +316,158 @@ bool enumerate_step(const BT& X, const BT& S, const StepSpec& spec, const BT* fi
     }
   }
   std::vector<P3>& trip = E.trip;
-  for (int xb = 0; xb < (int)X.blocks.size(); ++xb) {
-    SectKey k;
-    k.n = (uint8_t)xs.size();
-    for (size_t i = 0; i < xs.size(); ++i) k.v[i] = X.blocks[xb].sect[xs[i]];
-    auto g = groups.find(k);
-    if (g == groups.end()) continue;
-    for (int sb : g->second) {
-      SectKey ok;
-      ok.n = (uint8_t)no;
-      for (int o = 0; o < no; ++o)
-        ok.v[o] = src_side[o] ? S.blocks[sb].sect[src_pos[o]] : X.blocks[xb].sect[src_pos[o]];
-      auto it = out_index.find(ok);
-      int ob;
-      if (it == out_index.end()) {
-        if (fixed_out) {
-          if (spec.restrict_to_fixed) continue;
-          err = "a block pair produces a block outside the fixed output layout";
-          return false;
-        }
-        ob = (int)out_keys.size();
-        out_index.emplace(ok, ob);
-        out_keys.push_back(ok);
-      } else {
-        ob = it->second;
-      }
-      trip.push_back({xb, sb, ob});
-    }
+  // Output sector tuples packed in mixed radix (first leg most significant)
+  // when they fit 64 bits: numeric order is then the tuple order, and the X
+  // and S parts of a key are computed once per block and OR-ed per pair.
+  int shift[MAXL] = {0};
+  int tbits = 0;
+  for (int o = no - 1; o >= 0; --o) {
+    int b = 0;
+    while ((1ll << b) < (int64_t)out.cat[o]->nsect()) ++b;
+    shift[o] = tbits;
+    tbits += b;
   }
-  // output blocks sorted by sector tuple when not fixed
-  std::vector<int> remap(out_keys.size());
-  if (!fixed_out) {
-    std::vector<int> order(out_keys.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::sort(order.begin(), order.end(), [&](int a, int b) { return out_keys[a] < out_keys[b]; });
+  std::vector<int> remap;
+  if (!fixed_out && tbits <= 64) {
+    std::vector<uint64_t> xpart(X.blocks.size(), 0), spart(S.blocks.size(), 0);
+    for (int o = 0; o < no; ++o) {
+      if (src_side[o])
+        for (size_t b = 0; b < S.blocks.size(); ++b)
+          spart[b] |= (uint64_t)S.blocks[b].sect[src_pos[o]] << shift[o];
+      else
+        for (size_t b = 0; b < X.blocks.size(); ++b)
+          xpart[b] |= (uint64_t)X.blocks[b].sect[src_pos[o]] << shift[o];
+    }
+    // open-addressing index of the packed keys (value -1: empty slot)
+    std::vector<uint64_t> hkey(1024);
+    std::vector<int32_t> hval(1024, -1);
+    uint64_t hmask = 1023;
+    std::vector<uint64_t> keys;
+    auto hslot = [&](uint64_t k) {
+      uint64_t h = k * 0x9E3779B97F4A7C15ull;
+      uint64_t i = (h ^ (h >> 29)) & hmask;
+      while (hval[i] >= 0 && hkey[i] != k) i = (i + 1) & hmask;
+      return i;
+    };
+    for (int xb = 0; xb < (int)X.blocks.size(); ++xb) {
+      SectKey k;
+      k.n = (uint8_t)xs.size();
+      for (size_t i = 0; i < xs.size(); ++i) k.v[i] = X.blocks[xb].sect[xs[i]];
+      auto g = groups.find(k);
+      if (g == groups.end()) continue;
+      for (int sb : g->second) {
+        const uint64_t key = xpart[xb] | spart[sb];
+        uint64_t i = hslot(key);
+        if (hval[i] < 0) {
+          if (2 * (keys.size() + 1) > hkey.size()) {
+            std::vector<uint64_t> ok2(hkey.size() * 2);
+            std::vector<int32_t> ov2(hkey.size() * 2, -1);
+            hkey.swap(ok2);
+            hval.swap(ov2);
+            hmask = hkey.size() - 1;
+            for (size_t j = 0; j < ok2.size(); ++j)
+              if (ov2[j] >= 0) {
+                const uint64_t q = hslot(ok2[j]);
+                hkey[q] = ok2[j];
+                hval[q] = ov2[j];
+              }
+            i = hslot(key);
+          }
+          hkey[i] = key;
+          hval[i] = (int32_t)keys.size();
+          keys.push_back(key);
+        }
+        if (!spec.symbolic) trip.push_back({xb, sb, hval[i]});
+      }
+    }
+    std::vector<std::pair<uint64_t, int>> order(keys.size());
+    for (size_t i = 0; i < keys.size(); ++i) order[i] = {keys[i], (int)i};
+    std::sort(order.begin(), order.end());
+    remap.resize(keys.size());
     out.blocks.resize(order.size());
     int64_t off = 0;
     for (size_t i = 0; i < order.size(); ++i) {
-      remap[order[i]] = (int)i;
+      remap[order[i].second] = (int)i;
       Block& b = out.blocks[i];
-      for (int o = 0; o < no; ++o) b.sect[o] = out_keys[order[i]].v[o];
+      for (int o = 0; o < no; ++o) {
+        const int nb = (o == 0 ? tbits : shift[o - 1]) - shift[o];
+        b.sect[o] = (uint16_t)((order[i].first >> shift[o]) & ((nb >= 64 ? 0ull : (1ull << nb)) - 1ull));
+      }
       b.base = off;
       set_rowmajor(out, b);
       off += out.block_elems(b);
     }
     out.size = off;
   } else {
-    std::iota(remap.begin(), remap.end(), 0);
+    for (int xb = 0; xb < (int)X.blocks.size(); ++xb) {
+      SectKey k;
+      k.n = (uint8_t)xs.size();
+      for (size_t i = 0; i < xs.size(); ++i) k.v[i] = X.blocks[xb].sect[xs[i]];
+      auto g = groups.find(k);
+      if (g == groups.end()) continue;
+      for (int sb : g->second) {
+        SectKey ok;
+        ok.n = (uint8_t)no;
+        for (int o = 0; o < no; ++o)
+          ok.v[o] = src_side[o] ? S.blocks[sb].sect[src_pos[o]] : X.blocks[xb].sect[src_pos[o]];
+        auto it = out_index.find(ok);
+        int ob;
+        if (it == out_index.end()) {
+          if (fixed_out) {
+            if (spec.restrict_to_fixed) continue;
+            err = "a block pair produces a block outside the fixed output layout";
+            return false;
+          }
+          ob = (int)out_keys.size();
+          out_index.emplace(ok, ob);
+          out_keys.push_back(ok);
+        } else {
+          ob = it->second;
+        }
+        trip.push_back({xb, sb, ob});
+      }
+    }
+    // output blocks sorted by sector tuple when not fixed
+    remap.assign(out_keys.size(), 0);
+    if (!fixed_out) {
+      std::vector<int> order(out_keys.size());
+      std::iota(order.begin(), order.end(), 0);
+      std::sort(order.begin(), order.end(), [&](int a, int b) { return out_keys[a] < out_keys[b]; });
+      out.blocks.resize(order.size());
+      int64_t off = 0;
+      for (size_t i = 0; i < order.size(); ++i) {
+        remap[order[i]] = (int)i;
+        Block& b = out.blocks[i];
+        for (int o = 0; o < no; ++o) b.sect[o] = out_keys[order[i]].v[o];
+        b.base = off;
+        set_rowmajor(out, b);
+        off += out.block_elems(b);
+      }
+      out.size = off;
+    } else {
+      std::iota(remap.begin(), remap.end(), 0);
+    }
   }
-  for (auto& t : trip) t.ob = remap[t.ob];
   if (spec.symbolic) return true;
-  std::stable_sort(trip.begin(), trip.end(), [](const P3& a, const P3& b) { return a.ob < b.ob; });
+  // triples ordered by output block, in enumeration order within a block
+  // (a counting sort)
+  {
+    std::vector<int64_t> start(out.blocks.size() + 1, 0);
+    for (auto& t : trip) {
+      t.ob = remap[t.ob];
+      ++start[t.ob + 1];
+    }
+    for (size_t b = 0; b < out.blocks.size(); ++b) start[b + 1] += start[b];
+    std::vector<P3> sorted(trip.size());
+    for (const P3& t : trip) sorted[start[t.ob]++] = t;
+    trip.swap(sorted);
+  }
 
   // keys of the per-pair scalar
+  if (spec.key_order.size() > 2 * MAXL) {
+    err = "key order too long";
+    return false;
+  }
   const BT& KT = spec.key_side == 0 ? X : out;
   for (int n : spec.key_order) {
     int p = KT.pos(n);
@@ -360,16 +484,28 @@ bool enumerate_step(const BT& X, const BT& S, const StepSpec& spec, const BT* fi
   return true;
 }
 
-double trip_alpha(const StepEnum& E, const BT& X, const BT& S, const BT& out,
-                  const StepSpec& spec, const SymInfo& sym, const P3& t) {
+double trip_alpha(StepEnum& E, const BT& X, const BT& S, const BT& out, const StepSpec& spec,
+                  const SymInfo& sym, const P3& t) {
   if (sym.kind != SYM_SU2 && !sym.fermionic) return 1.0;
   const BT& KT = spec.key_side == 0 ? X : out;
-  const Block& kb = spec.key_side == 0 ? X.blocks[t.xb] : out.blocks[t.ob];
+  const int kbi = spec.key_side == 0 ? t.xb : t.ob;
+  if (E.head.empty()) {
+    E.head.resize(KT.blocks.size());
+    E.head_set.assign(KT.blocks.size(), 0);
+  }
+  if (!E.head_set[kbi]) {
+    const Block& kb = KT.blocks[kbi];
+    const int nx = (int)E.kpos.size();
+    const int32_t* xl[2 * MAXL];
+    for (int i = 0; i < nx; ++i) xl[i] = KT.cat[E.kpos[i]]->label(kb.sect[E.kpos[i]]);
+    E.head[kbi] = alpha_head(sym, spec.step, xl, nx, E.kshared.data(), E.nlab);
+    E.head_set[kbi] = 1;
+  }
   const Block& sbk = S.blocks[t.sb];
-  std::vector<const int32_t*> xl(E.kpos.size()), tl(S.nlegs());
-  for (size_t i = 0; i < E.kpos.size(); ++i) xl[i] = KT.cat[E.kpos[i]]->label(kb.sect[E.kpos[i]]);
-  for (int q = 0; q < S.nlegs(); ++q) tl[q] = S.cat[q]->label(sbk.sect[q]);
-  return pair_alpha(sym, spec.step, xl, tl, E.kshared, E.sshared, E.nlab);
+  const int nt = S.nlegs();
+  const int32_t* tl[MAXL];
+  for (int q = 0; q < nt; ++q) tl[q] = S.cat[q]->label(sbk.sect[q]);
+  return alpha_tail(sym, E.head[kbi], tl, nt, E.sshared.data(), E.nlab);
 }
 
 }  // namespace
@@ -643,6 +779,7 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
     pstart[out.blocks.size()] = (int)trip.size();
   }
   int64_t tiles = 0;
+  std::vector<double> palpha;
   for (auto& kv : gmap) {
     const int ob0 = kv.second.front();
     const Block& cb0 = out.blocks[ob0];
@@ -755,6 +892,10 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
       // every chunk re-reads the row's inputs
       const int64_t nchunks = (Nb + ncmax - 1) / ncmax;
       const int64_t cw = (Nb + nchunks - 1) / nchunks;
+      // the pair scalars of this block, shared by its chunks
+      palpha.resize((size_t)(pstart[ob + 1] - pstart[ob]));
+      for (int pi = pstart[ob]; pi < pstart[ob + 1]; ++pi)
+        palpha[pi - pstart[ob]] = trip_alpha(E, X, S, out, spec, sym, trip[pi]);
       for (int64_t n0 = 0; n0 < Nb; n0 += cw) {
         const int nc = (int)std::min<int64_t>(cw, Nb - n0);
         RtOut o = base_o;
@@ -763,7 +904,6 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
         o.p0 = (int32_t)rt.pairs.size();
         for (int pi = pstart[ob]; pi < pstart[ob + 1]; ++pi) {
           const P3& t = trip[pi];
-          const Block& xb = X.blocks[t.xb];
           const Block& sb = S.blocks[t.sb];
           RtPair pr;
           const int32_t kbi = kmap.at(t.xb);
@@ -816,7 +956,7 @@ bool plan_step_rt(const BT& X, const BT& S, const StepSpec& spec, const SymInfo&
                                                                         all.begin() + n0 + nc),
                                                  &ok)).first;
           pk.sntab = it->second;
-          pk.alpha = trip_alpha(E, X, S, out, spec, sym, t);
+          pk.alpha = palpha[pi - pstart[ob]];
           rt.pack_size += Kb * nc;
           rt.packs.push_back(pk);
           rt.pairs.push_back(pr);

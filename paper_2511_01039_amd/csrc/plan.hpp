@@ -143,9 +143,10 @@ void choose_tile(const std::vector<std::pair<int64_t, int64_t>>& mn,
 // times the parity sign. ``xlabs`` are the labels of the sketch-side
 // intermediate block in its canonical leg order, ``tlabs`` those of the step
 // tensor block; ``xshared``/``tshared`` flag the contracted legs.
-double pair_alpha(const SymInfo& sym, int step, const std::vector<const int32_t*>& xlabs,
-                  const std::vector<const int32_t*>& tlabs, const std::vector<bool>& xshared,
-                  const std::vector<bool>& tshared, int nlab);
+// ``nx`` and ``nt`` count the entries of the label and flag arrays.
+double pair_alpha(const SymInfo& sym, int step, const int32_t* const* xlabs, int nx,
+                  const int32_t* const* tlabs, int nt, const char* xshared, const char* tshared,
+                  int nlab);
 
 uint64_t splitmix64_mix(uint64_t z);
 
