@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <future>
 #include <map>
 
 namespace fp {
@@ -591,6 +592,9 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     R.size = 1;
   }
   int rcur = 0;
+  // the remainder's squared norm, summed on the device and not yet divided out
+  const double* r_nrm = nullptr;
+  int64_t r_len = 0;
   // The previous site's analysis and plans: a site whose structure key,
   // widths, budget and precision are equal reuses them (interior sites of a
   // row often share their block structure) and only uploads them again.
@@ -638,6 +642,17 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
       op.unit_size = cache.unit_size;
     } else {
       FP_TRY(op.analyse());
+    }
+    if (r_nrm) {
+      double h = 0;
+      FP_HIP(hipMemcpyAsync(&h, r_nrm, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      FP_TRY(ctx->sync());
+      if (!(h > 0.0) || !std::isfinite(h))
+        return fail(FPEPS_ERR_NUMERIC, "remainder has zero or non-finite norm");
+      const double nu = std::sqrt(h);
+      FP_HIP(launch_scale(Rbuf[rcur], r_len, 1.0 / nu, ctx->stream));
+      lg += std::log(nu);
+      r_nrm = nullptr;
     }
     const int ns = (int)op.sect.size();
     SiteDiag& dg = ctx->diag[x];
@@ -711,6 +726,11 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     io.c2 = (uint32_t)x;
     io.c3 = (uint32_t)(o->row & 0xFFFF);
     double t_plan = 0;
+    // The transposed-chain plans are first used after the sketch product
+    // M Omega: they are planned on a host thread while the device runs it,
+    // and uploaded before the first transposed application.
+    std::future<Status> bwd_job;
+    bool bwd_wait = false;
     io.prepare = [&](const std::vector<int32_t>& k) {
       const double t0 = wall();
       Status st = Status::ok();
@@ -720,19 +740,37 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
         ++cache_hits;
       } else {
         plp = std::make_shared<SiteOp::Plans>();
-        st = op.plan_host(k, budget, *plp, true, f32);
-        if (st.good()) st = op.upload(ctx, *plp);
+        st = op.plan_host(k, budget, *plp, false, f32);
+        if (st.good()) st = op.upload(ctx, *plp, 1);
+        if (st.good()) {
+          const SiteOp* opc = &op;
+          std::shared_ptr<SiteOp::Plans> pl = plp;
+          bwd_job = std::async(std::launch::async, [opc, k, pl]() { return opc->plan_bwd(k, *pl); });
+          bwd_wait = true;
+        }
       }
       t_plan += wall() - t0;
       return st;
     };
+    auto join_bwd = [&](bool up) -> Status {
+      if (!bwd_wait) return Status::ok();
+      bwd_wait = false;
+      const double t0 = wall();
+      FP_TRY(bwd_job.get());
+      op.sum_plans(*plp);
+      if (up) FP_TRY(op.upload(ctx, *plp, 2));
+      t_plan += wall() - t0;
+      return Status::ok();
+    };
     io.apply = [&](bool t, bool fin, const double* xi, double* yo) {
+      if (t) FP_TRY(join_bwd(true));
       return op.apply(ctx, *plp, t, xi, yo, f32 && !fin);
     };
     RsvdOut rs;
     const double tw1 = wall();
     {
       Status st = rsvd_run(ctx, io, o->chi, o->oversample, o->power_iters, o->seed, rs, o->sv_cut);
+      if (st.good()) st = join_bwd(false);
       if (!st.good()) return fail(st.code, "site " + std::to_string(x) + ": " + st.msg);
     }
     fallbacks |= rs.fallbacks;
@@ -867,18 +905,17 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     } else {
       cap_fail = true;
     }
-    // normalise the remainder
-    double *part = nullptr, *nrm = nullptr;
-    FP_TRY(ctx->bufT("nrm_part", 512, &part));
-    FP_TRY(ctx->bufT("nrm_out", 1, &nrm));
-    FP_HIP(launch_sumsq(Rbuf[rn], rt, part, nrm, ctx->stream));
-    double h = 0;
-    FP_HIP(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    FP_TRY(ctx->sync());
-    if (!(h > 0.0) || !std::isfinite(h)) return fail(FPEPS_ERR_NUMERIC, "remainder has zero or non-finite norm");
-    const double nu = std::sqrt(h);
-    FP_HIP(launch_scale(Rbuf[rn], rt, 1.0 / nu, ctx->stream));
-    lg += std::log(nu);
+    // normalise the remainder: its norm is summed here and read after the
+    // next site's structure analysis, so that host work overlaps the factor
+    // products still running on the device
+    {
+      double *part = nullptr, *nrm = nullptr;
+      FP_TRY(ctx->bufT("nrm_part", 512, &part));
+      FP_TRY(ctx->bufT("nrm_out", 1, &nrm));
+      FP_HIP(launch_sumsq(Rbuf[rn], rt, part, nrm, ctx->stream));
+      r_nrm = nrm;
+      r_len = rt;
+    }
     // R for the next site: per-sector matrices (kept_J x n_J), blocks by column tuple
     BT Rn;
     Rn.names = {N_c, N_a, N_lk, N_lw, N_lb};

@@ -386,16 +386,40 @@ Status SiteOp::plan_host(const std::vector<int32_t>& k, int64_t budget, Plans& o
     for (auto& x : th) x.join();
   }
   for (auto& e : st) FP_TRY(e);
+  sum_plans(out);
+  return Status::ok();
+}
+
+Status SiteOp::plan_bwd(const std::vector<int32_t>& k, Plans& out) const {
+  const size_t ntask = out.slices.size();
+  std::vector<Status> st(ntask);
+  {
+    const unsigned hc = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>(ntask, std::min(16u, hc));
+    auto work = [&](size_t t) {
+      for (size_t i = t; i < ntask; i += nt) st[i] = plan_slice(k, out, out.slices[i], true);
+    };
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < nt; ++t) th.emplace_back(work, t);
+    if (nt > 0) work(0);
+    for (auto& x : th) x.join();
+  }
+  for (auto& e : st) FP_TRY(e);
+  return Status::ok();
+}
+
+void SiteOp::sum_plans(Plans& out) const {
+  out.flops_fwd = out.flops_bwd = 0;
+  out.ws1 = out.ws2 = 0;
   for (const Slice& sl : out.slices) {
     out.flops_fwd += sl.flops_fwd;
     out.flops_bwd += sl.flops_bwd;
     out.ws1 = std::max(out.ws1, std::max(sl.size1, sl.bsize1));
     out.ws2 = std::max(out.ws2, std::max(sl.size2, sl.bsize2));
   }
-  return Status::ok();
 }
 
-Status SiteOp::upload(fpeps_ctx_s* ctx, Plans& out) const {
+Status SiteOp::upload(fpeps_ctx_s* ctx, Plans& out, int which) const {
   const bool f32 = out.f32;
   // uploads through the pinned arena, asynchronous on the stream
   const auto up0 = std::chrono::steady_clock::now();
@@ -403,10 +427,13 @@ Status SiteOp::upload(fpeps_ctx_s* ctx, Plans& out) const {
   // one arena region per plan set, written on host threads, then one copy each
   std::vector<PlanSet*> sets;
   std::vector<std::string> tags;
+  const bool up_f = (which & 1) != 0, up_b = (which & 2) != 0;
   for (size_t i = 0; i < out.slices.size(); ++i) {
-    sets.push_back(out.slices[i].ps.get());
-    tags.push_back("site" + std::to_string(i) + "f");
-    if (out.slices[i].psb) {
+    if (up_f) {
+      sets.push_back(out.slices[i].ps.get());
+      tags.push_back("site" + std::to_string(i) + "f");
+    }
+    if (up_b && out.slices[i].psb) {
       sets.push_back(out.slices[i].psb.get());
       tags.push_back("site" + std::to_string(i) + "b");
     }
@@ -435,11 +462,11 @@ Status SiteOp::upload(fpeps_ctx_s* ctx, Plans& out) const {
     // layer sub-blocks scaled by the per-pair scalars (the bra shares the
     // ket's data)
     for (int s = 0; s < 5; ++s) {
-      if (sl.fwd_rt[s]) {
+      if (up_f && sl.fwd_rt[s]) {
         const bool w = s == 2;
         FP_TRY(sl.ps->pack(ctx, sl.fwd[s], w ? dev.W : dev.A, w ? dev.W_size : dev.A_size));
       }
-      if (sl.psb && sl.bwd[s] >= 0 && sl.bwd_rt[s]) {
+      if (up_b && sl.psb && sl.bwd[s] >= 0 && sl.bwd_rt[s]) {
         const bool w = s == 2;   // bwd order: T5, T4, T3, T2, T1
         FP_TRY(sl.psb->pack(ctx, sl.bwd[s], w ? dev.W : dev.A, w ? dev.W_size : dev.A_size));
       }
@@ -533,11 +560,13 @@ Status SiteOp::plan_slice(const std::vector<int32_t>& k, const Plans& pl, Slice&
         sl.bwd[s] = ps.add(std::move(r.plan));
       }
       sl.bwd_rt[s] = layer;
+      // its own fields: the forward chain of this slice is planned on
+      // another thread at the same time
       if (s < 4) {
         if (s % 2 == 0)
-          sl.size2 = std::max(sl.size2, r.out.size);
+          sl.bsize2 = std::max(sl.bsize2, r.out.size);
         else
-          sl.size1 = std::max(sl.size1, r.out.size);
+          sl.bsize1 = std::max(sl.bsize1, r.out.size);
       }
       Z = std::move(r.out);
     }

@@ -84,7 +84,15 @@ class SiteOp {
   // with the same structure key can be uploaded for this one)
   Status plan_host(const std::vector<int32_t>& k, int64_t budget, Plans& out, bool with_bwd,
                    bool f32) const;
-  Status upload(fpeps_ctx_s* ctx, Plans& pl) const;
+  // the transposed-chain plans of every slice of ``out`` (planned by
+  // plan_host without them). Thread safe against apply() of the forward
+  // chain: it writes only the transposed fields of the slices. Call
+  // sum_plans() afterwards, on the thread that uses ``out``.
+  Status plan_bwd(const std::vector<int32_t>& k, Plans& out) const;
+  // totals of ``out`` (flops, intermediate sizes) from its slices
+  void sum_plans(Plans& out) const;
+  // which: 1 the forward plans, 2 the transposed ones, 3 both
+  Status upload(fpeps_ctx_s* ctx, Plans& pl, int which = 3) const;
   // y = M x (transpose = false) or M^T x, per-sector matrices at the offsets
   // of ``pl`` (x: col layout for M, row layout for M^T). ``f32`` stores the
   // chain intermediates of this application in FP32 (arithmetic stays FP64).
