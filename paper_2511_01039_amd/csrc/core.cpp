@@ -2,6 +2,7 @@
 #include "core.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 
 fpeps_ctx_s::~fpeps_ctx_s() {
@@ -13,6 +14,21 @@ fpeps_ctx_s::~fpeps_ctx_s() {
   for (auto& kv : bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (stage) (void)hipHostFree(stage);
+}
+
+void fpeps_ctx_s::release_later(std::shared_ptr<void> p) {
+  if (!p) return;
+  reaping.erase(std::remove_if(reaping.begin(), reaping.end(),
+                               [](std::future<void>& f) {
+                                 return f.wait_for(std::chrono::seconds(0)) ==
+                                        std::future_status::ready;
+                               }),
+                reaping.end());
+  try {
+    reaping.push_back(std::async(std::launch::async, [q = std::move(p)]() mutable { q.reset(); }));
+  } catch (...) {
+    // no helper thread: the captured reference is dropped here instead
+  }
 }
 
 fp::Status fpeps_ctx_s::ensure_stream2() {

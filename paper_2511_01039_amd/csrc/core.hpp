@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <array>
+#include <future>
 #include <map>
 #include <memory>
 #include <string>
@@ -99,6 +100,13 @@ struct fpeps_ctx_s {
   // device buffer ``name`` filled from ``host`` (an arena region: an
   // asynchronous copy between stage_begin and stage_end, else a blocking one)
   fp::Status upload_region(const std::string& name, const char* host, size_t bytes, void** dev);
+
+  // Host objects dropped on helper threads: the plan sets of a site take
+  // milliseconds to free, which would otherwise leave the device idle
+  // between sites. Finished releases are pruned on the next call; the rest
+  // are waited for when the context is destroyed.
+  std::vector<std::future<void>> reaping;
+  void release_later(std::shared_ptr<void> p);
 
   ~fpeps_ctx_s();
   // device buffer ``name`` of at least ``bytes`` (grown, contents lost on growth)

@@ -948,6 +948,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     cache.key = std::move(key);
     cache.sect = op.sect;
     cache.unit_size = op.unit_size;
+    ctx->release_later(std::move(cache.pl));
     cache.pl = plp;
     cache.k = rs.k;
     // diagnostics and report
@@ -976,6 +977,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     if (rs.cut.s_next >= 0 && rs.cut.s_last > 0)
       gap = std::min(gap, (rs.cut.s_last - rs.cut.s_next) / rs.cut.s_last);
   }
+  ctx->release_later(std::move(cache.pl));
   FP_HIP(hipEventRecord(ev1, ctx->stream));
   FP_HIP(hipEventSynchronize(ev1));
   float ms = 0;
