@@ -606,6 +606,9 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     std::vector<int32_t> k;
   } cache;
   int cache_hits = 0;
+  // the remainder-independent part of the last analysis (interior sites of
+  // a row share their T, ket and PEPO structure)
+  FwdAnalysis fwd_an;
   for (int x = 0; x < L; ++x) {
     BT T, K, W;
     FP_TRY(tensor_to_bt(&env_in[x], {N_a, N_tk, N_tw, N_tb, N_b}, nlab, T));
@@ -641,7 +644,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
       op.sect = cache.sect;
       op.unit_size = cache.unit_size;
     } else {
-      FP_TRY(op.analyse());
+      FP_TRY(op.analyse(&fwd_an));
     }
     if (r_nrm) {
       double h = 0;

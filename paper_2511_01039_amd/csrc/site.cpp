@@ -122,71 +122,110 @@ void sizes_by_sector(const BT& bt, int jpos, std::vector<int64_t>& acc) {
 }
 }  // namespace
 
-Status SiteOp::analyse() {
-  const int pb = T.pos(N_b), prk = ket.pos(N_rk), prw = W.pos(N_rw), prb = bra.pos(N_rb);
-  std::vector<const Leg*> cl = {T.cat[pb].get(), ket.cat[prk].get(), W.cat[prw].get(),
-                                bra.cat[prb].get()};
-  std::map<std::vector<int32_t>, Sector> by;
-  std::array<uint16_t, 4> t{};
-  for (t[0] = 0; t[0] < cl[0]->nsect(); ++t[0])
-    for (t[1] = 0; t[1] < cl[1]->nsect(); ++t[1])
-      for (t[2] = 0; t[2] < cl[2]->nsect(); ++t[2])
-        for (t[3] = 0; t[3] < cl[3]->nsect(); ++t[3]) {
-          int64_t d = 1;
-          for (int i = 0; i < 4; ++i) d *= cl[i]->dim[t[i]];
-          for (auto& J : col_labels(sym, nlab, cl, t)) {
-            Sector& s = by[J];
-            s.label = J;
-            s.cols.push_back(t);
-            s.crow.push_back(s.n);
-            s.cdim.push_back(d);
-            s.n += d;
-          }
-        }
-  sect.clear();
-  for (auto& kv : by) sect.push_back(std::move(kv.second));
-  const int ns = (int)sect.size();
-  if (ns == 0) return fail(FPEPS_ERR_SHAPE, "empty column space");
-
-  // structure-only pass with one column per sector: the rows of Y_J and the
-  // size of every intermediate per unit of width
-  std::vector<int32_t> k1(ns, 1);
-  std::vector<int64_t> off(ns);
-  int64_t tot = 0;
-  for (int J = 0; J < ns; ++J) {
-    off[J] = tot;
-    tot += sect[J].n;
-  }
+Status SiteOp::analyse(FwdAnalysis* fwdc) {
+  std::string tkw;
+  if (fwdc) tkw = structure_key_tkw();
+  const bool reuse = fwdc && !fwdc->key.empty() && fwdc->key == tkw;
+  int ns = 0;
+  std::vector<int32_t> k1;
   std::vector<SliceCol> all;
-  for (int J = 0; J < ns; ++J) all.push_back({J, 0, 1});
-  BT X = omega_layout(all, k1, off, tot, false);
-  TablePool dummy;
   std::string err;
-  const std::vector<int>* store[5] = {&STORE_X1, &STORE_X2, &STORE_X3, &STORE_X4, &ORDER_X[5]};
-  const BT* S[5] = {&T, &ket, &W, &bra, &R};
-  const bool mx[5] = {false, true, true, true, false};
-  unit_size.assign(ns, std::vector<int64_t>(8, 0));
-  std::vector<BT> fwd(5);
-  for (int s = 0; s < 5; ++s) {
-    StepSpec sp;
-    sp.step = s + 1;
-    sp.m_is_x = mx[s];
-    sp.key_side = 0;
-    sp.out_names = *store[s];
-    sp.key_order = ORDER_X[s];
-    sp.symbolic = true;
-    StepResult r;
-    if (!plan_step(s == 0 ? X : fwd[s - 1], *S[s], sp, sym, dummy, nullptr, r, err))
-      return fail(FPEPS_ERR_SHAPE, "chain step " + std::to_string(s + 1) + ": " + err);
-    fwd[s] = std::move(r.out);
-    if (s < 4) {
+  BT X4;
+  if (reuse) {
+    sect = fwdc->sect;
+    ns = (int)sect.size();
+    unit_size.assign(ns, std::vector<int64_t>(8, 0));
+    for (int J = 0; J < ns; ++J)
+      for (int s = 0; s < 4; ++s) unit_size[J][s] = fwdc->unit[J][s];
+    X4 = fwdc->x4;
+    k1.assign(ns, 1);
+    for (int J = 0; J < ns; ++J) all.push_back({J, 0, 1});
+  } else {
+    const int pb = T.pos(N_b), prk = ket.pos(N_rk), prw = W.pos(N_rw), prb = bra.pos(N_rb);
+    std::vector<const Leg*> cl = {T.cat[pb].get(), ket.cat[prk].get(), W.cat[prw].get(),
+                                  bra.cat[prb].get()};
+    std::map<std::vector<int32_t>, Sector> by;
+    std::array<uint16_t, 4> t{};
+    for (t[0] = 0; t[0] < cl[0]->nsect(); ++t[0])
+      for (t[1] = 0; t[1] < cl[1]->nsect(); ++t[1])
+        for (t[2] = 0; t[2] < cl[2]->nsect(); ++t[2])
+          for (t[3] = 0; t[3] < cl[3]->nsect(); ++t[3]) {
+            int64_t d = 1;
+            for (int i = 0; i < 4; ++i) d *= cl[i]->dim[t[i]];
+            for (auto& J : col_labels(sym, nlab, cl, t)) {
+              Sector& s = by[J];
+              s.label = J;
+              s.cols.push_back(t);
+              s.crow.push_back(s.n);
+              s.cdim.push_back(d);
+              s.n += d;
+            }
+          }
+    sect.clear();
+    for (auto& kv : by) sect.push_back(std::move(kv.second));
+    ns = (int)sect.size();
+    if (ns == 0) return fail(FPEPS_ERR_SHAPE, "empty column space");
+
+    // structure-only pass with one column per sector: the rows of Y_J and
+    // the size of every intermediate per unit of width
+    k1.assign(ns, 1);
+    std::vector<int64_t> off(ns);
+    int64_t tot = 0;
+    for (int J = 0; J < ns; ++J) {
+      off[J] = tot;
+      tot += sect[J].n;
+    }
+    for (int J = 0; J < ns; ++J) all.push_back({J, 0, 1});
+    BT X = omega_layout(all, k1, off, tot, false);
+    TablePool dummy;
+    const std::vector<int>* store[4] = {&STORE_X1, &STORE_X2, &STORE_X3, &STORE_X4};
+    const BT* S[4] = {&T, &ket, &W, &bra};
+    const bool mx[4] = {false, true, true, true};
+    unit_size.assign(ns, std::vector<int64_t>(8, 0));
+    for (int s = 0; s < 4; ++s) {
+      StepSpec sp;
+      sp.step = s + 1;
+      sp.m_is_x = mx[s];
+      sp.key_side = 0;
+      sp.out_names = *store[s];
+      sp.key_order = ORDER_X[s];
+      sp.symbolic = true;
+      StepResult r;
+      if (!plan_step(X, *S[s], sp, sym, dummy, nullptr, r, err))
+        return fail(FPEPS_ERR_SHAPE, "chain step " + std::to_string(s + 1) + ": " + err);
+      X = std::move(r.out);
       std::vector<int64_t> acc(ns, 0);
-      sizes_by_sector(fwd[s], fwd[s].pos(N_j), acc);
+      sizes_by_sector(X, X.pos(N_j), acc);
       for (int J = 0; J < ns; ++J) unit_size[J][s] = acc[J];
     }
+    X4 = std::move(X);
+    if (fwdc) {
+      fwdc->key = std::move(tkw);
+      fwdc->sect = sect;
+      fwdc->unit.assign(ns, std::vector<int64_t>(4, 0));
+      for (int J = 0; J < ns; ++J)
+        for (int s = 0; s < 4; ++s) fwdc->unit[J][s] = unit_size[J][s];
+      fwdc->x4 = X4;
+    }
   }
+  // the last forward step (the remainder) fixes the rows of every sector
+  TablePool dummy;
+  BT Y;
+  {
+    StepSpec sp;
+    sp.step = 5;
+    sp.m_is_x = false;
+    sp.key_side = 0;
+    sp.out_names = ORDER_X[5];
+    sp.key_order = ORDER_X[4];
+    sp.symbolic = true;
+    StepResult r;
+    if (!plan_step(X4, R, sp, sym, dummy, nullptr, r, err))
+      return fail(FPEPS_ERR_SHAPE, "chain step 5: " + err);
+    Y = std::move(r.out);
+  }
+  const BT* S[5] = {&T, &ket, &W, &bra, &R};
   // rows of every sector, lexicographic in (c, dk, dw, db)
-  const BT& Y = fwd[4];
   for (const Block& b : Y.blocks) {
     std::array<uint16_t, 4> r = {b.sect[0], b.sect[1], b.sect[2], b.sect[3]};
     sect[b.sect[4]].rows.push_back(r);
@@ -307,6 +346,14 @@ void key_bt(std::string& s, const BT& bt) {
   key_put(s, &bt.size, sizeof bt.size);
 }
 }  // namespace
+
+std::string SiteOp::structure_key_tkw() const {
+  std::string s;
+  const int64_t h[4] = {sym.kind, sym.fermionic ? 1 : 0, (int64_t)sym.coef_seed, nlab};
+  key_put(s, h, sizeof h);
+  for (const BT* b : {&T, &ket, &W}) key_bt(s, *b);
+  return s;
+}
 
 std::string SiteOp::structure_key() const {
   std::string s;

@@ -5,6 +5,7 @@
 
 #include <array>
 #include <memory>
+#include <string>
 #include <vector>
 
 #include "core.hpp"
@@ -36,6 +37,16 @@ struct SiteData {
   int64_t T_size = 0, A_size = 0, W_size = 0, R_size = 0;
 };
 
+// The part of a site's structure analysis that depends only on T, the ket
+// and the PEPO (not on the remainder): the column sectors, and the forward
+// chain up to X4 at unit width. Interior sites of a row share it.
+struct FwdAnalysis {
+  std::string key;                              // structure of T, ket and W
+  std::vector<Sector> sect;                     // column sectors (rows empty)
+  std::vector<std::vector<int64_t>> unit;       // [sector][X1..X4 elements per unit width]
+  BT x4;                                        // X4 structure at unit width
+};
+
 class SiteOp {
  public:
   SymInfo sym;
@@ -49,12 +60,17 @@ class SiteOp {
   Status init(const SymInfo& s, int nlab_, BT&& T_, BT&& ket_, BT&& W_, BT&& R_,
               const SiteData& d);
   // Sector structure (columns, rows via a structure-only forward pass).
-  Status analyse();
+  // ``fwd``, when given, holds the remainder-independent part of a previous
+  // site's analysis: it is reused when that site's T, ket and W structure
+  // equals this one's, and replaced otherwise.
+  Status analyse(FwdAnalysis* fwd = nullptr);
   // Everything the analysis and the plans depend on, serialised: symmetry,
   // and the legs, block sectors, offsets and strides of T, ket, W, bra and
   // R (not their data). Two sites with equal keys have equal sectors, and
   // equal plans for equal widths.
   std::string structure_key() const;
+  // the same for T, ket and W only (the bra is the ket)
+  std::string structure_key_tkw() const;
 
   // Plans of M (fwd) and M^T (bwd) for per-sector widths k, sliced so that
   // the chain intermediates of one slice fit ``budget`` bytes.
