@@ -7,7 +7,7 @@ randomized-SVD truncation at every bond.
 A step is one full row absorption (8 sites: sketch, chain applications,
 orthonormalisation, projection, core factorisation, cut, new environment and
 remainder) on inputs resident in HBM. The timed steps run the library as a
-caller would (slices of a site alternate between two streams); the per-kernel
+caller would (slices of a site spread over four streams); the per-kernel
 figures of the roofline come from one more step on one stream with every
 launch timed by HIP events. Prints one JSON line.
 
@@ -327,7 +327,7 @@ def main():
         """W untimed + K timed absorptions of the row; device-resident inputs."""
         kw = dict(chi=row.chi, oversample=row.oversample, power_iters=row.power_iters, seed=0,
                   row=row.row, precision=precision, slice_budget=int(a.slice_budget_gib * 2**30))
-        # timed steps: the library's default two streams (slices overlap);
+        # timed steps: the library's default four streams (slices overlap);
         # kernel figures: one more step on one stream with every launch timed
         # by HIP events (overlapping launches would stretch each other's
         # durations)
@@ -413,8 +413,8 @@ def main():
         "k_gemm_f64": {"seconds_per_step": gem_s, "TFLOP/s": gemm_tfs,
                        "frac_fp64_mfma": gemm_tfs / PEAK["fp64"]}}
     roof["timing"] = ("HIP events around every launch, one extra step of the same row on one "
-                      "stream (launches do not overlap); the timed steps run slices on two "
-                      "streams")
+                      "stream (launches do not overlap); the timed steps spread slices over "
+                      "four streams")
     line = {"metric": METRIC, "value": R["value"], "unit": "TFLOP/s", "n_gpus": 1,
             "steps": a.steps, "warmup": a.warmup, "ms_per_step": R["sec"] * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

@@ -126,8 +126,9 @@ typedef struct {
   int32_t fermionic;      /* 1: parity sign on every contracted block pair */
   uint64_t coef_seed;     /* SU(2): key of the synthetic recoupling scalars */
   int64_t slice_budget;   /* bytes for chain intermediates per slice (0: automatic). The
-                             slices of a site alternate between two streams, so two
-                             slices' intermediates are live (see FPEPS_FLAG_ONE_STREAM) */
+                             slices of a site are spread round-robin over four streams, so
+                             up to four slices' intermediates are live (see
+                             FPEPS_FLAG_ONE_STREAM) */
   uint32_t flags;         /* FPEPS_FLAG_* */
   int32_t tag;            /* explicit-matrix calls: counter word c2 of the sketch */
   double sv_cut;          /* singular values <= sv_cut * largest are never kept

@@ -6,11 +6,11 @@
 #include <cstring>
 
 fpeps_ctx_s::~fpeps_ctx_s() {
-  if (!bufs.empty() || !evpool.empty() || stage || stream2) (void)hipDeviceSynchronize();
+  if (!bufs.empty() || !evpool.empty() || stage || !xstreams.empty()) (void)hipDeviceSynchronize();
   for (auto e : evpool) (void)hipEventDestroy(e);
   if (ev_fork) (void)hipEventDestroy(ev_fork);
-  if (ev_join) (void)hipEventDestroy(ev_join);
-  if (stream2) (void)hipStreamDestroy(stream2);
+  for (auto e : xjoin) (void)hipEventDestroy(e);
+  for (auto x : xstreams) (void)hipStreamDestroy(x);
   for (auto& kv : bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (stage) (void)hipHostFree(stage);
@@ -31,11 +31,23 @@ void fpeps_ctx_s::release_later(std::shared_ptr<void> p) {
   }
 }
 
-fp::Status fpeps_ctx_s::ensure_stream2() {
-  if (!stream2) FP_HIP(hipStreamCreateWithFlags(&stream2, hipStreamNonBlocking));
+fp::Status fpeps_ctx_s::ensure_streams(int n) {
   if (!ev_fork) FP_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
-  if (!ev_join) FP_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+  while ((int)xstreams.size() < n - 1) {
+    hipStream_t x = nullptr;
+    hipEvent_t e = nullptr;
+    FP_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    xstreams.push_back(x);
+    FP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    xjoin.push_back(e);
+  }
   return fp::Status::ok();
+}
+
+int fpeps_ctx_s::stream_index(hipStream_t s) const {
+  for (size_t i = 0; i < xstreams.size(); ++i)
+    if (xstreams[i] == s) return (int)i + 1;
+  return 0;
 }
 
 fp::Status fpeps_ctx_s::stage_begin() {
@@ -399,10 +411,12 @@ Status run_gemm_mixed(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double
   if (b_f32 && c_f32) return fail(FPEPS_ERR_UNSUPPORTED, "GEMM with both B and C in FP32");
   // split-K parts are summed in FP64 and rounded once into C
   double* part = nullptr;
-  // each stream has its own partial buffer (slices on two streams overlap)
-  if (p.partial_size > 0)
-    FP_TRY(ctx->bufT(ctx->stream2 && ctx->stream == ctx->stream2 ? "gemm_part2" : "gemm_part",
+  // each stream has its own partial buffer (slices on several streams overlap)
+  if (p.partial_size > 0) {
+    const int si = ctx->stream_index(ctx->stream);
+    FP_TRY(ctx->bufT(si ? "gemm_part" + std::to_string(si + 1) : std::string("gemm_part"),
                      (size_t)p.partial_size, &part));
+  }
   hipEvent_t ea = nullptr, eb = nullptr;
   const bool tk = timed && ctx->time_kernels;
   if (tk) {

@@ -61,12 +61,18 @@ struct SiteDiag {
 struct fpeps_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
-  // second stream for alternate slices of a site (default priority; created
-  // on first use), with the fork and join events between the two
-  hipStream_t stream2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  bool two_streams = true;   // cleared by FPEPS_FLAG_ONE_STREAM
-  fp::Status ensure_stream2();
+  // extra streams for the slices of a site (default priority; created on
+  // first use): slice i runs on stream i % n, stream 0 being the context's.
+  // One fork event orders them after the context's stream, and one join
+  // event each orders the context's stream after them.
+  std::vector<hipStream_t> xstreams;
+  std::vector<hipEvent_t> xjoin;
+  hipEvent_t ev_fork = nullptr;
+  bool two_streams = true;   // cleared by FPEPS_FLAG_ONE_STREAM (then one stream)
+  int max_streams = 4;       // streams the slices of a site are spread over
+  fp::Status ensure_streams(int n);   // n - 1 extra streams
+  // 0 for the context's stream, i for xstreams[i - 1]
+  int stream_index(hipStream_t s) const;
   std::string err;
   std::map<std::string, fp::DevBuf> bufs;
   std::vector<fp::SiteDiag> diag;

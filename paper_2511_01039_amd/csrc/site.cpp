@@ -627,23 +627,30 @@ Status SiteOp::apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const do
   const size_t es = f32 ? sizeof(float) : sizeof(double);
   const int64_t s1 = std::max<int64_t>(pl.ws1, 1), s2 = std::max<int64_t>(pl.ws2, 1);
   // Slices are independent (disjoint sketch columns, disjoint outputs): they
-  // alternate between the context's stream and a second one, each with its
-  // own ping-pong intermediates, so the GEMM steps of one slice can run
-  // beside the layer steps of the next.
-  const bool two = ctx->two_streams && pl.slices.size() > 1;
-  void* b[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-  FP_TRY(ctx->buf("chain1", (size_t)s1 * es + 256, &b[0][0]));
-  FP_TRY(ctx->buf("chain2", (size_t)s2 * es + 256, &b[0][1]));
+  // are spread round-robin over the context's stream and up to
+  // max_streams - 1 more, each with its own ping-pong intermediates, so the
+  // GEMM steps of one slice can run beside the layer steps of the others.
+  const int nst = ctx->two_streams ? (int)std::min<size_t>(pl.slices.size(),
+                                                           (size_t)std::max(1, ctx->max_streams))
+                                   : 1;
+  std::vector<std::array<void*, 2>> b((size_t)nst, std::array<void*, 2>{nullptr, nullptr});
   hipStream_t s0 = ctx->stream;
-  if (two) {
-    FP_TRY(ctx->ensure_stream2());
-    FP_TRY(ctx->buf("chain1b", (size_t)s1 * es + 256, &b[1][0]));
-    FP_TRY(ctx->buf("chain2b", (size_t)s2 * es + 256, &b[1][1]));
-    // the second stream starts after everything queued so far (x is ready)
-    FP_HIP(hipEventRecord(ctx->ev_fork, s0));
-    FP_HIP(hipStreamWaitEvent(ctx->stream2, ctx->ev_fork, 0));
+  std::vector<hipStream_t> sq(1, s0);
+  if (nst > 1) {
+    FP_TRY(ctx->ensure_streams(nst));
+    for (int q = 1; q < nst; ++q) sq.push_back(ctx->xstreams[q - 1]);
   }
-  ctx->peak_ws = std::max(ctx->peak_ws, (double)(s1 + s2) * (double)es * (two ? 2.0 : 1.0));
+  for (int q = 0; q < nst; ++q) {
+    const std::string sfx = q ? "_s" + std::to_string(q + 1) : std::string();
+    FP_TRY(ctx->buf("chain1" + sfx, (size_t)s1 * es + 256, &b[q][0]));
+    FP_TRY(ctx->buf("chain2" + sfx, (size_t)s2 * es + 256, &b[q][1]));
+  }
+  if (nst > 1) {
+    // the other streams start after everything queued so far (x is ready)
+    FP_HIP(hipEventRecord(ctx->ev_fork, s0));
+    for (int q = 1; q < nst; ++q) FP_HIP(hipStreamWaitEvent(sq[q], ctx->ev_fork, 0));
+  }
+  ctx->peak_ws = std::max(ctx->peak_ws, (double)(s1 + s2) * (double)es * (double)nst);
   const bool f = f32;
   auto run_slice = [&](const Slice& sl, void* c1, void* c2) -> Status {
     if (!transpose) {
@@ -670,15 +677,15 @@ Status SiteOp::apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const do
   };
   Status st = Status::ok();
   for (size_t i = 0; i < pl.slices.size() && st.good(); ++i) {
-    const int q = two ? (int)(i & 1) : 0;
-    ctx->stream = q ? ctx->stream2 : s0;
+    const int q = (int)(i % (size_t)nst);
+    ctx->stream = sq[q];
     st = run_slice(pl.slices[i], b[q][0], b[q][1]);
   }
   ctx->stream = s0;
-  if (two) {
-    // the context's stream continues after both
-    FP_HIP(hipEventRecord(ctx->ev_join, ctx->stream2));
-    FP_HIP(hipStreamWaitEvent(s0, ctx->ev_join, 0));
+  // the context's stream continues after all of them
+  for (int q = 1; q < nst; ++q) {
+    FP_HIP(hipEventRecord(ctx->xjoin[q - 1], sq[q]));
+    FP_HIP(hipStreamWaitEvent(s0, ctx->xjoin[q - 1], 0));
   }
   return st;
 }

@@ -134,7 +134,7 @@ def test_site_chain_slicing_is_invariant(ctx):
 
 
 def test_two_streams_match_one_stream(ctx):
-    """Slices alternate between two streams by default; the products are the
+    """Slices are spread over several streams by default; the products are the
     same bit for bit as with every slice on one stream, forward and
     transposed."""
     import torch
