@@ -46,7 +46,9 @@ def build(verbose=False):
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "--offload-arch=gfx950", "-o", tmp] + objs
+    # every symbol resolved at link time: a missing definition fails the
+    # build instead of the first load
+    cmd = [hipcc(), "-shared", "--offload-arch=gfx950", "-Wl,--no-undefined", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -148,7 +148,7 @@ fpeps_status fpeps_site_apply(fpeps_ctx ctx, const fpeps_tensor* R, const fpeps_
     FP_HIP(hipEventCreate(&e0));
     FP_HIP(hipEventCreate(&e1));
     FP_HIP(hipEventRecord(e0, ctx->stream));
-    ctx->two_streams = (opts->flags & FPEPS_FLAG_ONE_STREAM) == 0;
+    ctx->multi_stream = (opts->flags & FPEPS_FLAG_ONE_STREAM) == 0;
     FP_TRY(op.apply(ctx, pl, transpose != 0, x_in, y_out, opts->precision == FPEPS_FP32));
     FP_HIP(hipEventRecord(e1, ctx->stream));
     FP_HIP(hipEventSynchronize(e1));

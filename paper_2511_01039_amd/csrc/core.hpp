@@ -68,7 +68,7 @@ struct fpeps_ctx_s {
   std::vector<hipStream_t> xstreams;
   std::vector<hipEvent_t> xjoin;
   hipEvent_t ev_fork = nullptr;
-  bool two_streams = true;   // cleared by FPEPS_FLAG_ONE_STREAM (then one stream)
+  bool multi_stream = true;   // cleared by FPEPS_FLAG_ONE_STREAM (then one stream)
   int max_streams = 4;       // streams the slices of a site are spread over
   fp::Status ensure_streams(int n);   // n - 1 extra streams
   // 0 for the context's stream, i for xstreams[i - 1]

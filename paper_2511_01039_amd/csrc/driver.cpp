@@ -536,7 +536,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
   ctx->peak_ws = 0;
   ctx->nslices = 0;
   ctx->time_kernels = (o->flags & FPEPS_FLAG_TIME_KERNELS) != 0;
-  ctx->two_streams = (o->flags & FPEPS_FLAG_ONE_STREAM) == 0;
+  ctx->multi_stream = (o->flags & FPEPS_FLAG_ONE_STREAM) == 0;
   ctx->kt_seconds = ctx->kt_flops = 0;
   ctx->kt_launches = 0;
   ctx->evused = 0;

@@ -630,7 +630,7 @@ Status SiteOp::apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const do
   // are spread round-robin over the context's stream and up to
   // max_streams - 1 more, each with its own ping-pong intermediates, so the
   // GEMM steps of one slice can run beside the layer steps of the others.
-  const int nst = ctx->two_streams ? (int)std::min<size_t>(pl.slices.size(),
+  const int nst = ctx->multi_stream ? (int)std::min<size_t>(pl.slices.size(),
                                                            (size_t)std::max(1, ctx->max_streams))
                                    : 1;
   std::vector<std::array<void*, 2>> b((size_t)nst, std::array<void*, 2>{nullptr, nullptr});
