@@ -378,8 +378,11 @@ Status SiteOp::plan_host(const std::vector<int32_t>& k, int64_t budget, Plans& o
     out.row_total += sect[J].m * (int64_t)k[J];
   }
   // slices: whole sectors packed greedily; a sector larger than the budget
-  // is split into column ranges
-  const double elem_budget = (double)budget / (f32 ? sizeof(float) : sizeof(double));
+  // is split into column ranges. The budget counts FP64 elements also when
+  // the intermediates are stored in FP32: a mixed-precision site applies the
+  // same slices with FP64 intermediates too (its last range-finder product
+  // and the projection).
+  const double elem_budget = (double)budget / sizeof(double);
   std::vector<std::vector<SliceCol>> slices;
   std::vector<SliceCol> cur;
   double used = 0;
@@ -467,7 +470,6 @@ void SiteOp::sum_plans(Plans& out) const {
 }
 
 Status SiteOp::upload(fpeps_ctx_s* ctx, Plans& out, int which) const {
-  const bool f32 = out.f32;
   // uploads through the pinned arena, asynchronous on the stream
   const auto up0 = std::chrono::steady_clock::now();
   FP_TRY(ctx->stage_begin());
@@ -524,7 +526,7 @@ Status SiteOp::upload(fpeps_ctx_s* ctx, Plans& out, int which) const {
   ctx->plan_up_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - up0).count();
   ctx->peak_ws = std::max(ctx->peak_ws,
-                          (double)(out.ws1 + out.ws2) * (f32 ? sizeof(float) : sizeof(double)));
+                          (double)(out.ws1 + out.ws2) * sizeof(double));
   ctx->nslices = std::max(ctx->nslices, (int)out.slices.size());
   return Status::ok();
 }
