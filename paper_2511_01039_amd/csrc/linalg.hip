@@ -138,13 +138,18 @@ hipError_t launch_chol_inv(const SmallDesc* d, int nd, double* buf, int* status,
 // Cyclic Jacobi for a symmetric k x k matrix (Golub & Van Loan, Sec. 8.5),
 // parallel ordering by the round-robin (circle) schedule: every round
 // rotates k/2 disjoint pairs, first all row pairs then all column pairs.
+// With LDS, the matrix being rotated lives in LDS (a copy; the k x k input in
+// global memory is left as it was), otherwise in place in global memory.
+// Same arithmetic in the same order either way.
 // ---------------------------------------------------------------------------
+constexpr int JAC_SCRATCH = 2560;   // doubles of rotation and reduction scratch
+
+template <bool LDS>
 __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d,
                                                  double* __restrict__ buf,
                                                  int* __restrict__ status) {
   const SmallDesc g = d[blockIdx.x];
   const int k = g.k;
-  double* A = buf + g.a_off;
   double* V = buf + g.b_off;
   double* lam = buf + g.c_off;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -154,9 +159,14 @@ __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d
   int* pp = (int*)(sm + 1024);   // [kp/2]
   int* qq = pp + 512;            // [kp/2]
   double* red = sm + 1536;       // [1024]
+  double* A = LDS ? sm + JAC_SCRATCH : buf + g.a_off;   // [k * k]
   __shared__ int done;
   const int kp = k + (k & 1);
   const int npair = kp / 2;
+  if (LDS) {
+    const double* Ag = buf + g.a_off;
+    for (int64_t e = tid; e < (int64_t)k * k; e += nt) A[e] = Ag[e];
+  }
   // V = I
   for (int64_t e = tid; e < (int64_t)k * k; e += nt) V[e] = (e / k == e % k) ? 1.0 : 0.0;
   __syncthreads();
@@ -245,7 +255,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d
     if (sweep == 39 && tid == 0) atomicOr(status, 4);
   }
   // sort eigenvalues descending (ties by index) and permute columns of V
-  // into the k x k scratch that held A (A is no longer needed).
+  // into the k x k storage of A (A is no longer needed).
   for (int i = tid; i < k; i += nt) {
     const double li = A[(int64_t)i * k + i];
     int rank = 0;
@@ -269,9 +279,14 @@ __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d
 hipError_t launch_jacobi_eig(const SmallDesc* d, int nd, int max_k, double* buf, int* status,
                              hipStream_t s) {
   if (nd <= 0) return hipSuccess;
-  if (max_k > 1024) return hipErrorInvalidValue;
-  const size_t shm = (size_t)(1536 + 1024) * sizeof(double);
-  k_jacobi<<<nd, 1024, shm, s>>>(d, buf, status);
+  if (max_k > 1024 || max_k < 0) return hipErrorInvalidValue;
+  // the matrix in LDS when it fits beside the scratch in 64 KiB
+  const size_t scratch = (size_t)JAC_SCRATCH * sizeof(double);
+  const size_t mat = (size_t)max_k * max_k * sizeof(double);
+  if (scratch + mat <= 64 * 1024)
+    k_jacobi<true><<<nd, 1024, scratch + mat, s>>>(d, buf, status);
+  else
+    k_jacobi<false><<<nd, 1024, scratch, s>>>(d, buf, status);
   return hipGetLastError();
 }
 
