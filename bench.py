@@ -362,6 +362,9 @@ def main():
         print(f"{precision} kernel-timing step (one stream): {krep['seconds']:.3f} s device",
               file=sys.stderr, flush=True)
         r["cls"], r["out"], r["lg"] = cls, out, lg
+        # singular values of every truncated site (the kernel-timing step's,
+        # same arithmetic as the timed steps)
+        r["sig"] = [ctx.absorb_diag(x)[0] for x in range(len(out) - 1)]
         return r
 
     precs = ["fp64", "fp32"] if a.precision == "mixed-vs-fp64" else [a.precision]
@@ -388,7 +391,13 @@ def main():
                "tolerance": 1e-6, "fp64_value": res["fp64"]["value"],
                "fp64_ms_per_step": 1e3 * res["fp64"]["sec"],
                "mixed_value": res["fp32"]["value"], "mixed_ms_per_step": 1e3 * res["fp32"]["sec"],
-               "fp64_other_seed_s_row_rel": seed_rel}
+               "fp64_other_seed_s_row_rel": seed_rel,
+               # largest norm-wise relative difference of a site's singular
+               # values (all computed ones, kept and cut) between the two paths
+               "sigma_rel_max": max(
+                   (float(np.linalg.norm(a32 - a64) / max(np.linalg.norm(a64), 1e-300))
+                    for a32, a64 in zip(res["fp32"]["sig"], res["fp64"]["sig"])
+                    if a32.shape == a64.shape and a64.size), default=float("nan"))}
     # the reported figure: the mixed path when it meets the 1e-6 bound against
     # FP64, else the FP64 path
     rep_prec = "fp32" if (cmp and cmp["s_row_rel_err"] <= 1e-6) else precs[0]
