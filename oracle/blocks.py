@@ -109,3 +109,30 @@ def pair_flops(X: BT, T: BT, symbolic_out=None):
             ksz = int(np.prod([X.legs[shared[j]].dims[xk[xs[j]]] for j in range(len(shared))]))
             total += 2 * xsz * tsz // max(ksz, 1)
     return total
+
+
+def pair_flops_to(X: BT, T: BT, out_names, keep=None):
+    """2 * m * n * k summed over the block pairs whose output block (sector
+    tuple in ``out_names`` order) is in ``keep`` (every pair when None)."""
+    shared = [n for n in X.names if n in T.legs]
+    xs = [X.names.index(n) for n in shared]
+    ts = [T.names.index(n) for n in shared]
+    xfree = [i for i, n in enumerate(X.names) if n not in shared]
+    tfree = [i for i, n in enumerate(T.names) if n not in shared]
+    raw_names = [X.names[i] for i in xfree] + [T.names[i] for i in tfree]
+    perm = [raw_names.index(n) for n in out_names]
+    groups = {}
+    for tk in T.blocks:
+        groups.setdefault(tuple(tk[i] for i in ts), []).append(tk)
+    total = 0
+    for xk in X.blocks:
+        xsz = int(np.prod(block_shape(X, xk)))
+        for tk in groups.get(tuple(xk[i] for i in xs), ()):
+            if keep is not None:
+                raw = tuple(xk[i] for i in xfree) + tuple(tk[i] for i in tfree)
+                if tuple(raw[q] for q in perm) not in keep:
+                    continue
+            tsz = int(np.prod(block_shape(T, tk)))
+            ksz = int(np.prod([X.legs[shared[j]].dims[xk[xs[j]]] for j in range(len(shared))]))
+            total += 2 * xsz * tsz // max(ksz, 1)
+    return total

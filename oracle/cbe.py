@@ -20,22 +20,22 @@ from __future__ import annotations
 import numpy as np
 
 from .rng import gaussian_matrix
-from .rsvd import sketch_widths, global_cut, orth, SV_CUT
+from .rsvd import rsvd_adaptive
 
 
-def residual_widths(mats, U, V, chi_extra, p):
-    m = [a.shape[0] - u.shape[1] for a, u in zip(mats, U)]
-    n = [a.shape[1] - v.shape[0] for a, v in zip(mats, V)]
-    return sketch_widths([max(x, 0) for x in m], [max(x, 0) for x in n], chi_extra, p)
+def residual_dims(mats, U, V):
+    m = [max(a.shape[0] - u.shape[1], 0) for a, u in zip(mats, U)]
+    n = [max(a.shape[1] - v.shape[0], 0) for a, v in zip(mats, V)]
+    return m, n
 
 
 def cbe_explicit(mats, U, V, chi_extra, p, seed, tag=0, stream=1, split=True, q=0,
-                 sv_cut=SV_CUT):
+                 sv_cut=None):
     """Truncated complement of every matrix; one global cut of size
-    ``chi_extra``. Returns dict with Q (m_i x e_i, orthogonal to U_i),
-    sigma of the kept complement directions, and counts."""
-    k = residual_widths(mats, U, V, chi_extra, p)
-    out_Q, S_, Ut_, Q_ = [], [], [], []
+    ``chi_extra``. The sketch widths follow the rule of ``rsvd`` on the
+    residual's dimensions (m_i - r_i) x (n_i - r_i). Returns dict with Q
+    (m_i x e_i, orthogonal to U_i), sigma of the kept complement directions,
+    and counts."""
     if split:
         ap = lambda i, X: (lambda Z: Z - U[i] @ (U[i].T @ Z))(mats[i] @ (X - V[i].T @ (V[i] @ X)))
         at = lambda i, Y: (lambda Z: Z - V[i].T @ (V[i] @ Z))(mats[i].T @ (Y - U[i] @ (U[i].T @ Y)))
@@ -44,22 +44,15 @@ def cbe_explicit(mats, U, V, chi_extra, p, seed, tag=0, stream=1, split=True, q=
         PV = [np.eye(a.shape[1]) - v.T @ v for a, v in zip(mats, V)]
         ap = lambda i, X: PU[i] @ (mats[i] @ (PV[i] @ X))
         at = lambda i, Y: PV[i] @ (mats[i].T @ (PU[i] @ Y))
-    for i, a in enumerate(mats):
-        om = gaussian_matrix(seed, i, tag, (stream << 16), a.shape[1], k[i])
-        Y = ap(i, om)
-        Q = orth(Y)
-        for _ in range(q):
-            Q = orth(ap(i, orth(at(i, Q))))
-        B = at(i, Q).T
-        if B.shape[0]:
-            Ut, s, _ = np.linalg.svd(B, full_matrices=False)
-        else:
-            Ut, s = np.zeros((0, 0)), np.zeros(0)
-        Q_.append(Q); Ut_.append(Ut); S_.append(s)
-    kept, disc, gap = global_cut(S_, chi_extra, sv_cut=sv_cut)
+    mr, nr = residual_dims(mats, U, V)
+    r = rsvd_adaptive(lambda X: [ap(i, x) for i, x in enumerate(X)],
+                      lambda Y: [at(i, y) for i, y in enumerate(Y)], mr, nr, chi_extra, p, q,
+                      lambda k: [gaussian_matrix(seed, i, tag, (stream << 16), a.shape[1], k[i])
+                                 for i, a in enumerate(mats)], sv_cut=sv_cut)
     from .zipup import fix_signs
+    kept, out_Q = r["kept"], []
     for i in range(len(mats)):
-        q = Q_[i] @ Ut_[i][:, :kept[i]]
-        out_Q.append(fix_signs(q, np.zeros((q.shape[1], 0)))[0])
-    return dict(Q=out_Q, sigma=[S_[i][:kept[i]] for i in range(len(mats))], kept=kept, k=k,
-                gap=gap)
+        qi = r["Q"][i] @ r["Ut"][i][:, :kept[i]]
+        out_Q.append(fix_signs(qi, np.zeros((qi.shape[1], 0)))[0])
+    return dict(Q=out_Q, sigma=[r["S"][i][:kept[i]] for i in range(len(mats))], kept=kept,
+                k=r["k"], gap=r["gap"], passes=r["passes"])

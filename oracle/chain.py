@@ -23,7 +23,7 @@ import math
 import numpy as np
 
 from workloads.tensor import Leg
-from .blocks import BT, contract, from_tensor, pair_flops
+from .blocks import BT, contract, from_tensor, pair_flops, pair_flops_to
 from .rng import hash_words, unit_from_hash, gaussian_block
 
 # canonical leg orders of the intermediates of the chain
@@ -174,6 +174,17 @@ class SiteOperator:
             S = self.tensors[s]
             total += pair_flops(X, S)
             X = contract(X, S, ORDERS[s + 1], symbolic=True)
+        return total
+
+    def chain_flops_t(self, Y_struct: BT, col_blocks):
+        """Flops 2 m n k over the block pairs of one application of the
+        mirrored chain to ``Y_struct``; the last step counts only pairs whose
+        output block is in ``col_blocks`` (M's domain)."""
+        Z, total = Y_struct, 0
+        for s in reversed(range(5)):
+            S = self.tensors[s]
+            total += pair_flops_to(Z, S, ORDERS[s], col_blocks if s == 0 else None)
+            Z = contract(Z, S, ORDERS[s], symbolic=True)
         return total
 
 

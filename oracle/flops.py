@@ -1,39 +1,65 @@
 """Algorithmic flop count of a row absorption (oracle).
 
 Definition used for every throughput figure:
-* chain: 2 m n k over every contributing block pair of every chain step,
-  for each of the 2 + 2q applications of M or M^T per truncated site
-  (one for the final site);
-* orthonormalisation of an m x k block: 2 m k^2 - 2 k^3 / 3 (Householder QR);
-* core SVD of the k x n block B: 2 n k^2 + 12 k^3;
-* U = Q U~: 2 m k c and R = U~^T B: 2 k c n with c kept columns.
-Anything an implementation adds (padding, masked tiles, extra passes of a
+* chain: 2 m n k over every block pair of every chain step. The rSVD of a
+  truncated site applies M (the forward chain) 1 + q times and M^T (the
+  mirrored chain, counted over its own block pairs) 1 + q times; the final
+  site applies M once. The mirrored chain counts, at its last step, only
+  the pairs whose output lands on a column tuple of M (M^T acts on M's
+  domain);
+* orthonormalisation of an m x k block: 2 m k^2 - 2 k^3 / 3 (Householder QR,
+  Golub & Van Loan, Matrix Computations, 4th ed., Alg. 5.2.1);
+* core SVD of the k x n block B: 2 n k^2 + 11 k^3 (R-SVD of the n x k
+  transpose, singular values and right vectors; Golub & Van Loan,
+  Fig. 8.6.1);
+* U = Q U~: 2 m k c and R = U~^T B: 2 k c n with c kept columns, once per
+  truncated site.
+Every factorisation pass of a site counts (a site whose saturated sectors
+were widened is factorised again with the wider sketch). Anything an
+implementation adds (padding, masked tiles, extra passes of a
 split-precision product) is not counted.
 """
 from __future__ import annotations
 
 
 def chain_flops(sp, kvec):
+    """Forward chain M X with per-sector widths ``kvec``."""
     op = sp.op
     om = op.omega_bt(sp.sect, kvec)
     om.blocks = {k: v for k, v in om.blocks.items() if kvec[k[-1]] > 0}
     return op.chain_flops(om)
 
 
-def site_flops(sp, kvec, kept, q):
-    f = chain_flops(sp, kvec) * (2 + 2 * q)
-    for m, n, k, c in zip(sp.m, sp.n, kvec, kept):
+def chain_flops_t(sp, kvec):
+    """Mirrored chain M^T Y with per-sector widths ``kvec``."""
+    return sp.op.chain_flops_t(sp.y_struct(kvec), sp.col_blocks(kvec))
+
+
+def pass_flops(sp, kvec, q):
+    f = (1 + q) * (chain_flops(sp, kvec) + chain_flops_t(sp, kvec))
+    for m, n, k in zip(sp.m, sp.n, kvec):
         if k == 0:
             continue
         f += (q + 1) * (2 * m * k * k - 2 * k ** 3 / 3.0) + q * (2 * n * k * k - 2 * k ** 3 / 3.0)
-        f += 2 * n * k * k + 12 * k ** 3
-        f += 2 * m * k * c + 2 * k * c * n
+        f += 2 * n * k * k + 11 * k ** 3
+    return f
+
+
+def site_flops(sp, passes, q):
+    """``passes``: [(k, kept)] of every factorisation of the site."""
+    f = 0.0
+    for kvec, _ in passes:
+        f += pass_flops(sp, kvec, q)
+    kvec, kept = passes[-1]
+    for m, n, k, c in zip(sp.m, sp.n, kvec, kept):
+        if k > 0:
+            f += 2 * m * k * c + 2 * k * c * n
     return f
 
 
 def row_flops(record, info, q):
     """``record``/``info`` as filled by zipup.absorb_row(record=[...])."""
     total = 0.0
-    for r, kept in zip(record, info["kept"]):
-        total += site_flops(r["sp"], r["kvec"], kept, q)
+    for r in record:
+        total += site_flops(r["sp"], r["passes"], q)
     return total

@@ -18,7 +18,7 @@ import numpy as np
 from workloads.tensor import Leg, Tensor
 from .blocks import BT, to_tensor
 from .chain import (SiteOperator, ORDERS, R_NAMES, trivial_remainder, sketch_arrays, flip)
-from .rsvd import sketch_widths, global_cut, orth, SV_CUT
+from .rsvd import global_cut, rank_floor, rsvd_adaptive
 
 
 SIGN_TIE = 1e-5
@@ -114,6 +114,23 @@ class SiteProblem:
         return [np.hstack([p[i] for p in parts]) if parts else np.zeros((rows_out[i], 0))
                 for i in range(len(mats))]
 
+    def y_struct(self, kvec):
+        """Structure (values None) of a row-layout block of vectors with
+        per-sector widths ``kvec``; sectors of width 0 have no blocks."""
+        jl = self.op.j_leg([J for J, _ in self.sect], kvec)
+        legs = dict(self.y_legs); legs["j"] = jl
+        bt = BT(list(ORDERS[5]), legs, {})
+        for ji in range(len(self.sect)):
+            if kvec[ji] > 0:
+                for key in self.row_keys[ji]:
+                    bt.blocks[key[:4] + (ji,)] = None
+        return bt
+
+    def col_blocks(self, kvec):
+        """Column-layout block keys (b, rk, rw, rb, j) of M's domain."""
+        return {tuple(t) + (ji,) for ji, (_, tuples) in enumerate(self.sect) if kvec[ji] > 0
+                for t in tuples}
+
     def apply_m(self, mats):
         return self._chunked(self._apply_m, mats, self.m)
 
@@ -183,15 +200,20 @@ def _remainder(sp: SiteProblem, R_mats, kept, labels, sel):
 
 
 def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0.0,
-               bra=None, record=None, max_cols=None, progress=None, sv_cut=SV_CUT):
+               bra=None, record=None, max_cols=None, progress=None, sv_cut=None):
     """Absorb one row (ket A[x], PEPO W[x]) into the top environment T[x].
 
     Returns (new environment sites, log_norm, info). With ``exact_svd`` the
     operator of every sector is formed explicitly and factorised by LAPACK
-    (truncated SVD), which bounds the error of the randomized version."""
+    (truncated SVD), which bounds the error of the randomized version.
+    The sketch width of a sector starts from the previous site's kept count
+    for the same sector label (the proportional share at the first site and
+    for new labels); see ``rsvd``. ``sv_cut`` replaces the rank floor."""
     L = len(T)
     R = trivial_remainder(sym, T[0], A[0], W[0])
-    env, info = [], dict(sigma=[], kept=[], k=[], m=[], n=[], discarded=[], gap=[], nu=[])
+    env = []
+    info = dict(sigma=[], kept=[], k=[], m=[], n=[], discarded=[], gap=[], nu=[], passes=[])
+    prev_kept = None
     for x in range(L):
         op = SiteOperator(sym, R, T[x], A[x], W[x], bra=None if bra is None else bra[x])
         sp = SiteProblem(op, max_cols)
@@ -221,16 +243,24 @@ def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0
                     continue
                 u, s, vt = np.linalg.svd(Mf, full_matrices=False)
                 U_.append(u); S_.append(s); B_.append(Mf)
-            kept, disc, gap = global_cut(S_, chi, labels, sv_cut=sv_cut)
+            fl = sv_cut if sv_cut else rank_floor(sp.m, sp.n)
+            kept, disc, gap = global_cut(S_, chi, labels, fl)
             Umats = [U_[i][:, :kept[i]] for i in range(len(kept))]
             Rmats = [Umats[i].T @ B_[i] for i in range(len(kept))]
             kvec = [len(s) for s in S_]
         else:
-            kvec = sketch_widths(sp.m, sp.n, chi, p)
-            oms = sketch_arrays(sp.sect, kvec, sp.col_dims, seed, 0, x, row, 0)
-            omats = [np.vstack(o) if len(o) else np.zeros((0, kvec[i])) for i, o in enumerate(oms)]
-            Q, Ut, S_, Bm = _rsvd(sp, omats, q)
-            kept, disc, gap = global_cut(S_, chi, labels, sv_cut=sv_cut)
+            hint = None if prev_kept is None else [prev_kept.get(tuple(J)) for J in labels]
+
+            def omegas(kv):
+                oms = sketch_arrays(sp.sect, kv, sp.col_dims, seed, 0, x, row, 0)
+                return [np.vstack(o) if len(o) else np.zeros((0, kv[i])) for i, o in enumerate(oms)]
+
+            r = rsvd_adaptive(sp.apply_m, sp.apply_mt, sp.m, sp.n, chi, p, q, omegas, labels,
+                              hint, sv_cut)
+            Q, Ut, S_, Bm, kept, kvec = r["Q"], r["Ut"], r["S"], r["B"], r["kept"], r["k"]
+            disc, gap = r["discarded"], r["gap"]
+            info["passes"].append(r["passes"])
+            prev_kept = {tuple(J): c for J, c in zip(labels, kept)}
             Umats = [Q[i] @ Ut[i][:, :kept[i]] for i in range(len(kept))]
             Rmats = [Ut[i][:, :kept[i]].T @ Bm[i] for i in range(len(kept))]
         fixed = [fix_signs(u, r) for u, r in zip(Umats, Rmats)]
@@ -246,10 +276,6 @@ def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0
                          ("discarded", disc), ("gap", gap), ("nu", nu)):
             info[key].append(val)
         if record is not None:
-            record.append(dict(x=x, sp=sp, kvec=kvec))
+            record.append(dict(x=x, sp=sp, kvec=kvec,
+                               passes=info["passes"][-1] if not exact_svd else [(kvec, kept)]))
     return env, log_norm, info
-
-
-def _rsvd(sp, omats, q):
-    from .rsvd import rsvd_sectors
-    return rsvd_sectors(sp.apply_m, sp.apply_mt, omats, q)

@@ -13,7 +13,7 @@ from oracle.blocks import BT, from_tensor
 from oracle.chain import SiteOperator, trivial_remainder, ORDERS, flip
 from oracle.exact import pepo_matrix
 from oracle.zipup import SiteProblem
-from oracle.flops import chain_flops
+from oracle.flops import chain_flops, chain_flops_t
 from oracle.rng import splitmix64_mix
 
 
@@ -210,6 +210,68 @@ def test_dense_flop_count_closed_form():
     want = 2 * (2 * chi ** 2 * k * S ** 2 + 2 * chi * k * d * w ** 2 * D ** 6
                 + chi * k * D ** 4 * d ** 2 * w ** 4)
     assert chain_flops(sp, [k]) == want
+    # the mirrored chain has the transposed products of the same shapes
+    assert chain_flops_t(sp, [k]) == want
+
+
+def spin_ops(tj):
+    """S_z and S_+ of spin j = tj / 2 in the basis m = j, j-1, ..., -j."""
+    j = tj / 2.0
+    ms = j - np.arange(tj + 1)
+    sz = np.diag(ms)
+    sp = np.zeros((tj + 1, tj + 1))
+    for i in range(1, tj + 1):          # S_+ |m> = sqrt(j(j+1) - m(m+1)) |m+1>
+        m = ms[i]
+        sp[i - 1, i] = math.sqrt(j * (j + 1) - m * (m + 1))
+    return sz, sp
+
+
+def total_spins(tjs):
+    """The set of 2J whose multiplets occur in the product of spins tjs/2:
+    eigenvalues J(J+1) of the total S^2 = S_z^2 + (S_+ S_- + S_- S_+)/2 built
+    from the spin matrices of every factor."""
+    dims = [tj + 1 for tj in tjs]
+    N = int(np.prod(dims))
+    Sz, Sp = np.zeros((N, N)), np.zeros((N, N))
+    for i, tj in enumerate(tjs):
+        sz, sp = spin_ops(tj)
+        left, right = np.eye(int(np.prod(dims[:i]))), np.eye(int(np.prod(dims[i + 1:])))
+        Sz += np.kron(np.kron(left, sz), right)
+        Sp += np.kron(np.kron(left, sp), right)
+    S2 = Sz @ Sz + 0.5 * (Sp @ Sp.T + Sp.T @ Sp)
+    lam = np.linalg.eigvalsh(S2)
+    twoJ = np.rint(np.sqrt(1.0 + 4.0 * np.maximum(lam, 0)) - 1.0).astype(int)
+    assert np.allclose(twoJ / 2.0 * (twoJ / 2.0 + 1.0), lam, atol=1e-8)
+    return set(int(v) for v in twoJ)
+
+
+def test_su2_column_sectors_are_the_spins_of_the_coupled_legs():
+    """Config-4 catalogue (environment 2j = 0..6, virtual 2j <= 2, PEPO
+    2j <= 1): the sketch sectors J of every column tuple (b, rk, rw, rb) are
+    exactly the total spins of the product of its four spins, found by
+    diagonalising the total S^2 of the spin matrices (not by the triangle
+    rule the operator uses)."""
+    sym = wl.Sym("su2", coef_seed=1, fermionic=True)
+    cat = wl.legs_su2(14)
+    rng = np.random.default_rng(0)
+    A = wl.random_tensor(sym, wl.configs.peps_site_legs(cat, 1, 1, 3, 3), rng)
+    W = wl.random_tensor(sym, wl.configs.pepo_site_legs(cat, 1, 1, 3, 3), rng)
+    T = wl.random_tensor(sym, wl.configs.env_site_legs(cat, A.legs[3], W.legs[4], False, False), rng)
+    row = wl.RowProblem(sym, [T] * 3, [A] * 3, [W] * 3, 14, 2, 1)
+    R = random_remainder(sym, row, 1, cat["env"], rng)
+    op = SiteOperator(sym, R, T, A, W)
+    legs = op.col_legs()
+    assert [int(l[0]) for l in legs[0].labels] == list(range(7))
+    got = {}
+    for J, tuples in op.sectors():
+        for t in tuples:
+            got.setdefault(tuple(t), set()).add(int(J[0]))
+    checked = 0
+    for t in itertools.product(*[range(l.nsect) for l in legs]):
+        tjs = [int(legs[i].labels[s][0]) for i, s in enumerate(t)]
+        assert got.get(tuple(t), set()) == total_spins(tjs), (t, tjs)
+        checked += 1
+    assert checked == 7 * 3 * 2 * 3
 
 
 # ---------------------------------------------------------------------------

@@ -5,7 +5,8 @@ import math
 import numpy as np
 import pytest
 
-from oracle.rsvd import rsvd_explicit, sketch_widths, global_cut
+from oracle.rsvd import (rsvd_explicit, sketch_widths, global_cut, saturated, grown_widths,
+                         rank_floor, EPS)
 from oracle.cbe import cbe_explicit
 
 
@@ -87,6 +88,51 @@ def test_truncated_error_not_below_optimal():
 def test_sketch_widths_rule():
     assert sketch_widths([100, 50, 0], [80, 200, 10], chi=30, p=4) == [24, 14, 0]
     assert sketch_widths([3], [1000], chi=500, p=20) == [3]
+    # a hint (the previous site's kept count) replaces the proportional share
+    assert sketch_widths([100, 50, 40], [80, 200, 90], chi=30, p=4, hint=[2, None, 50]) == [6, 12, 40]
+
+
+def test_saturation_rule_and_growth():
+    k, m, n = [10, 10, 10, 7], [50, 50, 50, 7], [60, 60, 60, 9]
+    # 10 - 4/2 = 8: kept 9 or 10 saturates, 8 does not; a covered sector never
+    assert saturated(k, [9, 8, 10, 7], m, n, p=4) == [True, False, True, False]
+    assert grown_widths(k, [True, False, True, False], m, n, p=4) == [24, 10, 24, 7]
+    assert grown_widths([30], [True], [50], [40], p=4) == [40]
+
+
+def test_weight_in_one_sector_is_found_by_widening():
+    """All of the spectrum in one of three equal sectors: the proportional
+    widths (chi/3 + p) saturate that sector; widening it recovers LAPACK's
+    chi largest values of the block-diagonal matrix exactly (its rank is
+    covered by the widened sketch) and the kept count is chi there."""
+    sig = [np.geomspace(5.0, 0.5, 32), np.array([1e-3, 5e-4]), np.array([2e-3])]
+    mats = [prescribed(200, 150, s, 20 + i)[0] for i, s in enumerate(sig)]
+    out = rsvd_explicit(mats, chi=30, p=6, q=1, seed=2)
+    assert len(out["passes"]) >= 2
+    assert out["passes"][0][0] == [16, 16, 16]
+    assert out["passes"][0][1][0] == 16          # saturated at the proportional width
+    assert out["kept"] == [30, 0, 0]
+    big = np.zeros((600, 450))
+    for i, a in enumerate(mats):
+        big[200 * i:200 * (i + 1), 150 * i:150 * (i + 1)] = a
+    s = np.linalg.svd(big, compute_uv=False)
+    assert np.allclose(out["sigma"][0], s[:30], rtol=1e-12)
+    u = np.linalg.svd(mats[0])[0][:, :30]
+    assert np.abs(out["U"][0] @ out["U"][0].T - u @ u.T).max() < 1e-10
+
+
+def test_spectrum_down_to_1e12_is_resolved_and_kept():
+    """Prescribed singular values from 1 to 1e-12 (above the rank floor
+    eps max(m, n) = 6.7e-14): all are kept, and each agrees with the
+    prescribed value to a few eps times the largest (backward stability)."""
+    s = np.logspace(0, -12, 40)
+    a, u, _ = prescribed(300, 200, s, 11)
+    out = rsvd_explicit([a], chi=60, p=10, q=1, seed=5)
+    assert rank_floor([300], [200]) == pytest.approx(300 * EPS)
+    assert out["kept"] == [40]
+    assert np.abs(out["sigma"][0] - s).max() < 50 * EPS * s[0]
+    # vectors to eps sigma_max / gap (Davis-Kahan): the top 20 (gap ~ 1e-6)
+    assert np.abs(out["U"][0][:, :20] @ out["U"][0][:, :20].T - u[:, :20] @ u[:, :20].T).max() < 1e-9
 
 
 def test_global_cut_ties_and_counts():
