@@ -49,6 +49,7 @@
 #ifndef FPEPS_H
 #define FPEPS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -72,16 +73,19 @@ typedef enum {
 
 typedef enum {
   FPEPS_FP64 = 0,     /* every product and intermediate in double precision */
-  FPEPS_FP32 = 1,     /* mixed: the chain intermediates (X1..X4 and their
-                         transposes) of the range finder's sketch and power
-                         iterations, except its last product, are stored in
-                         FP32, halving the HBM traffic of the layer steps;
-                         every product still accumulates in FP64, and the
+  FPEPS_FP32 = 1,     /* mixed: in the range finder's sketch and power
+                         iterations, except its last product, the
+                         environment and remainder contractions (chain steps
+                         1 and 5 and their transposes) run on FP32 MFMA with
+                         FP32 accumulation from FP32 copies of T and R, and
+                         the chain intermediates (X1..X4 and their
+                         transposes) are stored in FP32 (the layer steps
+                         read and write FP32 and accumulate in FP64). The
                          last range-finder product, the projection
                          B = Q^T M, orthonormalisation, core factorisation,
                          cut and norms are FP64. Available in
                          fpeps_env_absorb and fpeps_site_apply (which applies
-                         the chain with FP32 intermediates). */
+                         the chain in this mixed form). */
   FPEPS_BF16X3 = 2    /* reserved (FPEPS_ERR_UNSUPPORTED) */
 } fpeps_precision;
 
@@ -116,7 +120,10 @@ typedef struct {
 
 typedef struct {
   int32_t chi;            /* bond kept after truncation (multiplets for SU(2)) */
-  int32_t oversample;     /* p: sketch width k_J = min(m_J, n_J, ceil(chi m_J / sum m) + p) */
+  int32_t oversample;     /* p: first sketch width k_J = min(m_J, n_J, h_J + p), h_J the
+                             previous site's kept count of the sector's label (absorption)
+                             or ceil(chi m_J / sum m); widened while saturated (see
+                             fpeps_report.rsvd_passes) */
   int32_t power_iters;    /* q: subspace iterations */
   int32_t cbe_extra;      /* directions added by CBE per bond (0: none) */
   uint64_t seed;          /* Philox4x32-10 key of the Gaussian sketch */
@@ -125,14 +132,17 @@ typedef struct {
   int32_t symmetry;       /* fpeps_symmetry */
   int32_t fermionic;      /* 1: parity sign on every contracted block pair */
   uint64_t coef_seed;     /* SU(2): key of the synthetic recoupling scalars */
-  int64_t slice_budget;   /* bytes for chain intermediates per slice (0: automatic). The
-                             slices of a site are spread round-robin over four streams, so
-                             up to four slices' intermediates are live (see
-                             FPEPS_FLAG_ONE_STREAM) */
+  int64_t slice_budget;   /* bytes of chain intermediates live at once, over all streams
+                             (0: 64 GiB). The slices of a site are spread round-robin over
+                             four streams, so every slice is sized for a quarter of it
+                             (also with FPEPS_FLAG_ONE_STREAM, so that the slicing does
+                             not depend on the streams) */
   uint32_t flags;         /* FPEPS_FLAG_* */
   int32_t tag;            /* explicit-matrix calls: counter word c2 of the sketch */
-  double sv_cut;          /* singular values <= sv_cut * largest are never kept
-                             (numerically zero; no defined vectors). <= 0: 1e-7 */
+  double sv_cut;          /* singular values <= sv_cut * largest are never kept. <= 0: the
+                             rank floor eps * max_J max(m_J, n_J) (eps = 2^-52, the rank
+                             tolerance of Numerical Recipes Sec. 2.6): values below it are
+                             not resolved by a backward-stable factorisation */
 } fpeps_opts;
 
 #define FPEPS_FLAG_NO_GRAPH 1u      /* do not capture per-site launch sequences */
@@ -147,10 +157,13 @@ typedef struct {
   double discarded_weight; /* largest per-site sum(s^2 cut)/sum(s^2) */
   double min_rel_gap;      /* smallest (s_kept_last - s_cut_first)/s_kept_last */
   double log_norm;         /* sum of log of the norms divided out */
-  double peak_workspace;   /* bytes of chain intermediates (largest slice) */
+  double peak_workspace;   /* bytes of chain intermediates live at once (all streams) */
   int32_t kept_total;      /* sum of kept values over sites / matrices */
   int32_t nslices;         /* chain slices used (largest site) */
-  uint32_t fallbacks;      /* bit 0: orthonormalisation used the shifted pass */
+  uint32_t fallbacks;      /* bit 0: an orthonormalisation needed more than one shifted
+                              CholeskyQR pass (rank-deficient or very ill-conditioned
+                              sketch); bit 1: a Jacobi eigen-decomposition stopped at its
+                              40-sweep limit */
   int32_t required_blocks; /* on FPEPS_ERR_CAPACITY: blocks needed */
   int64_t required_elem;   /* on FPEPS_ERR_CAPACITY: elements needed */
   int32_t required_sect;   /* on FPEPS_ERR_CAPACITY: sectors per leg needed */
@@ -173,6 +186,13 @@ typedef struct {
      previous site (equal block structure of T, A, W and the remainder, equal
      sketch widths); they are uploaded again with the site's own layer data. */
   int32_t plan_reuses;
+  /* factorisation passes (summed over the sites of an absorption): a pass
+     whose cut kept more than k_J - p/2 values of a sector its sketch does not
+     cover is repeated with that sector's width raised to
+     min(m_J, n_J, 2 k_J + p) */
+  int32_t rsvd_passes;
+  double workspace_bytes;  /* device workspace the context holds at the end of the call
+                              (every buffer; freed by fpeps_destroy or a new allocator) */
 } fpeps_report;
 
 /* Context: one per host thread. ``stream`` is a hipStream_t (NULL: default
@@ -182,6 +202,19 @@ fpeps_status fpeps_destroy(fpeps_ctx ctx);
 fpeps_status fpeps_set_stream(fpeps_ctx ctx, void* stream);
 const char* fpeps_last_error(fpeps_ctx ctx);
 const char* fpeps_version(void);
+
+/* Device memory of the context's workspace (chain intermediates, sketch and
+ * range matrices, plans) from the caller's allocator, for instance a
+ * framework's caching allocator: alloc(bytes, user) returns device memory of
+ * the context's device or NULL (the call needing it then fails with
+ * FPEPS_ERR_NOMEM); free_(ptr, user) takes back a pointer alloc returned.
+ * The library frees a buffer only after the work using it on every stream
+ * of the context has finished. Both NULL restores hipMalloc / hipFree.
+ * Workspace held from the previous allocator is freed to it first (the call
+ * waits for the device). Not to be called while another call on the same
+ * context runs. */
+fpeps_status fpeps_set_allocator(fpeps_ctx ctx, void* (*alloc)(size_t bytes, void* user),
+                                 void (*free_)(void* ptr, void* user), void* user);
 
 /* Absorb one row of L sites into the top environment env_in[0..L-1].
  * ket[x] (5 legs) and pepo[x] (6 legs) are the row tensors; the bra is the
@@ -276,12 +309,18 @@ fpeps_status fpeps_cbe_expand_grouped(fpeps_ctx ctx, int32_t nmat, const int64_t
                                       const fpeps_opts* opts, double* const* Q_out,
                                       int32_t* kept, double* sigma, fpeps_report* report);
 
-/* Network value of a top environment (L sites) and a bottom environment
- * whose bundle legs (k, w, b') match the top's: the contraction of all
- * sites, left and right bonds of dimension 1 at the ends. Log-norms are not
- * applied. *value is a host double. */
+/* Network value Z of a top environment (L sites) and a bottom environment
+ * whose bundle legs (k, w, b') match the top's (Sec. 2, Fig. 1 once both
+ * environments exist): the contraction of all sites, left and right bonds
+ * of dimension 1 at the ends, times exp(log_norm_top + log_norm_bottom)
+ * (the logarithms of the norms the absorptions divided out). Returned as
+ * *sign (host: +1, -1, or 0 for an exact zero) and *log_abs = log |Z| (host;
+ * -inf for zero): the partial contraction is normalised after every site
+ * and its logarithm accumulated, so |Z| may lie far outside the range of a
+ * double. Non-finite data gives FPEPS_ERR_NUMERIC. Synchronises. */
 fpeps_status fpeps_expect(fpeps_ctx ctx, int32_t L, const fpeps_tensor* top,
-                          const fpeps_tensor* bottom, double* value);
+                          const fpeps_tensor* bottom, double log_norm_top,
+                          double log_norm_bottom, int32_t* sign, double* log_abs);
 
 #ifdef __cplusplus
 }

@@ -63,3 +63,27 @@ def row_flops(record, info, q):
     for r in record:
         total += site_flops(r["sp"], r["passes"], q)
     return total
+
+
+def explicit_flops(m, n, passes, q, r=None):
+    """Explicit matrices (``rsvd_explicit``, ``cbe_explicit`` with kept ranks
+    ``r``): per pass 1 + q products with A and with A^T (2 m n k each), for
+    an expansion the projector splits (4 r k (m + n) per product pair),
+    orthonormalisation and core SVD as for a site; the factors U = Q U~
+    (2 m k c) and, for a truncation, R = U~^T B (2 k c n) once."""
+    f = 0.0
+    for kvec, _ in passes:
+        for i, k in enumerate(kvec):
+            if k <= 0:
+                continue
+            mi, ni = m[i], n[i]
+            f += (2 + 2 * q) * 2.0 * mi * ni * k
+            if r is not None:
+                f += (2 + 2 * q) * 4.0 * r[i] * k * (mi + ni)
+            f += (q + 1) * (2 * mi * k * k - 2 * k ** 3 / 3.0) + q * (2 * ni * k * k - 2 * k ** 3 / 3.0)
+            f += 2 * ni * k * k + 11 * k ** 3
+    kvec, kept = passes[-1]
+    for i, (k, c) in enumerate(zip(kvec, kept)):
+        if k > 0:
+            f += 2.0 * m[i] * k * c + (0.0 if r is not None else 2.0 * k * c * n[i])
+    return f

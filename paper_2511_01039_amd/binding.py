@@ -8,10 +8,15 @@ raises instead of computing anything itself.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from dataclasses import dataclass
 
 import numpy as np
+
+# workspace allocator callbacks of fpeps_set_allocator
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfpeps.so")
@@ -60,7 +65,8 @@ class CReport(C.Structure):
                 ("layer_flops", C.c_double), ("layer_bytes", C.c_double),
                 ("gemm_launches", C.c_int32), ("gemm_seconds", C.c_double),
                 ("gemm_flops", C.c_double), ("gemm_bytes", C.c_double),
-                ("plan_reuses", C.c_int32)]
+                ("plan_reuses", C.c_int32), ("rsvd_passes", C.c_int32),
+                ("workspace_bytes", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -116,7 +122,9 @@ def load():
                                       P(C.c_void_p), P(C.c_int32), P(C.c_int32), P(C.c_void_p),
                                       P(C.c_void_p), P(COpts), P(C.c_void_p), P(C.c_int32),
                                       P(C.c_double), P(CReport)], C.c_int),
-        "fpeps_expect": ([C.c_void_p, C.c_int32, T, T, P(C.c_double)], C.c_int),
+        "fpeps_expect": ([C.c_void_p, C.c_int32, T, T, C.c_double, C.c_double, P(C.c_int32),
+                          P(C.c_double)], C.c_int),
+        "fpeps_set_allocator": ([C.c_void_p, ALLOC_FN, FREE_FN, C.c_void_p], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -128,7 +136,7 @@ def load():
 
 def exported_symbols():
     return ["fpeps_version", "fpeps_create", "fpeps_destroy", "fpeps_set_stream",
-            "fpeps_last_error", "fpeps_env_absorb", "fpeps_absorb_diag", "fpeps_site_shape",
+            "fpeps_last_error", "fpeps_set_allocator", "fpeps_env_absorb", "fpeps_absorb_diag", "fpeps_site_shape",
             "fpeps_site_apply", "fpeps_rsvd_truncate", "fpeps_rsvd_truncate_grouped",
             "fpeps_cbe_expand", "fpeps_cbe_expand_grouped", "fpeps_expect"]
 
@@ -230,22 +238,50 @@ def opts_for(sym, **kw):
 class Context:
     """One library context on one GPU, bound to torch's current stream."""
 
-    def __init__(self, device=0, stream=None):
+    def __init__(self, device=0, stream=None, torch_allocator=False):
         import torch
         self.lib = load()
         self.device = device
         if stream is None:
             stream = torch.cuda.current_stream(device).cuda_stream
+        self.stream = stream
         h = C.c_void_p()
         rc = self.lib.fpeps_create(C.byref(h), int(device), C.c_void_p(stream))
         if rc != FPEPS_OK:
             raise FpepsError(rc, "fpeps_create failed (no gfx950 device?)")
         self.h = h
+        self._alloc_cbs = None
+        if torch_allocator:
+            self.use_torch_allocator()
+
+    def use_torch_allocator(self):
+        """Take the library's workspace from PyTorch's caching allocator
+        (blocks on the context's stream) instead of hipMalloc."""
+        import torch
+        dev, stream = self.device, torch.cuda.ExternalStream(self.stream, device=self.device)
+
+        def _alloc(nbytes, user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+            except Exception:       # out of memory: the library reports FPEPS_ERR_NOMEM
+                return None
+
+        def _free(ptr, user):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        cbs = (ALLOC_FN(_alloc), FREE_FN(_free))
+        self.check(self.lib.fpeps_set_allocator(self.h, cbs[0], cbs[1], None))
+        self._alloc_cbs = cbs        # the library calls them until the context is closed
+
+    def use_hip_allocator(self):
+        self.check(self.lib.fpeps_set_allocator(self.h, ALLOC_FN(), FREE_FN(), None))
+        self._alloc_cbs = None
 
     def close(self):
         if getattr(self, "h", None):
             self.lib.fpeps_destroy(self.h)
             self.h = None
+        self._alloc_cbs = None
 
     def __del__(self):
         try:
@@ -406,14 +442,22 @@ class Context:
             p += kept[i]
         return Qs, sigs, kept, rep.as_dict()
 
-    def expect(self, top, bottom):
+    def expect_log(self, top, bottom, log_norm_top=0.0, log_norm_bottom=0.0):
+        """Network value of two environments as (sign, log |Z|)."""
         keep = []
         L = len(top)
         ta = (CTensor * L)(*[t.ctensor(keep) for t in top])
         ba = (CTensor * L)(*[t.ctensor(keep) for t in bottom])
-        v = C.c_double()
-        self.check(self.lib.fpeps_expect(self.h, L, ta, ba, C.byref(v)))
-        return v.value
+        sg = C.c_int32()
+        la = C.c_double()
+        self.check(self.lib.fpeps_expect(self.h, L, ta, ba, C.c_double(log_norm_top),
+                                         C.c_double(log_norm_bottom), C.byref(sg), C.byref(la)))
+        return int(sg.value), float(la.value)
+
+    def expect(self, top, bottom):
+        """The same as a plain float (no log-norms applied)."""
+        sg, la = self.expect_log(top, bottom)
+        return sg * math.exp(la) if sg else 0.0
 
 
 def output_caps(env_in, ket, pepo, x, chi):

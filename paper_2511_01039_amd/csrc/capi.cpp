@@ -74,6 +74,20 @@ fpeps_status fpeps_set_stream(fpeps_ctx ctx, void* stream) {
 
 const char* fpeps_last_error(fpeps_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+fpeps_status fpeps_set_allocator(fpeps_ctx ctx, void* (*alloc)(size_t, void*),
+                                 void (*free_)(void*, void*), void* user) {
+  return guarded(ctx, [&]() -> fp::Status {
+    if ((alloc == nullptr) != (free_ == nullptr))
+      return fp::fail(FPEPS_ERR_ARG, "give both allocator functions or neither");
+    // buffers from the previous allocator go back to it first
+    FP_TRY(ctx->release_workspace());
+    ctx->alloc_fn = alloc;
+    ctx->free_fn = free_;
+    ctx->alloc_user = alloc ? user : nullptr;
+    return fp::Status::ok();
+  });
+}
+
 fpeps_status fpeps_env_absorb(fpeps_ctx ctx, int32_t L, const fpeps_tensor* env_in,
                               const fpeps_tensor* ket, const fpeps_tensor* pepo,
                               const fpeps_opts* opts, fpeps_tensor* env_out, double* log_norm,
@@ -140,13 +154,17 @@ fpeps_status fpeps_site_apply(fpeps_ctx ctx, const fpeps_tensor* R, const fpeps_
     for (int v : kk)
       if (v < 0) return fp::fail(FPEPS_ERR_ARG, "negative width");
     fp::SiteOp::Plans pl;
-    const int64_t budget = opts->slice_budget > 0 ? opts->slice_budget : ((int64_t)24 << 30);
+    // one budget for the chain intermediates of all streams: up to
+  // max_streams slices are live at once, each within its share
+  const int64_t budget = std::max<int64_t>(
+      1, (opts->slice_budget > 0 ? opts->slice_budget : ((int64_t)64 << 30)) / std::max(1, ctx->max_streams));
     ctx->peak_ws = 0;
     ctx->nslices = 0;
     FP_TRY(op.plan(ctx, kk, budget, pl, transpose != 0, opts->precision == FPEPS_FP32));
-    hipEvent_t e0, e1;
-    FP_HIP(hipEventCreate(&e0));
-    FP_HIP(hipEventCreate(&e1));
+    if (opts->precision == FPEPS_FP32) FP_TRY(op.make_f32_operands(ctx));
+    fp::EventPair evp;
+    FP_HIP(evp.create());
+    hipEvent_t e0 = evp.a, e1 = evp.b;
     FP_HIP(hipEventRecord(e0, ctx->stream));
     ctx->multi_stream = (opts->flags & FPEPS_FLAG_ONE_STREAM) == 0;
     FP_TRY(op.apply(ctx, pl, transpose != 0, x_in, y_out, opts->precision == FPEPS_FP32));
@@ -154,12 +172,11 @@ fpeps_status fpeps_site_apply(fpeps_ctx ctx, const fpeps_tensor* R, const fpeps_
     FP_HIP(hipEventSynchronize(e1));
     float ms = 0;
     FP_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (report) {
       report->alg_flops = transpose ? pl.flops_bwd : pl.flops_fwd;
       report->seconds = ms * 1e-3;
       report->peak_workspace = ctx->peak_ws;
+      report->workspace_bytes = (double)ctx->ws_bytes;
       report->nslices = ctx->nslices;
     }
     return fp::Status::ok();
@@ -217,8 +234,11 @@ fpeps_status fpeps_cbe_expand(fpeps_ctx ctx, int32_t nmat, const int64_t* m, con
 }
 
 fpeps_status fpeps_expect(fpeps_ctx ctx, int32_t L, const fpeps_tensor* top,
-                          const fpeps_tensor* bottom, double* value) {
-  return guarded(ctx, [&] { return fp::overlap(ctx, L, top, bottom, value); });
+                          const fpeps_tensor* bottom, double log_norm_top,
+                          double log_norm_bottom, int32_t* sign, double* log_abs) {
+  return guarded(ctx, [&] {
+    return fp::overlap(ctx, L, top, bottom, log_norm_top + log_norm_bottom, sign, log_abs);
+  });
 }
 
 }  // extern "C"

@@ -12,8 +12,36 @@ fpeps_ctx_s::~fpeps_ctx_s() {
   for (auto e : xjoin) (void)hipEventDestroy(e);
   for (auto x : xstreams) (void)hipStreamDestroy(x);
   for (auto& kv : bufs)
-    if (kv.second.p) (void)hipFree(kv.second.p);
+    if (kv.second.p) dev_free(kv.second.p);
   if (stage) (void)hipHostFree(stage);
+}
+
+void* fpeps_ctx_s::dev_alloc(size_t bytes) {
+  if (alloc_fn) return alloc_fn(bytes, alloc_user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void fpeps_ctx_s::dev_free(void* p) {
+  if (!p) return;
+  if (free_fn)
+    free_fn(p, alloc_user);
+  else
+    (void)hipFree(p);
+}
+
+fp::Status fpeps_ctx_s::release_workspace() {
+  if (bufs.empty()) return fp::Status::ok();
+  FP_HIP(hipDeviceSynchronize());
+  for (auto& kv : bufs)
+    if (kv.second.p) dev_free(kv.second.p);
+  bufs.clear();
+  ws_bytes = 0;
+  return fp::Status::ok();
 }
 
 void fpeps_ctx_s::release_later(std::shared_ptr<void> p) {
@@ -61,20 +89,23 @@ fp::Status fpeps_ctx_s::buf(const std::string& name, size_t bytes, void** out) {
   fp::DevBuf& b = bufs[name];
   if (b.bytes < bytes) {
     if (b.p) {
+      // every stream of the context joins the context's stream before a
+      // call returns, so its work on the old buffer is done after this
       FP_HIP(hipStreamSynchronize(stream));
-      FP_HIP(hipFree(b.p));
+      dev_free(b.p);
+      ws_bytes -= b.bytes;
       b.p = nullptr;
       b.bytes = 0;
     }
     size_t want = std::max(bytes, (size_t)4096);
     want = (want + 4095) / 4096 * 4096;
-    if (hipMalloc(&b.p, want) != hipSuccess) {
-      (void)hipGetLastError();
-      b.p = nullptr;
+    b.p = dev_alloc(want);
+    if (!b.p)
       return fp::fail(FPEPS_ERR_NOMEM, "device allocation of " + std::to_string(want) +
                                            " bytes failed (" + name + ")");
-    }
     b.bytes = want;
+    ws_bytes += want;
+    ws_peak = std::max(ws_peak, ws_bytes);
   }
   *out = b.p;
   return fp::Status::ok();
@@ -398,6 +429,20 @@ Status run_gemm(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A, i
 Status run_gemm_mixed(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A,
                       int64_t a_size, const void* B, bool b_f32, int64_t b_size, void* C,
                       bool c_f32, int64_t c_size, bool timed, int label) {
+  return run_gemm_any(ctx, ps, idx, A, nullptr, a_size, B, b_f32, b_size, C, c_f32, c_size, timed,
+                      label);
+}
+
+Status run_gemm_f32(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const float* A, int64_t a_size,
+                    const void* B, bool b_f32, int64_t b_size, void* C, bool c_f32, int64_t c_size,
+                    bool timed, int label) {
+  return run_gemm_any(ctx, ps, idx, nullptr, A, a_size, B, b_f32, b_size, C, c_f32, c_size, timed,
+                      label);
+}
+
+Status run_gemm_any(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A,
+                    const float* A32, int64_t a_size, const void* B, bool b_f32, int64_t b_size,
+                    void* C, bool c_f32, int64_t c_size, bool timed, int label) {
   const GemmPlan& p = ps.plans[idx];
   if (p.jobs.empty()) return Status::ok();
   // every table-addressed access must stay inside its buffer
@@ -407,8 +452,8 @@ Status run_gemm_mixed(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double
                                      std::to_string(p.b_extent) + "/" + std::to_string(b_size) +
                                      ", c " + std::to_string(p.c_extent) + "/" +
                                      std::to_string(c_size) + ")");
-  if (!A || !B || !C) return fail(FPEPS_ERR_ARG, "null operand buffer");
-  if (b_f32 && c_f32) return fail(FPEPS_ERR_UNSUPPORTED, "GEMM with both B and C in FP32");
+  if ((!A && !A32) || !B || !C) return fail(FPEPS_ERR_ARG, "null operand buffer");
+  if (A && b_f32 && c_f32) return fail(FPEPS_ERR_UNSUPPORTED, "FP64 GEMM with B and C in FP32");
   // split-K parts are summed in FP64 and rounded once into C
   double* part = nullptr;
   // each stream has its own partial buffer (slices on several streams overlap)
@@ -428,11 +473,16 @@ Status run_gemm_mixed(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double
     FP_HIP(hipEventRecord(ea, ctx->stream));
   }
   if (part) {
-    FP_HIP(launch_gemm_mixed(ps.dev[idx], A, B, b_f32, part, false, ps.dtab, ctx->stream));
+    if (A)
+      FP_HIP(launch_gemm_mixed(ps.dev[idx], A, B, b_f32, part, false, ps.dtab, ctx->stream));
+    else
+      FP_HIP(launch_gemm_f32(ps.dev[idx], A32, B, b_f32, part, false, ps.dtab, ctx->stream));
     FP_HIP(launch_reduce_tab(ps.dev[idx].reduces, ps.dev[idx].nred, p.max_red_mn, C, c_f32, part,
                              ps.dtab, ctx->stream));
-  } else {
+  } else if (A) {
     FP_HIP(launch_gemm_mixed(ps.dev[idx], A, B, b_f32, C, c_f32, ps.dtab, ctx->stream));
+  } else {
+    FP_HIP(launch_gemm_f32(ps.dev[idx], A32, B, b_f32, C, c_f32, ps.dtab, ctx->stream));
   }
   if (tk) FP_HIP(hipEventRecord(eb, ctx->stream));
   return Status::ok();

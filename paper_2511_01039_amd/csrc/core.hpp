@@ -75,6 +75,17 @@ struct fpeps_ctx_s {
   int stream_index(hipStream_t s) const;
   std::string err;
   std::map<std::string, fp::DevBuf> bufs;
+  // device memory of the workspace: the caller's allocator when set
+  // (fpeps_set_allocator), else hipMalloc / hipFree
+  void* (*alloc_fn)(size_t, void*) = nullptr;
+  void (*free_fn)(void*, void*) = nullptr;
+  void* alloc_user = nullptr;
+  void* dev_alloc(size_t bytes);
+  void dev_free(void* p);
+  // frees every workspace buffer (waits for the device first)
+  fp::Status release_workspace();
+  size_t ws_bytes = 0;   // workspace bytes held now
+  size_t ws_peak = 0;    // and at most since the last reset (a call's start)
   std::vector<fp::SiteDiag> diag;
   double peak_ws = 0;
   int nslices = 0;
@@ -197,7 +208,38 @@ Status run_gemm(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A, i
 Status run_gemm_mixed(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A,
                       int64_t a_size, const void* B, bool b_f32, int64_t b_size, void* C,
                       bool c_f32, int64_t c_size, bool timed = false, int label = 0);
+// The same on FP32 MFMA with FP32 accumulation: A an FP32 copy, B and C in
+// FP32 or FP64
+Status run_gemm_f32(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const float* A, int64_t a_size,
+                    const void* B, bool b_f32, int64_t b_size, void* C, bool c_f32, int64_t c_size,
+                    bool timed = false, int label = 0);
+// exactly one of A (FP64) and A32 (FP32) is given
+Status run_gemm_any(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A,
+                    const float* A32, int64_t a_size, const void* B, bool b_f32, int64_t b_size,
+                    void* C, bool c_f32, int64_t c_size, bool timed, int label);
 Status run_rt(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const void* X, int64_t x_size,
               void* Y, int64_t y_size, bool f32, bool timed = false, int label = 0);
+
+// Two timing events released on every return path.
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() = default;
+  EventPair(const EventPair&) = delete;
+  EventPair& operator=(const EventPair&) = delete;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+  hipError_t create() {
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) {
+      a = nullptr;
+      return e;
+    }
+    e = hipEventCreate(&b);
+    if (e != hipSuccess) b = nullptr;
+    return e;
+  }
+};
 
 }  // namespace fp

@@ -142,7 +142,7 @@ Status orth(fpeps_ctx_s* ctx, DensePlans& dp, int side, const Layout& L, double*
   double *part = nullptr, *small = nullptr;
   int* status = nullptr;
   FP_TRY(ctx->bufT("rs_part", (size_t)std::max<int64_t>(dp.part_total[side], 1), &part));
-  FP_TRY(ctx->bufT("rs_small", (size_t)(2 * dp.S + dp.lam_total + 1), &small));
+  FP_TRY(ctx->bufT("rs_small", (size_t)(3 * dp.S + dp.lam_total + 1), &small));
   FP_TRY(ctx->bufT("rs_status", L.k.size() + 2, &status));
   ReduceDesc* dred = nullptr;
   FP_TRY(ctx->upload("rs_red" + std::to_string(side), dp.red[side].data(),
@@ -165,51 +165,53 @@ Status orth(fpeps_ctx_s* ctx, DensePlans& dp, int side, const Layout& L, double*
   FP_TRY(ctx->upload("rs_chol0", ch_shift.data(), ch_shift.size() * sizeof(SmallDesc), (void**)&dch));
   SmallDesc* dch1 = nullptr;
   FP_TRY(ctx->upload("rs_chol1", ch.data(), ch.size() * sizeof(SmallDesc), (void**)&dch1));
-  FP_HIP(hipMemsetAsync(status, 0, (L.k.size() + 2) * sizeof(int), ctx->stream));
-  const int64_t small_n = 2 * dp.S + dp.lam_total + 1;
-  // shifted CholeskyQR3: one shifted pass, then two plain passes. A plain
-  // pass that breaks down (a rank-deficient block: the shifted pass leaves
-  // its null directions at rounding level) is replaced by two SVQB passes
-  // (Stathopoulos & Wu, SIAM J. Sci. Comput. 23 (2002) 2165) in which the
-  // null directions become exact zero columns.
-  bool svqb = false;
-  for (int pass = 0; pass < 3; ++pass) {
+  const int64_t small_n = 3 * dp.S + dp.lam_total + 1;
+  // Shifted CholeskyQR3 (Fukaya et al.): one shifted pass, then two plain
+  // passes. A plain pass whose Cholesky breaks down (a rank-deficient
+  // sketch: its null directions are still at rounding level after the
+  // shifted pass) is replaced by one more shifted pass, which lifts the
+  // smallest directions by a factor of about 1/sqrt(shift) each time, until
+  // a plain pass succeeds. Null directions become an arbitrary orthonormal
+  // completion (as with Householder QR); small but genuine directions keep
+  // their share of the range.
+  auto pass = [&](bool shifted) -> Status {
     FP_TRY(run_gemm(ctx, dp.ps, dp.gram[side], Y, L.total, Y, L.total, part,
                     std::max<int64_t>(dp.part_total[side], 1)));
     FP_HIP(launch_reduce_partials(dred, (int)dp.red[side].size(), dp.max_red_mn, small, part,
                                   ctx->stream));
-    FP_HIP(launch_chol_inv(pass == 0 ? dch : dch1, (int)ch.size(), small, status, ctx->stream));
-    if (pass == 1) {
-      int hs = 0;
-      FP_HIP(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-      FP_TRY(ctx->sync());
-      if (hs & 1) {
-        svqb = true;
-        break;
-      }
-    }
+    FP_HIP(launch_chol_inv(shifted ? dch : dch1, (int)ch.size(), small, status, ctx->stream));
+    return Status::ok();
+  };
+  auto apply_r = [&]() -> Status {
     FP_TRY(run_gemm(ctx, dp.ps, dp.qmul[side], Y, L.total, small, small_n, Wb, L.total));
     std::swap(Y, Wb);
+    return Status::ok();
+  };
+  int nshift = 1;
+  FP_TRY(pass(true));
+  FP_TRY(apply_r());
+  for (;;) {
+    FP_HIP(launch_fill_int(status, (int64_t)L.k.size() + 2, 0, ctx->stream));
+    FP_TRY(pass(false));
+    int hs = 0;
+    FP_HIP(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    FP_TRY(ctx->sync());
+    if (!(hs & 1)) break;
+    if (nshift >= 6)
+      return fail(FPEPS_ERR_NUMERIC, "orthonormalisation: Cholesky breakdown after 6 shifted passes");
+    *fallbacks |= 1u;
+    FP_TRY(pass(true));   // the failed factorisation overwrote the Gram matrix
+    FP_TRY(apply_r());
+    ++nshift;
   }
-  if (svqb) {
-    *fallbacks |= 4u;
-    for (int pass = 0; pass < 2; ++pass) {
-      FP_TRY(run_gemm(ctx, dp.ps, dp.gram[side], Y, L.total, Y, L.total, part,
-                      std::max<int64_t>(dp.part_total[side], 1)));
-      FP_HIP(launch_reduce_partials(dred, (int)dp.red[side].size(), dp.max_red_mn, small, part,
-                                    ctx->stream));
-      FP_HIP(launch_jacobi_eig(dch1, (int)ch.size(), dp.max_k, small, status + 1, ctx->stream));
-      FP_HIP(launch_svqb_scale(dch1, (int)ch.size(), small, 1e-12, ctx->stream));
-      FP_TRY(run_gemm(ctx, dp.ps, dp.qmul[side], Y, L.total, small, small_n, Wb, L.total));
-      std::swap(Y, Wb);
-    }
-  }
+  FP_TRY(apply_r());
+  FP_HIP(launch_fill_int(status, (int64_t)L.k.size() + 2, 0, ctx->stream));
+  FP_TRY(pass(false));
+  FP_TRY(apply_r());
   int hs = 0;
   FP_HIP(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   FP_TRY(ctx->sync());
-  if (hs & 2) *fallbacks |= 1u;
-  if ((hs & 1) && !svqb)
-    return fail(FPEPS_ERR_NUMERIC, "Cholesky breakdown in the orthonormalisation");
+  if (hs & 1) return fail(FPEPS_ERR_NUMERIC, "Cholesky breakdown in the orthonormalisation");
   *Qout = Y;
   return Status::ok();
 }
@@ -219,31 +221,17 @@ Status orth(fpeps_ctx_s* ctx, DensePlans& dp, int side, const Layout& L, double*
 // ---------------------------------------------------------------------------
 // generic randomized SVD over sectors
 // ---------------------------------------------------------------------------
-Status rsvd_run(fpeps_ctx_s* ctx, RsvdIO& io, int chi, int p, int q, uint64_t seed,
-                RsvdOut& out, double sv_cut) {
-  if (!(sv_cut > 0.0)) sv_cut = 1e-7;
+namespace {
+
+// One factorisation with fixed sketch widths k (Halko et al. Ex. 1.6): range
+// finder with q power iterations, B^T = M^T Q, core factorisation of B and
+// the global cut of every group.
+Status rsvd_pass(fpeps_ctx_s* ctx, RsvdIO& io, const std::vector<int32_t>& k, int chi, int q,
+                 uint64_t seed, const std::vector<double>& gfloor, RsvdOut& out) {
   const int ns = (int)io.m.size();
-  // sketch widths k_J = min(m_J, n_J, ceil(chi m_J / sum m) + p), the sum
-  // over the sector's group
-  const std::vector<int64_t>& wm = io.width_m.empty() ? io.m : io.width_m;
-  const std::vector<int64_t>& wn = io.width_n.empty() ? io.n : io.width_n;
-  if (!io.grp.empty() && (int)io.grp.size() != ns) return fail(FPEPS_ERR_ARG, "group list size");
-  if (!io.c2v.empty() && (int)io.c2v.size() != ns) return fail(FPEPS_ERR_ARG, "tag list size");
-  int ngrp = 1;
-  for (int g : io.grp) {
-    if (g < 0) return fail(FPEPS_ERR_ARG, "negative group");
-    ngrp = std::max(ngrp, g + 1);
-  }
+  const int ngrp = (int)gfloor.size();
   auto grp_of = [&](int J) { return io.grp.empty() ? 0 : io.grp[J]; };
-  std::vector<int64_t> msum(ngrp, 0);
-  for (int J = 0; J < ns; ++J) msum[grp_of(J)] += std::max<int64_t>(wm[J], 0);
-  out.k.assign(ns, 0);
-  for (int J = 0; J < ns; ++J) {
-    const int64_t ms = msum[grp_of(J)];
-    if (wm[J] <= 0 || wn[J] <= 0 || ms <= 0) continue;
-    const int64_t want = ((int64_t)chi * wm[J] + ms - 1) / ms + p;
-    out.k[J] = (int32_t)std::min({wm[J], wn[J], want});
-  }
+  out.k = k;
   FP_TRY(io.prepare(out.k));
   Layout RL, CL;
   RL.build(io.m, out.k);
@@ -292,24 +280,29 @@ Status rsvd_run(fpeps_ctx_s* ctx, RsvdIO& io, int chi, int p, int q, uint64_t se
     double* other = (Yb == r0) ? r1 : r0;
     FP_TRY(orth(ctx, dp, 0, RL, Yb, other, &Q, &out.fallbacks));
   }
-  // stage B: B^T = M^T Q, core factorisation of B B^T
+  // stage B: B^T = M^T Q
   double* Bt = c0;
   FP_TRY(io.apply(true, true, Q, Bt));
   out.Q = Q;
   out.Bt = Bt;
+  // Core factorisation of B without squaring its condition number in the
+  // result: (1) V0 = eigenvectors of B B^T (Gram of the columns of B^T,
+  // Jacobi); (2) C = B^T V0 has nearly orthogonal columns whose norms are
+  // the singular values, so the Jacobi eigen-decomposition of C^T C with
+  // the relative stopping rule resolves every value to its own size
+  // (Demmel & Veselic 1992); (3) U~ = V0 V1. The values then carry an
+  // absolute error of a few eps times the largest, like a backward-stable
+  // SVD of B.
   double *part = nullptr, *small = nullptr;
   int* status = nullptr;
   FP_TRY(ctx->bufT("rs_part", (size_t)std::max<int64_t>(dp.part_total[1], 1), &part));
-  FP_TRY(ctx->bufT("rs_small", (size_t)(2 * dp.S + dp.lam_total + 1), &small));
+  FP_TRY(ctx->bufT("rs_small", (size_t)(3 * dp.S + dp.lam_total + 1), &small));
   FP_TRY(ctx->bufT("rs_status", 4, &status));
   ReduceDesc* dred = nullptr;
   FP_TRY(ctx->upload("rs_red1", dp.red[1].data(), dp.red[1].size() * sizeof(ReduceDesc),
                      (void**)&dred));
-  FP_TRY(run_gemm(ctx, dp.ps, dp.gram[1], Bt, CL.total, Bt, CL.total, part,
-                  std::max<int64_t>(dp.part_total[1], 1)));
-  FP_HIP(launch_reduce_partials(dred, (int)dp.red[1].size(), dp.max_red_mn, small, part,
-                                ctx->stream));
-  std::vector<SmallDesc> jd;
+  std::vector<SmallDesc> jd, md;
+  const int64_t v0_base = 2 * dp.S + dp.lam_total;
   for (int J = 0; J < ns; ++J) {
     if (out.k[J] <= 0) continue;
     SmallDesc d{};
@@ -318,19 +311,39 @@ Status rsvd_run(fpeps_ctx_s* ctx, RsvdIO& io, int chi, int p, int q, uint64_t se
     d.c_off = 2 * dp.S + dp.lam_off[J];
     d.k = out.k[J];
     jd.push_back(d);
+    SmallDesc e = d;
+    e.c_off = v0_base + dp.small_off[J];
+    md.push_back(e);
   }
-  SmallDesc* djd = nullptr;
+  SmallDesc *djd = nullptr, *dmd = nullptr;
   FP_TRY(ctx->upload("rs_jac", jd.data(), jd.size() * sizeof(SmallDesc), (void**)&djd));
-  FP_HIP(hipMemsetAsync(status, 0, sizeof(int), ctx->stream));
-  FP_HIP(launch_jacobi_eig(djd, (int)jd.size(), dp.max_k, small, status, ctx->stream));
+  FP_TRY(ctx->upload("rs_mm", md.data(), md.size() * sizeof(SmallDesc), (void**)&dmd));
+  FP_HIP(launch_fill_int(status, 4, 0, ctx->stream));
+  FP_TRY(run_gemm(ctx, dp.ps, dp.gram[1], Bt, CL.total, Bt, CL.total, part,
+                  std::max<int64_t>(dp.part_total[1], 1)));
+  FP_HIP(launch_reduce_partials(dred, (int)dp.red[1].size(), dp.max_red_mn, small, part,
+                                ctx->stream));
+  FP_HIP(launch_jacobi_eig(djd, (int)jd.size(), dp.max_k, small, status, ctx->stream, false));
+  if (dp.S > 0)
+    FP_HIP(hipMemcpyAsync(small + v0_base, small + dp.S, dp.S * sizeof(double),
+                          hipMemcpyDeviceToDevice, ctx->stream));
+  const int64_t small_n = 3 * dp.S + dp.lam_total + 1;
+  FP_TRY(run_gemm(ctx, dp.ps, dp.qmul[1], Bt, CL.total, small, small_n, c1, CL.total));
+  FP_TRY(run_gemm(ctx, dp.ps, dp.gram[1], c1, CL.total, c1, CL.total, part,
+                  std::max<int64_t>(dp.part_total[1], 1)));
+  FP_HIP(launch_reduce_partials(dred, (int)dp.red[1].size(), dp.max_red_mn, small, part,
+                                ctx->stream));
+  FP_HIP(launch_jacobi_eig(djd, (int)jd.size(), dp.max_k, small, status, ctx->stream, true));
+  FP_HIP(launch_small_mm(dmd, (int)md.size(), small, ctx->stream));
   // global cut of every group (sectors listed group by group)
   std::vector<int64_t> loff;
   std::vector<int32_t> kk;
   std::vector<int> sidx;
-  std::vector<CutGroup> cg(ngrp, CutGroup{0, 0, 0, 0});
+  std::vector<CutGroup> cg(ngrp, CutGroup{0, 0, 0, 0, 0.0});
   int max_ns = 0, max_total = 0;
   for (int g = 0; g < ngrp; ++g) {
     cg[g].s0 = (int32_t)kk.size();
+    cg[g].floor = gfloor[g];
     for (int J = 0; J < ns; ++J) {
       if (out.k[J] <= 0 || grp_of(J) != g) continue;
       loff.push_back(2 * dp.S + dp.lam_off[J]);
@@ -354,7 +367,7 @@ Status rsvd_run(fpeps_ctx_s* ctx, RsvdIO& io, int chi, int p, int q, uint64_t se
   FP_TRY(ctx->bufT("rs_cut", (size_t)ngrp, &dcut));
   if (max_total > 6144 || max_ns > 1024)
     return fail(FPEPS_ERR_UNSUPPORTED, "too many singular values for the on-chip cut");
-  FP_HIP(launch_cut(dcg, ngrp, max_ns, max_total, dloff, dkk, chi, sv_cut, small, dkept, dcut,
+  FP_HIP(launch_cut(dcg, ngrp, max_ns, max_total, dloff, dkk, chi, small, dkept, dcut,
                     ctx->stream));
   std::vector<int32_t> kept_c(kk.size());
   int hs = 0;
@@ -376,6 +389,69 @@ Status rsvd_run(fpeps_ctx_s* ctx, RsvdIO& io, int chi, int p, int q, uint64_t se
   out.small = small;
   for (double v : out.lam)
     if (!std::isfinite(v)) return fail(FPEPS_ERR_NUMERIC, "non-finite singular value");
+  return Status::ok();
+}
+
+}  // namespace
+
+Status rsvd_run(fpeps_ctx_s* ctx, RsvdIO& io, int chi, int p, int q, uint64_t seed,
+                RsvdOut& out, double sv_cut) {
+  const int ns = (int)io.m.size();
+  // Sketch widths (Halko et al. Sec. 4.2: the target rank plus p columns):
+  // k_J = min(m_J, n_J, h_J + p) with h_J the caller's guess of the kept
+  // count (hint) or the share ceil(chi m_J / sum m) of chi in the sector's
+  // group. A sector is saturated when its sketch does not cover it and the
+  // cut kept more than k_J - p/2 of its values; saturated sectors are
+  // widened to min(m_J, n_J, 2 k_J + p) and the factorisation is repeated.
+  const std::vector<int64_t>& wm = io.width_m.empty() ? io.m : io.width_m;
+  const std::vector<int64_t>& wn = io.width_n.empty() ? io.n : io.width_n;
+  if (!io.grp.empty() && (int)io.grp.size() != ns) return fail(FPEPS_ERR_ARG, "group list size");
+  if (!io.c2v.empty() && (int)io.c2v.size() != ns) return fail(FPEPS_ERR_ARG, "tag list size");
+  if (!io.hint.empty() && (int)io.hint.size() != ns) return fail(FPEPS_ERR_ARG, "hint list size");
+  int ngrp = 1;
+  for (int g : io.grp) {
+    if (g < 0) return fail(FPEPS_ERR_ARG, "negative group");
+    ngrp = std::max(ngrp, g + 1);
+  }
+  auto grp_of = [&](int J) { return io.grp.empty() ? 0 : io.grp[J]; };
+  std::vector<int64_t> msum(ngrp, 0), maxdim(ngrp, 0);
+  for (int J = 0; J < ns; ++J) {
+    msum[grp_of(J)] += std::max<int64_t>(wm[J], 0);
+    maxdim[grp_of(J)] = std::max({maxdim[grp_of(J)], wm[J], wn[J]});
+  }
+  // truncation floor per group: eps * max(m_J, n_J) relative to the largest
+  // value (the rank tolerance of Numerical Recipes Sec. 2.6), or sv_cut
+  std::vector<double> gfloor(ngrp);
+  for (int g = 0; g < ngrp; ++g)
+    gfloor[g] = sv_cut > 0.0 ? sv_cut : 2.220446049250313e-16 * (double)maxdim[g];
+  std::vector<int32_t> k(ns, 0);
+  for (int J = 0; J < ns; ++J) {
+    const int64_t ms = msum[grp_of(J)];
+    if (wm[J] <= 0 || wn[J] <= 0 || ms <= 0) continue;
+    const int64_t h = (!io.hint.empty() && io.hint[J] >= 0) ? io.hint[J]
+                                                             : ((int64_t)chi * wm[J] + ms - 1) / ms;
+    k[J] = (int32_t)std::min({wm[J], wn[J], h + p});
+  }
+  out.pass_k.clear();
+  out.pass_kept.clear();
+  uint32_t fb = 0;
+  for (;;) {
+    out.fallbacks = 0;
+    FP_TRY(rsvd_pass(ctx, io, k, chi, q, seed, gfloor, out));
+    fb |= out.fallbacks;
+    out.pass_k.push_back(out.k);
+    out.pass_kept.push_back(out.kept);
+    bool any = false;
+    for (int J = 0; J < ns; ++J) {
+      const int64_t cover = std::min(wm[J], wn[J]);
+      if (k[J] > 0 && k[J] < cover && 2 * (int64_t)out.kept[J] + p > 2 * (int64_t)k[J]) {
+        k[J] = (int32_t)std::min<int64_t>(cover, 2 * (int64_t)k[J] + p);
+        any = true;
+      }
+    }
+    if (!any) break;
+  }
+  out.fallbacks = fb;
   return Status::ok();
 }
 
@@ -531,7 +607,10 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
   sym.coef_seed = o->coef_seed;
   if (sym.kind < 0 || sym.kind > 2) return fail(FPEPS_ERR_ARG, "bad symmetry");
   const int nlab = sym.kind == SYM_U1U1 ? 2 : 1;
-  const int64_t budget = o->slice_budget > 0 ? o->slice_budget : ((int64_t)24 << 30);
+  // one budget for the chain intermediates of all streams: up to
+  // max_streams slices are live at once, each within its share
+  const int64_t budget = std::max<int64_t>(
+      1, (o->slice_budget > 0 ? o->slice_budget : ((int64_t)64 << 30)) / std::max(1, ctx->max_streams));
   ctx->diag.assign(L, SiteDiag());
   ctx->peak_ws = 0;
   ctx->nslices = 0;
@@ -550,9 +629,9 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     ctx->verbose = v ? std::max(1, std::atoi(v)) : 0;
   }
   auto wall = [] { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); };
-  hipEvent_t ev0, ev1;
-  FP_HIP(hipEventCreate(&ev0));
-  FP_HIP(hipEventCreate(&ev1));
+  EventPair evp;
+  FP_HIP(evp.create());
+  hipEvent_t ev0 = evp.a, ev1 = evp.b;
   FP_HIP(hipEventRecord(ev0, ctx->stream));
   double lg = 0.0, flops = 0.0, disc = 0.0, gap = INFINITY;
   int kept_total = 0;
@@ -609,6 +688,11 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
   // the remainder-independent part of the last analysis (interior sites of
   // a row share their T, ket and PEPO structure)
   FwdAnalysis fwd_an;
+  // kept count per sector label of the previous truncated site: the first
+  // guess of this site's sketch widths
+  std::map<std::vector<int32_t>, int32_t> prev_kept;
+  bool have_prev = false;
+  int total_passes = 0;
   for (int x = 0; x < L; ++x) {
     BT T, K, W;
     FP_TRY(tensor_to_bt(&env_in[x], {N_a, N_tk, N_tw, N_tb, N_b}, nlab, T));
@@ -626,7 +710,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     if (o->flags & FPEPS_FLAG_CHECK_FINITE) {
       int* flag = nullptr;
       FP_TRY(ctx->bufT("finite_flag", 1, &flag));
-      FP_HIP(hipMemsetAsync(flag, 0, sizeof(int), ctx->stream));
+      FP_HIP(launch_fill_int(flag, 1, 0, ctx->stream));
       FP_HIP(launch_check_finite(d.T, d.T_size, flag, ctx->stream));
       FP_HIP(launch_check_finite(d.A, d.A_size, flag, ctx->stream));
       FP_HIP(launch_check_finite(d.W, d.W_size, flag, ctx->stream));
@@ -728,6 +812,15 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     }
     io.c2 = (uint32_t)x;
     io.c3 = (uint32_t)(o->row & 0xFFFF);
+    if (have_prev) {
+      io.hint.assign(ns, -1);
+      for (int J = 0; J < ns; ++J) {
+        auto it = prev_kept.find(op.sect[J].label);
+        if (it != prev_kept.end()) io.hint[J] = it->second;
+      }
+    }
+    // chain flops (forward, transposed) of the plans of every factorisation pass
+    std::vector<std::array<double, 2>> pass_fl;
     double t_plan = 0;
     // The transposed-chain plans are first used after the sketch product
     // M Omega: they are planned on a host thread while the device runs it,
@@ -737,6 +830,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     io.prepare = [&](const std::vector<int32_t>& k) {
       const double t0 = wall();
       Status st = Status::ok();
+      if (plp) pass_fl.push_back({plp->flops_fwd, plp->flops_bwd});
       if (same && cache.pl && cache.k == k && cache.pl->f32 == f32) {
         plp = cache.pl;
         st = op.upload(ctx, *plp);
@@ -771,12 +865,15 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     };
     RsvdOut rs;
     const double tw1 = wall();
+    if (f32) FP_TRY(op.make_f32_operands(ctx));
     {
       Status st = rsvd_run(ctx, io, o->chi, o->oversample, o->power_iters, o->seed, rs, o->sv_cut);
       if (st.good()) st = join_bwd(false);
       if (!st.good()) return fail(st.code, "site " + std::to_string(x) + ": " + st.msg);
     }
     fallbacks |= rs.fallbacks;
+    pass_fl.push_back({plp->flops_fwd, plp->flops_bwd});
+    total_passes += (int)rs.pass_k.size();
     if (ctx->verbose) {
       int64_t mt = 0, nt = 0;
       for (int J = 0; J < ns; ++J) {
@@ -963,18 +1060,32 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
         dg.sigma.push_back(l > 0 ? std::sqrt(l) : 0.0);
         dg.sector.push_back(J);
       }
-    double site_flops = plp->flops_fwd * (2 + 2 * o->power_iters);
-    for (int J = 0; J < ns; ++J) {
-      const double m = (double)op.sect[J].m, n = (double)op.sect[J].n, k = rs.k[J],
-                   c = rs.kept[J];
-      if (k <= 0) continue;
+    // algorithmic flops: every pass applies M and M^T 1 + q times each and
+    // factorises; the output factors once
+    double site_flops = 0;
+    {
       const int q = o->power_iters;
-      site_flops += (q + 1) * (2 * m * k * k - 2 * k * k * k / 3.0) +
-                    q * (2 * n * k * k - 2 * k * k * k / 3.0);
-      site_flops += 2 * n * k * k + 12 * k * k * k;
-      site_flops += 2 * m * k * c + 2 * k * c * n;
+      for (size_t ps = 0; ps < rs.pass_k.size(); ++ps) {
+        site_flops += (1 + q) * (pass_fl[ps][0] + pass_fl[ps][1]);
+        for (int J = 0; J < ns; ++J) {
+          const double m = (double)op.sect[J].m, n = (double)op.sect[J].n,
+                       k = rs.pass_k[ps][J];
+          if (k <= 0) continue;
+          site_flops += (q + 1) * (2 * m * k * k - 2 * k * k * k / 3.0) +
+                        q * (2 * n * k * k - 2 * k * k * k / 3.0);
+          site_flops += 2 * n * k * k + 11 * k * k * k;
+        }
+      }
+      for (int J = 0; J < ns; ++J) {
+        const double m = (double)op.sect[J].m, n = (double)op.sect[J].n, k = rs.k[J],
+                     c = rs.kept[J];
+        if (k > 0) site_flops += 2 * m * k * c + 2 * k * c * n;
+      }
     }
     flops += site_flops;
+    prev_kept.clear();
+    for (int J = 0; J < ns; ++J) prev_kept[op.sect[J].label] = rs.kept[J];
+    have_prev = true;
     for (int v : rs.kept) kept_total += v;
     if (rs.cut.total2 > 0) disc = std::max(disc, 1.0 - rs.cut.kept2 / rs.cut.total2);
     if (rs.cut.s_next >= 0 && rs.cut.s_last > 0)
@@ -985,8 +1096,6 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
   FP_HIP(hipEventSynchronize(ev1));
   float ms = 0;
   FP_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
   FP_TRY(ctx->sync());
   if (cap_fail) return fail(FPEPS_ERR_CAPACITY, "output tensor capacity too small (see report)");
   *log_norm += lg;
@@ -997,10 +1106,12 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     rep->min_rel_gap = std::isfinite(gap) ? gap : -1.0;
     rep->log_norm = lg;
     rep->peak_workspace = ctx->peak_ws;
+    rep->workspace_bytes = (double)ctx->ws_bytes;
     rep->kept_total = kept_total;
     rep->nslices = ctx->nslices;
     rep->fallbacks = fallbacks;
     rep->plan_reuses = cache_hits;
+    rep->rsvd_passes = total_passes;
     rep->kernel_launches = (int32_t)ctx->kt_launches;
     rep->kernel_seconds = ctx->kt_seconds;
     rep->kernel_flops = ctx->kt_flops;
@@ -1208,9 +1319,9 @@ Status explicit_rsvd(fpeps_ctx_s* ctx, int nmat, const int64_t* m, const int64_t
       if (group[i] < 0 || group[i] >= nmat) return fail(FPEPS_ERR_ARG, "group ids must be 0 .. nmat-1");
   if (o->precision != FPEPS_FP64)
     return fail(FPEPS_ERR_UNSUPPORTED, "explicit matrices: only FPEPS_FP64 is available");
-  hipEvent_t ev0, ev1;
-  FP_HIP(hipEventCreate(&ev0));
-  FP_HIP(hipEventCreate(&ev1));
+  EventPair evp;
+  FP_HIP(evp.create());
+  hipEvent_t ev0 = evp.a, ev1 = evp.b;
   FP_HIP(hipEventRecord(ev0, ctx->stream));
   ExplicitOp e;
   for (int i = 0; i < nmat; ++i) {
@@ -1322,24 +1433,29 @@ Status explicit_rsvd(fpeps_ctx_s* ctx, int nmat, const int64_t* m, const int64_t
   FP_HIP(hipEventSynchronize(ev1));
   float ms = 0;
   FP_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
   if (rep) {
     // algorithmic flops, counted as for a site of the absorption: (2 + 2q)
     // dense products (plus the projector splits of the expansion),
     // orthonormalisation, core factorisation and the output factors
     const int qq = cbe ? 0 : o->power_iters;
     double fl = 0;
+    for (const auto& pk : rs.pass_k)
+      for (int i = 0; i < nmat; ++i) {
+        const double mi = (double)e.m[i], ni = (double)e.n[i], k = pk[i];
+        if (k <= 0) continue;
+        fl += (2 + 2 * qq) * 2.0 * mi * ni * k;
+        if (cbe) fl += (2 + 2 * qq) * 4.0 * (rr ? rr[i] : 0) * k * (mi + ni);
+        fl += (qq + 1) * (2 * mi * k * k - 2 * k * k * k / 3.0) +
+              qq * (2 * ni * k * k - 2 * k * k * k / 3.0);
+        fl += 2 * ni * k * k + 11 * k * k * k;
+      }
     for (int i = 0; i < nmat; ++i) {
       const double mi = (double)e.m[i], ni = (double)e.n[i], k = rs.k[i], c = rs.kept[i];
-      if (k <= 0) continue;
-      fl += (2 + 2 * qq) * 2.0 * mi * ni * k;
-      if (cbe) fl += (2 + 2 * qq) * 4.0 * (rr ? rr[i] : 0) * k * (mi + ni);
-      fl += (qq + 1) * (2 * mi * k * k - 2 * k * k * k / 3.0) + qq * (2 * ni * k * k - 2 * k * k * k / 3.0);
-      fl += 2 * ni * k * k + 12 * k * k * k;
-      fl += 2 * mi * k * c + (cbe ? 0.0 : 2 * k * c * ni);
+      if (k > 0) fl += 2 * mi * k * c + (cbe ? 0.0 : 2 * k * c * ni);
     }
     rep->alg_flops = fl;
+    rep->rsvd_passes = (int32_t)rs.pass_k.size();
+    rep->workspace_bytes = (double)ctx->ws_bytes;
     rep->seconds = ms * 1e-3;
     rep->fallbacks = rs.fallbacks;
     int tot = 0;
@@ -1361,8 +1477,16 @@ Status explicit_rsvd(fpeps_ctx_s* ctx, int nmat, const int64_t* m, const int64_t
 // overlap of two environments
 // ---------------------------------------------------------------------------
 Status overlap(fpeps_ctx_s* ctx, int L, const fpeps_tensor* top, const fpeps_tensor* bot,
-               double* value) {
-  if (L < 1 || !top || !bot || !value) return fail(FPEPS_ERR_ARG, "null argument");
+               double log_norm, int32_t* sign, double* log_abs) {
+  if (L < 1 || !top || !bot || !sign || !log_abs) return fail(FPEPS_ERR_ARG, "null argument");
+  if (!std::isfinite(log_norm)) return fail(FPEPS_ERR_ARG, "non-finite log-norm");
+  // E is divided by its Frobenius norm after every site; the logarithms are
+  // accumulated, so the value is returned as (sign, log |value|) whatever
+  // its magnitude
+  double lg = log_norm;
+  double *npart = nullptr, *nout = nullptr;
+  FP_TRY(ctx->bufT("ov_npart", 512, &npart));
+  FP_TRY(ctx->bufT("ov_nout", 1, &nout));
   const int nlab = top[0].nlab;
   SymInfo none;
   // E[at, ab]
@@ -1413,6 +1537,18 @@ Status overlap(fpeps_ctx_s* ctx, int L, const fpeps_tensor* top, const fpeps_ten
     FP_TRY(ctx->bufT(nx ? "ov_E1" : "ov_E0b", (size_t)es, &Ebuf[nx]));
     FP_TRY(run_gemm(ctx, ps, i1, top[x].data, top[x].nelem, Ebuf[cur], Esize, X, xs));
     FP_TRY(run_gemm(ctx, ps, i2, X, xs, bot[x].data, bot[x].nelem, Ebuf[nx], es));
+    if (x + 1 < L) {
+      FP_HIP(launch_sumsq(Ebuf[nx], es, npart, nout, ctx->stream));
+      double h = 0;
+      FP_HIP(hipMemcpyAsync(&h, nout, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      FP_TRY(ctx->sync());
+      if (!std::isfinite(h)) return fail(FPEPS_ERR_NUMERIC, "non-finite environment overlap");
+      if (h > 0.0) {
+        const double nu = std::sqrt(h);
+        FP_HIP(launch_scale(Ebuf[nx], es, 1.0 / nu, ctx->stream));
+        lg += std::log(nu);
+      }
+    }
     FP_TRY(ctx->sync());
     E = BT();
     E.names = {N_a, N_c};
@@ -1429,7 +1565,9 @@ Status overlap(fpeps_ctx_s* ctx, int L, const fpeps_tensor* top, const fpeps_ten
   FP_TRY(ctx->sync());
   double v = 0;
   for (const Block& b : E.blocks) v += h[b.base];
-  *value = v;
+  if (!std::isfinite(v)) return fail(FPEPS_ERR_NUMERIC, "non-finite environment overlap");
+  *sign = v > 0.0 ? 1 : (v < 0.0 ? -1 : 0);
+  *log_abs = v != 0.0 ? lg + std::log(std::fabs(v)) : -INFINITY;
   return Status::ok();
 }
 

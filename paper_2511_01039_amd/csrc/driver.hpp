@@ -24,6 +24,9 @@ struct RsvdIO {
   // sector
   std::vector<int32_t> grp;
   std::vector<uint32_t> c2v;
+  // guess of each sector's kept count (-1: none; empty: none), e.g. the
+  // previous site's kept count for the same sector label
+  std::vector<int32_t> hint;
   std::function<Status(const std::vector<int32_t>&)> prepare;
   // apply(transpose, final, x, y): y = M x or M^T x; ``final`` marks the
   // last range-finder product (it fixes Q) and the projection B^T = M^T Q
@@ -39,11 +42,14 @@ struct RsvdOut {
   int64_t S = 0;
   double* Q = nullptr;       // row layout
   double* Bt = nullptr;      // column layout, B^T = M^T Q
-  double* small = nullptr;   // [G | eigenvectors | eigenvalues]
+  double* small = nullptr;   // [G | U~ (k x k per sector) | eigenvalues | V0]
   std::vector<double> lam;   // eigenvalues of B B^T, per sector descending
   CutOut cut{};                // group 0 (the only one of a single problem)
   std::vector<CutOut> cuts;    // every group
   uint32_t fallbacks = 0;
+  // widths and kept counts of every factorisation pass (a pass with a
+  // saturated sector is followed by one with that sector widened)
+  std::vector<std::vector<int32_t>> pass_k, pass_kept;
 };
 
 Status rsvd_run(fpeps_ctx_s* ctx, RsvdIO& io, int chi, int p, int q, uint64_t seed, RsvdOut& out,
@@ -62,7 +68,7 @@ Status explicit_rsvd(fpeps_ctx_s* ctx, int nmat, const int64_t* m, const int64_t
                      const int32_t* r, const double* const* U, const double* const* V, bool cbe,
                      const int32_t* group = nullptr);
 Status overlap(fpeps_ctx_s* ctx, int L, const fpeps_tensor* top, const fpeps_tensor* bot,
-               double* value);
+               double log_norm, int32_t* sign, double* log_abs);
 Status axpy_inplace(fpeps_ctx_s* ctx, double* x, const double* y, int64_t n);
 
 }  // namespace fp

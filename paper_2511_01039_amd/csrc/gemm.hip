@@ -8,9 +8,11 @@
 // tile is written to C[c_off + tcm[m] + tcn[n]].
 //
 // Tiles are staged through LDS (KT = 16 deep, double-buffered); each of the
-// four waves runs v_mfma_f64_16x16x4f64 on its sub-tile. Register layout of that
-// instruction (checked on the device): A[i][k] in lane i + 16k, B[k][j] in
-// lane j + 16k, result register r of lane l holds D[4r + l/16][l % 16].
+// four waves runs v_mfma_f64_16x16x4f64 (FP64) or v_mfma_f32_16x16x4f32
+// (FP32 operands, FP32 accumulation) on its sub-tile. Register layouts
+// (checked on the device): A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
+// result register r of lane l holds D[4r + l/16][l % 16] for the FP64
+// instruction and D[4(l/16) + r][l % 16] for the FP32 one.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -18,6 +20,30 @@
 namespace fp {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// The matrix instruction of each compute type.
+template <class TM>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef d4 acc;
+  static __device__ __forceinline__ acc zero() { return d4{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc run(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of the 16 x 16 result held by register r of a lane in lane group lk
+  static __device__ __forceinline__ int row(int r, int lk) { return 4 * r + lk; }
+};
+template <>
+struct Mfma<float> {
+  typedef f4 acc;
+  static __device__ __forceinline__ acc zero() { return f4{0.0f, 0.0f, 0.0f, 0.0f}; }
+  static __device__ __forceinline__ acc run(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int lk) { return 4 * lk + r; }
+};
 
 // Position of one K tile in a job's sequence of (pair, K range) tiles.
 struct TileCursor {
@@ -25,25 +51,25 @@ struct TileCursor {
   int kb;   // first K of the tile
 };
 
-template <int MT, int NT, int KT>
+template <int MT, int NT, int KT, class TM>
 struct TileRegs {
-  double a[(MT * KT) / 256];
-  double b[(NT * KT) / 256];
-  double alpha;
+  TM a[(MT * KT) / 256];
+  TM b[(NT * KT) / 256];
+  TM alpha;
   uint32_t valid;   // bit i: a[i] in range; bit NA + i: b[i] in range
   bool akf, bnf;
 };
 
-template <int MT, int NT, int KT, class TB>
-__device__ __forceinline__ void load_tile(const double* __restrict__ A,
+template <int MT, int NT, int KT, class TA, class TB, class TM>
+__device__ __forceinline__ void load_tile(const TA* __restrict__ A,
                                           const TB* __restrict__ B,
                                           const GemmPair* __restrict__ pairs,
                                           const int32_t* __restrict__ tab, const GemmJob& job,
                                           const TileCursor& t, int tid,
-                                          TileRegs<MT, NT, KT>& r) {
+                                          TileRegs<MT, NT, KT, TM>& r) {
   const GemmPair pr = pairs[t.p];
   const int kend = job.k1 < pr.K ? job.k1 : pr.K;
-  const double* Ab = A + pr.a_off;
+  const TA* Ab = A + pr.a_off;
   const TB* Bb = B + pr.b_off;
   const int32_t* tam = tab + pr.tam;
   const int32_t* tak = tab + pr.tak;
@@ -78,30 +104,30 @@ __device__ __forceinline__ void load_tile(const double* __restrict__ A,
     ob[i] = tbk[min(k, kend - 1)] + tbn[min(n, job.N - 1)];
   }
 #pragma unroll
-  for (int i = 0; i < NA; ++i) r.a[i] = Ab[oa[i]];
+  for (int i = 0; i < NA; ++i) r.a[i] = (TM)Ab[oa[i]];
 #pragma unroll
-  for (int i = 0; i < NB; ++i) r.b[i] = (double)Bb[ob[i]];
-  r.alpha = pr.alpha;
+  for (int i = 0; i < NB; ++i) r.b[i] = (TM)Bb[ob[i]];
+  r.alpha = (TM)pr.alpha;
   r.valid = valid;
 }
 
-template <int MT, int NT, int KT>
-__device__ __forceinline__ void store_tile(double (*sA)[MT + 1], double (*sB)[NT + 1], int tid,
-                                           const TileRegs<MT, NT, KT>& r) {
+template <int MT, int NT, int KT, class TM>
+__device__ __forceinline__ void store_tile(TM (*sA)[MT + 1], TM (*sB)[NT + 1], int tid,
+                                           const TileRegs<MT, NT, KT, TM>& r) {
   constexpr int NA = (MT * KT) / 256;
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
     const int e = tid + i * 256;
     const int mm = r.akf ? e / KT : e % MT;
     const int kk = r.akf ? e % KT : e / MT;
-    sA[kk][mm] = (r.valid >> i) & 1u ? r.a[i] * r.alpha : 0.0;
+    sA[kk][mm] = (r.valid >> i) & 1u ? r.a[i] * r.alpha : (TM)0;
   }
 #pragma unroll
   for (int i = 0; i < (NT * KT) / 256; ++i) {
     const int e = tid + i * 256;
     const int nn = r.bnf ? e % NT : e / KT;
     const int kk = r.bnf ? e / NT : e % KT;
-    sB[kk][nn] = (r.valid >> (NA + i)) & 1u ? r.b[i] : 0.0;
+    sB[kk][nn] = (r.valid >> (NA + i)) & 1u ? r.b[i] : (TM)0;
   }
 }
 
@@ -121,22 +147,21 @@ __device__ __forceinline__ bool next_tile(const GemmPair* __restrict__ pairs, co
 
 // One workgroup (four waves, WM x WN) per output tile; K tiles are
 // prefetched into registers while the previous tile is multiplied out of
-// LDS (double-buffered, one barrier per tile).
-template <int MT, int NT, int WM, int WN, class TB, class TC>
-__global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ A,
-                                                  const TB* __restrict__ B,
-                                                  TC* __restrict__ C,
-                                                  const GemmJob* __restrict__ jobs,
-                                                  const GemmPair* __restrict__ pairs,
-                                                  const int32_t* __restrict__ tab, int swz) {
+// LDS (double-buffered, one barrier per tile). TM is the compute type (the
+// MFMA operand and accumulator type).
+template <int MT, int NT, int WM, int WN, class TA, class TB, class TC, class TM>
+__device__ __forceinline__ void gemm_tile(const TA* __restrict__ A, const TB* __restrict__ B,
+                                          TC* __restrict__ C, const GemmJob* __restrict__ jobs,
+                                          const GemmPair* __restrict__ pairs,
+                                          const int32_t* __restrict__ tab, int swz,
+                                          TM (*sA)[16][MT + 1], TM (*sB)[16][NT + 1]) {
   constexpr int KT = 16;
   constexpr int WTM = MT / WM, WTN = NT / WN;
   constexpr int FM = WTM / 16, FN = WTN / 16;
   static_assert(WM * WN == 4, "four waves");
   static_assert(FM >= 1 && FN >= 1, "wave tile at least 16x16");
   static_assert((MT * KT) % 256 == 0 && (NT * KT) % 256 == 0, "tile loads cover 256 threads");
-  __shared__ double sA[2][KT][MT + 1];
-  __shared__ double sB[2][KT][NT + 1];
+  typedef Mfma<TM> MF;
 
   const GemmJob job = jobs[xcd_swizzle((int)blockIdx.x, (int)gridDim.x, swz)];
   const int tid = threadIdx.x;
@@ -145,11 +170,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ 
   const int wm = wave % WM, wn = wave / WM;
   const int lrow = lane & 15, lk = lane >> 4;
 
-  d4 acc[FM][FN];
+  typename MF::acc acc[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FN; ++j) acc[i][j] = MF::zero();
 
   // first tile of the job (jobs without any tile write zeros)
   TileCursor cur{job.p0, job.k0 > 0 ? job.k0 : 0};
@@ -163,17 +188,17 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ 
     cur.kb = job.k0 > 0 ? job.k0 : 0;
   }
   if (have) {
-    TileRegs<MT, NT, KT> regs;
-    load_tile<MT, NT, KT, TB>(A, B, pairs, tab, job, cur, tid, regs);
-    store_tile<MT, NT, KT>(sA[0], sB[0], tid, regs);
+    TileRegs<MT, NT, KT, TM> regs;
+    load_tile<MT, NT, KT, TA, TB, TM>(A, B, pairs, tab, job, cur, tid, regs);
+    store_tile<MT, NT, KT, TM>(sA[0], sB[0], tid, regs);
     __syncthreads();
     int buf = 0;
     while (true) {
       const bool more = next_tile(pairs, job, cur, KT);
-      if (more) load_tile<MT, NT, KT, TB>(A, B, pairs, tab, job, cur, tid, regs);
+      if (more) load_tile<MT, NT, KT, TA, TB, TM>(A, B, pairs, tab, job, cur, tid, regs);
 #pragma unroll
       for (int kk = 0; kk < KT; kk += 4) {
-        double a[FM], b[FN];
+        TM a[FM], b[FN];
 #pragma unroll
         for (int i = 0; i < FM; ++i) a[i] = sA[buf][kk + lk][wm * WTM + i * 16 + lrow];
 #pragma unroll
@@ -181,11 +206,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ 
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-          for (int j = 0; j < FN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < FN; ++j) acc[i][j] = MF::run(a[i], b[j], acc[i][j]);
       }
       if (!more) break;
-      store_tile<MT, NT, KT>(sA[buf ^ 1], sB[buf ^ 1], tid, regs);
+      store_tile<MT, NT, KT, TM>(sA[buf ^ 1], sB[buf ^ 1], tid, regs);
       __syncthreads();
       buf ^= 1;
     }
@@ -200,7 +224,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ 
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = job.m0 + wm * WTM + i * 16 + 4 * r + lk;
+      const int m = job.m0 + wm * WTM + i * 16 + MF::row(r, lk);
       om[i][r] = tcm[min(m, job.M - 1)];
     }
 #pragma unroll
@@ -215,10 +239,35 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ 
     for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = job.m0 + wm * WTM + i * 16 + 4 * r + lk;
+        const int m = job.m0 + wm * WTM + i * 16 + MF::row(r, lk);
         const int n = job.n0 + wn * WTN + j * 16 + lrow;
         if (m < job.M && n < job.N) Cb[(int64_t)om[i][r] + on[j]] = (TC)acc[i][j][r];
       }
+}
+
+template <int MT, int NT, int WM, int WN, class TB, class TC>
+__global__ __launch_bounds__(256, 2) void k_gemm_f64(const double* __restrict__ A,
+                                                  const TB* __restrict__ B,
+                                                  TC* __restrict__ C,
+                                                  const GemmJob* __restrict__ jobs,
+                                                  const GemmPair* __restrict__ pairs,
+                                                  const int32_t* __restrict__ tab, int swz) {
+  __shared__ double sA[2][16][MT + 1];
+  __shared__ double sB[2][16][NT + 1];
+  gemm_tile<MT, NT, WM, WN, double, TB, TC, double>(A, B, C, jobs, pairs, tab, swz, sA, sB);
+}
+
+// FP32 operands (A an FP32 copy), FP32 MFMA, FP32 accumulation.
+template <int MT, int NT, int WM, int WN, class TB, class TC>
+__global__ __launch_bounds__(256, 2) void k_gemm_f32(const float* __restrict__ A,
+                                                  const TB* __restrict__ B,
+                                                  TC* __restrict__ C,
+                                                  const GemmJob* __restrict__ jobs,
+                                                  const GemmPair* __restrict__ pairs,
+                                                  const int32_t* __restrict__ tab, int swz) {
+  __shared__ float sA[2][16][MT + 1];
+  __shared__ float sB[2][16][NT + 1];
+  gemm_tile<MT, NT, WM, WN, float, TB, TC, float>(A, B, C, jobs, pairs, tab, swz, sA, sB);
 }
 
 // Runs of 4 consecutive jobs per XCD: larger runs (or one contiguous range
@@ -245,6 +294,55 @@ static hipError_t launch_typed(const DevGemm& g, const double* A, const TB* B, T
   FP_GEMM_TILE(16, 256, 1, 4)
 #undef FP_GEMM_TILE
   return hipErrorInvalidValue;
+}
+
+template <class TB, class TC>
+static hipError_t launch_typed_f32(const DevGemm& g, const float* A, const TB* B, TC* C,
+                                   const int32_t* tables, hipStream_t s) {
+  dim3 grid(g.njobs), block(256);
+#define FP_GEMM_TILE(mt_, nt_, wm_, wn_)                                                 \
+  if (g.mt == mt_ && g.nt == nt_) {                                                      \
+    k_gemm_f32<mt_, nt_, wm_, wn_, TB, TC>                                               \
+        <<<grid, block, 0, s>>>(A, B, C, g.jobs, g.pairs, tables, GEMM_XCD_RUN); \
+    return hipGetLastError();                                                            \
+  }
+  FP_GEMM_TILE(128, 128, 2, 2)
+  FP_GEMM_TILE(128, 64, 2, 2)
+  FP_GEMM_TILE(64, 128, 2, 2)
+  FP_GEMM_TILE(64, 64, 2, 2)
+  FP_GEMM_TILE(128, 32, 4, 1)
+  FP_GEMM_TILE(32, 128, 1, 4)
+  FP_GEMM_TILE(256, 16, 4, 1)
+  FP_GEMM_TILE(16, 256, 1, 4)
+#undef FP_GEMM_TILE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemm_f32(const DevGemm& g, const float* A, const void* B, bool b_f32, void* C,
+                           bool c_f32, const int32_t* tables, hipStream_t s) {
+  if (g.njobs <= 0) return hipSuccess;
+  if (b_f32 && !c_f32)
+    return launch_typed_f32<float, double>(g, A, (const float*)B, (double*)C, tables, s);
+  if (!b_f32 && c_f32)
+    return launch_typed_f32<double, float>(g, A, (const double*)B, (float*)C, tables, s);
+  if (!b_f32 && !c_f32)
+    return launch_typed_f32<double, double>(g, A, (const double*)B, (double*)C, tables, s);
+  return launch_typed_f32<float, float>(g, A, (const float*)B, (float*)C, tables, s);
+}
+
+// FP64 -> FP32 copy (round to nearest)
+__global__ void k_to_f32(float* __restrict__ dst, const double* __restrict__ src, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = (float)src[e];
+}
+
+hipError_t launch_to_f32(float* dst, const double* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t nb = (n + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  k_to_f32<<<(unsigned)nb, 256, 0, s>>>(dst, src, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_gemm_f64(const DevGemm& g, const double* A, const double* B, double* C,

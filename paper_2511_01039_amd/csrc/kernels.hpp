@@ -40,6 +40,12 @@ struct DevGemm {
 // C[job tiles] = sum over pairs alpha * A(tables) * B(tables), FP64 MFMA.
 hipError_t launch_gemm_f64(const DevGemm& g, const double* A, const double* B, double* C,
                            const int32_t* tables, hipStream_t s);
+// The same with an FP32 copy of A, B and C in FP32 or FP64, on FP32 MFMA with
+// FP32 accumulation (B rounded to FP32 when loaded, C rounded from FP32).
+hipError_t launch_gemm_f32(const DevGemm& g, const float* A, const void* B, bool b_f32, void* C,
+                           bool c_f32, const int32_t* tables, hipStream_t s);
+// dst[i] = (float)src[i]
+hipError_t launch_to_f32(float* dst, const double* src, int64_t n, hipStream_t s);
 
 // A row-thread layer-step plan resident on the device.
 struct DevRt {
@@ -108,8 +114,15 @@ hipError_t launch_chol_inv(const SmallDesc* d, int nd, double* buf, int* status,
 
 // Symmetric Jacobi eigensolver per matrix: A (k x k) -> eigenvalues
 // descending at c_off, eigenvectors as columns of the k x k matrix at b_off.
+// ``rel``: stop by the relative rule |a_pq| <= k eps sqrt(a_pp a_qq) for
+// every pair (each eigenvalue resolved to its own size on a Gram matrix of
+// nearly orthogonal columns); otherwise by the off-diagonal norm.
+// status |= 4 when 40 sweeps do not converge.
 hipError_t launch_jacobi_eig(const SmallDesc* d, int nd, int max_k, double* buf, int* status,
-                             hipStream_t s);
+                             hipStream_t s, bool rel = false);
+// In place per matrix: the k x k matrix at b_off becomes (matrix at c_off)
+// times itself; a_off is k x k scratch.
+hipError_t launch_small_mm(const SmallDesc* d, int nd, double* buf, hipStream_t s);
 
 // Global truncation over sectors: eigenvalues (descending per sector) at
 // lam_off[i] with k[i] entries; keeps the ``chi`` largest sqrt(lam).
@@ -122,16 +135,14 @@ struct CutOut {
 // One cut per group: group g ranks the values of sectors [s0, s0 + ns) of
 // the lists (lam_off, k), ``total`` values in all, keeps ranks < chi, and
 // writes kept[s0 ..] and out[g]. One workgroup per group.
+// Values at or below ``floor`` times the group's largest are never kept.
 struct CutGroup {
   int32_t s0, ns, total, pad;
+  double floor;
 };
 hipError_t launch_cut(const CutGroup* groups, int ngroups, int max_ns, int max_total,
-                      const int64_t* lam_off, const int32_t* k, int chi, double sv_cut,
+                      const int64_t* lam_off, const int32_t* k, int chi,
                       const double* buf, int32_t* kept, CutOut* out, hipStream_t s);
-// SVQB scaling: column i of the k x k eigenvector matrix at b_off is
-// multiplied by 1/sqrt(lambda_i) (eigenvalues at c_off, descending), or set to
-// zero when lambda_i <= tau * lambda_0 (numerically null direction).
-hipError_t launch_svqb_scale(const SmallDesc* d, int nd, double* buf, double tau, hipStream_t s);
 
 // Canonical signs of a truncated factorisation: column c of U (m x ncol,
 // row-major at u_off) is flipped together with row c of R (ncol x n at
@@ -149,6 +160,7 @@ hipError_t launch_sign_fix(const SignDesc* d, int nd, int total_cols, const int3
 hipError_t launch_sumsq(const double* x, int64_t n, double* partial, double* out, hipStream_t s);
 hipError_t launch_scale(double* x, int64_t n, double a, hipStream_t s);
 hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill_int(int* x, int64_t n, int v, hipStream_t s);
 // x[i] += y[i]
 hipError_t launch_add(double* x, const double* y, int64_t n, hipStream_t s);
 // 1 in *flag if any x is not finite

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_chol_inv(const SmallDesc* __restrict__ 
   const int tid = threadIdx.x, nt = blockDim.x;
   __shared__ double red[256];
   __shared__ double sh_shift;
-  if (g.shift > 0.0) {
+  {
     double t = 0.0;
     for (int i = tid; i < k; i += nt) t += A[(int64_t)i * k + i];
     red[tid] = t;
@@ -86,6 +86,14 @@ __global__ __launch_bounds__(256) void k_chol_inv(const SmallDesc* __restrict__ 
       if (tid < w) red[tid] += red[tid + w];
       __syncthreads();
     }
+  }
+  // an exactly zero block (a sector the operator maps to zero) has an empty
+  // range: X = 0 makes its Q zero, and no breakdown is reported
+  if (!(red[0] > 0.0)) {
+    for (int64_t e = tid; e < (int64_t)k * k; e += nt) X[e] = 0.0;
+    return;
+  }
+  if (g.shift > 0.0) {
     if (tid == 0) {
       const double eps = 1.1102230246251565e-16;
       sh_shift = g.shift * ((double)g.rows * k + (double)k * (k + 1)) * eps * red[0];
@@ -141,10 +149,17 @@ hipError_t launch_chol_inv(const SmallDesc* d, int nd, double* buf, int* status,
 // With LDS, the matrix being rotated lives in LDS (a copy; the k x k input in
 // global memory is left as it was), otherwise in place in global memory.
 // Same arithmetic in the same order either way.
+// Two stopping rules: the off-diagonal Frobenius norm below 1e-15 of the
+// diagonal's (REL false), or (REL true) the rule of Demmel & Veselic (SIAM
+// J. Matrix Anal. Appl. 13 (1992) 1204): a pair is rotated only while
+// |a_pq| > k eps sqrt(a_pp a_qq), and the iteration stops after a sweep
+// without rotations. On a Gram matrix whose columns are nearly orthogonal
+// the relative rule resolves every eigenvalue to its own size, not to the
+// largest one's.
 // ---------------------------------------------------------------------------
 constexpr int JAC_SCRATCH = 2560;   // doubles of rotation and reduction scratch
 
-template <bool LDS>
+template <bool LDS, bool REL>
 __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d,
                                                  double* __restrict__ buf,
                                                  int* __restrict__ status) {
@@ -161,6 +176,8 @@ __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d
   double* red = sm + 1536;       // [1024]
   double* A = LDS ? sm + JAC_SCRATCH : buf + g.a_off;   // [k * k]
   __shared__ int done;
+  __shared__ int nrot;
+  const double rel_tol = (double)k * 2.220446049250313e-16;
   const int kp = k + (k & 1);
   const int npair = kp / 2;
   if (LDS) {
@@ -171,6 +188,10 @@ __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d
   for (int64_t e = tid; e < (int64_t)k * k; e += nt) V[e] = (e / k == e % k) ? 1.0 : 0.0;
   __syncthreads();
   for (int sweep = 0; sweep < 40; ++sweep) {
+    if (REL) {
+      if (tid == 0) nrot = 0;
+      __syncthreads();
+    } else {
     // convergence test: off-diagonal vs diagonal Frobenius norms
     double off = 0.0, dia = 0.0;
     for (int64_t e = tid; e < (int64_t)k * k; e += nt) {
@@ -197,6 +218,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d
     if (tid == 0) done = (offsum <= 1e-30 * red[0]) || (offsum == 0.0);
     __syncthreads();
     if (done) break;
+    }
     for (int rnd = 0; rnd < kp - 1; ++rnd) {
       for (int i = tid; i < npair; i += nt) {
         // circle method: position 0 fixed, others rotate by rnd
@@ -211,11 +233,17 @@ __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d
         if (q < k) {
           const double apq = A[(int64_t)p * k + q];
           const double app = A[(int64_t)p * k + p], aqq = A[(int64_t)q * k + q];
-          if (apq != 0.0 && fabs(apq) > 1e-300) {
+          const bool rot = REL ? fabs(apq) > rel_tol * sqrt(fabs(app * aqq))
+                               : (apq != 0.0 && fabs(apq) > 1e-300);
+          if (rot) {
             const double tau = (aqq - app) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), ~ 1 / (2 tau) for large |tau|
+            const double t = fabs(tau) > 1e150
+                                 ? 0.5 / tau
+                                 : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
+            if (REL && s != 0.0) atomicAdd(&nrot, 1);
           }
         }
         cs[i] = c;
@@ -252,6 +280,10 @@ __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d
       }
       __syncthreads();
     }
+    if (REL) {
+      __syncthreads();
+      if (nrot == 0) break;
+    }
     if (sweep == 39 && tid == 0) atomicOr(status, 4);
   }
   // sort eigenvalues descending (ties by index) and permute columns of V
@@ -277,16 +309,49 @@ __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d
 }
 
 hipError_t launch_jacobi_eig(const SmallDesc* d, int nd, int max_k, double* buf, int* status,
-                             hipStream_t s) {
+                             hipStream_t s, bool rel) {
   if (nd <= 0) return hipSuccess;
   if (max_k > 1024 || max_k < 0) return hipErrorInvalidValue;
   // the matrix in LDS when it fits beside the scratch in 64 KiB
   const size_t scratch = (size_t)JAC_SCRATCH * sizeof(double);
   const size_t mat = (size_t)max_k * max_k * sizeof(double);
-  if (scratch + mat <= 64 * 1024)
-    k_jacobi<true><<<nd, 1024, scratch + mat, s>>>(d, buf, status);
+  const bool lds = scratch + mat <= 64 * 1024;
+  if (lds && rel)
+    k_jacobi<true, true><<<nd, 1024, scratch + mat, s>>>(d, buf, status);
+  else if (lds)
+    k_jacobi<true, false><<<nd, 1024, scratch + mat, s>>>(d, buf, status);
+  else if (rel)
+    k_jacobi<false, true><<<nd, 1024, scratch, s>>>(d, buf, status);
   else
-    k_jacobi<false><<<nd, 1024, scratch, s>>>(d, buf, status);
+    k_jacobi<false, false><<<nd, 1024, scratch, s>>>(d, buf, status);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Product of two k x k matrices per descriptor, in place: the matrix at b_off
+// becomes X B, X the matrix at c_off (both row-major k x k); a_off is k x k
+// scratch. One workgroup per matrix.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_small_mm(const SmallDesc* __restrict__ d,
+                                                  double* __restrict__ buf) {
+  const SmallDesc g = d[blockIdx.x];
+  const int k = g.k;
+  const double* X = buf + g.c_off;
+  double* B = buf + g.b_off;
+  double* T = buf + g.a_off;
+  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += blockDim.x) {
+    const int i = (int)(e / k), j = (int)(e % k);
+    double acc = 0.0;
+    for (int l = 0; l < k; ++l) acc += X[(int64_t)i * k + l] * B[(int64_t)l * k + j];
+    T[e] = acc;
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += blockDim.x) B[e] = T[e];
+}
+
+hipError_t launch_small_mm(const SmallDesc* d, int nd, double* buf, hipStream_t s) {
+  if (nd <= 0) return hipSuccess;
+  k_small_mm<<<nd, 256, 0, s>>>(d, buf);
   return hipGetLastError();
 }
 
@@ -298,7 +363,7 @@ hipError_t launch_jacobi_eig(const SmallDesc* d, int nd, int max_k, double* buf,
 __global__ __launch_bounds__(1024) void k_cut(const CutGroup* __restrict__ groups,
                                               const int64_t* __restrict__ lam_off_all,
                                               const int32_t* __restrict__ kk_all, int chi,
-                                              double sv_cut, const double* __restrict__ buf,
+                                              const double* __restrict__ buf,
                                               int32_t* __restrict__ kept_all,
                                               CutOut* __restrict__ outs) {
   extern __shared__ double sm[];
@@ -335,10 +400,10 @@ __global__ __launch_bounds__(1024) void k_cut(const CutGroup* __restrict__ group
     n_above = 0;
   }
   __syncthreads();
-  // values at or below sv_cut * max are never kept
+  // values at or below floor * max are never kept
   {
     int c = 0;
-    for (int i = tid; i < total; i += nt) c += sig[i] > sv_cut * s_max ? 1 : 0;
+    for (int i = tid; i < total; i += nt) c += sig[i] > G.floor * s_max ? 1 : 0;
     atomicAdd(&n_above, c);
   }
   __syncthreads();
@@ -380,32 +445,13 @@ __global__ __launch_bounds__(1024) void k_cut(const CutGroup* __restrict__ group
 }
 
 hipError_t launch_cut(const CutGroup* groups, int ngroups, int max_ns, int max_total,
-                      const int64_t* lam_off, const int32_t* k, int chi, double sv_cut,
+                      const int64_t* lam_off, const int32_t* k, int chi,
                       const double* buf, int32_t* kept, CutOut* out, hipStream_t s) {
   if (ngroups <= 0) return hipSuccess;
   if (max_ns > 1024) return hipErrorInvalidValue;
   const size_t shm = (size_t)max_total * (sizeof(double) + 2 * sizeof(int));
   if (shm > 96 * 1024) return hipErrorInvalidValue;
-  k_cut<<<dim3(ngroups), 1024, shm, s>>>(groups, lam_off, k, chi, sv_cut, buf, kept, out);
-  return hipGetLastError();
-}
-
-__global__ void k_svqb_scale(const SmallDesc* __restrict__ d, double* __restrict__ buf, double tau) {
-  const SmallDesc g = d[blockIdx.x];
-  const int k = g.k;
-  double* V = buf + g.b_off;
-  const double* lam = buf + g.c_off;
-  const double l0 = lam[0];
-  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += blockDim.x) {
-    const int col = (int)(e % k);
-    const double l = lam[col];
-    V[e] *= (l > tau * l0 && l > 0.0) ? 1.0 / sqrt(l) : 0.0;
-  }
-}
-
-hipError_t launch_svqb_scale(const SmallDesc* d, int nd, double* buf, double tau, hipStream_t s) {
-  if (nd <= 0) return hipSuccess;
-  k_svqb_scale<<<nd, 256, 0, s>>>(d, buf, tau);
+  k_cut<<<dim3(ngroups), 1024, shm, s>>>(groups, lam_off, k, chi, buf, kept, out);
   return hipGetLastError();
 }
 
@@ -524,6 +570,20 @@ hipError_t launch_fill(double* x, int64_t n, double v, hipStream_t s) {
   int64_t nb = (n + 255) / 256;
   if (nb > 4096) nb = 4096;
   k_fill<<<(unsigned)nb, 256, 0, s>>>(x, n, v);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_int(int* __restrict__ x, int64_t n, int v) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    x[e] = v;
+}
+
+hipError_t launch_fill_int(int* x, int64_t n, int v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t nb = (n + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  k_fill_int<<<(unsigned)nb, 256, 0, s>>>(x, n, v);
   return hipGetLastError();
 }
 

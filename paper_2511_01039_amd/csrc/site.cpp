@@ -624,8 +624,21 @@ Status SiteOp::plan_slice(const std::vector<int32_t>& k, const Plans& pl, Slice&
   return own->serialize();
 }
 
+Status SiteOp::make_f32_operands(fpeps_ctx_s* ctx) {
+  float *t = nullptr, *r = nullptr;
+  FP_TRY(ctx->bufT("T32", (size_t)std::max<int64_t>(dev.T_size, 1), &t));
+  FP_TRY(ctx->bufT("R32", (size_t)std::max<int64_t>(dev.R_size, 1), &r));
+  FP_HIP(launch_to_f32(t, dev.T, dev.T_size, ctx->stream));
+  FP_HIP(launch_to_f32(r, dev.R, dev.R_size, ctx->stream));
+  dev.T32 = t;
+  dev.R32 = r;
+  return Status::ok();
+}
+
 Status SiteOp::apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const double* x, double* y,
                      bool f32) {
+  if (f32 && (!dev.T32 || !dev.R32))
+    return fail(FPEPS_ERR_ARG, "mixed-precision chain without FP32 operand copies");
   const size_t es = f32 ? sizeof(float) : sizeof(double);
   const int64_t s1 = std::max<int64_t>(pl.ws1, 1), s2 = std::max<int64_t>(pl.ws2, 1);
   // Slices are independent (disjoint sketch columns, disjoint outputs): they
@@ -655,25 +668,31 @@ Status SiteOp::apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const do
   ctx->peak_ws = std::max(ctx->peak_ws, (double)(s1 + s2) * (double)es * (double)nst);
   const bool f = f32;
   auto run_slice = [&](const Slice& sl, void* c1, void* c2) -> Status {
+    // in mixed precision the FP64 masters T, R are replaced by their FP32
+    // copies (FP32 MFMA); otherwise A32 is null and the FP64 kernel runs
+    const double* T64 = f ? nullptr : dev.T;
+    const double* R64 = f ? nullptr : dev.R;
+    const float* T32 = f ? dev.T32 : nullptr;
+    const float* R32 = f ? dev.R32 : nullptr;
     if (!transpose) {
       const PlanSet& ps = *sl.ps;
-      FP_TRY(run_gemm_mixed(ctx, ps, sl.fwd[0], dev.T, dev.T_size, x, false, pl.col_total, c1, f,
-                            s1, true, 1));
+      FP_TRY(run_gemm_any(ctx, ps, sl.fwd[0], T64, T32, dev.T_size, x, false, pl.col_total, c1, f,
+                          s1, true, 1));
       FP_TRY(run_rt(ctx, ps, sl.fwd[1], c1, s1, c2, s2, f, true, 2));
       FP_TRY(run_rt(ctx, ps, sl.fwd[2], c2, s2, c1, s1, f, true, 3));
       FP_TRY(run_rt(ctx, ps, sl.fwd[3], c1, s1, c2, s2, f, true, 4));
-      FP_TRY(run_gemm_mixed(ctx, ps, sl.fwd[4], dev.R, dev.R_size, c2, f, s2, y, false,
-                            pl.row_total, true, 5));
+      FP_TRY(run_gemm_any(ctx, ps, sl.fwd[4], R64, R32, dev.R_size, c2, f, s2, y, false,
+                          pl.row_total, true, 5));
     } else {
       if (sl.bwd[0] < 0 || !sl.psb) return fail(FPEPS_ERR_ARG, "transposed chain was not planned");
       const PlanSet& psb = *sl.psb;
-      FP_TRY(run_gemm_mixed(ctx, psb, sl.bwd[0], dev.R, dev.R_size, x, false, pl.row_total, c2, f,
-                            s2, true, 15));
+      FP_TRY(run_gemm_any(ctx, psb, sl.bwd[0], R64, R32, dev.R_size, x, false, pl.row_total, c2, f,
+                          s2, true, 15));
       FP_TRY(run_rt(ctx, psb, sl.bwd[1], c2, s2, c1, s1, f, true, 14));
       FP_TRY(run_rt(ctx, psb, sl.bwd[2], c1, s1, c2, s2, f, true, 13));
       FP_TRY(run_rt(ctx, psb, sl.bwd[3], c2, s2, c1, s1, f, true, 12));
-      FP_TRY(run_gemm_mixed(ctx, psb, sl.bwd[4], dev.T, dev.T_size, c1, f, s1, y, false,
-                            pl.col_total, true, 11));
+      FP_TRY(run_gemm_any(ctx, psb, sl.bwd[4], T64, T32, dev.T_size, c1, f, s1, y, false,
+                          pl.col_total, true, 11));
     }
     return Status::ok();
   };

@@ -35,6 +35,10 @@ struct SiteData {
   const double* W = nullptr;
   const double* R = nullptr;
   int64_t T_size = 0, A_size = 0, W_size = 0, R_size = 0;
+  // FP32 copies of T and R (mixed precision: the environment and remainder
+  // products of the earlier range-finder applications run on FP32 MFMA)
+  const float* T32 = nullptr;
+  const float* R32 = nullptr;
 };
 
 // The part of a site's structure analysis that depends only on T, the ket
@@ -111,9 +115,13 @@ class SiteOp {
   Status upload(fpeps_ctx_s* ctx, Plans& pl, int which = 3) const;
   // y = M x (transpose = false) or M^T x, per-sector matrices at the offsets
   // of ``pl`` (x: col layout for M, row layout for M^T). ``f32`` stores the
-  // chain intermediates of this application in FP32 (arithmetic stays FP64).
+  // chain intermediates of this application in FP32 and runs its
+  // environment and remainder products on FP32 MFMA with FP32 accumulation
+  // (make_f32_operands first); the layer steps keep FP64 arithmetic.
   Status apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const double* x, double* y,
                bool f32);
+  // FP32 copies of T and R in the context's workspace (for apply with f32)
+  Status make_f32_operands(fpeps_ctx_s* ctx);
 
  private:
   BT omega_layout(const std::vector<SliceCol>& cols, const std::vector<int32_t>& k,

@@ -439,6 +439,65 @@ def config4_lattice(Lx=8, Ly=8, seed=0):
     return su2_lattice(Lx, Ly, legs_su2(500), seed=seed)
 
 
+def lowrank_su2_lattice(Lx=8, Ly=8, chi=500, seed=0, eps=0.5):
+    """An 8x8 SU(2)-synthetic lattice at the leg shapes of the headline row
+    (reduced D = 6, w = 4, d = 3, environment catalogue for chi = 500) whose
+    boundary MPS is exact at chi: every ket carries its horizontal bonds on
+    one state (the first state of the trivial sector; the blocks of the other
+    states are zero) and every PEPO its horizontal bonds on the two states of
+    the trivial sector, so after y rows the boundary bond is at most 2^y
+    <= 256 < chi (vertical legs carry all six states). No truncation is
+    needed, and <W> = Z_W / Z_1 depends on the arithmetic only, not on which
+    values a cut keeps. The PEPO is 1 + eps R per site as in
+    ``near_identity_pepo``; returns (Lattice with W, identity PEPO)."""
+    sym = Sym("su2", coef_seed=seed, fermionic=True)
+    cat = legs_su2(chi)
+    rng = np.random.default_rng(seed)
+    zero = lambda leg: int(np.flatnonzero((leg.labels == 0).all(axis=1))[0])
+
+    A = []
+    for y in range(Ly):
+        row = []
+        for x in range(Lx):
+            legs = peps_site_legs(cat, x, y, Lx, Ly)
+            zl, zr = zero(legs[1]), zero(legs[2])
+            allowed = lambda tup, legs=legs, zl=zl, zr=zr: (
+                tup[1] == zl and tup[2] == zr and
+                block_allowed(sym, [tuple(l.labels[s]) for l, s in zip(legs, tup)],
+                              [l.dir for l in legs]))
+            t = random_tensor(sym, legs, rng, allowed=allowed)
+            for i in range(t.nblocks):
+                b = t.block(i)
+                b[:, 1:, :, :, :] = 0.0
+                b[:, :, 1:, :, :] = 0.0
+            row.append(t)
+        A.append(row)
+    W = []
+    for y in range(Ly):
+        row = []
+        for x in range(Lx):
+            legs = pepo_site_legs(cat, x, y, Lx, Ly)
+            zl, zr = zero(legs[2]), zero(legs[3])
+            allowed = lambda tup, legs=legs, zl=zl, zr=zr: (
+                tup[2] == zl and tup[3] == zr and
+                block_allowed(sym, [tuple(l.labels[s]) for l, s in zip(legs, tup)],
+                              [l.dir for l in legs]))
+            t = random_tensor(sym, legs, rng, allowed=allowed)
+            t.data *= eps
+            z = [zero(l) for l in legs[2:]]
+            for s in range(legs[0].nsect):
+                i = t.find((s, s) + tuple(z))
+                assert i is not None, "identity block must be present"
+                t.block(i)[:, :, 0, 0, 0, 0] += np.eye(int(legs[0].dims[s]))
+            row.append(t)
+        W.append(row)
+    lat = Lattice(sym, A, W, Lx, Ly)
+    return lat, identity_pepo(sym, Lx, Ly, cat["phys"])
+
+
+LOWRANK_PARAMS = dict(chi=500, oversample=20, power_iters=2, seed=0)
+
+
 def config1_params():
     return dict(chi=32, oversample=8, power_iters=1, seed=0)
 
