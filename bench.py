@@ -227,19 +227,34 @@ def profiled_traffic(kernel, precision="fp64"):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(row, budget_s=20.0):
-    """The FP64 oracle on a bounded sample of the same workload: the chain
-    product M_x X at the first interior site (x = 1, remainder from the
-    oracle's own truncation of site 0 would need the full site; a random
-    remainder of the same structure is used) for a few sketch columns per
-    sector, repeated with more columns until ~budget_s of CPU work."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(row, row_flops, budget_s=20.0, one_thread_s=8.0):
+    """The FP64 oracle as it stands, on a bounded sample of the same unit.
+    The unit's dominant work (over 95% of its flops) is the chain: here the
+    oracle applies M_x at the first interior site (x = 1; a random remainder
+    of the structure the truncation of site 0 gives) to the site's full
+    first-pass sketch (k_J = min(m_J, n_J, ceil(chi m_J / sum m) + p)
+    columns), 4 columns of one sector at a time, until ``budget_s`` of work
+    on every host thread; then one piece on one thread. The rate times the
+    row's algorithmic flops gives the oracle's estimated time for the row."""
     import numpy as np
     import workloads as wl
+    from threadpoolctl import threadpool_limits, threadpool_info
     from workloads.tensor import Leg
     from oracle.blocks import BT
     from oracle.chain import SiteOperator
     from oracle.zipup import SiteProblem
     from oracle.flops import chain_flops
+    from oracle.rsvd import sketch_widths
     x = 1
     rng = np.random.default_rng(0)
     T, A, W = row.T[x], row.A[x], row.W[x]
@@ -251,22 +266,41 @@ def cpu_baseline(row, budget_s=20.0):
     names = ["c", "a", "lk", "lw", "lb"]
     R = BT(names, dict(zip(names, Rt.legs)), Rt.to_dict())
     sp = SiteProblem(SiteOperator(row.sym, R, T, A, W))
-    width, done, flops, secs = 1, False, 0.0, 0.0
-    while not done:
-        k = [width] * len(sp.sect)
-        X = [rng.standard_normal((n, width)) for n in sp.n]
-        t0 = time.perf_counter()
-        sp.apply_m(X)
-        dt = time.perf_counter() - t0
-        flops, secs = float(chain_flops(sp, k)), dt
-        if dt > budget_s / 3 or width >= 64:
-            done = True
-        else:
-            width *= 2
-    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
-    return {"value": flops / secs / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"one product M_x X at site 1 of the same row, {width} column(s) per sector "
-                      f"({len(sp.sect)} sectors), {flops:.3e} flops in {secs:.2f} s"}
+    k = sketch_widths(sp.m, sp.n, row.chi, row.oversample)
+    ncol = 4
+    # tasks: 4 columns of one sector each (sector by sector, largest first)
+    order = sorted(range(len(k)), key=lambda J: -sp.n[J])
+    tasks = [(J, c0) for J in order for c0 in range(0, k[J], ncol)]
+
+    def run_tasks(limit_s, max_tasks):
+        done_flops, secs, count = 0.0, 0.0, 0
+        for J, c0 in tasks:
+            kc = [min(ncol, k[J] - c0) if i == J else 0 for i in range(len(k))]
+            X = [rng.standard_normal((n, w)) for n, w in zip(sp.n, kc)]
+            t0 = time.perf_counter()
+            sp.apply_m(X)
+            secs += time.perf_counter() - t0
+            done_flops += float(chain_flops(sp, kc))
+            count += 1
+            if secs >= limit_s or count >= max_tasks:
+                break
+        return done_flops, secs, count
+
+    threads = max((p.get("num_threads", 1) for p in threadpool_info()), default=1)
+    f_all, s_all, c_all = run_tasks(budget_s, 10 ** 6)
+    with threadpool_limits(limits=1):
+        f_one, s_one, c_one = run_tasks(one_thread_s, 1)
+    rate = f_all / s_all
+    return {"value": rate / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"oracle M_x X at site 1 of the same row with the site's first-pass sketch "
+                      f"widths ({sum(k)} columns over {len(sp.sect)} sectors), {ncol} columns "
+                      f"of one sector at a time, largest sectors first: {c_all} of "
+                      f"{len(tasks)} pieces, {f_all:.3e} flops in {s_all:.1f} s on "
+                      f"{threads} threads",
+            "one_thread": {"value": f_one / s_one / 1e12, "unit": "TFLOP/s",
+                           "sample": f"{c_one} piece, {f_one:.3e} flops in {s_one:.1f} s"},
+            "row_seconds_estimate": row_flops / rate}
 
 
 def main():
@@ -341,7 +375,7 @@ def main():
                   flush=True)
             caps = [(max(256, max(l.nsect for l in t.legs)), max(t.blocks.shape[0], 1),
                      max(t.nelem, 1)) for t in out]
-        r = dict(flops=0.0, dev_s=0.0)
+        r = dict(flops=0.0, dev_s=0.0, alg_bytes=0.0)
         cls = {k: 0.0 for k in ("layer_launches", "layer_seconds", "layer_flops", "layer_bytes",
                                 "gemm_launches", "gemm_seconds", "gemm_flops", "gemm_bytes")}
         torch.cuda.synchronize()
@@ -349,6 +383,7 @@ def main():
         for i in range(a.steps):
             out, lg, rep = ctx.env_absorb(T, A, W, opts, caps=caps)
             r["flops"] += rep["alg_flops"]
+            r["alg_bytes"] += rep["alg_bytes"]
             r["dev_s"] += rep["seconds"]
             print(f"{precision} step {i}: {rep['seconds']:.3f} s device", file=sys.stderr,
                   flush=True)
@@ -405,33 +440,54 @@ def main():
         rep_prec = precs[0]
     R = res[rep_prec]
     cls = R["cls"]
-    # dominant kernel by measured time: the layer-step kernel (HBM bound,
-    # algorithmic bytes = distinct input blocks read once + output written
-    # once) or the environment/remainder GEMM (MFMA bound, 2 m n k flops)
+    # Dominant kernel by measured time, with its ALGORITHMIC work per launch
+    # (the oracle's count: 2 m n k over the block pairs the launch
+    # contracts) over its average launch duration. The layer-step kernel
+    # (ket, PEPO and bra contractions) runs on the FP64 vector ALU (peak
+    # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s); the
+    # environment/remainder kernel on MFMA (FP64 78.6, FP32 157.3 TFLOP/s).
+    # Counter traffic (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated on a
+    # plain copy) is reported beside it and against the path's algorithmic
+    # bytes (T, R, ket and PEPO read once and the output written once per
+    # chain application; the chain intermediates are not algorithmic).
     lay_s, gem_s = cls["layer_seconds"], cls["gemm_seconds"]
-    layer_gbs = cls["layer_bytes"] / lay_s / 1e9 if lay_s > 0 else 0.0
+    nl, ng = max(cls["layer_launches"], 1), max(cls["gemm_launches"], 1)
+    layer_tfs = cls["layer_flops"] / lay_s / 1e12 if lay_s > 0 else 0.0
     gemm_tfs = cls["gemm_flops"] / gem_s / 1e12 if gem_s > 0 else 0.0
+    layer_traffic = profiled_traffic("k_rt_f64", rep_prec)
+    gemm_traffic = profiled_traffic("k_gemm_f64", rep_prec)
+    gemm_peak = PEAK["fp64"]
     if lay_s >= gem_s:
-        nl = max(cls["layer_launches"], 1)
-        roof = {"bound": "hbm", "achieved": layer_gbs, "peak": HBM_PEAK, "unit": "GB/s",
-                "frac": layer_gbs / HBM_PEAK, "traffic": profiled_traffic("k_rt_f64", rep_prec),
-                "kernel": "k_rt_f64 (ket/PEPO/bra layer steps and transposes)",
-                "launches_per_step": cls["layer_launches"],
-                "avg_launch_ms": 1e3 * lay_s / nl,
-                "bytes_per_launch": cls["layer_bytes"] / nl}
+        roof = {"bound": "alu", "achieved": layer_tfs, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                "frac": layer_tfs / PEAK["fp64"], "traffic": layer_traffic,
+                "kernel": "k_rt_f64 (ket/PEPO/bra layer steps and transposes; FP64 vector FMA)",
+                "launches_per_step": cls["layer_launches"], "avg_launch_ms": 1e3 * lay_s / nl,
+                "flops_per_launch": cls["layer_flops"] / nl,
+                "counter_vs_intermediate_bytes": (layer_traffic / (cls["layer_bytes"] / nl))
+                if layer_traffic else None}
     else:
-        ng = max(cls["gemm_launches"], 1)
-        roof = {"bound": "mfma", "achieved": gemm_tfs, "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                "frac": gemm_tfs / PEAK["fp64"], "traffic": profiled_traffic("k_gemm_f64", rep_prec),
-                "kernel": "k_gemm_f64 (environment/remainder contractions)",
-                "launches_per_step": cls["gemm_launches"],
-                "avg_launch_ms": 1e3 * gem_s / ng,
+        roof = {"bound": "mfma", "achieved": gemm_tfs, "peak": gemm_peak, "unit": "TFLOP/s",
+                "frac": gemm_tfs / gemm_peak, "traffic": gemm_traffic,
+                "kernel": "k_gemm (environment/remainder contractions, FP64 MFMA)",
+                "launches_per_step": cls["gemm_launches"], "avg_launch_ms": 1e3 * gem_s / ng,
                 "flops_per_launch": cls["gemm_flops"] / ng}
     roof["kernels"] = {
-        "k_rt_f64": {"seconds_per_step": lay_s, "GB/s": layer_gbs,
-                     "frac_hbm": layer_gbs / HBM_PEAK},
-        "k_gemm_f64": {"seconds_per_step": gem_s, "TFLOP/s": gemm_tfs,
-                       "frac_fp64_mfma": gemm_tfs / PEAK["fp64"]}}
+        "k_rt_f64": {"seconds_per_step": lay_s, "TFLOP/s": layer_tfs,
+                     "frac_fp64_alu": layer_tfs / PEAK["fp64"],
+                     "intermediate_GB/s": cls["layer_bytes"] / lay_s / 1e9 if lay_s > 0 else 0.0,
+                     "counter_bytes_per_launch": layer_traffic},
+        "k_gemm": {"seconds_per_step": gem_s, "TFLOP/s": gemm_tfs,
+                   "frac_fp64_mfma": gemm_tfs / PEAK["fp64"],
+                   "counter_bytes_per_launch": gemm_traffic}}
+    alg_b = R["alg_bytes"] / a.steps
+    counter_step = None
+    if layer_traffic and gemm_traffic:
+        counter_step = layer_traffic * cls["layer_launches"] + gemm_traffic * cls["gemm_launches"]
+    roof["path"] = {"alg_flops_per_step": R["flops"] / a.steps, "alg_bytes_per_step": alg_b,
+                    "row_frac_fp64_peak": R["value"] / PEAK["fp64"],
+                    "counter_bytes_per_step": counter_step,
+                    "counter_over_algorithmic_bytes": (counter_step / alg_b)
+                    if counter_step and alg_b > 0 else None}
     roof["timing"] = ("HIP events around every launch, one extra step of the same row on one "
                       "stream (launches do not overlap); the timed steps spread slices over "
                       "four streams")
@@ -450,7 +506,7 @@ def main():
     if cmp is not None:
         line["mixed_vs_fp64"] = cmp
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(row)
+        line["cpu_baseline"] = cpu_baseline(row, R["flops"] / a.steps)
     print(json.dumps(line), flush=True)
 
 

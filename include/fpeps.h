@@ -21,6 +21,8 @@
  *                        (1 - V^T V), projectors split as in Fig. 5(b)-(g).
  *   fpeps_expect         network value of a top and a bottom environment
  *                        (the sandwich of Fig. 1 once environments exist).
+ *   fpeps_heff_apply     the effective single-site operator of the Davidson
+ *                        step applied to a PEPS tensor (Fig. 2(b)).
  *
  * Conventions (all calls)
  *   - Tensor data is double precision, on the device of the context, owned
@@ -77,7 +79,8 @@ typedef enum {
                          iterations, except its last product, the
                          environment and remainder contractions (chain steps
                          1 and 5 and their transposes) run on FP32 MFMA with
-                         FP32 accumulation from FP32 copies of T and R, and
+                         FP32 accumulation inside each 16-deep K tile (the
+                         tiles summed in FP64) from FP32 copies of T and R, and
                          the chain intermediates (X1..X4 and their
                          transposes) are stored in FP32 (the layer steps
                          read and write FP32 and accumulate in FP64). The
@@ -163,7 +166,8 @@ typedef struct {
   uint32_t fallbacks;      /* bit 0: an orthonormalisation needed more than one shifted
                               CholeskyQR pass (rank-deficient or very ill-conditioned
                               sketch); bit 1: a Jacobi eigen-decomposition stopped at its
-                              40-sweep limit */
+                              40-sweep limit; bit 2: a sketch was exactly rank-deficient
+                              and finished by SVQB (its null directions are zero columns) */
   int32_t required_blocks; /* on FPEPS_ERR_CAPACITY: blocks needed */
   int64_t required_elem;   /* on FPEPS_ERR_CAPACITY: elements needed */
   int32_t required_sect;   /* on FPEPS_ERR_CAPACITY: sectors per leg needed */
@@ -193,6 +197,9 @@ typedef struct {
   int32_t rsvd_passes;
   double workspace_bytes;  /* device workspace the context holds at the end of the call
                               (every buffer; freed by fpeps_destroy or a new allocator) */
+  double alg_bytes;        /* fpeps_env_absorb: algorithmic HBM bytes, every chain
+                              application reading T, R, the ket and the PEPO once and
+                              writing its output once (intermediates not counted) */
 } fpeps_report;
 
 /* Context: one per host thread. ``stream`` is a hipStream_t (NULL: default
@@ -321,6 +328,28 @@ fpeps_status fpeps_cbe_expand_grouped(fpeps_ctx ctx, int32_t nmat, const int64_t
 fpeps_status fpeps_expect(fpeps_ctx ctx, int32_t L, const fpeps_tensor* top,
                           const fpeps_tensor* bottom, double log_norm_top,
                           double log_norm_bottom, int32_t* sign, double* log_abs);
+
+/* The effective single-site operator of the Davidson step applied to a PEPS
+ * tensor (Sec. 3, contraction pattern of Fig. 2(b)):
+ *   y[q, lb, rb, tb, db] = sum T[a, tk, tw, tb, b] L[a, lk, lw, lb, c]
+ *                              B[c, dk, dw, db, d] R[b, rk, rw, rb, d]
+ *                              W[q, p, lw, rw, tw, dw] A[p, lk, rk, tk, dk]
+ * with T the top boundary site, L and R the left and right environments, B
+ * the bottom boundary site (each leg k, w, b' facing the ket, PEPO and bra
+ * legs of the site), W the site's PEPO and A the ket (the Davidson vector).
+ * Evaluated as ((T L) C) (B R), the sandwich C = (A, W) applied layer by
+ * layer; every step is one grouped block-pair GEMM, and for FPEPS_SYM_SU2
+ * each block pair carries the synthetic scalar of its step (11 .. 15) and
+ * blocks, so this association is part of the definition. Inputs are device
+ * tensors in the block layout above; y_out (bra-side legs q, lb, rb, tb, db)
+ * is filled like an absorption output (FPEPS_ERR_CAPACITY and the required
+ * sizes in the report when a capacity is short). FP64 only. The report
+ * gives the algorithmic flops (2 m n k over the block pairs) and the device
+ * time. Synchronises. */
+fpeps_status fpeps_heff_apply(fpeps_ctx ctx, const fpeps_tensor* T, const fpeps_tensor* L,
+                              const fpeps_tensor* B, const fpeps_tensor* R, const fpeps_tensor* W,
+                              const fpeps_tensor* A, const fpeps_opts* opts, fpeps_tensor* y_out,
+                              fpeps_report* report);
 
 #ifdef __cplusplus
 }

@@ -9,5 +9,6 @@ Modules: rng (Philox4x32-10, SplitMix64, Box-Muller), blocks (dict-of-blocks
 contraction), chain (the implicit site operator and its transpose), rsvd
 (randomized SVD, Halko et al. Example 1.6), zipup (row absorption),
 expect (network value), exact (state-vector pins), cbe (controlled bond
-expansion), flops (algorithmic flop count).
+expansion), flops (algorithmic flop count), heff (the effective single-site
+operator of the Davidson step).
 """

@@ -87,6 +87,7 @@ class SiteOperator:
         bra.legs = {n: flip(l) for n, l in bra.legs.items()}
         self.bra = bra
         self.tensors = [self.T, self.ket, self.W, self.bra, self.R]
+        self._alpha_memo = {}
 
     # --- structure of the column space ---------------------------------
     def col_legs(self):
@@ -145,13 +146,27 @@ class SiteOperator:
         return bt
 
     # --- the chain -------------------------------------------------------
+    def _alpha(self, step, xbt, xkey, tbt, tkey):
+        """pair_alpha, remembered per (step, sketch-side block, step-tensor
+        block): it depends only on their sector labels. The sketch-side leg
+        catalogues of a step are the same in every application, except the
+        sketch leg j, whose sector labels are part of the key."""
+        jl = xbt.legs.get("j")
+        jlab = tuple(int(v) for v in jl.labels[xkey[xbt.names.index("j")]]) if jl is not None else ()
+        key = (step, xkey, tkey, jlab)
+        a = self._alpha_memo.get(key)
+        if a is None:
+            a = pair_alpha(self.sym, step, xbt, xkey, tbt, tkey)
+            self._alpha_memo[key] = a
+        return a
+
     def apply(self, Om: BT, symbolic=False):
         X = Om
         for s in range(5):
             S = self.tensors[s]
             X = contract(X, S, ORDERS[s + 1], symbolic=symbolic,
                          alpha=(lambda xk, tk, ok, s=s, X=X, S=S:
-                                pair_alpha(self.sym, s + 1, X, xk, S, tk)))
+                                self._alpha(s + 1, X, xk, S, tk)))
         return X
 
     def apply_t(self, Z: BT, symbolic=False):
@@ -160,7 +175,7 @@ class SiteOperator:
             tmpl = BT(list(ORDERS[s]), {n: self._leg_of(n, Z, S) for n in ORDERS[s]}, {})
             Z = contract(Z, S, ORDERS[s], symbolic=symbolic,
                          alpha=(lambda zk, tk, ok, s=s, S=S, tmpl=tmpl:
-                                pair_alpha(self.sym, s + 1, tmpl, ok, S, tk)))
+                                self._alpha(s + 1, tmpl, ok, S, tk)))
         return Z
 
     @staticmethod

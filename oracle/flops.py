@@ -45,8 +45,14 @@ def pass_flops(sp, kvec, q):
     return f
 
 
-def site_flops(sp, passes, q):
-    """``passes``: [(k, kept)] of every factorisation of the site."""
+def site_flops(sp, passes, q, cbe_passes=(), cbe_kept=None):
+    """``passes``: [(k, kept)] of every factorisation of the site;
+    ``cbe_passes`` those of its bond expansion (``cbe_kept`` directions
+    added). An expansion pass applies M and M^T once each with the projector
+    splits around them (4 c k (m + n) per application, c the truncation's
+    kept count), orthonormalises once and factorises; then Q = Q_s U~
+    (2 m k e) and the expansion's remainder rows M^T Q (mirrored chain at
+    widths e)."""
     f = 0.0
     for kvec, _ in passes:
         f += pass_flops(sp, kvec, q)
@@ -54,6 +60,19 @@ def site_flops(sp, passes, q):
     for m, n, k, c in zip(sp.m, sp.n, kvec, kept):
         if k > 0:
             f += 2 * m * k * c + 2 * k * c * n
+    for kc, _ in cbe_passes:
+        f += chain_flops(sp, kc) + chain_flops_t(sp, kc)
+        for m, n, k, c in zip(sp.m, sp.n, kc, kept):
+            if k > 0:
+                f += 8.0 * c * k * (m + n)
+                f += 2 * m * k * k - 2 * k ** 3 / 3.0
+                f += 2 * n * k * k + 11 * k ** 3
+    if cbe_passes:
+        kc = cbe_passes[-1][0]
+        f += chain_flops_t(sp, cbe_kept)
+        for m, k, e in zip(sp.m, kc, cbe_kept):
+            if k > 0:
+                f += 2.0 * m * k * e
     return f
 
 
@@ -61,7 +80,8 @@ def row_flops(record, info, q):
     """``record``/``info`` as filled by zipup.absorb_row(record=[...])."""
     total = 0.0
     for r in record:
-        total += site_flops(r["sp"], r["passes"], q)
+        total += site_flops(r["sp"], r["passes"], q, r.get("cbe_passes") or (),
+                            r.get("cbe_kept"))
     return total
 
 

@@ -59,16 +59,39 @@ def _assemble(bt, keys, width):
     return np.vstack([bt.blocks[k].reshape(-1, width) for k in keys])
 
 
+_WORKER_SP = None
+
+
+def _sector_task(args):
+    """Worker side of SiteProblem.workers: one sector, one direction."""
+    transpose, J, mat = args
+    sp = _WORKER_SP
+    widths = [0] * len(sp.sect)
+    widths[J] = mat.shape[1]
+    rows = sp.n if not transpose else sp.m
+    mats = [mat if i == J else np.zeros((rows[i], 0)) for i in range(len(sp.sect))]
+    fn = sp._apply_mt if transpose else sp._apply_m
+    out_rows = sp.m if not transpose else sp.n
+    return J, sp._chunked(fn, mats, out_rows)[J]
+
+
 class SiteProblem:
     """Glue between SiteOperator (block tensors) and per-sector matrices.
 
     ``max_cols`` (optional) applies the operator to at most that many columns
     of every sector at a time: the operator acts on each column on its own,
-    so this only bounds the memory of the intermediates."""
+    so this only bounds the memory of the intermediates. ``workers`` > 1
+    evaluates the sectors in that many forked processes: M is block
+    diagonal over the sectors (sector J's columns reach only sector J's
+    rows), and a sector's blocks are summed in the same order whether or not
+    the other sectors are present, so the result is the same to the bit.
+    Call close() to end the workers."""
 
-    def __init__(self, op: SiteOperator, max_cols=None):
+    def __init__(self, op: SiteOperator, max_cols=None, workers=1):
         self.op = op
         self.max_cols = max_cols
+        self.workers = workers
+        self._pool = None
         self.sect = op.sectors()
         legs = op.col_legs()
         self.col_dims = [[op.col_dim(t) for t in tup] for _, tup in self.sect]
@@ -132,10 +155,35 @@ class SiteProblem:
                 for t in tuples}
 
     def apply_m(self, mats):
+        if self.workers > 1:
+            return self._parallel(False, mats)
         return self._chunked(self._apply_m, mats, self.m)
 
     def apply_mt(self, mats):
+        if self.workers > 1:
+            return self._parallel(True, mats)
         return self._chunked(self._apply_mt, mats, self.n)
+
+    def _parallel(self, transpose, mats):
+        global _WORKER_SP
+        if self._pool is None:
+            import multiprocessing as mp
+            _WORKER_SP = self
+            self._pool = mp.get_context("fork").Pool(self.workers)
+        rows_out = self.n if transpose else self.m
+        out = [np.zeros((rows_out[i], m.shape[1])) for i, m in enumerate(mats)]
+        # largest sectors first (their chains take longest)
+        todo = sorted((J for J, m in enumerate(mats) if m.shape[1] > 0 and rows_out[J] > 0),
+                      key=lambda J: -(self.n[J] + self.m[J]) * mats[J].shape[1])
+        for J, y in self._pool.imap_unordered(_sector_task, [(transpose, J, mats[J]) for J in todo]):
+            out[J] = y
+        return out
+
+    def close(self):
+        if self._pool is not None:
+            self._pool.close()
+            self._pool.join()
+            self._pool = None
 
     def _apply_m(self, mats):
         Y = self.op.apply(self.omega_from_mats(mats))
@@ -199,8 +247,46 @@ def _remainder(sp: SiteProblem, R_mats, kept, labels, sel):
     return bt
 
 
+def cbe_site(sp, Umats, Rmats, sig, kept, cbe_extra, p, seed, x, row, labels, sv_cut=None):
+    """Controlled bond expansion of one truncated site (Sec. 4, Figs. 3-5):
+    with kept left space U (the new environment site) and kept right space
+    V (the rows of R = U^T M divided by their singular values), the
+    ``cbe_extra`` most weighty directions of the discarded part
+    (1 - U U^T) M (1 - V^T V), one cut over all sectors. The projectors are
+    split as in Fig. 5 and applied to the sketch first (fold):
+    Z = M (Om - V^T (V Om)), Y = Z - U (U^T Z); one application (q = 0);
+    sketch widths by the rule of ``rsvd`` on the residual's dimensions
+    (m_J - kept_J) x (n_J - kept_J); sketch stream 1. Returns the expansion
+    Q_J (sign-fixed) with its remainder rows Q_J^T M_J, the counts and the
+    passes."""
+    V = [r / s[:c][:, None] if c > 0 else r for r, s, c in zip(Rmats, sig, kept)]
+
+    def am(X):
+        Z = sp.apply_m([x_ - v.T @ (v @ x_) for x_, v in zip(X, V)])
+        return [z - u @ (u.T @ z) for z, u in zip(Z, Umats)]
+
+    def amt(Y):
+        Z = sp.apply_mt([y - u @ (u.T @ y) for y, u in zip(Y, Umats)])
+        return [z - v.T @ (v @ z) for z, v in zip(Z, V)]
+
+    def omegas(kv):
+        oms = sketch_arrays(sp.sect, kv, sp.col_dims, seed, 0, x, row, 1)
+        return [np.vstack(o) if len(o) else np.zeros((0, kv[i])) for i, o in enumerate(oms)]
+
+    mr = [mj - c for mj, c in zip(sp.m, kept)]
+    nr = [nj - c for nj, c in zip(sp.n, kept)]
+    r = rsvd_adaptive(am, amt, mr, nr, cbe_extra, p, 0, omegas, labels, None, sv_cut)
+    e = r["kept"]
+    Qc = [r["Q"][J] @ r["Ut"][J][:, :e[J]] for J in range(len(e))]
+    Qc = [fix_signs(qc, np.zeros((qc.shape[1], 0)))[0] for qc in Qc]
+    # the remainder rows of the expansion: Q^T M (not projected)
+    Rc = [z.T for z in sp.apply_mt(Qc)]
+    return Qc, Rc, e, r["passes"], r["k"]
+
+
 def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0.0,
-               bra=None, record=None, max_cols=None, progress=None, sv_cut=None):
+               bra=None, record=None, max_cols=None, progress=None, sv_cut=None, workers=1,
+               cbe_extra=0):
     """Absorb one row (ket A[x], PEPO W[x]) into the top environment T[x].
 
     Returns (new environment sites, log_norm, info). With ``exact_svd`` the
@@ -216,7 +302,7 @@ def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0
     prev_kept = None
     for x in range(L):
         op = SiteOperator(sym, R, T[x], A[x], W[x], bra=None if bra is None else bra[x])
-        sp = SiteProblem(op, max_cols)
+        sp = SiteProblem(op, max_cols, workers)
         if progress:
             progress(f"site {x}: sectors {len(sp.sect)} m {sum(sp.m)} n {sum(sp.n)}")
         labels = [J for J, _ in sp.sect]
@@ -226,6 +312,7 @@ def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0
             mats = [np.zeros((nn, 0)) for nn in sp.n]
             mats[ji] = np.ones((1, 1))
             Y = sp.apply_m(mats)
+            sp.close()
             nu = math.sqrt(sum(float(np.sum(y * y)) for y in Y))
             kept = [m.shape[1] for m in Y]
             site, _ = _env_site(sp, [y / nu for y in Y], kept, labels)
@@ -266,6 +353,16 @@ def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0
         fixed = [fix_signs(u, r) for u, r in zip(Umats, Rmats)]
         Umats = [f[0] for f in fixed]
         Rmats = [f[1] for f in fixed]
+        cbe_passes, cbe_k, cbe_e = [], None, [0] * len(kept)
+        if cbe_extra > 0 and not exact_svd:
+            Qc, Rc, cbe_e, cbe_passes, cbe_k = cbe_site(sp, Umats, Rmats, S_, kept, cbe_extra, p,
+                                                        seed, x, row, labels, sv_cut)
+            Umats = [np.hstack([u, qc]) for u, qc in zip(Umats, Qc)]
+            Rmats = [np.vstack([r_, rc]) for r_, rc in zip(Rmats, Rc)]
+            kept = [c + e for c, e in zip(kept, cbe_e)]
+            prev_kept = {tuple(J): c for J, c in zip(labels, kept)}
+        info.setdefault("cbe", []).append(dict(kept=list(cbe_e), passes=cbe_passes))
+        sp.close()
         site, sel = _env_site(sp, Umats, kept, labels)
         env.append(site)
         R = _remainder(sp, Rmats, kept, labels, sel)
@@ -277,5 +374,6 @@ def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0
             info[key].append(val)
         if record is not None:
             record.append(dict(x=x, sp=sp, kvec=kvec,
-                               passes=info["passes"][-1] if not exact_svd else [(kvec, kept)]))
+                               passes=info["passes"][-1] if not exact_svd else [(kvec, kept)],
+                               cbe_passes=cbe_passes, cbe_kept=list(cbe_e)))
     return env, log_norm, info

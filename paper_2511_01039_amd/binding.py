@@ -66,7 +66,7 @@ class CReport(C.Structure):
                 ("gemm_launches", C.c_int32), ("gemm_seconds", C.c_double),
                 ("gemm_flops", C.c_double), ("gemm_bytes", C.c_double),
                 ("plan_reuses", C.c_int32), ("rsvd_passes", C.c_int32),
-                ("workspace_bytes", C.c_double)]
+                ("workspace_bytes", C.c_double), ("alg_bytes", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -125,6 +125,7 @@ def load():
         "fpeps_expect": ([C.c_void_p, C.c_int32, T, T, C.c_double, C.c_double, P(C.c_int32),
                           P(C.c_double)], C.c_int),
         "fpeps_set_allocator": ([C.c_void_p, ALLOC_FN, FREE_FN, C.c_void_p], C.c_int),
+        "fpeps_heff_apply": ([C.c_void_p, T, T, T, T, T, T, P(COpts), T, P(CReport)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -138,7 +139,8 @@ def exported_symbols():
     return ["fpeps_version", "fpeps_create", "fpeps_destroy", "fpeps_set_stream",
             "fpeps_last_error", "fpeps_set_allocator", "fpeps_env_absorb", "fpeps_absorb_diag", "fpeps_site_shape",
             "fpeps_site_apply", "fpeps_rsvd_truncate", "fpeps_rsvd_truncate_grouped",
-            "fpeps_cbe_expand", "fpeps_cbe_expand_grouped", "fpeps_expect"]
+            "fpeps_cbe_expand", "fpeps_cbe_expand_grouped", "fpeps_expect",
+            "fpeps_heff_apply"]
 
 
 def _i32(a):
@@ -453,6 +455,25 @@ class Context:
         self.check(self.lib.fpeps_expect(self.h, L, ta, ba, C.c_double(log_norm_top),
                                          C.c_double(log_norm_bottom), C.byref(sg), C.byref(la)))
         return int(sg.value), float(la.value)
+
+    def heff_apply(self, T, L, B, R, W, A, opts, caps=None):
+        """y = H_eff A (Fig. 2(b)); returns (DeviceTensor y, report)."""
+        keep = []
+        cts = [t.ctensor(keep) for t in (T, L, B, R, W, A)]
+        nlab = cts[0].nlab
+        caps = caps or (256, 1 << 16, max(1, int(A.nelem) * 64))
+        for attempt in range(2):
+            out = OutTensor(5, nlab, *caps)
+            rep = CReport()
+            rc = self.lib.fpeps_heff_apply(self.h, *[C.byref(c) for c in cts], C.byref(opts),
+                                           C.byref(out.ct), C.byref(rep))
+            if rc == -7 and attempt == 0:
+                caps = (max(caps[0], rep.required_sect), max(caps[1], rep.required_blocks),
+                        max(caps[2], rep.required_elem))
+                continue
+            self.check(rc)
+            return out.result(), rep.as_dict()
+        raise FpepsError(-7, "capacity")
 
     def expect(self, top, bottom):
         """The same as a plain float (no log-norms applied)."""

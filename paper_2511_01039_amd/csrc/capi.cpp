@@ -241,4 +241,14 @@ fpeps_status fpeps_expect(fpeps_ctx ctx, int32_t L, const fpeps_tensor* top,
   });
 }
 
+fpeps_status fpeps_heff_apply(fpeps_ctx ctx, const fpeps_tensor* T, const fpeps_tensor* L,
+                              const fpeps_tensor* B, const fpeps_tensor* R, const fpeps_tensor* W,
+                              const fpeps_tensor* A, const fpeps_opts* opts, fpeps_tensor* y_out,
+                              fpeps_report* report) {
+  return guarded(ctx, [&] {
+    if (report) std::memset(report, 0, sizeof(*report));
+    return fp::heff_apply(ctx, T, L, B, R, W, A, opts, y_out, report);
+  });
+}
+
 }  // extern "C"

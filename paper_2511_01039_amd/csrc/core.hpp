@@ -54,6 +54,7 @@ struct SiteDiag {
   std::vector<int32_t> kept;     // per sector
   std::vector<int64_t> m, n;
   std::vector<int32_t> k;
+  std::vector<int32_t> cbe;      // bond expansion per sector (empty: none)
 };
 
 }  // namespace fp
@@ -208,7 +209,8 @@ Status run_gemm(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A, i
 Status run_gemm_mixed(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A,
                       int64_t a_size, const void* B, bool b_f32, int64_t b_size, void* C,
                       bool c_f32, int64_t c_size, bool timed = false, int label = 0);
-// The same on FP32 MFMA with FP32 accumulation: A an FP32 copy, B and C in
+// The same on FP32 MFMA (FP32 accumulation per 16-deep K tile, tiles summed in
+// FP64): A an FP32 copy, B and C in
 // FP32 or FP64
 Status run_gemm_f32(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const float* A, int64_t a_size,
                     const void* B, bool b_f32, int64_t b_size, void* C, bool c_f32, int64_t c_size,

@@ -170,10 +170,15 @@ Status orth(fpeps_ctx_s* ctx, DensePlans& dp, int side, const Layout& L, double*
   // passes. A plain pass whose Cholesky breaks down (a rank-deficient
   // sketch: its null directions are still at rounding level after the
   // shifted pass) is replaced by one more shifted pass, which lifts the
-  // smallest directions by a factor of about 1/sqrt(shift) each time, until
-  // a plain pass succeeds. Null directions become an arbitrary orthonormal
-  // completion (as with Householder QR); small but genuine directions keep
-  // their share of the range.
+  // smallest directions by a factor of about 1/sqrt(shift) each time; null
+  // directions at rounding level become an arbitrary orthonormal completion
+  // (as with Householder QR) and small but genuine directions keep their
+  // share of the range. A sketch that is rank-deficient exactly (an operator
+  // block with fewer nonzero rows than sketch columns: no shift can lift
+  // what is structurally zero) still breaks down after three shifted
+  // passes; by then every genuine direction is of order one, and two SVQB
+  // passes (Stathopoulos & Wu) finish it, turning the exact null directions
+  // (Gram eigenvalues below 1e-8 of the largest) into zero columns.
   auto pass = [&](bool shifted) -> Status {
     FP_TRY(run_gemm(ctx, dp.ps, dp.gram[side], Y, L.total, Y, L.total, part,
                     std::max<int64_t>(dp.part_total[side], 1)));
@@ -188,6 +193,7 @@ Status orth(fpeps_ctx_s* ctx, DensePlans& dp, int side, const Layout& L, double*
     return Status::ok();
   };
   int nshift = 1;
+  bool svqb = false;
   FP_TRY(pass(true));
   FP_TRY(apply_r());
   for (;;) {
@@ -197,12 +203,29 @@ Status orth(fpeps_ctx_s* ctx, DensePlans& dp, int side, const Layout& L, double*
     FP_HIP(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     FP_TRY(ctx->sync());
     if (!(hs & 1)) break;
-    if (nshift >= 6)
-      return fail(FPEPS_ERR_NUMERIC, "orthonormalisation: Cholesky breakdown after 6 shifted passes");
     *fallbacks |= 1u;
+    if (nshift >= 3) {
+      svqb = true;
+      break;
+    }
     FP_TRY(pass(true));   // the failed factorisation overwrote the Gram matrix
     FP_TRY(apply_r());
     ++nshift;
+  }
+  if (svqb) {
+    *fallbacks |= 4u;
+    for (int sp = 0; sp < 2; ++sp) {
+      FP_TRY(run_gemm(ctx, dp.ps, dp.gram[side], Y, L.total, Y, L.total, part,
+                      std::max<int64_t>(dp.part_total[side], 1)));
+      FP_HIP(launch_reduce_partials(dred, (int)dp.red[side].size(), dp.max_red_mn, small, part,
+                                    ctx->stream));
+      FP_HIP(launch_jacobi_eig(dch1, (int)ch.size(), dp.max_k, small, status, ctx->stream, false));
+      FP_HIP(launch_svqb_scale(dch1, (int)ch.size(), small, 1e-8, ctx->stream));
+      FP_TRY(apply_r());
+    }
+    FP_TRY(ctx->sync());
+    *Qout = Y;
+    return Status::ok();
   }
   FP_TRY(apply_r());
   FP_HIP(launch_fill_int(status, (int64_t)L.k.size() + 2, 0, ctx->stream));
@@ -441,6 +464,13 @@ Status rsvd_run(fpeps_ctx_s* ctx, RsvdIO& io, int chi, int p, int q, uint64_t se
     fb |= out.fallbacks;
     out.pass_k.push_back(out.k);
     out.pass_kept.push_back(out.kept);
+    if (ctx->verbose) {
+      std::fprintf(stderr, "[fpeps] rsvd pass %zu: widths", out.pass_k.size());
+      for (int v : out.k) std::fprintf(stderr, " %d", v);
+      std::fprintf(stderr, " | kept");
+      for (int v : out.kept) std::fprintf(stderr, " %d", v);
+      std::fprintf(stderr, "\n");
+    }
     bool any = false;
     for (int J = 0; J < ns; ++J) {
       const int64_t cover = std::min(wm[J], wn[J]);
@@ -589,6 +619,199 @@ Status write_structure(const std::vector<LegP>& legs, const std::vector<int>& di
 
 }  // namespace
 
+namespace {
+
+// Bond expansion of one truncated site (Sec. 4, Figs. 3-5). With the kept
+// left space U (m_J x c_J per sector, row stride c_J) and R = U^T M
+// (c_J x n_J), the kept right space is V = diag(1/sigma) R. The randomized
+// SVD of the discarded part (1 - U U^T) M (1 - V^T V) runs through the
+// site's own chain, the projectors split as in Fig. 5 and applied around
+// each application (the sketch is folded first: M (Om - V^T (V Om)), then
+// Y - U (U^T Y)); one application (q = 0), widths from the residual's
+// dimensions (m_J - c_J, n_J - c_J), sketch stream 1, one cut of
+// ``cbe_extra`` directions over the sectors. Returns Q (m_J x e_J, row
+// stride e_J, canonical signs) and Z = M^T Q (n_J x e_J), whose transpose
+// are the expansion's remainder rows.
+struct CbeResult {
+  std::vector<int32_t> e;
+  double* Q = nullptr;
+  double* Z = nullptr;
+  std::vector<int64_t> qoff, zoff;
+  std::vector<std::vector<int32_t>> pass_k;
+  std::vector<std::array<double, 2>> pass_fl;   // chain flops of each pass's plans
+  double rem_flops = 0;                         // M^T Q
+  uint32_t fallbacks = 0;
+};
+
+Status cbe_site(fpeps_ctx_s* ctx, SiteOp& op, const RsvdOut& rs, const double* U,
+                const std::vector<int64_t>& uoff, int64_t u_total, const double* R,
+                const std::vector<int64_t>& roff, int64_t r_total, const fpeps_opts* o, int x,
+                int64_t budget, CbeResult& out) {
+  const int ns = (int)op.sect.size();
+  const std::vector<int32_t>& c = rs.kept;
+  // V = diag(1/sigma) R
+  std::vector<double> sc;
+  std::vector<SectDesc> vd;
+  std::vector<int64_t> voff(ns, 0);
+  int64_t vt = 0, maxe = 0;
+  for (int J = 0; J < ns; ++J) {
+    voff[J] = vt;
+    if (c[J] <= 0) continue;
+    SectDesc g{};
+    g.off_a = roff[J];
+    g.off_out = vt;
+    g.rows = c[J];
+    g.cols = (int32_t)op.sect[J].n;
+    g.s0 = (int32_t)sc.size();
+    for (int i = 0; i < c[J]; ++i) {
+      const double l = rs.lam[rs.lam_off[J] + i];
+      sc.push_back(l > 0 ? 1.0 / std::sqrt(l) : 0.0);
+    }
+    vd.push_back(g);
+    vt += (int64_t)c[J] * op.sect[J].n;
+    maxe = std::max<int64_t>(maxe, (int64_t)c[J] * op.sect[J].n);
+  }
+  double* V = nullptr;
+  FP_TRY(ctx->bufT("cbe_V", (size_t)std::max<int64_t>(vt, 1), &V));
+  if (!vd.empty()) {
+    SectDesc* dvd = nullptr;
+    double* dsc = nullptr;
+    FP_TRY(ctx->upload("cbe_vd", vd.data(), vd.size() * sizeof(SectDesc), (void**)&dvd));
+    FP_TRY(ctx->upload("cbe_sc", sc.data(), sc.size() * sizeof(double), (void**)&dsc));
+    FP_HIP(launch_row_scale(dvd, (int)vd.size(), maxe, R, V, dsc, ctx->stream));
+  }
+  RsvdIO io;
+  for (int J = 0; J < ns; ++J) {
+    io.m.push_back(op.sect[J].m);
+    io.n.push_back(op.sect[J].n);
+    io.width_m.push_back(op.sect[J].m - c[J]);
+    io.width_n.push_back(op.sect[J].n - c[J]);
+    io.c1.push_back((uint32_t)J);
+  }
+  io.c2 = (uint32_t)x;
+  io.c3 = (uint32_t)(o->row & 0xFFFF) | (1u << 16);
+  std::shared_ptr<SiteOp::Plans> plp;
+  PlanSet pj;
+  int pv1 = -1, pv2 = -1, pu1 = -1, pu2 = -1;
+  int64_t s_total = 0;
+  io.prepare = [&](const std::vector<int32_t>& k) -> Status {
+    if (plp) out.pass_fl.push_back({plp->flops_fwd, plp->flops_bwd});
+    plp = std::make_shared<SiteOp::Plans>();
+    FP_TRY(op.plan_host(k, budget, *plp, true, false));
+    FP_TRY(op.upload(ctx, *plp));
+    std::vector<DenseOp> v1, v2, u1, u2;
+    s_total = 0;
+    for (int J = 0; J < ns; ++J) {
+      const int64_t soff = s_total;
+      if (k[J] <= 0 || c[J] <= 0) continue;
+      s_total += (int64_t)c[J] * k[J];
+      const int32_t m = (int32_t)op.sect[J].m, n = (int32_t)op.sect[J].n;
+      DenseOp d{};
+      d.alpha = 1.0;
+      // s = V x  (c x k), x: n x k in the column layout
+      d.a_off = voff[J]; d.a_rs = n; d.a_cs = 1;
+      d.b_off = plp->col_off[J]; d.b_rs = k[J]; d.b_cs = 1;
+      d.c_off = soff; d.c_rs = k[J]; d.c_cs = 1;
+      d.M = c[J]; d.N = k[J]; d.K = n;
+      v1.push_back(d);
+      // tmp = -V^T s  (n x k)
+      DenseOp e{};
+      e.alpha = -1.0;
+      e.a_off = voff[J]; e.a_rs = 1; e.a_cs = n;
+      e.b_off = soff; e.b_rs = k[J]; e.b_cs = 1;
+      e.c_off = plp->col_off[J]; e.c_rs = k[J]; e.c_cs = 1;
+      e.M = n; e.N = k[J]; e.K = c[J];
+      v2.push_back(e);
+      // s = U^T y  (c x k), y: m x k in the row layout
+      DenseOp f{};
+      f.alpha = 1.0;
+      f.a_off = uoff[J]; f.a_rs = 1; f.a_cs = c[J];
+      f.b_off = plp->row_off[J]; f.b_rs = k[J]; f.b_cs = 1;
+      f.c_off = soff; f.c_rs = k[J]; f.c_cs = 1;
+      f.M = c[J]; f.N = k[J]; f.K = m;
+      u1.push_back(f);
+      // tmp = -U s  (m x k)
+      DenseOp g{};
+      g.alpha = -1.0;
+      g.a_off = uoff[J]; g.a_rs = c[J]; g.a_cs = 1;
+      g.b_off = soff; g.b_rs = k[J]; g.b_cs = 1;
+      g.c_off = plp->row_off[J]; g.c_rs = k[J]; g.c_cs = 1;
+      g.M = m; g.N = k[J]; g.K = c[J];
+      u2.push_back(g);
+    }
+    pj = PlanSet();
+    std::string err;
+    GemmPlan a, b, cc, dd;
+    if (!plan_dense(v1, pj.pool, 64, 64, 1, a, err)) return fail(FPEPS_ERR_SHAPE, err);
+    if (!plan_dense(v2, pj.pool, 64, 64, 1, b, err)) return fail(FPEPS_ERR_SHAPE, err);
+    if (!plan_dense(u1, pj.pool, 64, 64, 1, cc, err)) return fail(FPEPS_ERR_SHAPE, err);
+    if (!plan_dense(u2, pj.pool, 64, 64, 1, dd, err)) return fail(FPEPS_ERR_SHAPE, err);
+    pv1 = pj.add(std::move(a));
+    pv2 = pj.add(std::move(b));
+    pu1 = pj.add(std::move(cc));
+    pu2 = pj.add(std::move(dd));
+    return pj.upload(ctx, "cbe_proj");
+  };
+  // x <- x - V^T (V x) (column side) or x - U (U^T x) (row side), in place
+  auto project = [&](bool row_side, double* xv, int64_t xtotal) -> Status {
+    double *sb = nullptr, *tmp = nullptr;
+    FP_TRY(ctx->bufT("cbe_s", (size_t)std::max<int64_t>(s_total, 1), &sb));
+    FP_TRY(ctx->bufT("cbe_tmp", (size_t)std::max<int64_t>(xtotal, 1), &tmp));
+    // sectors without kept directions have no projection product: their
+    // part of tmp must add zero
+    FP_HIP(launch_fill(tmp, xtotal, 0.0, ctx->stream));
+    const int64_t st = std::max<int64_t>(s_total, 1);
+    if (!row_side) {
+      FP_TRY(run_gemm(ctx, pj, pv1, V, std::max<int64_t>(vt, 1), xv, xtotal, sb, st));
+      FP_TRY(run_gemm(ctx, pj, pv2, V, std::max<int64_t>(vt, 1), sb, st, tmp, xtotal));
+    } else {
+      FP_TRY(run_gemm(ctx, pj, pu1, U, u_total, xv, xtotal, sb, st));
+      FP_TRY(run_gemm(ctx, pj, pu2, U, u_total, sb, st, tmp, xtotal));
+    }
+    return axpy_inplace(ctx, xv, tmp, xtotal);
+  };
+  io.apply = [&](bool t, bool, const double* xi, double* yo) -> Status {
+    double* xc = const_cast<double*>(xi);
+    if (!t) {
+      FP_TRY(project(false, xc, plp->col_total));
+      FP_TRY(op.apply(ctx, *plp, false, xc, yo, false));
+      FP_TRY(project(true, yo, plp->row_total));
+    } else {
+      FP_TRY(project(true, xc, plp->row_total));
+      FP_TRY(op.apply(ctx, *plp, true, xc, yo, false));
+      FP_TRY(project(false, yo, plp->col_total));
+    }
+    return Status::ok();
+  };
+  RsvdOut rc;
+  FP_TRY(rsvd_run(ctx, io, o->cbe_extra, o->oversample, 0, o->seed, rc, o->sv_cut));
+  out.pass_fl.push_back({plp->flops_fwd, plp->flops_bwd});
+  out.pass_k = rc.pass_k;
+  out.e = rc.kept;
+  out.fallbacks = rc.fallbacks;
+  // Q = Q_sketch U~[:, :e] (canonical signs), then Z = M^T Q
+  out.qoff.assign(ns, 0);
+  int64_t qt = 0;
+  for (int J = 0; J < ns; ++J) {
+    out.qoff[J] = qt;
+    qt += op.sect[J].m * (int64_t)out.e[J];
+  }
+  FP_TRY(ctx->bufT("cbe_Q", (size_t)std::max<int64_t>(qt, 1), &out.Q));
+  FP_TRY(rsvd_factors(ctx, io, rc, out.qoff, out.Q, std::max<int64_t>(qt, 1), {}, nullptr, 0));
+  SiteOp::Plans pe;
+  FP_TRY(op.plan_host(out.e, budget, pe, true, false));
+  FP_TRY(op.upload(ctx, pe));
+  for (int J = 0; J < ns; ++J)
+    if (pe.row_off[J] != out.qoff[J]) return fail(FPEPS_ERR_SHAPE, "expansion layout mismatch");
+  out.zoff = pe.col_off;
+  out.rem_flops = pe.flops_bwd;
+  FP_TRY(ctx->bufT("cbe_Z", (size_t)std::max<int64_t>(pe.col_total, 1), &out.Z));
+  FP_TRY(op.apply(ctx, pe, true, out.Q, out.Z, false));
+  return Status::ok();
+}
+
+}  // namespace
+
 Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpeps_tensor* ket,
                   const fpeps_tensor* pepo, const fpeps_opts* o, fpeps_tensor* env_out,
                   double* log_norm, fpeps_report* rep) {
@@ -597,8 +820,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
   if (o->precision != FPEPS_FP64 && o->precision != FPEPS_FP32)
     return fail(FPEPS_ERR_UNSUPPORTED, "precision: FPEPS_FP64 or FPEPS_FP32");
   const bool f32 = o->precision == FPEPS_FP32;
-  if (o->cbe_extra != 0)
-    return fail(FPEPS_ERR_UNSUPPORTED, "bond expansion inside the absorption is not available");
+  if (o->cbe_extra < 0) return fail(FPEPS_ERR_ARG, "cbe_extra >= 0 required");
   if (o->chi < 1 || o->oversample < 0 || o->power_iters < 0)
     return fail(FPEPS_ERR_ARG, "chi >= 1, oversample >= 0, power_iters >= 0 required");
   SymInfo sym;
@@ -633,7 +855,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
   FP_HIP(evp.create());
   hipEvent_t ev0 = evp.a, ev1 = evp.b;
   FP_HIP(hipEventRecord(ev0, ctx->stream));
-  double lg = 0.0, flops = 0.0, disc = 0.0, gap = INFINITY;
+  double lg = 0.0, flops = 0.0, alg_bytes = 0.0, disc = 0.0, gap = INFINITY;
   int kept_total = 0;
   uint32_t fallbacks = 0;
   bool cap_fail = false;
@@ -961,43 +1183,99 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
                      mts / std::max(nplan, 1.0), nts / std::max(nplan, 1.0));
       }
     }
-    // outputs: environment site (U) and the next remainder (R)
+    // outputs: environment site (U) and the next remainder (R); with bond
+    // expansion [U | Q] and [R ; Q^T M]
+    std::vector<int32_t> kept = rs.kept;
+    std::vector<int64_t> uoff(ns, 0), roff(ns, 0);
+    int64_t ut = 0, rt = 0;
+    auto offsets = [&](const std::vector<int32_t>& kk, std::vector<int64_t>& uo,
+                       std::vector<int64_t>& ro, int64_t& u_t, int64_t& r_t) {
+      u_t = r_t = 0;
+      for (int J = 0; J < ns; ++J) {
+        uo[J] = u_t;
+        ro[J] = r_t;
+        u_t += op.sect[J].m * (int64_t)kk[J];
+        r_t += op.sect[J].n * (int64_t)kk[J];
+      }
+    };
+    const int rn = 1 - rcur;
+    double* ubuf = nullptr;
+    CbeResult cb;
+    if (o->cbe_extra > 0) {
+      std::vector<int64_t> uo0(ns), ro0(ns);
+      int64_t ut0 = 0, rt0 = 0;
+      offsets(rs.kept, uo0, ro0, ut0, rt0);
+      double *u0 = nullptr, *r0 = nullptr;
+      FP_TRY(ctx->bufT("U_trunc", (size_t)std::max<int64_t>(ut0, 1), &u0));
+      FP_TRY(ctx->bufT("R_trunc", (size_t)std::max<int64_t>(rt0, 1), &r0));
+      FP_TRY(rsvd_factors(ctx, io, rs, uo0, u0, std::max<int64_t>(ut0, 1), ro0, r0,
+                          std::max<int64_t>(rt0, 1)));
+      FP_TRY(cbe_site(ctx, op, rs, u0, uo0, std::max<int64_t>(ut0, 1), r0, ro0,
+                      std::max<int64_t>(rt0, 1), o, x, budget, cb));
+      fallbacks |= cb.fallbacks;
+      for (int J = 0; J < ns; ++J) kept[J] += cb.e[J];
+      offsets(kept, uoff, roff, ut, rt);
+      FP_TRY(ctx->bufT(rn == 0 ? "R_a" : "R_b", (size_t)std::max<int64_t>(rt, 1), &Rbuf[rn]));
+      FP_TRY(ctx->bufT("U_site", (size_t)std::max<int64_t>(ut, 1), &ubuf));
+      std::vector<SectDesc> mu, mr;
+      int64_t mue = 0, mre = 0;
+      for (int J = 0; J < ns; ++J) {
+        if (kept[J] <= 0) continue;
+        SectDesc a{};
+        a.off_a = uo0[J];
+        a.off_b = cb.qoff[J];
+        a.off_out = uoff[J];
+        a.rows = (int32_t)op.sect[J].m;
+        a.cols = rs.kept[J];
+        a.cols_b = cb.e[J];
+        mu.push_back(a);
+        mue = std::max<int64_t>(mue, op.sect[J].m * (int64_t)kept[J]);
+        SectDesc b{};
+        b.off_a = ro0[J];
+        b.off_b = cb.zoff[J];
+        b.off_out = roff[J];
+        b.rows = rs.kept[J];
+        b.cols = (int32_t)op.sect[J].n;
+        b.cols_b = cb.e[J];
+        mr.push_back(b);
+        mre = std::max<int64_t>(mre, op.sect[J].n * (int64_t)kept[J]);
+      }
+      SectDesc *dmu = nullptr, *dmr = nullptr;
+      FP_TRY(ctx->upload("cbe_mu", mu.data(), mu.size() * sizeof(SectDesc), (void**)&dmu));
+      FP_TRY(ctx->upload("cbe_mr", mr.data(), mr.size() * sizeof(SectDesc), (void**)&dmr));
+      FP_HIP(launch_merge_cols(dmu, (int)mu.size(), mue, u0, cb.Q, ubuf, ctx->stream));
+      FP_HIP(launch_stack_rows_t(dmr, (int)mr.size(), mre, r0, cb.Z, Rbuf[rn], ctx->stream));
+    } else {
+      offsets(kept, uoff, roff, ut, rt);
+      FP_TRY(ctx->bufT(rn == 0 ? "R_a" : "R_b", (size_t)std::max<int64_t>(rt, 1), &Rbuf[rn]));
+      FP_TRY(ctx->bufT("U_site", (size_t)std::max<int64_t>(ut, 1), &ubuf));
+      FP_TRY(rsvd_factors(ctx, io, rs, uoff, ubuf, std::max<int64_t>(ut, 1), roff, Rbuf[rn],
+                          std::max<int64_t>(rt, 1)));
+    }
     std::vector<int> sel;
     for (int J = 0; J < ns; ++J)
-      if (rs.kept[J] > 0) sel.push_back(J);
+      if (kept[J] > 0) sel.push_back(J);
     auto jl = std::make_shared<Leg>();
     jl->nlab = nlab;
     for (int J : sel) {
       for (int32_t v : op.sect[J].label) jl->lab.push_back(v);
-      jl->dim.push_back(rs.kept[J]);
+      jl->dim.push_back(kept[J]);
     }
     olegs[4] = jl;
-    std::vector<int64_t> uoff(ns, 0), roff(ns, 0);
-    int64_t ut = 0, rt = 0;
     std::vector<std::array<uint16_t, 5>> blocks;
     std::vector<int64_t> offs;
     for (size_t si = 0; si < sel.size(); ++si) {
       const int J = sel[si];
-      uoff[J] = ut;
-      roff[J] = rt;
       for (size_t t = 0; t < op.sect[J].rows.size(); ++t) {
         auto& r = op.sect[J].rows[t];
         blocks.push_back({r[0], r[1], r[2], r[3], (uint16_t)si});
-        offs.push_back(ut + op.sect[J].rrow[t] * rs.kept[J]);
+        offs.push_back(uoff[J] + op.sect[J].rrow[t] * kept[J]);
       }
-      ut += op.sect[J].m * (int64_t)rs.kept[J];
-      rt += op.sect[J].n * (int64_t)rs.kept[J];
     }
     std::vector<int> dirs = {1, op.ket.cat[op.ket.pos(N_dk)]->dir, op.W.cat[op.W.pos(N_dw)]->dir,
                              op.bra.cat[op.bra.pos(N_db)]->dir, -1};
     bool fits = false;
     FP_TRY(write_structure(olegs, dirs, blocks, offs, ut, &env_out[x], rep, &fits));
-    const int rn = 1 - rcur;
-    FP_TRY(ctx->bufT(rn == 0 ? "R_a" : "R_b", (size_t)std::max<int64_t>(rt, 1), &Rbuf[rn]));
-    double* ubuf = nullptr;
-    FP_TRY(ctx->bufT("U_site", (size_t)std::max<int64_t>(ut, 1), &ubuf));
-    FP_TRY(rsvd_factors(ctx, io, rs, uoff, ubuf, std::max<int64_t>(ut, 1), roff, Rbuf[rn],
-                        std::max<int64_t>(rt, 1)));
     if (fits) {
       if (ut > 0)
         FP_HIP(hipMemcpyAsync(env_out[x].data, ubuf, ut * sizeof(double), hipMemcpyDeviceToDevice,
@@ -1081,12 +1359,48 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
                      c = rs.kept[J];
         if (k > 0) site_flops += 2 * m * k * c + 2 * k * c * n;
       }
+      // bond expansion: per pass one application of M and of M^T with the
+      // projector splits (4 c k (m + n) each), one orthonormalisation and
+      // the core factorisation; then Q = Q_sketch U~ and M^T Q
+      for (size_t ps = 0; ps < cb.pass_k.size(); ++ps) {
+        site_flops += cb.pass_fl[ps][0] + cb.pass_fl[ps][1];
+        for (int J = 0; J < ns; ++J) {
+          const double m = (double)op.sect[J].m, n = (double)op.sect[J].n,
+                       k = cb.pass_k[ps][J], c = rs.kept[J];
+          if (k <= 0) continue;
+          site_flops += 8 * c * k * (m + n);
+          site_flops += 2 * m * k * k - 2 * k * k * k / 3.0;
+          site_flops += 2 * n * k * k + 11 * k * k * k;
+        }
+      }
+      if (!cb.pass_k.empty()) {
+        site_flops += cb.rem_flops;
+        for (int J = 0; J < ns; ++J) {
+          const double m = (double)op.sect[J].m, k = cb.pass_k.back()[J], e = cb.e[J];
+          if (k > 0) site_flops += 2 * m * k * e;
+        }
+      }
     }
     flops += site_flops;
+    // algorithmic bytes: every application reads T, R, the ket and the PEPO
+    // once and writes its output (m x k rows or n x k columns) once
+    {
+      const int q = o->power_iters;
+      const double in_b = 8.0 * (double)(d.T_size + d.R_size + d.A_size + d.W_size);
+      for (size_t ps = 0; ps < rs.pass_k.size(); ++ps) {
+        double rows = 0, cols = 0;
+        for (int J = 0; J < ns; ++J) {
+          rows += (double)op.sect[J].m * rs.pass_k[ps][J];
+          cols += (double)op.sect[J].n * rs.pass_k[ps][J];
+        }
+        alg_bytes += (1 + q) * (2 * in_b + 8.0 * rows + 8.0 * cols);
+      }
+    }
     prev_kept.clear();
-    for (int J = 0; J < ns; ++J) prev_kept[op.sect[J].label] = rs.kept[J];
+    for (int J = 0; J < ns; ++J) prev_kept[op.sect[J].label] = kept[J];
     have_prev = true;
-    for (int v : rs.kept) kept_total += v;
+    for (int v : kept) kept_total += v;
+    dg.cbe = cb.e;
     if (rs.cut.total2 > 0) disc = std::max(disc, 1.0 - rs.cut.kept2 / rs.cut.total2);
     if (rs.cut.s_next >= 0 && rs.cut.s_last > 0)
       gap = std::min(gap, (rs.cut.s_last - rs.cut.s_next) / rs.cut.s_last);
@@ -1112,6 +1426,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     rep->fallbacks = fallbacks;
     rep->plan_reuses = cache_hits;
     rep->rsvd_passes = total_passes;
+    rep->alg_bytes = alg_bytes;
     rep->kernel_launches = (int32_t)ctx->kt_launches;
     rep->kernel_seconds = ctx->kt_seconds;
     rep->kernel_flops = ctx->kt_flops;
@@ -1291,6 +1606,9 @@ Status project(fpeps_ctx_s* ctx, ExplicitOp& e, bool row_side, double* x, int64_
   double *s = nullptr, *tmp = nullptr;
   FP_TRY(ctx->bufT("expl_s", (size_t)std::max<int64_t>(e.s_total, 1), &s));
   FP_TRY(ctx->bufT("expl_tmp", (size_t)std::max<int64_t>(xtotal, 1), &tmp));
+  // matrices without kept directions have no projection product: their part
+  // of tmp must add zero
+  FP_HIP(launch_fill(tmp, xtotal, 0.0, ctx->stream));
   if (!row_side) {
     FP_TRY(run_gemm(ctx, e.ps, e.p_v1, e.V, e.vtotal, x, xtotal, s, std::max<int64_t>(e.s_total, 1)));
     FP_TRY(run_gemm(ctx, e.ps, e.p_v2, e.V, e.vtotal, s, std::max<int64_t>(e.s_total, 1), tmp, xtotal));

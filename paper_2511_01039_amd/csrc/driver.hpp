@@ -70,5 +70,10 @@ Status explicit_rsvd(fpeps_ctx_s* ctx, int nmat, const int64_t* m, const int64_t
 Status overlap(fpeps_ctx_s* ctx, int L, const fpeps_tensor* top, const fpeps_tensor* bot,
                double log_norm, int32_t* sign, double* log_abs);
 Status axpy_inplace(fpeps_ctx_s* ctx, double* x, const double* y, int64_t n);
+// y = H_eff A (heff.cpp)
+Status heff_apply(fpeps_ctx_s* ctx, const fpeps_tensor* T, const fpeps_tensor* L,
+                  const fpeps_tensor* B, const fpeps_tensor* R, const fpeps_tensor* W,
+                  const fpeps_tensor* A, const fpeps_opts* o, fpeps_tensor* y,
+                  fpeps_report* rep);
 
 }  // namespace fp

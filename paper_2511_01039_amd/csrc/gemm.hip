@@ -9,7 +9,8 @@
 //
 // Tiles are staged through LDS (KT = 16 deep, double-buffered); each of the
 // four waves runs v_mfma_f64_16x16x4f64 (FP64) or v_mfma_f32_16x16x4f32
-// (FP32 operands, FP32 accumulation) on its sub-tile. Register layouts
+// (FP32 operands, FP32 accumulation inside each 16-deep K tile, the tiles
+// summed in FP64) on its sub-tile. Register layouts
 // (checked on the device): A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
 // result register r of lane l holds D[4r + l/16][l % 16] for the FP64
 // instruction and D[4(l/16) + r][l % 16] for the FP32 one.
@@ -175,6 +176,17 @@ __device__ __forceinline__ void gemm_tile(const TA* __restrict__ A, const TB* __
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = MF::zero();
+  // FP32 MFMA: each 16-deep K tile accumulates in FP32 on the matrix core,
+  // the tiles are summed in FP64 (the rounding of the sum then does not grow
+  // with the contracted length)
+  constexpr bool kSplit = sizeof(TM) == 4;
+  d4 acc64[kSplit ? FM : 1][kSplit ? FN : 1];
+  if constexpr (kSplit) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc64[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  }
 
   // first tile of the job (jobs without any tile write zeros)
   TileCursor cur{job.p0, job.k0 > 0 ? job.k0 : 0};
@@ -207,6 +219,16 @@ __device__ __forceinline__ void gemm_tile(const TA* __restrict__ A, const TB* __
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j) acc[i][j] = MF::run(a[i], b[j], acc[i][j]);
+      }
+      if constexpr (kSplit) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
+            acc[i][j] = MF::zero();
+          }
       }
       if (!more) break;
       store_tile<MT, NT, KT, TM>(sA[buf ^ 1], sB[buf ^ 1], tid, regs);
@@ -241,7 +263,12 @@ __device__ __forceinline__ void gemm_tile(const TA* __restrict__ A, const TB* __
       for (int r = 0; r < 4; ++r) {
         const int m = job.m0 + wm * WTM + i * 16 + MF::row(r, lk);
         const int n = job.n0 + wn * WTN + j * 16 + lrow;
-        if (m < job.M && n < job.N) Cb[(int64_t)om[i][r] + on[j]] = (TC)acc[i][j][r];
+        if (m < job.M && n < job.N) {
+          if constexpr (kSplit)
+            Cb[(int64_t)om[i][r] + on[j]] = (TC)acc64[i][j][r];
+          else
+            Cb[(int64_t)om[i][r] + on[j]] = (TC)acc[i][j][r];
+        }
       }
 }
 

@@ -41,7 +41,8 @@ struct DevGemm {
 hipError_t launch_gemm_f64(const DevGemm& g, const double* A, const double* B, double* C,
                            const int32_t* tables, hipStream_t s);
 // The same with an FP32 copy of A, B and C in FP32 or FP64, on FP32 MFMA with
-// FP32 accumulation (B rounded to FP32 when loaded, C rounded from FP32).
+// FP32 accumulation per 16-deep K tile, the tiles summed in FP64 (B rounded to
+// FP32 when loaded, C rounded from FP64).
 hipError_t launch_gemm_f32(const DevGemm& g, const float* A, const void* B, bool b_f32, void* C,
                            bool c_f32, const int32_t* tables, hipStream_t s);
 // dst[i] = (float)src[i]
@@ -123,6 +124,10 @@ hipError_t launch_jacobi_eig(const SmallDesc* d, int nd, int max_k, double* buf,
 // In place per matrix: the k x k matrix at b_off becomes (matrix at c_off)
 // times itself; a_off is k x k scratch.
 hipError_t launch_small_mm(const SmallDesc* d, int nd, double* buf, hipStream_t s);
+// SVQB scaling: column i of the k x k eigenvector matrix at b_off times
+// 1/sqrt(lambda_i) (eigenvalues at c_off, descending), or zero when
+// lambda_i <= tau * lambda_0.
+hipError_t launch_svqb_scale(const SmallDesc* d, int nd, double* buf, double tau, hipStream_t s);
 
 // Global truncation over sectors: eigenvalues (descending per sector) at
 // lam_off[i] with k[i] entries; keeps the ``chi`` largest sqrt(lam).
@@ -155,6 +160,22 @@ struct SignDesc {
 };
 hipError_t launch_sign_fix(const SignDesc* d, int nd, int total_cols, const int32_t* col_desc,
                            double* U, double* R, hipStream_t s);
+
+// One sector's block in the per-sector helpers of the bond expansion.
+struct SectDesc {
+  int64_t off_a, off_b, off_out;
+  int32_t rows, cols, cols_b, s0;
+};
+// out = in with row i of each sector scaled by sc[s0 + i] (rows x cols blocks)
+hipError_t launch_row_scale(const SectDesc* d, int nd, int64_t max_elems, const double* in,
+                            double* out, const double* sc, hipStream_t s);
+// out = [A | B] per sector: rows x cols and rows x cols_b into rows x (cols + cols_b)
+hipError_t launch_merge_cols(const SectDesc* d, int nd, int64_t max_elems, const double* A,
+                             const double* B, double* out, hipStream_t s);
+// out = [A ; B^T] per sector: A rows x cols, B cols x cols_b (row-major) into
+// (rows + cols_b) x cols
+hipError_t launch_stack_rows_t(const SectDesc* d, int nd, int64_t max_elems, const double* A,
+                               const double* B, double* out, hipStream_t s);
 
 // sum of squares of x[0..n) into *out (deterministic two-pass reduction).
 hipError_t launch_sumsq(const double* x, int64_t n, double* partial, double* out, hipStream_t s);

@@ -455,6 +455,28 @@ hipError_t launch_cut(const CutGroup* groups, int ngroups, int max_ns, int max_t
   return hipGetLastError();
 }
 
+// SVQB scaling (Stathopoulos & Wu, SIAM J. Sci. Comput. 23 (2002) 2165):
+// column i of the k x k eigenvector matrix at b_off is multiplied by
+// 1/sqrt(lambda_i), or set to zero when lambda_i <= tau * lambda_0.
+__global__ void k_svqb_scale(const SmallDesc* __restrict__ d, double* __restrict__ buf, double tau) {
+  const SmallDesc g = d[blockIdx.x];
+  const int k = g.k;
+  double* V = buf + g.b_off;
+  const double* lam = buf + g.c_off;
+  const double l0 = lam[0];
+  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += blockDim.x) {
+    const int col = (int)(e % k);
+    const double l = lam[col];
+    V[e] *= (l > tau * l0 && l > 0.0) ? 1.0 / sqrt(l) : 0.0;
+  }
+}
+
+hipError_t launch_svqb_scale(const SmallDesc* d, int nd, double* buf, double tau, hipStream_t s) {
+  if (nd <= 0) return hipSuccess;
+  k_svqb_scale<<<nd, 256, 0, s>>>(d, buf, tau);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // canonical column signs
 // ---------------------------------------------------------------------------
@@ -503,6 +525,81 @@ hipError_t launch_sign_fix(const SignDesc* d, int nd, int total_cols, const int3
                            double* U, double* R, hipStream_t s) {
   if (nd <= 0 || total_cols <= 0) return hipSuccess;
   k_sign_fix<<<total_cols, 256, 0, s>>>(d, col_desc, U, R);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// per-sector helpers of the bond expansion
+// ---------------------------------------------------------------------------
+// out[o + i n + j] = in[o + i n + j] * sc[s0 + i] for the rows of every
+// sector (row-major rows x n blocks)
+__global__ void k_row_scale(const SectDesc* __restrict__ d, const double* __restrict__ in,
+                            double* __restrict__ out, const double* __restrict__ sc) {
+  const SectDesc g = d[blockIdx.y];
+  const int64_t tot = (int64_t)g.rows * g.cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[g.off_out + e] = in[g.off_a + e] * sc[g.s0 + e / g.cols];
+}
+
+hipError_t launch_row_scale(const SectDesc* d, int nd, int64_t max_elems, const double* in,
+                            double* out, const double* sc, hipStream_t s) {
+  if (nd <= 0) return hipSuccess;
+  int64_t bx = (max_elems + 255) / 256;
+  if (bx > 1024) bx = 1024;
+  if (bx < 1) bx = 1;
+  k_row_scale<<<dim3((unsigned)bx, nd), 256, 0, s>>>(d, in, out, sc);
+  return hipGetLastError();
+}
+
+// Columns side by side: out (rows x (ca + cb)) = [A (rows x ca) | B (rows x cb)]
+__global__ void k_merge_cols(const SectDesc* __restrict__ d, const double* __restrict__ A,
+                             const double* __restrict__ B, double* __restrict__ out) {
+  const SectDesc g = d[blockIdx.y];
+  const int c = g.cols + g.cols_b;
+  const int64_t tot = (int64_t)g.rows * c;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / c;
+    const int j = (int)(e % c);
+    out[g.off_out + e] = j < g.cols ? A[g.off_a + r * g.cols + j]
+                                    : B[g.off_b + r * g.cols_b + (j - g.cols)];
+  }
+}
+
+hipError_t launch_merge_cols(const SectDesc* d, int nd, int64_t max_elems, const double* A,
+                             const double* B, double* out, hipStream_t s) {
+  if (nd <= 0) return hipSuccess;
+  int64_t bx = (max_elems + 255) / 256;
+  if (bx > 1024) bx = 1024;
+  if (bx < 1) bx = 1;
+  k_merge_cols<<<dim3((unsigned)bx, nd), 256, 0, s>>>(d, A, B, out);
+  return hipGetLastError();
+}
+
+// Rows one after the other, B transposed: out ((ra + cb) x n) = [A (ra x n) ;
+// B^T], B given as n x cb (row-major)
+__global__ void k_stack_rows_t(const SectDesc* __restrict__ d, const double* __restrict__ A,
+                               const double* __restrict__ B, double* __restrict__ out) {
+  const SectDesc g = d[blockIdx.y];
+  const int n = g.cols;
+  const int64_t tot = (int64_t)(g.rows + g.cols_b) * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / n;
+    const int j = (int)(e % n);
+    out[g.off_out + e] = r < g.rows ? A[g.off_a + r * n + j]
+                                    : B[g.off_b + (int64_t)j * g.cols_b + (r - g.rows)];
+  }
+}
+
+hipError_t launch_stack_rows_t(const SectDesc* d, int nd, int64_t max_elems, const double* A,
+                               const double* B, double* out, hipStream_t s) {
+  if (nd <= 0) return hipSuccess;
+  int64_t bx = (max_elems + 255) / 256;
+  if (bx > 1024) bx = 1024;
+  if (bx < 1) bx = 1;
+  k_stack_rows_t<<<dim3((unsigned)bx, nd), 256, 0, s>>>(d, A, B, out);
   return hipGetLastError();
 }
 

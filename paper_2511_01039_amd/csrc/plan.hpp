@@ -24,7 +24,7 @@ enum SymKind { SYM_NONE = 0, SYM_U1U1 = 1, SYM_SU2 = 2 };
 // Leg names of the chain (identifiers only; data layouts are per tensor).
 enum LegName : int {
   N_a = 0, N_tk, N_tw, N_tb, N_b, N_rk, N_rw, N_rb, N_j, N_p, N_q, N_lk, N_lw, N_lb,
-  N_dk, N_dw, N_db, N_c, N_COUNT
+  N_dk, N_dw, N_db, N_c, N_d, N_COUNT
 };
 
 constexpr int MAXL = 10;

@@ -116,7 +116,8 @@ class SiteOp {
   // y = M x (transpose = false) or M^T x, per-sector matrices at the offsets
   // of ``pl`` (x: col layout for M, row layout for M^T). ``f32`` stores the
   // chain intermediates of this application in FP32 and runs its
-  // environment and remainder products on FP32 MFMA with FP32 accumulation
+  // environment and remainder products on FP32 MFMA (FP32 accumulation per K
+  // tile, tiles summed in FP64)
   // (make_f32_operands first); the layer steps keep FP64 arithmetic.
   Status apply(fpeps_ctx_s* ctx, const Plans& pl, bool transpose, const double* x, double* y,
                bool f32);

@@ -4,7 +4,7 @@ Calls only the FP64 oracle (oracle/) and the seeded input generators
 (workloads/). The GPU parity tests compare the device library against the
 file this writes; nothing in it comes from the device path.
 
-    python tests/golden/make_row_golden.py --config 4 [--max-cols 8]
+    python tests/golden/make_row_golden.py --config 4 [--max-cols 8] [--workers 6]
 
 Stored: per site the kept count and the sketch width of every sector, the
 singular values of every sector, the log-norm, and the gauge-invariant
@@ -45,6 +45,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--max-cols", type=int, default=8)
+    ap.add_argument("--workers", type=int, default=1,
+                    help="sectors evaluated in this many processes (same results)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
@@ -55,7 +57,7 @@ def main():
     record = []
     env, lg, info = absorb_row(row.sym, row.T, row.A, row.W, row.chi, row.oversample,
                                row.power_iters, a.seed, row=row.row, record=record,
-                               max_cols=a.max_cols, progress=log)
+                               max_cols=a.max_cols, progress=log, workers=a.workers)
     log("absorbed; flops and network value")
     flops = row_flops(record, info, row.power_iters)
     bot = wl.random_bottom_env(row.sym, env, bond, np.random.default_rng(5))

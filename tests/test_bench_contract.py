@@ -1,5 +1,5 @@
-"""The benchmark's command-line contract and the freshness of the committed
-profile summaries (host only)."""
+"""The benchmark's command-line contract and its use of the committed profile
+summaries (host only)."""
 import hashlib
 import os
 import subprocess
@@ -41,14 +41,24 @@ def fields(path):
 
 @pytest.mark.parametrize("kernel", ["k_rt_f64", "k_gemm_f64"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_profiles_match_kernel_sources(kernel, precision):
-    """Each committed HBM-traffic summary names the kernel source it was taken
-    from and its hash; the hash is that of the current source, so the
-    benchmark's traffic figure is never that of an older kernel."""
-    f = fields(os.path.join(ROOT, "profiles", f"{kernel}_config4_{precision}_hbm_traffic.txt"))
+def test_profile_traffic_only_for_current_source(kernel, precision):
+    """An HBM-traffic summary names the kernel source it was taken from and
+    that file's hash; the benchmark reports its traffic figure only while the
+    hash is that of the current source, and null once the kernel changed."""
+    sys.path.insert(0, ROOT)
+    import bench
+    path = os.path.join(ROOT, "profiles", f"{kernel}_config4_{precision}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        assert bench.profiled_traffic(kernel, precision) is None
+        return
+    f = fields(path)
     src = os.path.join(ROOT, f["kernel_source"])
-    assert hashlib.sha256(open(src, "rb").read()).hexdigest() == f["kernel_source_sha256"]
-    assert float(f["traffic_bytes_per_launch"]) > 0
+    fresh = hashlib.sha256(open(src, "rb").read()).hexdigest() == f["kernel_source_sha256"]
+    got = bench.profiled_traffic(kernel, precision)
+    if fresh:
+        assert got == float(f["traffic_bytes_per_launch"]) and got > 0
+    else:
+        assert got is None
 
 
 def test_profiles_name_their_commands():

@@ -115,3 +115,23 @@ def test_row_flop_count_and_passes_match_oracle(ctx, name, kw, chi):
           f"{rep['rsvd_passes']}")
     assert rep["rsvd_passes"] == npass
     assert rep["alg_flops"] == pytest.approx(want, rel=1e-12)
+
+
+def test_exactly_rank_deficient_sketch(ctx):
+    """A matrix with only five nonzero rows (its sketch is rank-deficient by
+    structure, so no shifted CholeskyQR pass can complete it): the
+    orthonormalisation finishes by SVQB, and kept count, singular values and
+    projector equal the oracle's (Householder QR)."""
+    from oracle.rsvd import rsvd_explicit
+    from paper_2511_01039_amd import make_opts
+    a = np.zeros((300, 200))
+    a[[3, 50, 77, 150, 299]] = np.random.default_rng(1).standard_normal((5, 200))
+    want = rsvd_explicit([a], chi=40, p=10, q=1, seed=5)
+    U, R, sig, kept, rep = ctx.rsvd_truncate([t(a)], make_opts(chi=40, oversample=10,
+                                                               power_iters=1, seed=5))
+    print(f"kept {list(kept)} oracle {want['kept']} fallbacks {rep['fallbacks']}")
+    assert list(kept) == want["kept"] == [5]
+    assert rep["fallbacks"] & 4
+    assert np.abs(sig[0] - want["sigma"][0]).max() < 1e-13 * want["sigma"][0][0]
+    Uh = U[0].cpu().numpy()
+    assert np.abs(Uh @ Uh.T - want["U"][0] @ want["U"][0].T).max() < 1e-12

@@ -360,3 +360,20 @@ def test_comb_pepo_lattice_equals_local_bond_form(shape):
 def test_comb_pepo_interior_site_has_19_transitions():
     W = wl.hubbard_pepo_site(2, 2, 5, 5)
     assert W.nblocks == 19
+
+
+def test_sector_parallel_and_chunked_evaluation_is_bitwise_equal():
+    """The oracle's memory and time bounding (column chunks, sectors in
+    worker processes) changes no bit of a row absorption: each sector's
+    blocks are summed in the same order either way."""
+    from oracle.zipup import absorb_row
+    row = wl.small_row("su2", L=4, seed=3, oversample=4, power_iters=1, env_scale=3, virt_scale=2)
+    e1, l1, i1 = absorb_row(row.sym, row.T, row.A, row.W, 10, 4, 1, 17, row=row.row)
+    e2, l2, i2 = absorb_row(row.sym, row.T, row.A, row.W, 10, 4, 1, 17, row=row.row, workers=3,
+                            max_cols=2)
+    assert l1 == l2
+    assert i1["kept"] == i2["kept"]
+    for s1, s2 in zip(i1["sigma"], i2["sigma"]):
+        assert all(np.array_equal(a, b) for a, b in zip(s1, s2))
+    for a, b in zip(e1, e2):
+        assert np.array_equal(a.data, b.data)

@@ -9,4 +9,4 @@ from .configs import (Sym, Lattice, RowProblem, block_allowed, largest_remainder
                       hubbard_pepo_site, hubbard_local_ops, identity_pepo, trivial_env,
                       random_top_env, random_peps, random_symmetric_pepo, config1_lattice,
                       config1_params, config2_row, random_bottom_env, config3_row, config4_row, small_row,
-                      decaying_matrix, CONFIG5, su2_lattice, config4_lattice, lowrank_su2_lattice, LOWRANK_PARAMS, bottom_closing, near_identity_pepo, KET_DIRS, PEPO_DIRS, ENV_DIRS)
+                      decaying_matrix, CONFIG5, su2_lattice, config4_lattice, lowrank_su2_lattice, LOWRANK_PARAMS, heff_inputs, bottom_closing, near_identity_pepo, KET_DIRS, PEPO_DIRS, ENV_DIRS)

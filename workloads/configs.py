@@ -567,6 +567,47 @@ def small_row(kind="none", L=3, d=2, D=2, w=2, chi=4, seed=0, oversample=2, powe
                       meta=dict(config="small", kind=kind, cat=cat))
 
 
+def heff_inputs(kind="none", seed=0, d=2, D=2, w=2, chi=3, env_scale=1, virt_scale=1,
+                symmetric=False):
+    """Random inputs of the effective single-site operator of Fig. 2(b) at an
+    interior site: ket A[p, l, r, u, d], PEPO W[q, p, l, r, u, d], top
+    boundary site T[a, k, w, b', b], left environment L[a, k, w, b', c],
+    bottom boundary site B[c, k, w, b', d] and right environment
+    R[b, k, w, b', d] (k, w, b' the ket, PEPO and bra legs they face).
+    Directions follow the row conventions (each shared leg opposite on its
+    two tensors). ``symmetric`` (dense kind only) makes every environment
+    symmetric under the exchange of its ket and bra legs and W symmetric in
+    (q, p), so that the operator is symmetric."""
+    if kind == "none":
+        sym, cat = Sym("none"), legs_dense(d, D, w, chi)
+    elif kind == "u1u1":
+        sym, cat = Sym("u1u1", coef_seed=seed, fermionic=True), legs_u1u1_mini(env_scale, virt_scale)
+    elif kind == "su2":
+        sym, cat = Sym("su2", coef_seed=seed, fermionic=True), legs_su2_mini(env_scale, virt_scale)
+    else:
+        raise ValueError(kind)
+    rng = np.random.default_rng(seed)
+    A = random_tensor(sym, peps_site_legs(cat, 1, 1, 3, 3), rng)
+    W = random_tensor(sym, pepo_site_legs(cat, 1, 1, 3, 3), rng)
+    env = cat["env"]
+    d_ = lambda leg, dr: Leg(leg.labels.copy(), leg.dims.copy(), int(dr))
+    T = random_tensor(sym, env_site_legs(cat, A.legs[3], W.legs[4], False, False), rng)
+    L = random_tensor(sym, [d_(env, -1), d_(A.legs[1], -1), d_(W.legs[2], -1), d_(A.legs[1], 1),
+                            d_(env, 1)], rng)
+    B = random_tensor(sym, [d_(env, -1), d_(A.legs[4], 1), d_(W.legs[5], 1), d_(A.legs[4], -1),
+                            d_(env, 1)], rng)
+    R = random_tensor(sym, [d_(env, 1), d_(A.legs[2], 1), d_(W.legs[3], 1), d_(A.legs[2], -1),
+                            d_(env, -1)], rng)
+    if symmetric:
+        assert kind == "none", "symmetric inputs are dense"
+        for t in (T, L, B, R):
+            x = t.block(0)
+            x[...] = 0.5 * (x + x.transpose(0, 3, 2, 1, 4))
+        w_ = W.block(0)
+        w_[...] = 0.5 * (w_ + w_.transpose(1, 0, 2, 3, 4, 5))
+    return dict(sym=sym, cat=cat, A=A, W=W, T=T, L=L, B=B, R=R)
+
+
 def random_bottom_env(sym, top_env, bond_leg, rng):
     """A random environment whose bundle legs face those of ``top_env``
     (same sectors, reversed directions) with bonds ``bond_leg`` (dim 1 at the
