@@ -351,6 +351,24 @@ fpeps_status fpeps_heff_apply(fpeps_ctx ctx, const fpeps_tensor* T, const fpeps_
                               const fpeps_tensor* A, const fpeps_opts* opts, fpeps_tensor* y_out,
                               fpeps_report* report);
 
+/* fpeps_expect for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same value, computed by the same kernels in the same order, with every
+ * workspace buffer (partial contractions, intermediates, reductions, GEMM
+ * plans) taken from one library-owned device array of 64 MiB per GPU,
+ * reserved for the life of the process. The call makes no hipMalloc,
+ * hipFree or other device allocation. A problem whose workspace exceeds the
+ * array (roughly environment bonds above 150 at D w D = 144) fails with
+ * FPEPS_ERR_CAPACITY and a message giving the bytes it needs. All calls on
+ * one GPU share its array: calls that overlap in time on one GPU (several
+ * contexts or host threads) race and must be serialised by the caller. The
+ * array keeps the last call's contents; every buffer a call reads is
+ * written by that call first. Host-side planning still uses the host heap.
+ * Synchronises. */
+fpeps_status fpeps_expect_noalloc(fpeps_ctx ctx, int32_t L, const fpeps_tensor* top,
+                                  const fpeps_tensor* bottom, double log_norm_top,
+                                  double log_norm_bottom, int32_t* sign, double* log_abs);
+
 #ifdef __cplusplus
 }
 #endif

@@ -125,6 +125,8 @@ def load():
         "fpeps_expect": ([C.c_void_p, C.c_int32, T, T, C.c_double, C.c_double, P(C.c_int32),
                           P(C.c_double)], C.c_int),
         "fpeps_set_allocator": ([C.c_void_p, ALLOC_FN, FREE_FN, C.c_void_p], C.c_int),
+        "fpeps_expect_noalloc": ([C.c_void_p, C.c_int32, T, T, C.c_double, C.c_double,
+                                  P(C.c_int32), P(C.c_double)], C.c_int),
         "fpeps_heff_apply": ([C.c_void_p, T, T, T, T, T, T, P(COpts), T, P(CReport)], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -140,7 +142,7 @@ def exported_symbols():
             "fpeps_last_error", "fpeps_set_allocator", "fpeps_env_absorb", "fpeps_absorb_diag", "fpeps_site_shape",
             "fpeps_site_apply", "fpeps_rsvd_truncate", "fpeps_rsvd_truncate_grouped",
             "fpeps_cbe_expand", "fpeps_cbe_expand_grouped", "fpeps_expect",
-            "fpeps_heff_apply"]
+            "fpeps_heff_apply", "fpeps_expect_noalloc"]
 
 
 def _i32(a):
@@ -474,6 +476,19 @@ class Context:
             self.check(rc)
             return out.result(), rep.as_dict()
         raise FpepsError(-7, "capacity")
+
+    def expect_log_noalloc(self, top, bottom, log_norm_top=0.0, log_norm_bottom=0.0):
+        """expect_log with no device allocation (fpeps_expect_noalloc)."""
+        keep = []
+        L = len(top)
+        ta = (CTensor * L)(*[t.ctensor(keep) for t in top])
+        ba = (CTensor * L)(*[t.ctensor(keep) for t in bottom])
+        sg = C.c_int32()
+        la = C.c_double()
+        self.check(self.lib.fpeps_expect_noalloc(self.h, L, ta, ba, C.c_double(log_norm_top),
+                                                 C.c_double(log_norm_bottom), C.byref(sg),
+                                                 C.byref(la)))
+        return int(sg.value), float(la.value)
 
     def expect(self, top, bottom):
         """The same as a plain float (no log-norms applied)."""

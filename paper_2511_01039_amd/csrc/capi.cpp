@@ -49,6 +49,8 @@ fpeps_status fpeps_create(fpeps_ctx* out, int32_t device, void* stream) {
     if (hipGetDeviceProperties(&p, device) != hipSuccess) return FPEPS_ERR_NODEVICE;
     if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) return FPEPS_ERR_NODEVICE;
     if (hipSetDevice(device) != hipSuccess) return FPEPS_ERR_HIP;
+    // device address of the no-allocation scratch array, once per device
+    if (!fp::scratch_init(device).good()) return FPEPS_ERR_HIP;
     fpeps_ctx c = new fpeps_ctx_s();
     c->device = device;
     c->stream = (hipStream_t)stream;
@@ -248,6 +250,15 @@ fpeps_status fpeps_heff_apply(fpeps_ctx ctx, const fpeps_tensor* T, const fpeps_
   return guarded(ctx, [&] {
     if (report) std::memset(report, 0, sizeof(*report));
     return fp::heff_apply(ctx, T, L, B, R, W, A, opts, y_out, report);
+  });
+}
+
+fpeps_status fpeps_expect_noalloc(fpeps_ctx ctx, int32_t L, const fpeps_tensor* top,
+                                  const fpeps_tensor* bottom, double log_norm_top,
+                                  double log_norm_bottom, int32_t* sign, double* log_abs) {
+  return guarded(ctx, [&] {
+    return fp::overlap_noalloc(ctx, L, top, bottom, log_norm_top + log_norm_bottom, sign,
+                               log_abs);
   });
 }
 

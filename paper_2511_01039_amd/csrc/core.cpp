@@ -86,6 +86,22 @@ fp::Status fpeps_ctx_s::stage_begin() {
 }
 
 fp::Status fpeps_ctx_s::buf(const std::string& name, size_t bytes, void** out) {
+  if (arena_base) {
+    fp::DevBuf& a = arena_bufs[name];
+    if (a.bytes < bytes) {
+      const size_t want = (std::max(bytes, (size_t)256) + 255) / 256 * 256;
+      if (arena_used + want > arena_cap)
+        return fp::fail(FPEPS_ERR_CAPACITY,
+                        "the no-allocation scratch of " + std::to_string(arena_cap >> 20) +
+                            " MiB is too small for this problem (" + name + ": needs " +
+                            std::to_string(arena_used + want) + " bytes in all)");
+      a.p = arena_base + arena_used;
+      a.bytes = want;
+      arena_used += want;
+    }
+    *out = a.p;
+    return fp::Status::ok();
+  }
   fp::DevBuf& b = bufs[name];
   if (b.bytes < bytes) {
     if (b.p) {

@@ -87,6 +87,24 @@ struct fpeps_ctx_s {
   fp::Status release_workspace();
   size_t ws_bytes = 0;   // workspace bytes held now
   size_t ws_peak = 0;    // and at most since the last reset (a call's start)
+  // Arena mode (fpeps_expect_noalloc): between arena_begin and arena_end,
+  // buf() carves named regions out of [base, base + cap) with a bump
+  // pointer instead of allocating; a request beyond it fails with
+  // FPEPS_ERR_CAPACITY. Nothing is freed.
+  char* arena_base = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
+  std::map<std::string, fp::DevBuf> arena_bufs;
+  void arena_begin(char* base, size_t cap) {
+    arena_base = base;
+    arena_cap = cap;
+    arena_used = 0;
+    arena_bufs.clear();
+  }
+  void arena_end() {
+    arena_base = nullptr;
+    arena_cap = arena_used = 0;
+    arena_bufs.clear();
+  }
   std::vector<fp::SiteDiag> diag;
   double peak_ws = 0;
   int nslices = 0;

@@ -76,4 +76,13 @@ Status heff_apply(fpeps_ctx_s* ctx, const fpeps_tensor* T, const fpeps_tensor* L
                   const fpeps_tensor* A, const fpeps_opts* o, fpeps_tensor* y,
                   fpeps_report* rep);
 
+// Bytes of the file-scope device array behind fpeps_expect_noalloc.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+// The array's device address on ``device`` (that device current), looked up
+// once per device.
+Status scratch_init(int device);
+// overlap() with every workspace buffer in that array (no allocation)
+Status overlap_noalloc(fpeps_ctx_s* ctx, int L, const fpeps_tensor* top, const fpeps_tensor* bot,
+                       double log_norm, int32_t* sign, double* log_abs);
+
 }  // namespace fp
