@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfpeps.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["gemm.hip", "layer.hip", "linalg.hip", "noalloc.hip", "plan.cpp", "core.cpp", "site.cpp",
+SOURCES = ["gemm.hip", "layer.hip", "linalg.hip", "dense.hip", "noalloc.hip", "plan.cpp", "core.cpp", "site.cpp",
            "driver.cpp", "heff.cpp", "capi.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -49,6 +49,9 @@ struct DensePlans {
   PlanSet ps;
   int gram[2] = {-1, -1};   // 0: row layout, 1: column layout
   int qmul[2] = {-1, -1};
+  int mm = -1;              // per sector: (k x k at v0) times (k x k at S), into [0, S)
+  int vtv = -1;             // per sector: V^T V of the k x k V at S, into [0, S)
+  int vx = -1;              // per sector: V (at S) times X (at v0), into [0, S)
   std::vector<ReduceDesc> red[2];
   int64_t part_total[2] = {0, 0};
   std::vector<int64_t> small_off, lam_off;
@@ -132,7 +135,105 @@ Status build_dense(fpeps_ctx_s* ctx, const Layout& L0, const Layout& L1, DensePl
     dp.gram[side] = dp.ps.add(std::move(gp));
     dp.qmul[side] = dp.ps.add(std::move(qp));
   }
+  // U~ = V0 V1 of the core factorisation: V0 kept after the S + lam part
+  std::vector<DenseOp> mops;
+  const int64_t v0_base = 2 * dp.S + dp.lam_total;
+  for (int J = 0; J < ns; ++J) {
+    const int k = L0.k[J];
+    if (k <= 0) continue;
+    DenseOp o{};
+    o.a_off = v0_base + dp.small_off[J];
+    o.b_off = dp.S + dp.small_off[J];
+    o.c_off = dp.small_off[J];
+    o.M = o.N = o.K = k;
+    o.a_rs = k;
+    o.a_cs = 1;
+    o.b_rs = k;
+    o.b_cs = 1;
+    o.c_rs = k;
+    o.c_cs = 1;
+    o.alpha = 1.0;
+    mops.push_back(o);
+  }
+  GemmPlan mp;
+  if (!plan_dense(mops, dp.ps.pool, 64, 64, 1, mp, err)) return fail(FPEPS_ERR_SHAPE, err);
+  dp.mm = dp.ps.add(std::move(mp));
+  // re-orthonormalisation of V (one CholeskyQR pass): V^T V and V X
+  std::vector<DenseOp> tops = mops, xops = mops;
+  for (size_t i = 0; i < mops.size(); ++i) {
+    tops[i].a_off = mops[i].b_off;   // V^T: V read by columns
+    tops[i].a_rs = 1;
+    tops[i].a_cs = mops[i].M;
+    xops[i].a_off = mops[i].b_off;   // V times X (X at the V0 place)
+    xops[i].b_off = mops[i].a_off;
+  }
+  GemmPlan tp, xp;
+  if (!plan_dense(tops, dp.ps.pool, 64, 64, 1, tp, err)) return fail(FPEPS_ERR_SHAPE, err);
+  if (!plan_dense(xops, dp.ps.pool, 64, 64, 1, xp, err)) return fail(FPEPS_ERR_SHAPE, err);
+  dp.vtv = dp.ps.add(std::move(tp));
+  dp.vx = dp.ps.add(std::move(xp));
   return dp.ps.upload(ctx, tag);
+}
+
+// Widths up to these run on one workgroup per matrix (the matrix in LDS for
+// the eigensolver); wider ones on the multi-workgroup blocked kernels. The
+// relative-rule eigensolver always runs on one workgroup (plane rotations
+// one at a time keep every eigenvalue's relative accuracy).
+constexpr int CHOL_ONE_WG_MAX_K = 64;
+constexpr int EIG_ONE_WG_MAX_K = 80;
+
+// Shifted Cholesky and inverse of a batch (contract of launch_chol_inv).
+Status chol_inv(fpeps_ctx_s* ctx, const SmallDesc* dd, int nd, int max_k, double* small,
+                int* status) {
+  if (max_k <= CHOL_ONE_WG_MAX_K) {
+    FP_HIP(launch_chol_inv(dd, nd, small, status, ctx->stream));
+    return Status::ok();
+  }
+  int* zf = nullptr;
+  FP_TRY(ctx->bufT("ch_zf", (size_t)std::max(nd, 1), &zf));
+  FP_HIP(launch_chol_inv_blocked(dd, nd, max_k, small, zf, status, ctx->stream));
+  return Status::ok();
+}
+
+// Symmetric eigen-decomposition of a batch (contract of launch_jacobi_eig).
+// The blocked solver (absolute rule, wide matrices; *blocked set) syncs once
+// per sweep to test convergence.
+Status eig_sym(fpeps_ctx_s* ctx, const SmallDesc* dd, int nd, int max_k, double* small,
+               int* status, bool rel, bool* blocked = nullptr) {
+  if (blocked) *blocked = false;
+  if (rel || max_k <= EIG_ONE_WG_MAX_K) {
+    if (max_k > JACOBI_MAX_K)
+      return fail(FPEPS_ERR_UNSUPPORTED, "sketch width above " + std::to_string(JACOBI_MAX_K));
+    FP_HIP(launch_jacobi_eig(dd, nd, max_k, small, status, ctx->stream, rel));
+    return Status::ok();
+  }
+  if (blocked) *blocked = true;
+  int* flags = nullptr;
+  double* work = nullptr;
+  FP_TRY(ctx->bufT("bj_flags", (size_t)2 * nd + 1, &flags));
+  FP_TRY(ctx->bufT("bj_work", bj_work_doubles(nd, max_k), &work));
+  FP_HIP(launch_fill_int(flags, 2 * (int64_t)nd + 1, 0, ctx->stream));
+  FP_HIP(launch_bj_init(dd, nd, max_k, small, flags, work, ctx->stream));
+  bool converged = false;
+  for (int sweep = 0; sweep < 30 && !converged; ++sweep) {
+    FP_HIP(launch_bj_sweep(dd, nd, max_k, small, flags, work, ctx->stream));
+    int left = 0;
+    FP_HIP(hipMemcpyAsync(&left, flags + 2 * nd, sizeof(int), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    FP_TRY(ctx->sync());
+    converged = left == 0;
+  }
+  FP_HIP(launch_bj_finish(dd, nd, max_k, small, work, ctx->stream));
+  if (!converged) {
+    // the Jacobi limit bit, as the one-workgroup solver reports it
+    int hs = 0;
+    FP_HIP(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    FP_TRY(ctx->sync());
+    hs |= 4;
+    FP_HIP(hipMemcpyAsync(status, &hs, sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    FP_TRY(ctx->sync());
+  }
+  return Status::ok();
 }
 
 // Shifted CholeskyQR3 of the per-sector blocks in ``Y`` (layout ``side``),
@@ -184,7 +285,7 @@ Status orth(fpeps_ctx_s* ctx, DensePlans& dp, int side, const Layout& L, double*
                     std::max<int64_t>(dp.part_total[side], 1)));
     FP_HIP(launch_reduce_partials(dred, (int)dp.red[side].size(), dp.max_red_mn, small, part,
                                   ctx->stream));
-    FP_HIP(launch_chol_inv(shifted ? dch : dch1, (int)ch.size(), small, status, ctx->stream));
+    FP_TRY(chol_inv(ctx, shifted ? dch : dch1, (int)ch.size(), dp.max_k, small, status));
     return Status::ok();
   };
   auto apply_r = [&]() -> Status {
@@ -219,7 +320,7 @@ Status orth(fpeps_ctx_s* ctx, DensePlans& dp, int side, const Layout& L, double*
                       std::max<int64_t>(dp.part_total[side], 1)));
       FP_HIP(launch_reduce_partials(dred, (int)dp.red[side].size(), dp.max_red_mn, small, part,
                                     ctx->stream));
-      FP_HIP(launch_jacobi_eig(dch1, (int)ch.size(), dp.max_k, small, status, ctx->stream, false));
+      FP_TRY(eig_sym(ctx, dch1, (int)ch.size(), dp.max_k, small, status, false));
       FP_HIP(launch_svqb_scale(dch1, (int)ch.size(), small, 1e-8, ctx->stream));
       FP_TRY(apply_r());
     }
@@ -324,7 +425,7 @@ Status rsvd_pass(fpeps_ctx_s* ctx, RsvdIO& io, const std::vector<int32_t>& k, in
   ReduceDesc* dred = nullptr;
   FP_TRY(ctx->upload("rs_red1", dp.red[1].data(), dp.red[1].size() * sizeof(ReduceDesc),
                      (void**)&dred));
-  std::vector<SmallDesc> jd, md;
+  std::vector<SmallDesc> jd;
   const int64_t v0_base = 2 * dp.S + dp.lam_total;
   for (int J = 0; J < ns; ++J) {
     if (out.k[J] <= 0) continue;
@@ -334,30 +435,52 @@ Status rsvd_pass(fpeps_ctx_s* ctx, RsvdIO& io, const std::vector<int32_t>& k, in
     d.c_off = 2 * dp.S + dp.lam_off[J];
     d.k = out.k[J];
     jd.push_back(d);
-    SmallDesc e = d;
-    e.c_off = v0_base + dp.small_off[J];
-    md.push_back(e);
   }
-  SmallDesc *djd = nullptr, *dmd = nullptr;
+  SmallDesc* djd = nullptr;
   FP_TRY(ctx->upload("rs_jac", jd.data(), jd.size() * sizeof(SmallDesc), (void**)&djd));
-  FP_TRY(ctx->upload("rs_mm", md.data(), md.size() * sizeof(SmallDesc), (void**)&dmd));
   FP_HIP(launch_fill_int(status, 4, 0, ctx->stream));
   FP_TRY(run_gemm(ctx, dp.ps, dp.gram[1], Bt, CL.total, Bt, CL.total, part,
                   std::max<int64_t>(dp.part_total[1], 1)));
   FP_HIP(launch_reduce_partials(dred, (int)dp.red[1].size(), dp.max_red_mn, small, part,
                                 ctx->stream));
-  FP_HIP(launch_jacobi_eig(djd, (int)jd.size(), dp.max_k, small, status, ctx->stream, false));
+  bool blocked = false;
+  FP_TRY(eig_sym(ctx, djd, (int)jd.size(), dp.max_k, small, status, false, &blocked));
+  const int64_t small_n = 3 * dp.S + dp.lam_total + 1;
+  if (blocked && dp.S > 0) {
+    // the block solver's V0 is orthogonal to about 1e-13 only; one
+    // CholeskyQR pass (V0 <- V0 R^{-1}, R^T R = V0^T V0) brings it to
+    // rounding level, so that C below keeps the singular values of B
+    std::vector<SmallDesc> od = jd;
+    for (size_t i = 0; i < od.size(); ++i) {
+      od[i].b_off = v0_base + jd[i].a_off;
+      od[i].rows = jd[i].k;
+      od[i].shift = 0.0;
+    }
+    SmallDesc* dod = nullptr;
+    int* ostat = nullptr;
+    FP_TRY(ctx->upload("rs_reorth", od.data(), od.size() * sizeof(SmallDesc), (void**)&dod));
+    FP_TRY(ctx->bufT("rs_ostat", od.size() + 2, &ostat));
+    FP_HIP(launch_fill_int(ostat, (int64_t)od.size() + 2, 0, ctx->stream));
+    FP_TRY(run_gemm(ctx, dp.ps, dp.vtv, small, small_n, small, small_n, small, small_n));
+    FP_TRY(chol_inv(ctx, dod, (int)od.size(), dp.max_k, small, ostat));
+    FP_TRY(run_gemm(ctx, dp.ps, dp.vx, small, small_n, small, small_n, small, small_n));
+    FP_HIP(hipMemcpyAsync(small + dp.S, small, dp.S * sizeof(double), hipMemcpyDeviceToDevice,
+                          ctx->stream));
+  }
   if (dp.S > 0)
     FP_HIP(hipMemcpyAsync(small + v0_base, small + dp.S, dp.S * sizeof(double),
                           hipMemcpyDeviceToDevice, ctx->stream));
-  const int64_t small_n = 3 * dp.S + dp.lam_total + 1;
   FP_TRY(run_gemm(ctx, dp.ps, dp.qmul[1], Bt, CL.total, small, small_n, c1, CL.total));
   FP_TRY(run_gemm(ctx, dp.ps, dp.gram[1], c1, CL.total, c1, CL.total, part,
                   std::max<int64_t>(dp.part_total[1], 1)));
   FP_HIP(launch_reduce_partials(dred, (int)dp.red[1].size(), dp.max_red_mn, small, part,
                                 ctx->stream));
-  FP_HIP(launch_jacobi_eig(djd, (int)jd.size(), dp.max_k, small, status, ctx->stream, true));
-  FP_HIP(launch_small_mm(dmd, (int)md.size(), small, ctx->stream));
+  FP_TRY(eig_sym(ctx, djd, (int)jd.size(), dp.max_k, small, status, true));
+  // U~ = V0 V1 (into the free [0, S) part, then back to V's place)
+  FP_TRY(run_gemm(ctx, dp.ps, dp.mm, small, small_n, small, small_n, small, small_n));
+  if (dp.S > 0)
+    FP_HIP(hipMemcpyAsync(small + dp.S, small, dp.S * sizeof(double), hipMemcpyDeviceToDevice,
+                          ctx->stream));
   // global cut of every group (sectors listed group by group)
   std::vector<int64_t> loff;
   std::vector<int32_t> kk;

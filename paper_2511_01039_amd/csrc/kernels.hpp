@@ -118,12 +118,29 @@ hipError_t launch_chol_inv(const SmallDesc* d, int nd, double* buf, int* status,
 // ``rel``: stop by the relative rule |a_pq| <= k eps sqrt(a_pp a_qq) for
 // every pair (each eigenvalue resolved to its own size on a Gram matrix of
 // nearly orthogonal columns); otherwise by the off-diagonal norm.
-// status |= 4 when 40 sweeps do not converge.
+// status |= 4 when 40 sweeps do not converge. One workgroup per matrix;
+// k <= JACOBI_MAX_K.
+constexpr int JACOBI_MAX_K = 2048;
 hipError_t launch_jacobi_eig(const SmallDesc* d, int nd, int max_k, double* buf, int* status,
                              hipStream_t s, bool rel = false);
-// In place per matrix: the k x k matrix at b_off becomes (matrix at c_off)
-// times itself; a_off is k x k scratch.
-hipError_t launch_small_mm(const SmallDesc* d, int nd, double* buf, hipStream_t s);
+// Multi-workgroup versions for widths beyond one workgroup's LDS (dense.hip).
+// Blocked shifted Cholesky and inverse: the contract of launch_chol_inv;
+// zf: nd ints of scratch.
+hipError_t launch_chol_inv_blocked(const SmallDesc* d, int nd, int max_k, double* buf, int* zf,
+                                   int* status, hipStream_t s);
+// Block Jacobi eigensolver: the contract of launch_jacobi_eig with the
+// absolute rule (rel = false) and no size limit, to absolute accuracy (a few
+// k eps |A|; eigenvectors orthogonal to about 1e-13), driven by the host:
+// flags (2 nd + 1 ints, zeroed by the caller) and work (bj_work_doubles) are
+// scratch; launch_bj_init, then launch_bj_sweep until flags[2 nd] (matrices
+// not converged) reads 0, then launch_bj_finish.
+size_t bj_work_doubles(int nd, int max_k);
+hipError_t launch_bj_init(const SmallDesc* d, int nd, int max_k, double* buf, int* flags,
+                          double* work, hipStream_t s);
+hipError_t launch_bj_sweep(const SmallDesc* d, int nd, int max_k, double* buf, int* flags,
+                           double* work, hipStream_t s);
+hipError_t launch_bj_finish(const SmallDesc* d, int nd, int max_k, double* buf, double* work,
+                            hipStream_t s);
 // SVQB scaling: column i of the k x k eigenvector matrix at b_off times
 // 1/sqrt(lambda_i) (eigenvalues at c_off, descending), or zero when
 // lambda_i <= tau * lambda_0.

@@ -5,6 +5,7 @@
 // arithmetic here is FP64.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.hpp"
@@ -155,26 +156,33 @@ hipError_t launch_chol_inv(const SmallDesc* d, int nd, double* buf, int* status,
 // |a_pq| > k eps sqrt(a_pp a_qq), and the iteration stops after a sweep
 // without rotations. On a Gram matrix whose columns are nearly orthogonal
 // the relative rule resolves every eigenvalue to its own size, not to the
-// largest one's.
+// largest one's. It stops at eigenvalues of eps^2 times the largest
+// diagonal entry (singular values of eps times the largest): pairs with
+// |a_pq| <= eps^2 a_max are left, which moves no singular value by more than
+// about eps times the largest, and without this floor the rule never holds
+// among null directions whose entries are rounding noise.
 // ---------------------------------------------------------------------------
-constexpr int JAC_SCRATCH = 2560;   // doubles of rotation and reduction scratch
+// LDS scratch in doubles for pair capacity ``npc`` (>= kp/2 of every
+// matrix): rotation cosines and sines, pair indices (ints, two per double),
+// and a 1024-entry reduction.
+__host__ __device__ constexpr int jac_scratch(int npc) { return 3 * npc + 1024; }
 
 template <bool LDS, bool REL>
 __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d,
                                                  double* __restrict__ buf,
-                                                 int* __restrict__ status) {
+                                                 int* __restrict__ status, int npc) {
   const SmallDesc g = d[blockIdx.x];
   const int k = g.k;
   double* V = buf + g.b_off;
   double* lam = buf + g.c_off;
   const int tid = threadIdx.x, nt = blockDim.x;
   extern __shared__ double sm[];
-  double* cs = sm;               // [kp/2]
-  double* sn = sm + 512;         // [kp/2]
-  int* pp = (int*)(sm + 1024);   // [kp/2]
-  int* qq = pp + 512;            // [kp/2]
-  double* red = sm + 1536;       // [1024]
-  double* A = LDS ? sm + JAC_SCRATCH : buf + g.a_off;   // [k * k]
+  double* cs = sm;                   // [npc]
+  double* sn = sm + npc;             // [npc]
+  int* pp = (int*)(sm + 2 * npc);    // [npc]
+  int* qq = pp + npc;                // [npc]
+  double* red = sm + 3 * npc;        // [1024]
+  double* A = LDS ? sm + jac_scratch(npc) : buf + g.a_off;   // [k * k]
   __shared__ int done;
   __shared__ int nrot;
   const double rel_tol = (double)k * 2.220446049250313e-16;
@@ -183,6 +191,20 @@ __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d
   if (LDS) {
     const double* Ag = buf + g.a_off;
     for (int64_t e = tid; e < (int64_t)k * k; e += nt) A[e] = Ag[e];
+  }
+  __shared__ double abs_floor;
+  if (REL) {
+    __syncthreads();
+    double mx = 0.0;
+    for (int i = tid; i < k; i += nt) mx = fmax(mx, fabs(A[(int64_t)i * k + i]));
+    red[tid] = mx;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+      __syncthreads();
+    }
+    if (tid == 0) abs_floor = 4.930380657631324e-32 * red[0];   // eps^2 a_max
+    __syncthreads();
   }
   // V = I
   for (int64_t e = tid; e < (int64_t)k * k; e += nt) V[e] = (e / k == e % k) ? 1.0 : 0.0;
@@ -233,7 +255,8 @@ __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d
         if (q < k) {
           const double apq = A[(int64_t)p * k + q];
           const double app = A[(int64_t)p * k + p], aqq = A[(int64_t)q * k + q];
-          const bool rot = REL ? fabs(apq) > rel_tol * sqrt(fabs(app * aqq))
+          const bool rot = REL ? fabs(apq) > rel_tol * sqrt(fabs(app * aqq)) &&
+                                     fabs(apq) > abs_floor
                                : (apq != 0.0 && fabs(apq) > 1e-300);
           if (rot) {
             const double tau = (aqq - app) / (2.0 * apq);
@@ -296,7 +319,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d
       if (lj > li || (lj == li && j < i)) ++rank;
     }
     lam[rank] = li;
-    pp[i] = rank;  // reuse (k <= 1024 guaranteed by launcher: pp has 512 ints + qq 512)
+    pp[i] = rank;  // reuse: pp and qq together hold 2 npc >= k ints
   }
   __syncthreads();
   // copy V into A with permuted columns, then back into V
@@ -311,47 +334,20 @@ __global__ __launch_bounds__(1024) void k_jacobi(const SmallDesc* __restrict__ d
 hipError_t launch_jacobi_eig(const SmallDesc* d, int nd, int max_k, double* buf, int* status,
                              hipStream_t s, bool rel) {
   if (nd <= 0) return hipSuccess;
-  if (max_k > 1024 || max_k < 0) return hipErrorInvalidValue;
+  if (max_k > JACOBI_MAX_K || max_k < 0) return hipErrorInvalidValue;
+  const int npc = std::max((max_k + 1) / 2, 1);
   // the matrix in LDS when it fits beside the scratch in 64 KiB
-  const size_t scratch = (size_t)JAC_SCRATCH * sizeof(double);
+  const size_t scratch = (size_t)jac_scratch(npc) * sizeof(double);
   const size_t mat = (size_t)max_k * max_k * sizeof(double);
   const bool lds = scratch + mat <= 64 * 1024;
   if (lds && rel)
-    k_jacobi<true, true><<<nd, 1024, scratch + mat, s>>>(d, buf, status);
+    k_jacobi<true, true><<<nd, 1024, scratch + mat, s>>>(d, buf, status, npc);
   else if (lds)
-    k_jacobi<true, false><<<nd, 1024, scratch + mat, s>>>(d, buf, status);
+    k_jacobi<true, false><<<nd, 1024, scratch + mat, s>>>(d, buf, status, npc);
   else if (rel)
-    k_jacobi<false, true><<<nd, 1024, scratch, s>>>(d, buf, status);
+    k_jacobi<false, true><<<nd, 1024, scratch, s>>>(d, buf, status, npc);
   else
-    k_jacobi<false, false><<<nd, 1024, scratch, s>>>(d, buf, status);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Product of two k x k matrices per descriptor, in place: the matrix at b_off
-// becomes X B, X the matrix at c_off (both row-major k x k); a_off is k x k
-// scratch. One workgroup per matrix.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_small_mm(const SmallDesc* __restrict__ d,
-                                                  double* __restrict__ buf) {
-  const SmallDesc g = d[blockIdx.x];
-  const int k = g.k;
-  const double* X = buf + g.c_off;
-  double* B = buf + g.b_off;
-  double* T = buf + g.a_off;
-  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += blockDim.x) {
-    const int i = (int)(e / k), j = (int)(e % k);
-    double acc = 0.0;
-    for (int l = 0; l < k; ++l) acc += X[(int64_t)i * k + l] * B[(int64_t)l * k + j];
-    T[e] = acc;
-  }
-  __syncthreads();
-  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += blockDim.x) B[e] = T[e];
-}
-
-hipError_t launch_small_mm(const SmallDesc* d, int nd, double* buf, hipStream_t s) {
-  if (nd <= 0) return hipSuccess;
-  k_small_mm<<<nd, 256, 0, s>>>(d, buf);
+    k_jacobi<false, false><<<nd, 1024, scratch, s>>>(d, buf, status, npc);
   return hipGetLastError();
 }
 

@@ -135,3 +135,55 @@ def test_exactly_rank_deficient_sketch(ctx):
     assert np.abs(sig[0] - want["sigma"][0]).max() < 1e-13 * want["sigma"][0][0]
     Uh = U[0].cpu().numpy()
     assert np.abs(Uh @ Uh.T - want["U"][0] @ want["U"][0].T).max() < 1e-12
+
+
+def test_wide_sketches_on_blocked_factorisations(ctx):
+    """Sketch widths of several hundred (the multi-workgroup Cholesky and
+    block Jacobi kernels) over ragged sectors, one of them exactly zero:
+    kept counts equal the oracle's, singular values agree to a few hundred
+    eps of the largest, the kept columns are orthonormal, and the subspaces
+    that the spectrum separates well (the top 20 of the first sector: gap
+    0.015 after them; all of the third: its smallest value is 1e-6) are the
+    exact ones to 1e-9. The cut itself sits in the 1e-12 tail of the first
+    sector, where the kept subspace is fixed only to about eps / 5e-13."""
+    from oracle.rsvd import rsvd_explicit
+    from paper_2511_01039_amd import make_opts
+    s1 = np.logspace(0, -12, 300)
+    s3 = np.logspace(-1, -6, 120)
+    a1, u1, _ = prescribed(1500, 1200, s1, 3)
+    a3, u3, _ = prescribed(700, 400, s3, 4)
+    mats = [a1, np.zeros((300, 250)), a3]
+    want = rsvd_explicit(mats, chi=400, p=20, q=1, seed=9)
+    U, R, sig, kept, rep = ctx.rsvd_truncate([t(a) for a in mats],
+                                             make_opts(chi=400, oversample=20, power_iters=1,
+                                                       seed=9))
+    print(f"kept {list(kept)} oracle {want['kept']} widths {want['k']} passes "
+          f"{len(want['passes'])} fallbacks {rep['fallbacks']}")
+    assert max(want["k"]) > 256
+    assert list(kept) == want["kept"]
+    for i in range(3):
+        if want["kept"][i]:
+            assert np.abs(sig[i] - want["sigma"][i]).max() < 300 * EPS
+            Uh = U[i].cpu().numpy()
+            assert np.abs(Uh.T @ Uh - np.eye(Uh.shape[1])).max() < 1e-12
+    U0, U2 = U[0].cpu().numpy(), U[2].cpu().numpy()
+    assert np.abs(U0[:, :20] @ U0[:, :20].T - u1[:, :20] @ u1[:, :20].T).max() < 1e-9
+    assert np.abs(U2 @ U2.T - u3 @ u3.T).max() < 1e-9
+
+
+def test_wide_exactly_rank_deficient_sketch(ctx):
+    """The SVQB finisher and the breakdown test of the blocked Cholesky at a
+    sketch width of 170: five nonzero rows, as in the narrow case."""
+    from oracle.rsvd import rsvd_explicit
+    from paper_2511_01039_amd import make_opts
+    a = np.zeros((600, 400))
+    a[[3, 50, 77, 150, 599]] = np.random.default_rng(1).standard_normal((5, 400))
+    want = rsvd_explicit([a], chi=150, p=20, q=1, seed=5)
+    U, R, sig, kept, rep = ctx.rsvd_truncate([t(a)], make_opts(chi=150, oversample=20,
+                                                               power_iters=1, seed=5))
+    print(f"kept {list(kept)} oracle {want['kept']} fallbacks {rep['fallbacks']}")
+    assert list(kept) == want["kept"] == [5]
+    assert rep["fallbacks"] & 4
+    assert np.abs(sig[0] - want["sigma"][0]).max() < 1e-13 * want["sigma"][0][0]
+    Uh = U[0].cpu().numpy()
+    assert np.abs(Uh @ Uh.T - want["U"][0] @ want["U"][0].T).max() < 1e-12
