@@ -21,6 +21,8 @@ split-precision product) is not counted.
 """
 from __future__ import annotations
 
+from .rsvd import final_widths
+
 
 def chain_flops(sp, kvec):
     """Forward chain M X with per-sector widths ``kvec``."""
@@ -56,7 +58,7 @@ def site_flops(sp, passes, q, cbe_passes=(), cbe_kept=None):
     f = 0.0
     for kvec, _ in passes:
         f += pass_flops(sp, kvec, q)
-    kvec, kept = passes[-1]
+    kvec, kept = final_widths(passes), passes[-1][1]
     for m, n, k, c in zip(sp.m, sp.n, kvec, kept):
         if k > 0:
             f += 2 * m * k * c + 2 * k * c * n
@@ -68,7 +70,7 @@ def site_flops(sp, passes, q, cbe_passes=(), cbe_kept=None):
                 f += 2 * m * k * k - 2 * k ** 3 / 3.0
                 f += 2 * n * k * k + 11 * k ** 3
     if cbe_passes:
-        kc = cbe_passes[-1][0]
+        kc = final_widths(cbe_passes)
         f += chain_flops_t(sp, cbe_kept)
         for m, k, e in zip(sp.m, kc, cbe_kept):
             if k > 0:
@@ -102,7 +104,7 @@ def explicit_flops(m, n, passes, q, r=None):
                 f += (2 + 2 * q) * 4.0 * r[i] * k * (mi + ni)
             f += (q + 1) * (2 * mi * k * k - 2 * k ** 3 / 3.0) + q * (2 * ni * k * k - 2 * k ** 3 / 3.0)
             f += 2 * ni * k * k + 11 * k ** 3
-    kvec, kept = passes[-1]
+    kvec, kept = final_widths(passes), passes[-1][1]
     for i, (k, c) in enumerate(zip(kvec, kept)):
         if k > 0:
             f += 2.0 * m[i] * k * c + (0.0 if r is not None else 2.0 * k * c * n[i])

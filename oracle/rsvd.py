@@ -127,23 +127,43 @@ def rsvd_adaptive(apply_m, apply_mt, m, n, chi, p, q, omega_fn, keys=None, hint=
     """The randomized SVD of a sector-diagonal operator with the width rule
     of this module: start from sketch_widths(m, n, chi, p, hint), widen the
     saturated sectors and repeat until none is. ``omega_fn(k)`` returns the
-    per-sector Gaussian sketches (n_J x k_J) for widths k. ``sv_cut`` (a
-    relative floor) replaces the rank floor when given. Returns a dict with
-    Q, Ut, sigma (all computed values), B, kept, k (final widths), the
-    discarded weight, gap, and passes = [(k, kept)] of every factorisation."""
+    per-sector Gaussian sketches (n_J x k_J) for widths k (a sector's sketch
+    depends on its own width only). A sector that is not widened would give
+    its previous factorisation again, so a repeat pass factorises the
+    widened sectors only and the others keep theirs; every pass ends with
+    the global cut over all sectors. ``sv_cut`` (a relative floor) replaces
+    the rank floor when given. Returns a dict with Q, Ut, sigma (all
+    computed values), B, kept, k (final widths), the discarded weight, gap,
+    and passes = [(k, kept)] of every factorisation pass, k listing the
+    widths factorised in that pass (0 for a sector it left as it was)."""
     floor = sv_cut if sv_cut is not None and sv_cut > 0 else rank_floor(m, n)
     k = sketch_widths(m, n, chi, p, hint)
-    passes = []
+    Q, Ut, S, B = rsvd_sectors(apply_m, apply_mt, omega_fn(k), q)
+    kept, disc, gap = global_cut(S, chi, keys, floor)
+    passes = [(list(k), list(kept))]
     while True:
-        Q, Ut, S, B = rsvd_sectors(apply_m, apply_mt, omega_fn(k), q)
-        kept, disc, gap = global_cut(S, chi, keys, floor)
-        passes.append((list(k), list(kept)))
         sat = saturated(k, kept, m, n, p)
         if not any(sat):
             break
-        k = grown_widths(k, sat, m, n, p)
-    return dict(Q=Q, Ut=Ut, S=S, B=B, kept=kept, k=k, discarded=disc, gap=gap, passes=passes,
-                floor=floor)
+        grow = [g if s else 0 for g, s in zip(grown_widths(k, sat, m, n, p), sat)]
+        Q2, Ut2, S2, B2 = rsvd_sectors(apply_m, apply_mt, omega_fn(grow), q)
+        for J, g in enumerate(grow):
+            if g > 0:
+                Q[J], Ut[J], S[J], B[J] = Q2[J], Ut2[J], S2[J], B2[J]
+                k[J] = g
+        kept, disc, gap = global_cut(S, chi, keys, floor)
+        passes.append((list(grow), list(kept)))
+    return dict(Q=Q, Ut=Ut, S=S, B=B, kept=kept, k=list(k), discarded=disc, gap=gap,
+                passes=passes, floor=floor)
+
+
+def final_widths(passes):
+    """Widths each sector ends with: its last factorised width over
+    ``passes`` (rsvd_adaptive's pass list)."""
+    k = list(passes[0][0])
+    for kv, _ in passes[1:]:
+        k = [b if b > 0 else a for a, b in zip(k, kv)]
+    return k
 
 
 def rsvd_explicit(mats, chi, p, q, seed, tag=0, stream=0, sv_cut=None):

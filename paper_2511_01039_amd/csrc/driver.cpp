@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <numeric>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -25,6 +26,11 @@ struct Layout {
   std::vector<int32_t> k;
   std::vector<int64_t> off;
   int64_t total = 0;
+  static int64_t total_of(const std::vector<int64_t>& r, const std::vector<int32_t>& kk) {
+    int64_t t = 0;
+    for (size_t J = 0; J < r.size(); ++J) t += r[J] * (int64_t)kk[J];
+    return t;
+  }
   void build(const std::vector<int64_t>& r, const std::vector<int32_t>& kk) {
     rows = r;
     k = kk;
@@ -347,14 +353,76 @@ Status orth(fpeps_ctx_s* ctx, DensePlans& dp, int side, const Layout& L, double*
 // ---------------------------------------------------------------------------
 namespace {
 
-// One factorisation with fixed sketch widths k (Halko et al. Ex. 1.6): range
-// finder with q power iterations, B^T = M^T Q, core factorisation of B and
-// the global cut of every group.
-Status rsvd_pass(fpeps_ctx_s* ctx, RsvdIO& io, const std::vector<int32_t>& k, int chi, int q,
-                 uint64_t seed, const std::vector<double>& gfloor, RsvdOut& out) {
+// Global cut of every group (sectors listed group by group) over the
+// eigenvalues in ``out.small``: kept counts, cut statistics and the host
+// copy of the eigenvalues.
+Status cut_run(fpeps_ctx_s* ctx, const RsvdIO& io, int chi, const std::vector<double>& gfloor,
+               RsvdOut& out) {
   const int ns = (int)io.m.size();
   const int ngrp = (int)gfloor.size();
   auto grp_of = [&](int J) { return io.grp.empty() ? 0 : io.grp[J]; };
+  double* small = out.small;
+  int64_t lam_total = 0;
+  for (int J = 0; J < ns; ++J) lam_total += std::max(out.k[J], 0);
+  std::vector<int64_t> loff;
+  std::vector<int32_t> kk;
+  std::vector<int> sidx;
+  std::vector<CutGroup> cg(ngrp, CutGroup{0, 0, 0, 0, 0.0});
+  int max_ns = 0, max_total = 0;
+  for (int g = 0; g < ngrp; ++g) {
+    cg[g].s0 = (int32_t)kk.size();
+    cg[g].floor = gfloor[g];
+    for (int J = 0; J < ns; ++J) {
+      if (out.k[J] <= 0 || grp_of(J) != g) continue;
+      loff.push_back(2 * out.S + out.lam_off[J]);
+      kk.push_back(out.k[J]);
+      sidx.push_back(J);
+      cg[g].total += out.k[J];
+    }
+    cg[g].ns = (int32_t)kk.size() - cg[g].s0;
+    max_ns = std::max(max_ns, (int)cg[g].ns);
+    max_total = std::max(max_total, (int)cg[g].total);
+  }
+  int64_t* dloff = nullptr;
+  int32_t* dkk = nullptr;
+  int32_t* dkept = nullptr;
+  CutOut* dcut = nullptr;
+  CutGroup* dcg = nullptr;
+  FP_TRY(ctx->upload("rs_loff", loff.data(), loff.size() * sizeof(int64_t), (void**)&dloff));
+  FP_TRY(ctx->upload("rs_kk", kk.data(), kk.size() * sizeof(int32_t), (void**)&dkk));
+  FP_TRY(ctx->upload("rs_cg", cg.data(), cg.size() * sizeof(CutGroup), (void**)&dcg));
+  FP_TRY(ctx->bufT("rs_kept", kk.size() + 1, &dkept));
+  FP_TRY(ctx->bufT("rs_cut", (size_t)ngrp, &dcut));
+  if (max_total > 6144 || max_ns > 1024)
+    return fail(FPEPS_ERR_UNSUPPORTED, "too many singular values for the on-chip cut");
+  FP_HIP(launch_cut(dcg, ngrp, max_ns, max_total, dloff, dkk, chi, small, dkept, dcut,
+                    ctx->stream));
+  std::vector<int32_t> kept_c(kk.size());
+  out.cuts.assign(ngrp, CutOut{});
+  FP_HIP(hipMemcpyAsync(kept_c.data(), dkept, kk.size() * sizeof(int32_t),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  FP_HIP(hipMemcpyAsync(out.cuts.data(), dcut, ngrp * sizeof(CutOut), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  out.lam.assign(lam_total, 0.0);
+  if (lam_total)
+    FP_HIP(hipMemcpyAsync(out.lam.data(), small + 2 * out.S, lam_total * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->stream));
+  FP_TRY(ctx->sync());
+  out.cut = out.cuts[0];
+  out.kept.assign(ns, 0);
+  for (size_t i = 0; i < sidx.size(); ++i) out.kept[sidx[i]] = kept_c[i];
+  for (double v : out.lam)
+    if (!std::isfinite(v)) return fail(FPEPS_ERR_NUMERIC, "non-finite singular value");
+  return Status::ok();
+}
+
+// One factorisation with fixed sketch widths k (Halko et al. Ex. 1.6): range
+// finder with q power iterations, B^T = M^T Q, core factorisation of B and
+// (do_cut) the global cut of every group. Sectors of width 0 are skipped.
+Status rsvd_pass(fpeps_ctx_s* ctx, RsvdIO& io, const std::vector<int32_t>& k, int chi, int q,
+                 uint64_t seed, const std::vector<double>& gfloor, RsvdOut& out,
+                 bool do_cut = true) {
+  const int ns = (int)io.m.size();
   out.k = k;
   FP_TRY(io.prepare(out.k));
   Layout RL, CL;
@@ -481,60 +549,12 @@ Status rsvd_pass(fpeps_ctx_s* ctx, RsvdIO& io, const std::vector<int32_t>& k, in
   if (dp.S > 0)
     FP_HIP(hipMemcpyAsync(small + dp.S, small, dp.S * sizeof(double), hipMemcpyDeviceToDevice,
                           ctx->stream));
-  // global cut of every group (sectors listed group by group)
-  std::vector<int64_t> loff;
-  std::vector<int32_t> kk;
-  std::vector<int> sidx;
-  std::vector<CutGroup> cg(ngrp, CutGroup{0, 0, 0, 0, 0.0});
-  int max_ns = 0, max_total = 0;
-  for (int g = 0; g < ngrp; ++g) {
-    cg[g].s0 = (int32_t)kk.size();
-    cg[g].floor = gfloor[g];
-    for (int J = 0; J < ns; ++J) {
-      if (out.k[J] <= 0 || grp_of(J) != g) continue;
-      loff.push_back(2 * dp.S + dp.lam_off[J]);
-      kk.push_back(out.k[J]);
-      sidx.push_back(J);
-      cg[g].total += out.k[J];
-    }
-    cg[g].ns = (int32_t)kk.size() - cg[g].s0;
-    max_ns = std::max(max_ns, (int)cg[g].ns);
-    max_total = std::max(max_total, (int)cg[g].total);
-  }
-  int64_t* dloff = nullptr;
-  int32_t* dkk = nullptr;
-  int32_t* dkept = nullptr;
-  CutOut* dcut = nullptr;
-  CutGroup* dcg = nullptr;
-  FP_TRY(ctx->upload("rs_loff", loff.data(), loff.size() * sizeof(int64_t), (void**)&dloff));
-  FP_TRY(ctx->upload("rs_kk", kk.data(), kk.size() * sizeof(int32_t), (void**)&dkk));
-  FP_TRY(ctx->upload("rs_cg", cg.data(), cg.size() * sizeof(CutGroup), (void**)&dcg));
-  FP_TRY(ctx->bufT("rs_kept", kk.size() + 1, &dkept));
-  FP_TRY(ctx->bufT("rs_cut", (size_t)ngrp, &dcut));
-  if (max_total > 6144 || max_ns > 1024)
-    return fail(FPEPS_ERR_UNSUPPORTED, "too many singular values for the on-chip cut");
-  FP_HIP(launch_cut(dcg, ngrp, max_ns, max_total, dloff, dkk, chi, small, dkept, dcut,
-                    ctx->stream));
-  std::vector<int32_t> kept_c(kk.size());
   int hs = 0;
-  out.cuts.assign(ngrp, CutOut{});
-  FP_HIP(hipMemcpyAsync(kept_c.data(), dkept, kk.size() * sizeof(int32_t),
-                        hipMemcpyDeviceToHost, ctx->stream));
-  FP_HIP(hipMemcpyAsync(out.cuts.data(), dcut, ngrp * sizeof(CutOut), hipMemcpyDeviceToHost,
-                        ctx->stream));
   FP_HIP(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  out.lam.assign(dp.lam_total, 0.0);
-  if (dp.lam_total)
-    FP_HIP(hipMemcpyAsync(out.lam.data(), small + 2 * dp.S, dp.lam_total * sizeof(double),
-                          hipMemcpyDeviceToHost, ctx->stream));
   FP_TRY(ctx->sync());
-  out.cut = out.cuts[0];
   if (hs & 4) out.fallbacks |= 2u;
-  out.kept.assign(ns, 0);
-  for (size_t i = 0; i < sidx.size(); ++i) out.kept[sidx[i]] = kept_c[i];
   out.small = small;
-  for (double v : out.lam)
-    if (!std::isfinite(v)) return fail(FPEPS_ERR_NUMERIC, "non-finite singular value");
+  if (do_cut) FP_TRY(cut_run(ctx, io, chi, gfloor, out));
   return Status::ok();
 }
 
@@ -580,29 +600,103 @@ Status rsvd_run(fpeps_ctx_s* ctx, RsvdIO& io, int chi, int p, int q, uint64_t se
   }
   out.pass_k.clear();
   out.pass_kept.clear();
-  uint32_t fb = 0;
+  auto log_pass = [&](const std::vector<int32_t>& kp) {
+    if (!ctx->verbose) return;
+    std::fprintf(stderr, "[fpeps] rsvd pass %zu: widths", out.pass_k.size());
+    for (int v : kp) std::fprintf(stderr, " %d", v);
+    std::fprintf(stderr, " | kept");
+    for (int v : out.kept) std::fprintf(stderr, " %d", v);
+    std::fprintf(stderr, "\n");
+  };
+  out.fallbacks = 0;
+  FP_TRY(rsvd_pass(ctx, io, k, chi, q, seed, gfloor, out));
+  uint32_t fb = out.fallbacks;
+  out.pass_k.push_back(out.k);
+  out.pass_kept.push_back(out.kept);
+  log_pass(out.k);
   for (;;) {
-    out.fallbacks = 0;
-    FP_TRY(rsvd_pass(ctx, io, k, chi, q, seed, gfloor, out));
-    fb |= out.fallbacks;
-    out.pass_k.push_back(out.k);
-    out.pass_kept.push_back(out.kept);
-    if (ctx->verbose) {
-      std::fprintf(stderr, "[fpeps] rsvd pass %zu: widths", out.pass_k.size());
-      for (int v : out.k) std::fprintf(stderr, " %d", v);
-      std::fprintf(stderr, " | kept");
-      for (int v : out.kept) std::fprintf(stderr, " %d", v);
-      std::fprintf(stderr, "\n");
-    }
+    std::vector<int32_t> grow(ns, 0);
     bool any = false;
     for (int J = 0; J < ns; ++J) {
       const int64_t cover = std::min(wm[J], wn[J]);
       if (k[J] > 0 && k[J] < cover && 2 * (int64_t)out.kept[J] + p > 2 * (int64_t)k[J]) {
-        k[J] = (int32_t)std::min<int64_t>(cover, 2 * (int64_t)k[J] + p);
+        grow[J] = (int32_t)std::min<int64_t>(cover, 2 * (int64_t)k[J] + p);
         any = true;
       }
     }
     if (!any) break;
+    // A sector keeps its sketch (the same Gaussian columns for the same
+    // width), so a repeated factorisation of an unwidened sector would give
+    // its previous result again: only the widened sectors are factorised,
+    // the others keep theirs, and the cut runs over all of them.
+    // The current results move aside first (the pass reuses the buffers).
+    const int64_t q_n = std::max<int64_t>(Layout::total_of(io.m, k), 1);
+    const int64_t b_n = std::max<int64_t>(Layout::total_of(io.n, k), 1);
+    const int64_t s_n = 3 * out.S + (int64_t)std::accumulate(k.begin(), k.end(), (int64_t)0) + 1;
+    double *kq = nullptr, *kb = nullptr, *ks = nullptr;
+    FP_TRY(ctx->bufT("rs_keep_q", (size_t)q_n, &kq));
+    FP_TRY(ctx->bufT("rs_keep_b", (size_t)b_n, &kb));
+    FP_TRY(ctx->bufT("rs_keep_s", (size_t)s_n, &ks));
+    FP_HIP(hipMemcpyAsync(kq, out.Q, q_n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    FP_HIP(hipMemcpyAsync(kb, out.Bt, b_n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    FP_HIP(hipMemcpyAsync(ks, out.small, s_n * sizeof(double), hipMemcpyDeviceToDevice,
+                          ctx->stream));
+    const RsvdOut prev = out;
+    RsvdOut part;
+    part.fallbacks = 0;
+    FP_TRY(rsvd_pass(ctx, io, grow, chi, q, seed, gfloor, part, false));
+    fb |= part.fallbacks;
+    // merged layout: widened sectors from this pass, the others from before
+    std::vector<int32_t> kf(ns);
+    for (int J = 0; J < ns; ++J) kf[J] = grow[J] > 0 ? grow[J] : k[J];
+    Layout RL, CL;
+    RL.build(io.m, kf);
+    CL.build(io.n, kf);
+    RsvdOut mg;
+    mg.k = kf;
+    mg.row_off = RL.off;
+    mg.col_off = CL.off;
+    mg.small_off.assign(ns, 0);
+    mg.lam_off.assign(ns, 0);
+    int64_t S = 0, lt = 0;
+    for (int J = 0; J < ns; ++J) {
+      mg.small_off[J] = S;
+      mg.lam_off[J] = lt;
+      S += (int64_t)kf[J] * kf[J];
+      lt += kf[J];
+    }
+    mg.S = S;
+    FP_TRY(ctx->bufT("rs_merge_q", (size_t)std::max<int64_t>(RL.total, 1), &mg.Q));
+    FP_TRY(ctx->bufT("rs_merge_b", (size_t)std::max<int64_t>(CL.total, 1), &mg.Bt));
+    FP_TRY(ctx->bufT("rs_merge_s", (size_t)(3 * S + lt + 1), &mg.small));
+    auto copy = [&](double* dst, const double* src, int64_t n) -> Status {
+      if (n > 0)
+        FP_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice,
+                              ctx->stream));
+      return Status::ok();
+    };
+    for (int J = 0; J < ns; ++J) {
+      const int kj = kf[J];
+      if (kj <= 0) continue;
+      const bool g = grow[J] > 0;
+      const RsvdOut& src = g ? part : prev;
+      const double* sq = g ? part.Q : kq;
+      const double* sb = g ? part.Bt : kb;
+      const double* ss = g ? part.small : ks;
+      FP_TRY(copy(mg.Q + mg.row_off[J], sq + src.row_off[J], io.m[J] * (int64_t)kj));
+      FP_TRY(copy(mg.Bt + mg.col_off[J], sb + src.col_off[J], io.n[J] * (int64_t)kj));
+      FP_TRY(copy(mg.small + S + mg.small_off[J], ss + src.S + src.small_off[J],
+                  (int64_t)kj * kj));
+      FP_TRY(copy(mg.small + 2 * S + mg.lam_off[J], ss + 2 * src.S + src.lam_off[J], kj));
+    }
+    FP_TRY(cut_run(ctx, io, chi, gfloor, mg));
+    mg.pass_k = std::move(out.pass_k);
+    mg.pass_kept = std::move(out.pass_kept);
+    out = std::move(mg);
+    k = kf;
+    out.pass_k.push_back(grow);
+    out.pass_kept.push_back(out.kept);
+    log_pass(grow);
   }
   out.fallbacks = fb;
   return Status::ok();
@@ -760,7 +854,8 @@ struct CbeResult {
   double* Q = nullptr;
   double* Z = nullptr;
   std::vector<int64_t> qoff, zoff;
-  std::vector<std::vector<int32_t>> pass_k;
+  std::vector<std::vector<int32_t>> pass_k;     // widths factorised in each pass
+  std::vector<int32_t> k;                       // final widths
   std::vector<std::array<double, 2>> pass_fl;   // chain flops of each pass's plans
   double rem_flops = 0;                         // M^T Q
   uint32_t fallbacks = 0;
@@ -910,6 +1005,7 @@ Status cbe_site(fpeps_ctx_s* ctx, SiteOp& op, const RsvdOut& rs, const double* U
   FP_TRY(rsvd_run(ctx, io, o->cbe_extra, o->oversample, 0, o->seed, rc, o->sv_cut));
   out.pass_fl.push_back({plp->flops_fwd, plp->flops_bwd});
   out.pass_k = rc.pass_k;
+  out.k = rc.k;
   out.e = rc.kept;
   out.fallbacks = rc.fallbacks;
   // Q = Q_sketch U~[:, :e] (canonical signs), then Z = M^T Q
@@ -1451,7 +1547,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
     cache.unit_size = op.unit_size;
     ctx->release_later(std::move(cache.pl));
     cache.pl = plp;
-    cache.k = rs.k;
+    cache.k = rs.pass_k.back();   // the widths plp was planned for
     // diagnostics and report
     dg.k = rs.k;
     dg.kept = rs.kept;
@@ -1499,7 +1595,7 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
       if (!cb.pass_k.empty()) {
         site_flops += cb.rem_flops;
         for (int J = 0; J < ns; ++J) {
-          const double m = (double)op.sect[J].m, k = cb.pass_k.back()[J], e = cb.e[J];
+          const double m = (double)op.sect[J].m, k = cb.k[J], e = cb.e[J];
           if (k > 0) site_flops += 2 * m * k * e;
         }
       }

@@ -121,6 +121,29 @@ def test_weight_in_one_sector_is_found_by_widening():
     assert np.abs(out["U"][0] @ out["U"][0].T - u @ u.T).max() < 1e-10
 
 
+def test_repeat_pass_factorises_widened_sectors_only():
+    """A repeat pass lists width 0 for the sectors it leaves, and leaving
+    them changes nothing: the result equals factorising every sector again
+    at the final widths (the same sketch columns, so the same values) and
+    cutting over all of them."""
+    from oracle.rng import gaussian_matrix
+    from oracle.rsvd import rsvd_sectors, final_widths
+    sig = [np.geomspace(5.0, 0.5, 32), np.geomspace(1.0, 0.2, 12), np.array([2e-3])]
+    mats = [prescribed(200, 150, s, 20 + i)[0] for i, s in enumerate(sig)]
+    out = rsvd_explicit(mats, chi=30, p=6, q=1, seed=2)
+    assert len(out["passes"]) >= 2
+    for (k0, _), (k1, _) in zip(out["passes"], out["passes"][1:]):
+        assert any(v > 0 for v in k1) and any(v == 0 for v in k1)
+    assert final_widths(out["passes"]) == out["k"]
+    omegas = [gaussian_matrix(2, i, 0, 0, 150, out["k"][i]) for i in range(3)]
+    Q, Ut, S, B = rsvd_sectors(lambda X: [a @ x for a, x in zip(mats, X)],
+                               lambda X: [a.T @ x for a, x in zip(mats, X)], omegas, 1)
+    kept, _, _ = global_cut(S, 30, None, rank_floor([200] * 3, [150] * 3))
+    assert kept == out["kept"]
+    for i in range(3):
+        assert np.array_equal(S[i][:kept[i]], out["sigma"][i])
+
+
 def test_spectrum_down_to_1e12_is_resolved_and_kept():
     """Prescribed singular values from 1 to 1e-12 (above the rank floor
     eps max(m, n) = 6.7e-14): all are kept, and each agrees with the
