@@ -4,12 +4,17 @@ Calls only the FP64 oracle (oracle/) and the seeded input generators
 (workloads/). The GPU parity tests compare the device library against the
 file this writes; nothing in it comes from the device path.
 
-    python tests/golden/make_row_golden.py --config 4 [--max-cols 8] [--workers 6]
+    python tests/golden/make_row_golden.py --config 2 [--max-cols 8] [--workers 6]
 
 Stored: per site the kept count and the sketch width of every sector, the
 singular values of every sector, the log-norm, and the gauge-invariant
 network value s_row = <new environment | bottom> for a seeded random bottom
 environment (bond = the environment catalogue of the configuration, seed 5).
+
+Committed rows: config 2 (about 30 min on 8 host cores). A config-4 row is
+out of reach of the oracle on such a host (about 1.5 h per site at sketch
+widths near 570); at that shape the parity tests check sampled columns of a
+full-size site and the chi = 500 lattice whose boundary MPS is exact.
 """
 from __future__ import annotations
 

@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
+from oracle.expect import overlap
 
 pytestmark = pytest.mark.gpu
 
@@ -71,3 +72,75 @@ def test_lowrank_lattice_W(ctx, precision, tol):
     assert sw == g["Z_W"]["sign"] and s1 == g["Z_1"]["sign"]
     assert rel < tol
     assert abs(lw - g["Z_W"]["log"]) < tol * max(1.0, abs(lw))
+
+
+ROWS = {2: ("config2_row", lambda: wl.legs_dense(4, 6, 6, 128)["env"]),
+        3: ("config3_row", lambda: wl.legs_u1u1(256)["env"]),
+        4: ("config4_row", lambda: wl.legs_su2(500)["env"])}
+ROW_GOLDENS = [c for c in sorted(ROWS) if os.path.exists(os.path.join(GOLDEN, f"config{c}_row.json"))]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("cfg", ROW_GOLDENS)
+def test_full_row_matches_golden(ctx, cfg, precision):
+    """A full-size row of the configuration absorbed on the device against
+    the oracle's stored row: kept counts of every site and sector exact,
+    singular values of every site, the log-norm and the network value
+    s_row = <new environment | seeded random bottom> within 1e-11 relative
+    in FP64, and in mixed precision within max(1e-6, 2^-24 / g) (g the
+    smallest relative gap at a cut of the oracle's row: a cut subspace
+    moves by the rounding over the gap, Davis-Kahan); s_row, which cancels,
+    within that bound times its condition number where that is larger."""
+    from paper_2511_01039_amd import opts_for
+    g = json.load(open(os.path.join(GOLDEN, f"config{cfg}_row.json")))
+    name, bond = ROWS[cfg]
+    row = getattr(wl, name)()
+    out, lg, rep = ctx.env_absorb(dev(row.T), dev(row.A), dev(row.W),
+                                  opts_for(row.sym, chi=g["chi"], oversample=g["oversample"],
+                                           power_iters=g["power_iters"], seed=g["seed"],
+                                           row=g["row"], precision=precision))
+    fp64 = precision == "fp64"
+    gaps = [x for x in g["gap"] if np.isfinite(x)]
+    tol = 1e-11 if fp64 else max(1e-6, 2.0 ** -24 / max(min(gaps) if gaps else 1.0, 1e-300))
+    worst = 0.0
+    for x in range(len(out) - 1):
+        sig, sec, kept = ctx.absorb_diag(x)
+        assert [int(v) for v in kept] == g["kept"][x]
+        want = np.concatenate([np.asarray(s) for s in g["sigma"][x]])
+        assert sig.shape == want.shape
+        worst = max(worst, float(np.abs(sig - want).max() / want.max()))
+    env_h = [t.to_host() for t in out]
+    bot_h = wl.random_bottom_env(row.sym, env_h, bond(), np.random.default_rng(5))
+    sg, la = ctx.expect_log(out, dev(bot_h), lg, 0.0)
+    dlog = abs(la - g["s_row_log"])
+    # s_row is an overlap with a random environment, which cancels: a
+    # relative change d of the environment (as a vector) moves it by up to
+    # kappa d, kappa = |env| |bot| / |<env|bot>| (norms by the oracle's
+    # contraction). d is bounded by the cut subspaces' rounding over their
+    # gap at each of the L - 1 truncated sites.
+    kappa = math.sqrt(overlap(env_h, mirror(env_h)) * overlap(mirror(bot_h), bot_h)) / \
+        abs(overlap(env_h, bot_h))
+    u = 2.0 ** -53 if fp64 else 2.0 ** -24
+    d = (len(out) - 1) * u / max(min(gaps) if gaps else 1.0, 1e-300)
+    tol_s = max(tol, kappa * d)
+    print(f"config {cfg} {precision}: s_row log {la:.12f} oracle {g['s_row_log']:.12f} "
+          f"(rel {dlog:.2e}, kappa {kappa:.3e}, bound {tol_s:.2e}), log-norm diff "
+          f"{abs(lg - g['log_norm']):.2e}, sigma max diff {worst:.2e} of the largest, bound "
+          f"{tol:.2e}, device {rep['seconds']:.3f} s")
+    assert sg == g["s_row_sign"]
+    assert dlog < tol_s
+    assert abs(lg - g["log_norm"]) < tol * max(1.0, abs(g["log_norm"]))
+    assert worst < (1e-10 if fp64 else tol)
+
+
+def mirror(env):
+    """The environment with its bundle legs reversed (same blocks and data):
+    the plain overlap of an environment with its mirror is its squared norm."""
+    from workloads.tensor import Leg, Tensor
+    out = []
+    for t in env:
+        legs = [Leg(t.legs[0].labels, t.legs[0].dims, -t.legs[0].dir)] + \
+            [t.legs[i].flipped() for i in (1, 2, 3)] + \
+            [Leg(t.legs[4].labels, t.legs[4].dims, -t.legs[4].dir)]
+        out.append(Tensor(legs, t.blocks, t.offsets, t.data))
+    return out
