@@ -52,6 +52,57 @@ def workload(cfg):
     return row, desc, bond
 
 
+def bench_config5_row(a):
+    """Config 5 on the row's own residuals: the U(1)xU(1) chi = 256 row of
+    config 3 absorbed by fpeps_env_absorb with rSVD truncation (p = 8, q = 1)
+    and, at every site, controlled bond expansion by ceil(0.1 chi) = 26
+    directions taken from the range of (1 - U U^T) M_x (1 - V^T V) on the
+    implicit site operator (projector splitting, q = 0). A step is one row;
+    the same row without expansion is timed beside it."""
+    import torch
+    import workloads as wl
+    from paper_2511_01039_amd import Context, DeviceTensor, opts_for
+    cfg = wl.CONFIG5
+    row = wl.config3_row()
+    ctx = Context(0)
+    dev = lambda ts: [DeviceTensor.from_host(t) for t in ts]
+    T, A, W = dev(row.T), dev(row.A), dev(row.W)
+    res = {}
+    for extra in (cfg["cbe_extra"], 0):
+        o = opts_for(row.sym, chi=cfg["chi"], oversample=cfg["oversample"],
+                     power_iters=cfg["power_iters"], cbe_extra=extra, seed=0, row=row.row)
+        caps = None
+        for _ in range(a.warmup):
+            out, lg, rep = ctx.env_absorb(T, A, W, o, caps=caps)
+            caps = [(max(256, max(l.nsect for l in t.legs)), max(t.blocks.shape[0], 1),
+                     max(t.nelem, 1)) for t in out]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        flops = 0.0
+        for i in range(a.steps):
+            out, lg, rep = ctx.env_absorb(T, A, W, o, caps=caps)
+            flops += rep["alg_flops"]
+            print(f"config 5 row, cbe_extra {extra}, step {i}: {rep['seconds']:.3f} s device",
+                  file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / a.steps
+        kept = [int(t.legs[4].dims.sum()) for t in out[:-1]]   # new bond dimensions
+        res[extra] = dict(sec=sec, flops=flops / a.steps, kept=kept)
+    e = res[cfg["cbe_extra"]]
+    line = {"metric": "row absorption with controlled bond expansion, per-row latency",
+            "value": 1e3 * e["sec"], "unit": "ms", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": 1e3 * e["sec"], "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "config 5: the 8x8 U(1)xU(1) chi=256 row of config 3, rSVD "
+                                   "truncation p=8 q=1 and CBE by 26 directions (p=8, q=0) at every "
+                                   "site on the implicit site operator",
+                       "alg_flops_per_step": e["flops"], "tflops": e["flops"] / e["sec"] / 1e12,
+                       "bond_dims_after_expansion": e["kept"],
+                       "without_cbe_ms_per_step": 1e3 * res[0]["sec"],
+                       "without_cbe_bond_dims": res[0]["kept"]}}
+    print(json.dumps(line), flush=True)
+
+
 def bench_config5(a):
     """Batched bond expansion over one row of config 3: for each interior site
     of the U(1)xU(1) chi = 256 row, the per-sector shapes of its site operator
@@ -314,7 +365,11 @@ def main():
                          "mixed one if its network value is within 1e-6 of FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-site", action="store_true",
-                    help="config 5: one truncation and one expansion call per site")
+                    help="config 5 --explicit: one truncation and one expansion call per site")
+    ap.add_argument("--explicit", action="store_true",
+                    help="config 5 on seeded explicit matrices of the sites' sector shapes "
+                         "(grouped truncation and expansion calls) instead of the row's own "
+                         "residuals")
     ap.add_argument("--slice-budget-gib", type=float, default=0.0,
                     help="workspace per slice set in GiB (0: the library's default)")
     ap.add_argument("--one-stream", action="store_true",
@@ -343,7 +398,10 @@ def main():
         return
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.config == 5:
-        bench_config5(a)
+        if a.explicit:
+            bench_config5(a)
+        else:
+            bench_config5_row(a)
         return
     if a.lattice:
         bench_lattice(a)

@@ -383,6 +383,19 @@ Status SiteOp::plan_host(const std::vector<int32_t>& k, int64_t budget, Plans& o
   // same slices with FP64 intermediates too (its last range-finder product
   // and the projection).
   const double elem_budget = (double)budget / sizeof(double);
+  // Slices are planned on host threads, one slice per thread: a site whose
+  // whole chain fits the budget (many small sectors) is still packed into at
+  // least MIN_SLICES slices of about equal work, so that its planning is
+  // spread over the threads (results do not depend on the slicing).
+  constexpr int MIN_SLICES = 8;
+  double total_work = 0;
+  for (int J = 0; J < ns; ++J) {
+    if (k[J] <= 0 || sect[J].m == 0) continue;
+    const auto& u = unit_size[J];
+    total_work += ((double)std::max({u[0], u[2], u[5], u[7]}) +
+                   (double)std::max({u[1], u[3], u[4], u[6]})) * k[J];
+  }
+  const double pack_cap = std::min(elem_budget, total_work / MIN_SLICES);
   std::vector<std::vector<SliceCol>> slices;
   std::vector<SliceCol> cur;
   double used = 0;
@@ -391,7 +404,7 @@ Status SiteOp::plan_host(const std::vector<int32_t>& k, int64_t budget, Plans& o
     const auto& u = unit_size[J];
     const double per = (double)std::max({u[0], u[2], u[5], u[7]}) +
                        (double)std::max({u[1], u[3], u[4], u[6]});
-    if (used + per * k[J] <= elem_budget) {
+    if (used + per * k[J] <= elem_budget && (cur.empty() || used + per * k[J] <= pack_cap)) {
       cur.push_back({J, 0, k[J]});
       used += per * k[J];
       continue;

@@ -95,7 +95,7 @@ class SiteOp {
     int64_t col_total = 0, row_total = 0;
     int64_t ws1 = 0, ws2 = 0;   // elements of the two ping-pong intermediates
     double flops_fwd = 0, flops_bwd = 0;
-    bool f32 = false;           // intermediates stored in FP32 (arithmetic stays FP64)
+    bool f32 = false;           // FP32 operands: steps 1 and 5 on FP32 MFMA, FP32 intermediates
   };
   Status plan(fpeps_ctx_s* ctx, const std::vector<int32_t>& k, int64_t budget, Plans& out,
               bool with_bwd = true, bool f32 = false);
