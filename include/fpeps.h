@@ -351,6 +351,33 @@ fpeps_status fpeps_heff_apply(fpeps_ctx ctx, const fpeps_tensor* T, const fpeps_
                               const fpeps_tensor* A, const fpeps_opts* opts, fpeps_tensor* y_out,
                               fpeps_report* report);
 
+/* The same operator prepared for repeated products with one environment
+ * (the Davidson iterations of a site, Sec. 3): T L and B R do not depend on
+ * the vector and are contracted once here; the three vector-dependent
+ * products are captured as a HIP graph and replayed by
+ * fpeps_heff_apply_prepared. Arguments as fpeps_heff_apply; A gives the
+ * structure of the vectors (and its data the first product, written to
+ * y_out with the output structure). T, L, B, R, W and A may be freed after
+ * the call: the handle keeps what it needs on the device, in buffers of its
+ * own. Synchronises. The handle belongs to ctx, must be released before
+ * fpeps_destroy, and is invalidated by fpeps_set_allocator (later products
+ * fail with FPEPS_ERR_ARG). */
+typedef struct fpeps_heff_s* fpeps_heff;
+fpeps_status fpeps_heff_prepare(fpeps_ctx ctx, const fpeps_tensor* T, const fpeps_tensor* L,
+                                const fpeps_tensor* B, const fpeps_tensor* R,
+                                const fpeps_tensor* W, const fpeps_tensor* A,
+                                const fpeps_opts* opts, fpeps_tensor* y_out, fpeps_heff* op,
+                                fpeps_report* report);
+/* y = H_eff a for a vector a in the prepared structure: a (device, a_elems
+ * doubles, equal to the prepared A's nelem) in A's block layout, y (device,
+ * y_elems >= the output's nelem) in the output layout written by the
+ * prepare call. Runs on the context's stream (copy in, graph replay, copy
+ * out) and synchronises; the report gives the three products' flops and the
+ * device time. Calls on one handle must not overlap. */
+fpeps_status fpeps_heff_apply_prepared(fpeps_heff op, const double* a, int64_t a_elems,
+                                       double* y, int64_t y_elems, fpeps_report* report);
+fpeps_status fpeps_heff_release(fpeps_heff op);
+
 /* fpeps_expect for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation):
  * the same value, computed by the same kernels in the same order, with every

@@ -128,6 +128,11 @@ def load():
         "fpeps_expect_noalloc": ([C.c_void_p, C.c_int32, T, T, C.c_double, C.c_double,
                                   P(C.c_int32), P(C.c_double)], C.c_int),
         "fpeps_heff_apply": ([C.c_void_p, T, T, T, T, T, T, P(COpts), T, P(CReport)], C.c_int),
+        "fpeps_heff_prepare": ([C.c_void_p, T, T, T, T, T, T, P(COpts), T, P(C.c_void_p),
+                                P(CReport)], C.c_int),
+        "fpeps_heff_apply_prepared": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                       P(CReport)], C.c_int),
+        "fpeps_heff_release": ([C.c_void_p], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -142,7 +147,8 @@ def exported_symbols():
             "fpeps_last_error", "fpeps_set_allocator", "fpeps_env_absorb", "fpeps_absorb_diag", "fpeps_site_shape",
             "fpeps_site_apply", "fpeps_rsvd_truncate", "fpeps_rsvd_truncate_grouped",
             "fpeps_cbe_expand", "fpeps_cbe_expand_grouped", "fpeps_expect",
-            "fpeps_heff_apply", "fpeps_expect_noalloc"]
+            "fpeps_heff_apply", "fpeps_heff_prepare", "fpeps_heff_apply_prepared",
+            "fpeps_heff_release", "fpeps_expect_noalloc"]
 
 
 def _i32(a):
@@ -477,6 +483,28 @@ class Context:
             return out.result(), rep.as_dict()
         raise FpepsError(-7, "capacity")
 
+    def heff_prepare(self, T, L, B, R, W, A, opts, caps=None):
+        """The prepared effective operator for vectors shaped like A:
+        returns (HeffOperator, DeviceTensor y = H_eff A, report)."""
+        keep = []
+        cts = [t.ctensor(keep) for t in (T, L, B, R, W, A)]
+        nlab = cts[0].nlab
+        caps = caps or (256, 1 << 16, max(1, int(A.nelem) * 64))
+        for attempt in range(2):
+            out = OutTensor(5, nlab, *caps)
+            rep = CReport()
+            h = C.c_void_p()
+            rc = self.lib.fpeps_heff_prepare(self.h, *[C.byref(c) for c in cts], C.byref(opts),
+                                             C.byref(out.ct), C.byref(h), C.byref(rep))
+            if rc == -7 and attempt == 0:
+                caps = (max(caps[0], rep.required_sect), max(caps[1], rep.required_blocks),
+                        max(caps[2], rep.required_elem))
+                continue
+            self.check(rc)
+            y = out.result()
+            return HeffOperator(self, h, int(A.nelem), y), y, rep.as_dict()
+        raise FpepsError(-7, "capacity")
+
     def expect_log_noalloc(self, top, bottom, log_norm_top=0.0, log_norm_bottom=0.0):
         """expect_log with no device allocation (fpeps_expect_noalloc)."""
         keep = []
@@ -494,6 +522,32 @@ class Context:
         """The same as a plain float (no log-norms applied)."""
         sg, la = self.expect_log(top, bottom)
         return sg * math.exp(la) if sg else 0.0
+
+
+class HeffOperator:
+    """A prepared effective operator (fpeps_heff_prepare): apply() replays
+    the captured products for a new vector of the prepared structure."""
+
+    def __init__(self, ctx, handle, a_elems, y_like):
+        self.ctx, self.h, self.a_elems, self.y_like = ctx, handle, a_elems, y_like
+
+    def apply(self, a_data, y_data=None):
+        """a_data: torch float64 device tensor with the vector's elements;
+        returns (y_data, report)."""
+        import torch
+        if y_data is None:
+            y_data = torch.empty(max(self.y_like.nelem, 1), dtype=torch.float64,
+                                 device=a_data.device)
+        rep = CReport()
+        self.ctx.check(self.ctx.lib.fpeps_heff_apply_prepared(
+            self.h, C.c_void_p(a_data.data_ptr()), int(self.a_elems),
+            C.c_void_p(y_data.data_ptr()), int(y_data.numel()), C.byref(rep)))
+        return y_data, rep.as_dict()
+
+    def close(self):
+        if self.h:
+            self.ctx.check(self.ctx.lib.fpeps_heff_release(self.h))
+            self.h = None
 
 
 def output_caps(env_in, ket, pepo, x, chi):

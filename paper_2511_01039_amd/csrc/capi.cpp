@@ -253,6 +253,31 @@ fpeps_status fpeps_heff_apply(fpeps_ctx ctx, const fpeps_tensor* T, const fpeps_
   });
 }
 
+fpeps_status fpeps_heff_prepare(fpeps_ctx ctx, const fpeps_tensor* T, const fpeps_tensor* L,
+                                const fpeps_tensor* B, const fpeps_tensor* R,
+                                const fpeps_tensor* W, const fpeps_tensor* A,
+                                const fpeps_opts* opts, fpeps_tensor* y_out, fpeps_heff* op,
+                                fpeps_report* report) {
+  return guarded(ctx, [&] {
+    if (report) std::memset(report, 0, sizeof(*report));
+    return fp::heff_prepare(ctx, T, L, B, R, W, A, opts, y_out, op, report);
+  });
+}
+
+fpeps_status fpeps_heff_apply_prepared(fpeps_heff op, const double* a, int64_t a_elems,
+                                       double* y, int64_t y_elems, fpeps_report* report) {
+  if (!op) return FPEPS_ERR_ARG;
+  return guarded(fp::heff_context(op), [&] {
+    if (report) std::memset(report, 0, sizeof(*report));
+    return fp::heff_apply_prepared(op, a, a_elems, y, y_elems, report);
+  });
+}
+
+fpeps_status fpeps_heff_release(fpeps_heff op) {
+  if (!op) return FPEPS_ERR_ARG;
+  return guarded(fp::heff_context(op), [&] { return fp::heff_release(op); });
+}
+
 fpeps_status fpeps_expect_noalloc(fpeps_ctx ctx, int32_t L, const fpeps_tensor* top,
                                   const fpeps_tensor* bottom, double log_norm_top,
                                   double log_norm_bottom, int32_t* sign, double* log_abs) {

@@ -41,6 +41,23 @@ fp::Status fpeps_ctx_s::release_workspace() {
     if (kv.second.p) dev_free(kv.second.p);
   bufs.clear();
   ws_bytes = 0;
+  ++ws_generation;
+  return fp::Status::ok();
+}
+
+fp::Status fpeps_ctx_s::release_prefix(const std::string& prefix) {
+  FP_HIP(hipStreamSynchronize(stream));
+  for (auto it = bufs.begin(); it != bufs.end();) {
+    if (it->first.compare(0, prefix.size(), prefix) == 0) {
+      if (it->second.p) {
+        dev_free(it->second.p);
+        ws_bytes -= std::min(ws_bytes, it->second.bytes);
+      }
+      it = bufs.erase(it);
+    } else {
+      ++it;
+    }
+  }
   return fp::Status::ok();
 }
 
@@ -458,7 +475,8 @@ Status run_gemm_f32(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const float* A
 
 Status run_gemm_any(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A,
                     const float* A32, int64_t a_size, const void* B, bool b_f32, int64_t b_size,
-                    void* C, bool c_f32, int64_t c_size, bool timed, int label) {
+                    void* C, bool c_f32, int64_t c_size, bool timed, int label,
+                    double* part_buf) {
   const GemmPlan& p = ps.plans[idx];
   if (p.jobs.empty()) return Status::ok();
   // every table-addressed access must stay inside its buffer
@@ -472,8 +490,11 @@ Status run_gemm_any(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* 
   if (A && b_f32 && c_f32) return fail(FPEPS_ERR_UNSUPPORTED, "FP64 GEMM with B and C in FP32");
   // split-K parts are summed in FP64 and rounded once into C
   double* part = nullptr;
-  // each stream has its own partial buffer (slices on several streams overlap)
-  if (p.partial_size > 0) {
+  if (p.partial_size > 0 && part_buf) {
+    part = part_buf;
+  } else if (p.partial_size > 0) {
+    // each stream has its own partial buffer (slices on several streams
+    // overlap)
     const int si = ctx->stream_index(ctx->stream);
     FP_TRY(ctx->bufT(si ? "gemm_part" + std::to_string(si + 1) : std::string("gemm_part"),
                      (size_t)p.partial_size, &part));

@@ -85,7 +85,11 @@ struct fpeps_ctx_s {
   void dev_free(void* p);
   // frees every workspace buffer (waits for the device first)
   fp::Status release_workspace();
+  // frees the workspace buffers whose names start with ``prefix`` (waits
+  // for the context's stream first)
+  fp::Status release_prefix(const std::string& prefix);
   size_t ws_bytes = 0;   // workspace bytes held now
+  uint64_t ws_generation = 0;   // counts release_workspace() calls
   size_t ws_peak = 0;    // and at most since the last reset (a call's start)
   // Arena mode (fpeps_expect_noalloc): between arena_begin and arena_end,
   // buf() carves named regions out of [base, base + cap) with a bump
@@ -233,10 +237,12 @@ Status run_gemm_mixed(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double
 Status run_gemm_f32(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const float* A, int64_t a_size,
                     const void* B, bool b_f32, int64_t b_size, void* C, bool c_f32, int64_t c_size,
                     bool timed = false, int label = 0);
-// exactly one of A (FP64) and A32 (FP32) is given
+// exactly one of A (FP64) and A32 (FP32) is given; ``part`` (at least the
+// plan's partial_size doubles) replaces the context's split-K buffer
 Status run_gemm_any(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* A,
                     const float* A32, int64_t a_size, const void* B, bool b_f32, int64_t b_size,
-                    void* C, bool c_f32, int64_t c_size, bool timed, int label);
+                    void* C, bool c_f32, int64_t c_size, bool timed, int label,
+                    double* part = nullptr);
 Status run_rt(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const void* X, int64_t x_size,
               void* Y, int64_t y_size, bool f32, bool timed = false, int label = 0);
 

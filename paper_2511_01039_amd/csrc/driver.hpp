@@ -75,6 +75,18 @@ Status heff_apply(fpeps_ctx_s* ctx, const fpeps_tensor* T, const fpeps_tensor* L
                   const fpeps_tensor* B, const fpeps_tensor* R, const fpeps_tensor* W,
                   const fpeps_tensor* A, const fpeps_opts* o, fpeps_tensor* y,
                   fpeps_report* rep);
+// The prepared effective operator (T L and B R once, the vector-dependent
+// steps as a replayed HIP graph); ``y`` receives the output structure and
+// the product for A.
+Status heff_prepare(fpeps_ctx_s* ctx, const fpeps_tensor* T, const fpeps_tensor* L,
+                    const fpeps_tensor* B, const fpeps_tensor* R, const fpeps_tensor* W,
+                    const fpeps_tensor* A, const fpeps_opts* o, fpeps_tensor* y,
+                    fpeps_heff_s** out, fpeps_report* rep);
+Status heff_apply_prepared(fpeps_heff_s* h, const double* a, int64_t a_elems, double* y,
+                           int64_t y_elems, fpeps_report* rep);
+fpeps_ctx_s* heff_context(fpeps_heff_s* h);
+// frees the handle and its device buffers
+Status heff_release(fpeps_heff_s* h);
 
 // Bytes of the file-scope device array behind fpeps_expect_noalloc.
 constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;

@@ -58,3 +58,55 @@ def test_heff_matches_oracle(ctx, kind, kw):
     assert err < 1e-12 * scale
     assert rep["alg_flops"] == pytest.approx(heff_flops(h["T"], h["L"], h["B"], h["R"], h["W"],
                                                         h["A"]), rel=1e-12)
+
+
+@pytest.mark.parametrize("kind,kw", CASES, ids=[c[0] for c in CASES])
+def test_prepared_operator_replays_equal_eager(ctx, kind, kw):
+    """The prepared operator (T L and B R once, the three vector-dependent
+    products replayed as a HIP graph): every replay, with other device work
+    and synchronisations between them, equals the eager fpeps_heff_apply of
+    the same vector bit for bit; one replay matches the oracle; the flops of
+    preparation and replay add up to the oracle's count; after the context's
+    workspace is released the handle refuses to replay."""
+    import torch
+    from oracle.heff import heff_apply, heff_flops
+    from oracle.blocks import to_tensor
+    from paper_2511_01039_amd import DeviceTensor, opts_for
+    from paper_2511_01039_amd.binding import FpepsError
+    h = wl.heff_inputs(kind, seed=11, **kw)
+    dv = {n: DeviceTensor.from_host(h[n]) for n in ("T", "L", "B", "R", "W", "A")}
+    opts = opts_for(h["sym"])
+    op, y0, prep = ctx.heff_prepare(dv["T"], dv["L"], dv["B"], dv["R"], dv["W"], dv["A"], opts)
+    ye, erep = ctx.heff_apply(dv["T"], dv["L"], dv["B"], dv["R"], dv["W"], dv["A"], opts)
+    n = ye.nelem
+    assert y0.nelem == n and torch.equal(y0.data[:n], ye.data[:n])
+    A = dv["A"]
+    g = torch.Generator(device="cuda").manual_seed(3)
+    for i in range(4):
+        a = torch.randn(A.nelem, generator=g, device="cuda", dtype=torch.float64)
+        yr, rrep = op.apply(a)
+        # other device work and a host synchronisation between replays
+        junk = torch.randn(256, 256, device="cuda", dtype=torch.float64)
+        (junk @ junk).sum().item()
+        Ai = DeviceTensor(A.legs, A.blocks, A.offsets, a, A.nelem)
+        yi, _ = ctx.heff_apply(dv["T"], dv["L"], dv["B"], dv["R"], dv["W"], Ai, opts)
+        assert torch.equal(yr[:n], yi.data[:n]), f"replay {i} differs from the eager product"
+        if i == 0:
+            host = h["A"]
+            Ah = type(host)(list(host.legs), host.blocks, host.offsets, a.cpu().numpy())
+            want = to_tensor(heff_apply(h["sym"], h["T"], h["L"], h["B"], h["R"], h["W"], Ah))
+            got = yi.to_host()
+            gd, wd = got.to_dict(), want.to_dict()
+            scale = max(float(np.abs(want.data).max()), 1e-300)
+            err = max(float(np.abs(gd[k] - wd[k]).max()) for k in wd if k in gd)
+            assert all(k in gd or np.abs(v).max() == 0 for k, v in wd.items())
+            assert err < 1e-12 * scale
+    assert prep["alg_flops"] + rrep["alg_flops"] == pytest.approx(
+        heff_flops(h["T"], h["L"], h["B"], h["R"], h["W"], h["A"]), rel=1e-12)
+    print(f"{kind}: prepare {prep['alg_flops']:.3e} flops, replay {rrep['alg_flops']:.3e} flops "
+          f"in {rrep['seconds'] * 1e3:.3f} ms")
+    # a released workspace invalidates the handle
+    ctx.use_hip_allocator()
+    with pytest.raises(FpepsError):
+        op.apply(a)
+    op.close()
