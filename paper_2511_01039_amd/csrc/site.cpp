@@ -387,7 +387,7 @@ Status SiteOp::plan_host(const std::vector<int32_t>& k, int64_t budget, Plans& o
   // whole chain fits the budget (many small sectors) is still packed into at
   // least MIN_SLICES slices of about equal work, so that its planning is
   // spread over the threads (results do not depend on the slicing).
-  constexpr int MIN_SLICES = 8;
+  constexpr int MIN_SLICES = 16;
   double total_work = 0;
   for (int J = 0; J < ns; ++J) {
     if (k[J] <= 0 || sect[J].m == 0) continue;
