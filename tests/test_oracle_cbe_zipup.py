@@ -90,3 +90,23 @@ def test_expanded_row_isometries():
     # every bond of the expanded row is its truncation plus the expansion
     for k1, c in zip(i1["kept"], i1["cbe"]):
         assert sum(k1) == sum(c["kept"]) + min(6, sum(k1) - sum(c["kept"]))
+
+
+def test_sign_gauge_rule():
+    """The canonical gauge of a truncated factorisation U R: each column of U
+    (with the matching row of R) is flipped so that its leading entry is
+    positive, the leading entry being the first in row order whose magnitude
+    lies within a relative 1e-5 of the column's largest. Entries 2e-5 below
+    the largest do not count as ties; entries 5e-6 below do."""
+    U = np.array([[0.3, -0.5, 0.5],
+                  [-0.6, 0.5 * (1 - 5e-6), -0.5 * (1 + 1e-6)],
+                  [0.6 * (1 - 2e-5), 0.1, 0.2]])
+    R = np.arange(9.0).reshape(3, 3)
+    U2, R2 = fix_signs(U, R)
+    # column 0: the largest is row 1 (negative), row 2 is outside the window
+    # column 1: rows 0 and 1 tie; row 0 leads and is negative
+    # column 2: rows 0 and 1 tie; row 0 leads and is positive (no flip)
+    assert U2[1, 0] > 0 and U2[0, 1] > 0 and U2[0, 2] > 0
+    assert np.array_equal(U2[:, 2], U[:, 2]) and np.array_equal(R2[2], R[2])
+    assert np.array_equal(U2[:, :2], -U[:, :2]) and np.array_equal(R2[:2], -R[:2])
+    assert np.allclose(U2 @ R2, U @ R, rtol=0, atol=0)
