@@ -81,28 +81,57 @@ __device__ __forceinline__ void load_tile(const TA* __restrict__ A,
   // branch-free: indices are clamped into the block (always a valid
   // address), every table and data load of the tile is issued before any is
   // used, and out-of-range elements are zeroed when the tile is stored to LDS
-  // (after the current tile's products, so the loads stay in flight meanwhile)
+  // (after the current tile's products, so the loads stay in flight meanwhile).
+  // Element i of a thread is e = tid + 256 i of the tile. With A contiguous
+  // along K (akf) it is (m, k) = (e / KT, e % KT), else (e % MT, e / MT); as
+  // MT, KT and 256 / KT divide 256, one of the two indices is the same for
+  // all i, and its table entry is loaded once. B likewise.
   constexpr int NA = (MT * KT) / 256, NB = (NT * KT) / 256;
   static_assert(NA + NB <= 32, "validity mask");
+  static_assert(256 % MT == 0 && 256 % NT == 0 && 256 % KT == 0, "tile divides 256");
   int32_t oa[NA], ob[NB];
   uint32_t valid = 0;
+  if (r.akf) {
+    const int k = t.kb + tid % KT;
+    const int32_t ok = tak[min(k, kend - 1)];
+    const bool kv = k < kend;
 #pragma unroll
-  for (int i = 0; i < NA; ++i) {
-    const int e = tid + i * 256;
-    const int mm = r.akf ? e / KT : e % MT;
-    const int kk = r.akf ? e % KT : e / MT;
-    const int m = job.m0 + mm, k = t.kb + kk;
-    valid |= (m < job.M && k < kend) ? (1u << i) : 0u;
-    oa[i] = tam[min(m, job.M - 1)] + tak[min(k, kend - 1)];
+    for (int i = 0; i < NA; ++i) {
+      const int m = job.m0 + tid / KT + i * (256 / KT);
+      valid |= (m < job.M && kv) ? (1u << i) : 0u;
+      oa[i] = tam[min(m, job.M - 1)] + ok;
+    }
+  } else {
+    const int m = job.m0 + tid % MT;
+    const int32_t om = tam[min(m, job.M - 1)];
+    const bool mv = m < job.M;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int k = t.kb + tid / MT + i * (256 / MT);
+      valid |= (mv && k < kend) ? (1u << i) : 0u;
+      oa[i] = om + tak[min(k, kend - 1)];
+    }
   }
+  if (r.bnf) {
+    const int n = job.n0 + tid % NT;
+    const int32_t on = tbn[min(n, job.N - 1)];
+    const bool nv = n < job.N;
 #pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    const int e = tid + i * 256;
-    const int nn = r.bnf ? e % NT : e / KT;
-    const int kk = r.bnf ? e / NT : e % KT;
-    const int n = job.n0 + nn, k = t.kb + kk;
-    valid |= (n < job.N && k < kend) ? (1u << (NA + i)) : 0u;
-    ob[i] = tbk[min(k, kend - 1)] + tbn[min(n, job.N - 1)];
+    for (int i = 0; i < NB; ++i) {
+      const int k = t.kb + tid / NT + i * (256 / NT);
+      valid |= (nv && k < kend) ? (1u << (NA + i)) : 0u;
+      ob[i] = tbk[min(k, kend - 1)] + on;
+    }
+  } else {
+    const int k = t.kb + tid % KT;
+    const int32_t ok = tbk[min(k, kend - 1)];
+    const bool kv = k < kend;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int n = job.n0 + tid / KT + i * (256 / KT);
+      valid |= (n < job.N && kv) ? (1u << (NA + i)) : 0u;
+      ob[i] = ok + tbn[min(n, job.N - 1)];
+    }
   }
 #pragma unroll
   for (int i = 0; i < NA; ++i) r.a[i] = (TM)Ab[oa[i]];
