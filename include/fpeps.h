@@ -148,7 +148,10 @@ typedef struct {
                              not resolved by a backward-stable factorisation */
 } fpeps_opts;
 
-#define FPEPS_FLAG_NO_GRAPH 1u      /* do not capture per-site launch sequences */
+#define FPEPS_FLAG_NO_GRAPH 1u      /* fpeps_heff_prepare: capture no HIP graph;
+                                       fpeps_heff_apply_prepared then launches the
+                                       three products itself (same kernels, same
+                                       results). No other call captures graphs */
 #define FPEPS_FLAG_CHECK_FINITE 2u  /* scan inputs for NaN/Inf first */
 #define FPEPS_FLAG_TIME_KERNELS 4u  /* time every chain launch with HIP events */
 #define FPEPS_FLAG_ONE_STREAM 8u    /* run every slice on the context's stream (one set of
@@ -359,7 +362,8 @@ fpeps_status fpeps_heff_apply(fpeps_ctx ctx, const fpeps_tensor* T, const fpeps_
  * structure of the vectors (and its data the first product, written to
  * y_out with the output structure). T, L, B, R, W and A may be freed after
  * the call: the handle keeps what it needs on the device, in buffers of its
- * own. Synchronises. The handle belongs to ctx, must be released before
+ * own. With FPEPS_FLAG_NO_GRAPH in opts->flags nothing is captured and each
+ * product launches the kernels directly. Synchronises. The handle belongs to ctx, must be released before
  * fpeps_destroy, and is invalidated by fpeps_set_allocator (later products
  * fail with FPEPS_ERR_ARG). */
 typedef struct fpeps_heff_s* fpeps_heff;

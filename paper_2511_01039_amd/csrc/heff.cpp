@@ -183,6 +183,7 @@ struct fpeps_heff_s {
   double *w = nullptr, *a_in = nullptr, *y_out = nullptr, *part = nullptr;
   int64_t s1 = 1, s2 = 1, s3 = 1, s4 = 1, w_size = 1, a_size = 1, y_size = 1;
   int64_t a_nelem = 0;              // elements of the prepared vector structure
+  bool eager = false;               // FPEPS_FLAG_NO_GRAPH: launch, do not replay
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -266,15 +267,18 @@ Status heff_prepare(fpeps_ctx_s* ctx, const fpeps_tensor* T, const fpeps_tensor*
                           ctx->stream));
   }
   FP_HIP(hipStreamSynchronize(ctx->stream));
-  FP_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
-  FP_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-  Status cs = heff_vec_steps(h.get(), h->cap);
-  hipGraph_t g = nullptr;
-  const hipError_t ce = hipStreamEndCapture(h->cap, &g);
-  FP_TRY(cs);
-  FP_HIP(ce);
-  h->graph = g;
-  FP_HIP(hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0));
+  h->eager = (o->flags & FPEPS_FLAG_NO_GRAPH) != 0;
+  if (!h->eager) {
+    FP_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    FP_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    Status cs = heff_vec_steps(h.get(), h->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(h->cap, &g);
+    FP_TRY(cs);
+    FP_HIP(ce);
+    h->graph = g;
+    FP_HIP(hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0));
+  }
   h->ws_gen = ctx->ws_generation;
   if (rep) {
     rep->alg_flops = hp.flops[0] + hp.flops[3];
@@ -307,7 +311,10 @@ Status heff_apply_prepared(fpeps_heff_s* h, const double* a, int64_t a_elems, do
   FP_HIP(hipEventRecord(evp.a, ctx->stream));
   FP_HIP(hipMemcpyAsync(h->a_in, a, a_elems * sizeof(double), hipMemcpyDeviceToDevice,
                         ctx->stream));
-  FP_HIP(hipGraphLaunch(h->exec, ctx->stream));
+  if (h->eager)
+    FP_TRY(heff_vec_steps(h, ctx->stream));
+  else
+    FP_HIP(hipGraphLaunch(h->exec, ctx->stream));
   if (h->hp.Y.size > 0)
     FP_HIP(hipMemcpyAsync(y, h->y_out, h->hp.Y.size * sizeof(double), hipMemcpyDeviceToDevice,
                           ctx->stream));

@@ -280,6 +280,10 @@ __device__ __forceinline__ void row_levels(const RtGroup& G, int m, int32_t (&id
   }
 }
 
+// Loads each thread keeps in flight while staging X rows into LDS (16
+// measured 1% faster over the layer steps of a row than 8).
+constexpr int RT_STAGE_BATCH = 16;
+
 template <class T>
 __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
     const T* __restrict__ X, const double* __restrict__ PK_, T* __restrict__ Y,
@@ -312,27 +316,28 @@ __global__ __launch_bounds__(RT_THREADS) void k_rt_f64(
   row_levels(G, live ? m : G.M - 1, idx);
   if (G.staged) {
     // stage the staged columns slot, slot + nslot, ... (slot = tid / rows
-    // is uniform per wave), eight loads in flight per batch
+    // is uniform per wave), RT_STAGE_BATCH loads in flight per batch
     const int nslot = RT_THREADS >> lrows;
     const int slot = __builtin_amdgcn_readfirstlane(tid >> lrows);
     const FP_CONST RtCol* gc = cols + G.c0;
     T* lst = lds + (r >> 6) * G.ktot * 64 + (r & 63);
-    for (int c0 = slot; c0 < G.ktot; c0 += 8 * nslot) {
+    constexpr int SB = RT_STAGE_BATCH;
+    for (int c0 = slot; c0 < G.ktot; c0 += SB * nslot) {
       // descriptors of the batch first (clamped: always valid), then the
-      // eight loads, then the LDS writes
-      RtCol C[8];
+      // loads, then the LDS writes
+      RtCol C[SB];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) C[u] = ld(gc + min(c0 + u * nslot, G.ktot - 1));
-      double v[8];
+      for (int u = 0; u < SB; ++u) C[u] = ld(gc + min(c0 + u * nslot, G.ktot - 1));
+      double v[SB];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < SB; ++u) {
         int32_t xo = 0;
 #pragma unroll
         for (int l = 0; l < RT_MAXLEV; ++l) xo += idx[l] * C[u].xs[l];
         v[u] = (double)X[C[u].xbase + xo];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < SB; ++u) {
         const int c = c0 + u * nslot;
         if (c < G.ktot) lst[c * 64] = (T)v[u];
       }

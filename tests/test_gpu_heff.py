@@ -110,3 +110,27 @@ def test_prepared_operator_replays_equal_eager(ctx, kind, kw):
     with pytest.raises(FpepsError):
         op.apply(a)
     op.close()
+
+
+def test_prepared_operator_without_graph(ctx):
+    """FPEPS_FLAG_NO_GRAPH: the prepared operator launches its three products
+    directly instead of replaying a graph; products equal the graph replays
+    bit for bit."""
+    import torch
+    from paper_2511_01039_amd import DeviceTensor, opts_for
+    from paper_2511_01039_amd.binding import FLAG_NO_GRAPH
+    kind, kw = CASES[-1]
+    h = wl.heff_inputs(kind, seed=12, **kw)
+    dv = {n: DeviceTensor.from_host(h[n]) for n in ("T", "L", "B", "R", "W", "A")}
+    ops = [ctx.heff_prepare(dv["T"], dv["L"], dv["B"], dv["R"], dv["W"], dv["A"],
+                            opts_for(h["sym"], flags=f))[0] for f in (0, FLAG_NO_GRAPH)]
+    g = torch.Generator(device="cuda").manual_seed(4)
+    n = ops[0].y_like.nelem
+    for _ in range(3):
+        a = torch.randn(dv["A"].nelem, generator=g, device="cuda", dtype=torch.float64)
+        yg, _ = ops[0].apply(a)
+        ye, rep = ops[1].apply(a)
+        assert rep["alg_flops"] > 0
+        assert torch.equal(yg[:n], ye[:n])
+    for op in ops:
+        op.close()
