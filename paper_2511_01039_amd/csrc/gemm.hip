@@ -85,52 +85,86 @@ __device__ __forceinline__ void load_tile(const TA* __restrict__ A,
   // Element i of a thread is e = tid + 256 i of the tile. With A contiguous
   // along K (akf) it is (m, k) = (e / KT, e % KT), else (e % MT, e / MT); as
   // MT, KT and 256 / KT divide 256, one of the two indices is the same for
-  // all i, and its table entry is loaded once. B likewise.
+  // all i, and its table entry is loaded once. B likewise. A table that is a
+  // row-major run (stride s > 0 in the pair) is not read at all: entry i is
+  // i * s.
   constexpr int NA = (MT * KT) / 256, NB = (NT * KT) / 256;
   static_assert(NA + NB <= 32, "validity mask");
   static_assert(256 % MT == 0 && 256 % NT == 0 && 256 % KT == 0, "tile divides 256");
   int32_t oa[NA], ob[NB];
   uint32_t valid = 0;
   if (r.akf) {
-    const int k = t.kb + tid % KT;
-    const int32_t ok = tak[min(k, kend - 1)];
+    const int k = t.kb + tid % KT, kc = min(k, kend - 1);
+    const int32_t ok = pr.sak > 0 ? kc * pr.sak : tak[kc];
     const bool kv = k < kend;
+    int mc[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int m = job.m0 + tid / KT + i * (256 / KT);
       valid |= (m < job.M && kv) ? (1u << i) : 0u;
-      oa[i] = tam[min(m, job.M - 1)] + ok;
+      mc[i] = min(m, job.M - 1);
+    }
+    if (pr.sam > 0) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) oa[i] = mc[i] * pr.sam + ok;
+    } else {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) oa[i] = tam[mc[i]] + ok;
     }
   } else {
-    const int m = job.m0 + tid % MT;
-    const int32_t om = tam[min(m, job.M - 1)];
+    const int m = job.m0 + tid % MT, mc = min(m, job.M - 1);
+    const int32_t om = pr.sam > 0 ? mc * pr.sam : tam[mc];
     const bool mv = m < job.M;
+    int kc[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int k = t.kb + tid / MT + i * (256 / MT);
       valid |= (mv && k < kend) ? (1u << i) : 0u;
-      oa[i] = om + tak[min(k, kend - 1)];
+      kc[i] = min(k, kend - 1);
+    }
+    if (pr.sak > 0) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) oa[i] = om + kc[i] * pr.sak;
+    } else {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) oa[i] = om + tak[kc[i]];
     }
   }
   if (r.bnf) {
-    const int n = job.n0 + tid % NT;
-    const int32_t on = tbn[min(n, job.N - 1)];
+    const int n = job.n0 + tid % NT, nc = min(n, job.N - 1);
+    const int32_t on = pr.sbn > 0 ? nc * pr.sbn : tbn[nc];
     const bool nv = n < job.N;
+    int kc[NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int k = t.kb + tid / NT + i * (256 / NT);
       valid |= (nv && k < kend) ? (1u << (NA + i)) : 0u;
-      ob[i] = tbk[min(k, kend - 1)] + on;
+      kc[i] = min(k, kend - 1);
+    }
+    if (pr.sbk > 0) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) ob[i] = kc[i] * pr.sbk + on;
+    } else {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) ob[i] = tbk[kc[i]] + on;
     }
   } else {
-    const int k = t.kb + tid % KT;
-    const int32_t ok = tbk[min(k, kend - 1)];
+    const int k = t.kb + tid % KT, kc = min(k, kend - 1);
+    const int32_t ok = pr.sbk > 0 ? kc * pr.sbk : tbk[kc];
     const bool kv = k < kend;
+    int nc[NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int n = job.n0 + tid / KT + i * (256 / KT);
       valid |= (n < job.N && kv) ? (1u << (NA + i)) : 0u;
-      ob[i] = ok + tbn[min(n, job.N - 1)];
+      nc[i] = min(n, job.N - 1);
+    }
+    if (pr.sbn > 0) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) ob[i] = ok + nc[i] * pr.sbn;
+    } else {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) ob[i] = ok + tbn[nc[i]];
     }
   }
 #pragma unroll

@@ -160,7 +160,27 @@ struct SectKeyHash {
 struct TabRef {
   int32_t id;
   int64_t maxoff;
+  int32_t lin = 0;   // > 0: entry i is i * lin
 };
+
+// Stride s when the offsets of legs ``dims``/``strides`` (last fastest) are
+// i * s for the row-major index i, else 0. Legs of dimension 1 do not count.
+int32_t linear_stride(const std::vector<int32_t>& dims, const std::vector<int64_t>& strides) {
+  int64_t s = 0, run = 0;
+  for (int i = (int)dims.size() - 1; i >= 0; --i) {
+    if (dims[i] <= 1) continue;
+    if (run == 0) {
+      s = strides[i];
+      if (s <= 0) return 0;
+      run = s * dims[i];
+    } else {
+      if (strides[i] != run) return 0;
+      run *= dims[i];
+    }
+  }
+  if (run == 0) return 1;   // every leg has dimension 1: one entry, 0
+  return s <= INT32_MAX ? (int32_t)s : 0;
+}
 
 TabRef make_table(TablePool& pool, const BT& bt, const Block& b, const std::vector<int>& pos,
                   bool* ok) {
@@ -177,13 +197,17 @@ TabRef make_table(TablePool& pool, const BT& bt, const Block& b, const std::vect
     dims.push_back(1);
     strides.push_back(0);
   }
-  return {pool.add(dims, strides, ok), mx};
+  TabRef t{pool.add(dims, strides, ok), mx};
+  t.lin = linear_stride(dims, strides);
+  return t;
 }
 
 TabRef make_table_dense(TablePool& pool, int32_t n, int64_t stride, bool* ok) {
   std::vector<int32_t> d{std::max(n, 1)};
   std::vector<int64_t> st{stride};
-  return {pool.add(d, st, ok), (int64_t)(std::max(n, 1) - 1) * stride};
+  TabRef t{pool.add(d, st, ok), (int64_t)(std::max(n, 1) - 1) * stride};
+  t.lin = linear_stride(d, st);
+  return t;
 }
 
 int64_t prod_dims(const BT& bt, const Block& b, const std::vector<int>& pos) {
@@ -577,6 +601,10 @@ bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sy
     gp.tak = tak.id;
     gp.tbk = tbk.id;
     gp.tbn = tbn.id;
+    gp.sam = tam.lin;
+    gp.sak = tak.lin;
+    gp.sbk = tbk.lin;
+    gp.sbn = tbn.lin;
     gp.flags = 0;
     if (!ak.empty() && abk.stride[ak.back()] == 1) gp.flags |= 1;
     if (!bfree.empty() && bbk.stride[bfree.back()] == 1) gp.flags |= 2;
@@ -1072,7 +1100,9 @@ bool plan_dense(const std::vector<DenseOp>& ops, TablePool& pool, int mt, int nt
   auto tab = [&](int32_t n, int64_t s) -> TabRef {
     std::vector<int32_t> d{std::max(n, 1)};
     std::vector<int64_t> st{s};
-    return {pool.add(d, st, &ok), (int64_t)(std::max(n, 1) - 1) * s};
+    TabRef t{pool.add(d, st, &ok), (int64_t)(std::max(n, 1) - 1) * s};
+    t.lin = linear_stride(d, st);
+    return t;
   };
   for (const DenseOp& op : ops) {
     if (op.M <= 0 || op.N <= 0) continue;
@@ -1086,6 +1116,10 @@ bool plan_dense(const std::vector<DenseOp>& ops, TablePool& pool, int mt, int nt
     gp.tak = tak.id;
     gp.tbk = tbk.id;
     gp.tbn = tbn.id;
+    gp.sam = tam.lin;
+    gp.sak = tak.lin;
+    gp.sbk = tbk.lin;
+    gp.sbn = tbn.lin;
     gp.flags = (op.a_cs == 1 ? 1 : 0) | (op.b_cs == 1 ? 2 : 0);
     gp.alpha = op.alpha;
     plan.a_extent = std::max(plan.a_extent, op.a_off + tam.maxoff + tak.maxoff + 1);

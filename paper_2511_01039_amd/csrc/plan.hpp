@@ -90,6 +90,9 @@ struct GemmPair {
   int32_t K;
   int32_t tam, tak, tbk, tbn;
   int32_t flags;   // bit0: A rows contiguous along K; bit1: B contiguous along N
+  // > 0: that table is i * stride (a row-major run of its legs), so the
+  // kernel computes the offset instead of reading it; 0: read the table
+  int32_t sam, sak, sbk, sbn;
   double alpha;
 };
 

@@ -9,8 +9,9 @@
 // column, X element, packed layer value, layer element and output element
 // of every row of every group. All of them must fall inside the buffers,
 // every output element must be written exactly once, and the flop counts
-// must equal 2 m n k over the block pairs. Exit status 0 when every check
-// holds.
+// must equal 2 m n k over the block pairs. A table the plan marks as a
+// row-major run (offset computed as i * stride, not read) must hold exactly
+// those values. Exit status 0 when every check holds.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -26,6 +27,7 @@ using namespace fp;
 namespace {
 
 int failures = 0;
+long linear_pairs = 0;
 #define CHECK(c)                                                                    \
   do {                                                                              \
     if (!(c)) {                                                                     \
@@ -117,6 +119,16 @@ void check_gemm(const BT& X, const BT& S, const StepResult& r, const TablePool& 
         tb = std::max(tb, T.at(pr.tbk, k));
         CHECK(T.at(pr.tak, k) >= 0 && T.at(pr.tbk, k) >= 0);
       }
+      // a table flagged as a row-major run must equal i * stride
+      auto linear_ok = [&](int32_t id, int32_t s, int n) {
+        if (s <= 0) return true;
+        for (int i = 0; i < n; ++i)
+          if (T.at(id, i) != (int64_t)i * s) return false;
+        return true;
+      };
+      CHECK(linear_ok(pr.tam, pr.sam, j.M) && linear_ok(pr.tak, pr.sak, pr.K));
+      CHECK(linear_ok(pr.tbk, pr.sbk, pr.K) && linear_ok(pr.tbn, pr.sbn, j.N));
+      if (pr.sam > 0 || pr.sak > 0 || pr.sbk > 0 || pr.sbn > 0) ++linear_pairs;
       amax = pr.a_off + tm + tk;
       bmax = pr.b_off + tb + tn;
       amin = pr.a_off;
@@ -311,9 +323,12 @@ int main(int argc, char** argv) {
       }
     }
   }
-  std::printf("planned %d GEMM steps (%d split-K), %d layer steps (%d staged groups); "
-              "%d refused%s%s; %d failed checks\n",
-              plans, splits, rt_plans, staged, refused, refused ? ": " : "", last_err.c_str(),
-              failures);
-  return failures == 0 && refused == 0 && plans > 0 && rt_plans > 0 && splits > 0 ? 0 : 1;
+  std::printf("planned %d GEMM steps (%d split-K, %ld pair visits with computed offsets), "
+              "%d layer steps (%d staged groups); %d refused%s%s; %d failed checks\n",
+              plans, splits, linear_pairs, rt_plans, staged, refused, refused ? ": " : "",
+              last_err.c_str(), failures);
+  return failures == 0 && refused == 0 && plans > 0 && rt_plans > 0 && splits > 0 &&
+                 linear_pairs > 0
+             ? 0
+             : 1;
 }
