@@ -364,6 +364,13 @@ def main():
                     help="mixed-vs-fp64 (default): time both paths on the same row and report the "
                          "mixed one if its network value is within 1e-6 of FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", type=int, default=2,
+                    help="tile candidates of the autotuner, run on the headline row in its first "
+                         "warmup step (slice budget and GEMM tiles measured on the row); 0: the "
+                         "planner's model")
+    ap.add_argument("--tune-file", default="",
+                    help="load this tuned table (written by --save-tune) instead of tuning")
+    ap.add_argument("--save-tune", default="", help="write the tuned table to this file")
     ap.add_argument("--per-site", action="store_true",
                     help="config 5 --explicit: one truncation and one expansion call per site")
     ap.add_argument("--explicit", action="store_true",
@@ -415,7 +422,7 @@ def main():
     T, A, W = dev(row.T), dev(row.A), dev(row.W)
     ctx = Context(0)
 
-    def run(precision, steps, warmup):
+    def run(precision, steps, warmup, tune_here):
         """``warmup`` untimed + ``steps`` timed absorptions of the row;
         device-resident inputs. The last warmup step (or one more step when
         there is none) is the kernel-timing step."""
@@ -430,8 +437,25 @@ def main():
         kopts = opts_for(row.sym, flags=FLAG_ONE_STREAM | FLAG_TIME_KERNELS, **kw)
         caps = None
         krep = None
+        tune = None
         for i in range(warmup):
             last = i == warmup - 1
+            if i == 0 and tune_here:
+                # slice budget and GEMM tiles measured on this row (untimed);
+                # the context keeps them for every later absorption
+                t0 = time.perf_counter()
+                out, lg, rep = ctx.env_absorb(T, A, W, opts, caps=caps, autotune=a.autotune)
+                n, b = ctx.tune_info()
+                tune = {"tile_candidates": a.autotune, "tuned_signatures": n,
+                        "slice_budget_gib": b / 2**30,
+                        "tuning_seconds": time.perf_counter() - t0}
+                print(f"{precision} autotune: {n} step signatures, slice budget "
+                      f"{b / 2**30:.0f} GiB, {tune['tuning_seconds']:.1f} s", file=sys.stderr,
+                      flush=True)
+                caps = [(max(256, max(l.nsect for l in t.legs)), max(t.blocks.shape[0], 1),
+                         max(t.nelem, 1)) for t in out]
+                if not last:
+                    continue
             out, lg, rep = ctx.env_absorb(T, A, W, kopts if last else opts, caps=caps)
             print(f"{precision} warmup {i}{' (kernel-timing, one stream)' if last else ''}: "
                   f"{rep['seconds']:.3f} s device", file=sys.stderr, flush=True)
@@ -463,6 +487,7 @@ def main():
             cls[k] = krep[k]
         r["kernel_step_s"] = krep["seconds"]
         r["cls"], r["out"], r["lg"] = cls, out, lg
+        r["tune"] = tune
         # singular values of every truncated site (the kernel-timing step's,
         # same arithmetic as the timed steps)
         r["sig"] = [ctx.absorb_diag(x)[0] for x in range(len(out) - 1)]
@@ -472,9 +497,16 @@ def main():
     # the headline path times exactly --steps steps; the mixed path beside it
     # (a comparison) at most 3 after at most 1 warmup step
     res = {}
+    # the autotuner runs once, on the headline path's row, in its first
+    # warmup step; a saved table (--tune-file) replaces it
+    if a.tune_file:
+        ctx.tune_load(a.tune_file)
     for i, p in enumerate(precs):
         res[p] = run(p, a.steps if i == 0 else min(a.steps, 3),
-                     a.warmup if i == 0 else min(a.warmup, 1))
+                     a.warmup if i == 0 else min(a.warmup, 1),
+                     i == 0 and a.autotune > 0 and not a.tune_file)
+    if a.save_tune and ctx.tune_info()[0] >= 0:
+        ctx.tune_save(a.save_tune)
     # mixed vs FP64: the gauge-invariant network value of the new environment
     # against one fixed random bottom environment, both on the device
     cmp = None
@@ -573,7 +605,9 @@ def main():
                        if rep_prec == "fp32" else "fp64",
                        "alg_flops_per_step": R["flops"] / R["steps"],
                        "device_seconds_per_step": R["dev_s"] / R["steps"]},
-            "roofline": roof}
+            "roofline": roof,
+            # how the slice budget and GEMM tiles of the timed steps were chosen
+            "autotune": R.get("tune") or ({"loaded": a.tune_file} if a.tune_file else None)}
     if cmp is not None:
         line["mixed_vs_fp64"] = cmp
     if not a.no_cpu_baseline:

@@ -239,6 +239,44 @@ fpeps_status fpeps_env_absorb(fpeps_ctx ctx, int32_t L, const fpeps_tensor* env_
                               const fpeps_opts* opts, fpeps_tensor* env_out,
                               double* log_norm, fpeps_report* report);
 
+/* fpeps_env_absorb with its slice budget and GEMM tiles chosen by
+ * measurement on this row (the autotuner). When opts->slice_budget is 0 the
+ * row is first absorbed once per budget candidate (16, 32 and 64 GiB) on the
+ * library's streams and the fastest is kept. Then, at that budget, it is
+ * absorbed tile_candidates times (1 to 4) on one stream with every GEMM
+ * launch timed: run r gives every grouped GEMM step the r-th tile of the
+ * planner's padding-efficiency ranking, and each step signature (a hash of
+ * the step and its output block sizes and contracted extents) keeps the
+ * tile with the smallest mean launch time. The table is stored in the
+ * context: later fpeps_env_absorb and fpeps_site_apply calls use the tuned
+ * tile of every step whose signature it holds (other steps keep the model's
+ * tile), and the tuned budget when their opts->slice_budget is 0. Finally the
+ * row is absorbed with the tuned choices into env_out, *log_norm and the
+ * report, as fpeps_env_absorb does (the tuning runs' results are discarded).
+ * Results differ from the untuned call only by rounding (tiles change the
+ * split of long contractions). On failure the context keeps its previous
+ * table. Synchronises many times; costs 4 + tile_candidates absorptions
+ * (1 + tile_candidates when opts->slice_budget is set). */
+fpeps_status fpeps_autotune_absorb(fpeps_ctx ctx, int32_t L, const fpeps_tensor* env_in,
+                                   const fpeps_tensor* ket, const fpeps_tensor* pepo,
+                                   const fpeps_opts* opts, int32_t tile_candidates,
+                                   fpeps_tensor* env_out, double* log_norm,
+                                   fpeps_report* report);
+/* The context's tuned table as a text file (on-disk autotune cache), and
+ * back. Format: lines starting with '#' are comments; "fpeps-tune 1";
+ * "slice_budget <bytes>"; then one "<signature, 16 hex digits> <mt> <nt>"
+ * line per tuned step. fpeps_tune_save fails with FPEPS_ERR_ARG when the
+ * context has no table or the file cannot be written; fpeps_tune_load
+ * replaces the context's table and fails, keeping it, on a file that is not
+ * a table of this format (or names a tile the kernel does not have).
+ * fpeps_tune_clear drops the table (the planner's model again).
+ * fpeps_tune_info: number of tuned signatures (-1 without a table) and the
+ * tuned slice budget in bytes (0: none). */
+fpeps_status fpeps_tune_save(fpeps_ctx ctx, const char* path);
+fpeps_status fpeps_tune_load(fpeps_ctx ctx, const char* path);
+fpeps_status fpeps_tune_clear(fpeps_ctx ctx);
+fpeps_status fpeps_tune_info(fpeps_ctx ctx, int32_t* entries, int64_t* slice_budget);
+
 /* Per-site diagnostics of the last fpeps_env_absorb on this context:
  * the singular values of every sector (sectors in label order, each
  * descending), the sector of each value and the kept count per sector. */
@@ -363,9 +401,9 @@ fpeps_status fpeps_heff_apply(fpeps_ctx ctx, const fpeps_tensor* T, const fpeps_
  * y_out with the output structure). T, L, B, R, W and A may be freed after
  * the call: the handle keeps what it needs on the device, in buffers of its
  * own. With FPEPS_FLAG_NO_GRAPH in opts->flags nothing is captured and each
- * product launches the kernels directly. Synchronises. The handle belongs to ctx, must be released before
- * fpeps_destroy, and is invalidated by fpeps_set_allocator (later products
- * fail with FPEPS_ERR_ARG). */
+ * product launches the kernels directly. Synchronises. The handle belongs
+ * to ctx, must be released before fpeps_destroy, and is invalidated by
+ * fpeps_set_allocator (later products fail with FPEPS_ERR_ARG). */
 typedef struct fpeps_heff_s* fpeps_heff;
 fpeps_status fpeps_heff_prepare(fpeps_ctx ctx, const fpeps_tensor* T, const fpeps_tensor* L,
                                 const fpeps_tensor* B, const fpeps_tensor* R,

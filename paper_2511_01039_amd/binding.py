@@ -133,6 +133,12 @@ def load():
         "fpeps_heff_apply_prepared": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                                        P(CReport)], C.c_int),
         "fpeps_heff_release": ([C.c_void_p], C.c_int),
+        "fpeps_autotune_absorb": ([C.c_void_p, C.c_int32, T, T, T, P(COpts), C.c_int32, T,
+                                   P(C.c_double), P(CReport)], C.c_int),
+        "fpeps_tune_save": ([C.c_void_p, C.c_char_p], C.c_int),
+        "fpeps_tune_load": ([C.c_void_p, C.c_char_p], C.c_int),
+        "fpeps_tune_clear": ([C.c_void_p], C.c_int),
+        "fpeps_tune_info": ([C.c_void_p, P(C.c_int32), P(C.c_int64)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -148,7 +154,8 @@ def exported_symbols():
             "fpeps_site_apply", "fpeps_rsvd_truncate", "fpeps_rsvd_truncate_grouped",
             "fpeps_cbe_expand", "fpeps_cbe_expand_grouped", "fpeps_expect",
             "fpeps_heff_apply", "fpeps_heff_prepare", "fpeps_heff_apply_prepared",
-            "fpeps_heff_release", "fpeps_expect_noalloc"]
+            "fpeps_heff_release", "fpeps_expect_noalloc", "fpeps_autotune_absorb",
+            "fpeps_tune_save", "fpeps_tune_load", "fpeps_tune_clear", "fpeps_tune_info"]
 
 
 def _i32(a):
@@ -304,8 +311,10 @@ class Context:
             raise FpepsError(rc, self.lib.fpeps_last_error(self.h).decode())
 
     # ---------------------------------------------------------------------
-    def env_absorb(self, env_in, ket, pepo, opts, log_norm=0.0, caps=None):
-        """Absorb one row. Returns (list of DeviceTensor, log_norm, report)."""
+    def env_absorb(self, env_in, ket, pepo, opts, log_norm=0.0, caps=None, autotune=0):
+        """Absorb one row. Returns (list of DeviceTensor, log_norm, report).
+        ``autotune`` > 0: fpeps_autotune_absorb with that many tile
+        candidates (the context keeps the tuned table)."""
         L = len(env_in)
         keep = []
         ein = (CTensor * L)(*[t.ctensor(keep) for t in env_in])
@@ -317,8 +326,13 @@ class Context:
             oarr = (CTensor * L)(*[o.ct for o in outs])
             ln = C.c_double(log_norm)
             rep = CReport()
-            rc = self.lib.fpeps_env_absorb(self.h, L, ein, kin, pin, C.byref(opts), oarr,
-                                           C.byref(ln), C.byref(rep))
+            if autotune:
+                rc = self.lib.fpeps_autotune_absorb(self.h, L, ein, kin, pin, C.byref(opts),
+                                                    int(autotune), oarr, C.byref(ln),
+                                                    C.byref(rep))
+            else:
+                rc = self.lib.fpeps_env_absorb(self.h, L, ein, kin, pin, C.byref(opts), oarr,
+                                               C.byref(ln), C.byref(rep))
             if rc == -7 and attempt == 0:
                 caps = [(max(c[0], rep.required_sect), max(c[1], rep.required_blocks),
                          max(c[2], rep.required_elem)) for c in caps]
@@ -328,6 +342,21 @@ class Context:
                 o.ct = oc
             return [o.result() for o in outs], ln.value, rep.as_dict()
         raise FpepsError(-7, "capacity")
+
+    def tune_save(self, path):
+        self.check(self.lib.fpeps_tune_save(self.h, os.fsencode(path)))
+
+    def tune_load(self, path):
+        self.check(self.lib.fpeps_tune_load(self.h, os.fsencode(path)))
+
+    def tune_clear(self):
+        self.check(self.lib.fpeps_tune_clear(self.h))
+
+    def tune_info(self):
+        """(tuned step signatures or -1 without a table, tuned slice budget in bytes)."""
+        n, b = C.c_int32(), C.c_int64()
+        self.check(self.lib.fpeps_tune_info(self.h, C.byref(n), C.byref(b)))
+        return n.value, b.value
 
     def absorb_diag(self, site, capacity=1 << 16):
         sig = np.zeros(capacity)

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfpeps.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["gemm.hip", "layer.hip", "linalg.hip", "dense.hip", "noalloc.hip", "plan.cpp", "core.cpp", "site.cpp",
-           "driver.cpp", "heff.cpp", "capi.cpp"]
+           "driver.cpp", "heff.cpp", "tune.cpp", "capi.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 instructions stay off: some of their forms have given

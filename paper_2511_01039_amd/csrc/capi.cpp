@@ -100,6 +100,34 @@ fpeps_status fpeps_env_absorb(fpeps_ctx ctx, int32_t L, const fpeps_tensor* env_
   });
 }
 
+fpeps_status fpeps_autotune_absorb(fpeps_ctx ctx, int32_t L, const fpeps_tensor* env_in,
+                                   const fpeps_tensor* ket, const fpeps_tensor* pepo,
+                                   const fpeps_opts* opts, int32_t tile_candidates,
+                                   fpeps_tensor* env_out, double* log_norm,
+                                   fpeps_report* report) {
+  return guarded(ctx, [&] {
+    if (report) std::memset(report, 0, sizeof(*report));
+    return fp::autotune_absorb(ctx, L, env_in, ket, pepo, opts, tile_candidates, env_out,
+                               log_norm, report);
+  });
+}
+
+fpeps_status fpeps_tune_save(fpeps_ctx ctx, const char* path) {
+  return guarded(ctx, [&] { return fp::tune_save(ctx, path); });
+}
+
+fpeps_status fpeps_tune_load(fpeps_ctx ctx, const char* path) {
+  return guarded(ctx, [&] { return fp::tune_load(ctx, path); });
+}
+
+fpeps_status fpeps_tune_clear(fpeps_ctx ctx) {
+  return guarded(ctx, [&] { return fp::tune_clear(ctx); });
+}
+
+fpeps_status fpeps_tune_info(fpeps_ctx ctx, int32_t* entries, int64_t* slice_budget) {
+  return guarded(ctx, [&] { return fp::tune_info(ctx, entries, slice_budget); });
+}
+
 fpeps_status fpeps_absorb_diag(fpeps_ctx ctx, int32_t site, int32_t capacity, double* sigma,
                                int32_t* sector, int32_t* count, int32_t* nsectors,
                                int32_t* kept) {

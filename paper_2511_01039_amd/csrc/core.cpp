@@ -224,12 +224,19 @@ fp::Status fpeps_ctx_s::harvest_timing() {
     b[3] += evbytes[i / 2];
     b[4] += evshape[i / 2][0];
     b[5] += evshape[i / 2][1];
+    if (tune_record && evsig[i / 2]) {
+      auto& t = tune_log[evsig[i / 2]][evtile[i / 2]];
+      t[0] += ms * 1e-3;
+      t[1] += 1;
+    }
   }
   evused = 0;
   evflops.clear();
   evlabel.clear();
   evbytes.clear();
   evshape.clear();
+  evsig.clear();
+  evtile.clear();
   return fp::Status::ok();
 }
 
@@ -443,6 +450,8 @@ Status run_rt(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const void* X, int64
       ctx->evlabel.push_back(ctx->verbose >= 2 ? label + 100 * (c + 1) : label);
       ctx->evbytes.push_back(f32 ? 0.5 * p.l_bytes[c] : p.l_bytes[c]);
       ctx->evshape.push_back({(double)p.l_ntiles[c], (double)p.l_lds[c]});
+      ctx->evsig.push_back(0);
+      ctx->evtile.push_back({0, 0});
       FP_HIP(hipEventRecord(a, ctx->stream));
       FP_HIP(launch_rt_f64(d, c, X, f32, ps.dpack, Y, ps.dtab, ctx->stream));
       FP_HIP(hipEventRecord(b, ctx->stream));
@@ -507,6 +516,8 @@ Status run_gemm_any(fpeps_ctx_s* ctx, const PlanSet& ps, int idx, const double* 
     ctx->evlabel.push_back(label);
     ctx->evbytes.push_back(p.bytes);
     ctx->evshape.push_back({0.0, 0.0});
+    ctx->evsig.push_back(p.sig);
+    ctx->evtile.push_back({p.mt, p.nt});
     FP_HIP(hipEventRecord(ea, ctx->stream));
   }
   if (part) {

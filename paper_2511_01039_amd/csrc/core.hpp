@@ -122,6 +122,21 @@ struct fpeps_ctx_s {
   std::vector<std::array<double, 2>> evshape;  // layer launches: tiles, LDS bytes
   // label -> {seconds, flops, launches, algorithmic bytes, tiles, LDS bytes}
   std::map<int, std::array<double, 6>> kt_by_label;
+  // autotuning: the tuned table the planner consults (absent until a tuning
+  // run or a load), the candidate rank forced during tuning runs, and the
+  // measured seconds per GEMM signature and tile of those runs
+  std::shared_ptr<fp::TuneTable> tune;
+  int tile_rank = -1;
+  bool tune_record = false;
+  std::vector<uint64_t> evsig;   // per timed launch: GEMM signature (0: not a GEMM)
+  std::vector<std::array<int, 2>> evtile;
+  // signature -> tile -> {seconds, launches}
+  std::map<uint64_t, std::map<std::array<int, 2>, std::array<double, 2>>> tune_log;
+  // the SymInfo fields the planner takes from the context
+  void tune_into(fp::SymInfo& s) const {
+    s.tune = tune.get();
+    s.tile_rank = tile_rank;
+  }
   double kt_seconds = 0, kt_flops = 0;
   long kt_launches = 0;
   int verbose = 0;  // FPEPS_VERBOSE: 1 per site and step, 2 also per layer launch class

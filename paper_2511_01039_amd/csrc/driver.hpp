@@ -88,6 +88,16 @@ fpeps_ctx_s* heff_context(fpeps_heff_s* h);
 // frees the handle and its device buffers
 Status heff_release(fpeps_heff_s* h);
 
+// Autotuner (tune.cpp): measures slice budgets and GEMM tiles on the row,
+// keeps the table in the context, and returns the row absorbed with it.
+Status autotune_absorb(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in,
+                       const fpeps_tensor* ket, const fpeps_tensor* pepo, const fpeps_opts* o,
+                       int ncand, fpeps_tensor* env_out, double* log_norm, fpeps_report* rep);
+Status tune_save(fpeps_ctx_s* ctx, const char* path);
+Status tune_load(fpeps_ctx_s* ctx, const char* path);
+Status tune_clear(fpeps_ctx_s* ctx);
+Status tune_info(fpeps_ctx_s* ctx, int32_t* entries, int64_t* slice_budget);
+
 // Bytes of the file-scope device array behind fpeps_expect_noalloc.
 constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
 // The array's device address on ``device`` (that device current), looked up

@@ -218,35 +218,71 @@ int64_t prod_dims(const BT& bt, const Block& b, const std::vector<int>& pos) {
 
 }  // namespace
 
-void choose_tile(const std::vector<std::pair<int64_t, int64_t>>& mn,
-                 const std::vector<int64_t>& ktot, int* mt, int* nt) {
-  static const int cand[][2] = {{128, 128}, {128, 64}, {64, 128}, {64, 64},
-                                {128, 32},  {32, 128}, {256, 16}, {16, 256}};
-  constexpr int NC = sizeof(cand) / sizeof(cand[0]);
-  double eff[NC];
-  double best = 0;
-  for (int c = 0; c < NC; ++c) {
+namespace {
+const int TILE_CAND[][2] = {{128, 128}, {128, 64}, {64, 128}, {64, 64},
+                            {128, 32},  {32, 128}, {256, 16}, {16, 256}};
+constexpr int NTILE = sizeof(TILE_CAND) / sizeof(TILE_CAND[0]);
+
+// padding efficiency of every tile: useful / padded products, weighted by
+// the contracted extent of each output block
+void tile_efficiency(const std::vector<std::pair<int64_t, int64_t>>& mn,
+                     const std::vector<int64_t>& ktot, double* eff, double* best) {
+  *best = 0;
+  for (int c = 0; c < NTILE; ++c) {
     double padded = 0, useful = 0;
     for (size_t i = 0; i < mn.size(); ++i) {
       const int64_t M = mn[i].first, N = mn[i].second;
       const double w = (double)std::max<int64_t>(ktot[i], 1);
-      padded += w * (double)((M + cand[c][0] - 1) / cand[c][0] * cand[c][0]) *
-                (double)((N + cand[c][1] - 1) / cand[c][1] * cand[c][1]);
+      padded += w * (double)((M + TILE_CAND[c][0] - 1) / TILE_CAND[c][0] * TILE_CAND[c][0]) *
+                (double)((N + TILE_CAND[c][1] - 1) / TILE_CAND[c][1] * TILE_CAND[c][1]);
       useful += w * (double)M * (double)N;
     }
     eff[c] = padded > 0 ? useful / padded : 1.0;
-    best = std::max(best, eff[c]);
+    *best = std::max(*best, eff[c]);
   }
+}
+}  // namespace
+
+bool valid_tile(int mt, int nt) {
+  for (int c = 0; c < NTILE; ++c)
+    if (TILE_CAND[c][0] == mt && TILE_CAND[c][1] == nt) return true;
+  return false;
+}
+
+void choose_tile(const std::vector<std::pair<int64_t, int64_t>>& mn,
+                 const std::vector<int64_t>& ktot, int* mt, int* nt) {
+  double eff[NTILE], best = 0;
+  tile_efficiency(mn, ktot, eff, &best);
   // the largest tile (most reuse per loaded element) among those within 15%
   // of the best padding efficiency; candidates are ordered by preference
-  for (int c = 0; c < NC; ++c)
+  for (int c = 0; c < NTILE; ++c)
     if (eff[c] >= 0.85 * best) {
-      *mt = cand[c][0];
-      *nt = cand[c][1];
+      *mt = TILE_CAND[c][0];
+      *nt = TILE_CAND[c][1];
       return;
     }
   *mt = 64;
   *nt = 64;
+}
+
+std::vector<std::array<int, 2>> tile_candidates(const std::vector<std::pair<int64_t, int64_t>>& mn,
+                                                const std::vector<int64_t>& ktot, int max_n) {
+  std::vector<std::array<int, 2>> out;
+  int mt = 64, nt = 64;
+  choose_tile(mn, ktot, &mt, &nt);
+  out.push_back({mt, nt});
+  double eff[NTILE], best = 0;
+  tile_efficiency(mn, ktot, eff, &best);
+  std::vector<int> order;
+  for (int c = 0; c < NTILE; ++c)
+    if (eff[c] >= 0.7 * best && !(TILE_CAND[c][0] == mt && TILE_CAND[c][1] == nt))
+      order.push_back(c);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return eff[a] > eff[b]; });
+  for (int c : order) {
+    if ((int)out.size() >= max_n) break;
+    out.push_back({TILE_CAND[c][0], TILE_CAND[c][1]});
+  }
+  return out;
 }
 
 namespace {
@@ -574,7 +610,35 @@ bool plan_step(const BT& X, const BT& S, const StepSpec& spec, const SymInfo& sy
   for (size_t ob = 0; ob < out.blocks.size(); ++ob)
     for (int t = pstart[ob]; t < pstart[ob + 1]; ++t)
       ktot[ob] += prod_dims(A, spec.m_is_x ? X.blocks[trip[t].xb] : S.blocks[trip[t].sb], ak);
-  choose_tile(mn, ktot, &plan.mt, &plan.nt);
+  {
+    // signature: step, operand roles, and every output block's M, N and
+    // contracted extent in order
+    uint64_t h = splitmix64_mix(0x9e3779b97f4a7c15ull ^ (uint64_t)spec.step);
+    h = splitmix64_mix(h ^ (spec.m_is_x ? 1u : 2u) ^ ((uint64_t)mn.size() << 8));
+    for (size_t ob = 0; ob < mn.size(); ++ob) {
+      h = splitmix64_mix(h ^ (uint64_t)mn[ob].first);
+      h = splitmix64_mix(h ^ (uint64_t)mn[ob].second);
+      h = splitmix64_mix(h ^ (uint64_t)ktot[ob]);
+    }
+    plan.sig = h;
+    const std::array<int16_t, 2>* tuned = nullptr;
+    if (sym.tune) {
+      auto it = sym.tune->tiles.find(h);
+      if (it != sym.tune->tiles.end() && valid_tile(it->second[0], it->second[1]))
+        tuned = &it->second;
+    }
+    if (tuned) {
+      plan.mt = (*tuned)[0];
+      plan.nt = (*tuned)[1];
+    } else if (sym.tile_rank > 0) {
+      const auto c = tile_candidates(mn, ktot, sym.tile_rank + 1);
+      const auto& t = c[std::min<size_t>((size_t)sym.tile_rank, c.size() - 1)];
+      plan.mt = t[0];
+      plan.nt = t[1];
+    } else {
+      choose_tile(mn, ktot, &plan.mt, &plan.nt);
+    }
+  }
   plan.pairs.reserve(trip.size());
   // tables depend only on the block: built once per block
   std::vector<TabRef> c_am(A.blocks.size(), TabRef{-1, 0}), c_ak(A.blocks.size(), TabRef{-1, 0});

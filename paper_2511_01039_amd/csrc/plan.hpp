@@ -76,10 +76,22 @@ struct BT {
 // Row-major contiguous strides for a block of ``bt`` given its sectors.
 void set_rowmajor(const BT& bt, Block& b);
 
+// Measured tile choices (the autotuner's table): GEMM step signature ->
+// tile (M, N), and the slice budget that was fastest for the tuned row.
+struct TuneTable {
+  std::unordered_map<uint64_t, std::array<int16_t, 2>> tiles;
+  int64_t slice_budget = 0;   // bytes; 0: not tuned
+};
+
 struct SymInfo {
   int kind = SYM_NONE;
   bool fermionic = false;
   uint64_t coef_seed = 0;
+  // GEMM tile selection: a tuned tile for the step's signature when the
+  // table has one; else, with tile_rank >= 0, that candidate of the padding
+  // model's ranking (autotuning runs); else the model's first choice
+  const TuneTable* tune = nullptr;
+  int tile_rank = -1;
 };
 
 // One block-pair product inside a GEMM job. Offsets are element offsets
@@ -128,6 +140,9 @@ struct GemmPlan {
   int64_t b_extent = 0;
   int64_t c_extent = 0;
   int mt = 64, nt = 64;    // tile used for the jobs
+  // signature of the step's shape (step, operand roles, output block sizes
+  // and contracted extents): the key of tuned tiles
+  uint64_t sig = 0;
   double bytes = 0;        // algorithmic: distinct A, B blocks read once, C written once
   // split-K: when partial_size > 0 every job writes a row-major part of its
   // output block into a partial buffer of that many elements, and
@@ -141,6 +156,13 @@ struct GemmPlan {
 // contracted extent summed over each block's pairs.
 void choose_tile(const std::vector<std::pair<int64_t, int64_t>>& mn,
                  const std::vector<int64_t>& ktot, int* mt, int* nt);
+// The tiles the autotuner tries, best first by the padding model: its first
+// choice, then the other tiles within 30% of the best padding efficiency in
+// order of efficiency (at most ``max_n``).
+std::vector<std::array<int, 2>> tile_candidates(const std::vector<std::pair<int64_t, int64_t>>& mn,
+                                                const std::vector<int64_t>& ktot, int max_n);
+// Whether (mt, nt) is one of the GEMM kernel's tile shapes.
+bool valid_tile(int mt, int nt);
 
 // Per-pair scalar of a chain step: synthetic recoupling coefficient (SU(2))
 // times the parity sign. ``xlabs`` are the labels of the sketch-side
