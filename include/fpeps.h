@@ -136,10 +136,12 @@ typedef struct {
   int32_t fermionic;      /* 1: parity sign on every contracted block pair */
   uint64_t coef_seed;     /* SU(2): key of the synthetic recoupling scalars */
   int64_t slice_budget;   /* bytes of chain intermediates live at once, over all streams
-                             (0: 64 GiB). The slices of a site are spread round-robin over
-                             four streams, so every slice is sized for a quarter of it
-                             (also with FPEPS_FLAG_ONE_STREAM, so that the slicing does
-                             not depend on the streams) */
+                             (0: a budget tuned by fpeps_autotune_absorb, else the smaller
+                             of 128 GiB and 45% of the device's memory). The slices of a
+                             site are spread round-robin over four streams, so every
+                             slice is sized for a quarter of it (also with
+                             FPEPS_FLAG_ONE_STREAM, so that the slicing does not depend
+                             on the streams) */
   uint32_t flags;         /* FPEPS_FLAG_* */
   int32_t tag;            /* explicit-matrix calls: counter word c2 of the sketch */
   double sv_cut;          /* singular values <= sv_cut * largest are never kept. <= 0: the
@@ -241,7 +243,8 @@ fpeps_status fpeps_env_absorb(fpeps_ctx ctx, int32_t L, const fpeps_tensor* env_
 
 /* fpeps_env_absorb with its slice budget and GEMM tiles chosen by
  * measurement on this row (the autotuner). When opts->slice_budget is 0 the
- * row is first absorbed once per budget candidate (16, 32 and 64 GiB) on the
+ * row is first absorbed once per budget candidate (32 GiB and 64 GiB when
+ * below the default of fpeps_opts.slice_budget, and that default) on the
  * library's streams and the fastest is kept. Then, at that budget, it is
  * absorbed tile_candidates times (1 to 4) on one stream with every GEMM
  * launch timed: run r gives every grouped GEMM step the r-th tile of the

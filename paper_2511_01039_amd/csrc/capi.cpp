@@ -185,9 +185,9 @@ fpeps_status fpeps_site_apply(fpeps_ctx ctx, const fpeps_tensor* R, const fpeps_
       if (v < 0) return fp::fail(FPEPS_ERR_ARG, "negative width");
     fp::SiteOp::Plans pl;
     // one budget for the chain intermediates of all streams: up to
-  // max_streams slices are live at once, each within its share
-  const int64_t budget = std::max<int64_t>(
-      1, (opts->slice_budget > 0 ? opts->slice_budget : ((int64_t)64 << 30)) / std::max(1, ctx->max_streams));
+    // max_streams slices are live at once, each within its share
+    const int64_t budget =
+        std::max<int64_t>(1, ctx->total_budget(opts) / std::max(1, ctx->max_streams));
     ctx->peak_ws = 0;
     ctx->nslices = 0;
     FP_TRY(op.plan(ctx, kk, budget, pl, transpose != 0, opts->precision == FPEPS_FP32));

@@ -192,6 +192,25 @@ fp::Status fpeps_ctx_s::upload(const std::string& name, const void* host, size_t
   return upload_region(name, (const char*)host, bytes, dev);
 }
 
+int64_t fpeps_ctx_s::default_budget() {
+  if (mem_total == 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      (void)hipGetLastError();
+      tot = 0;
+    }
+    mem_total = tot > 0 ? tot : ((size_t)64 << 30) * 2;   // unknown: 64 GiB below
+  }
+  const int64_t cap = (int64_t)128 << 30;
+  return std::min<int64_t>(cap, (int64_t)(0.45 * (double)mem_total));
+}
+
+int64_t fpeps_ctx_s::total_budget(const fpeps_opts* o) {
+  if (o && o->slice_budget > 0) return o->slice_budget;
+  if (tune && tune->slice_budget > 0) return tune->slice_budget;
+  return default_budget();
+}
+
 fp::Status fpeps_ctx_s::sync() {
   FP_HIP(hipStreamSynchronize(stream));
   if (time_kernels && evused) return harvest_timing();

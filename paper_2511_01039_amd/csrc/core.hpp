@@ -132,6 +132,16 @@ struct fpeps_ctx_s {
   std::vector<std::array<int, 2>> evtile;
   // signature -> tile -> {seconds, launches}
   std::map<uint64_t, std::map<std::array<int, 2>, std::array<double, 2>>> tune_log;
+  // Bytes of chain intermediates the slices of a call may hold at once (all
+  // streams): the caller's opts->slice_budget, else the tuned budget, else
+  // default_budget().
+  int64_t total_budget(const fpeps_opts* o);
+  // min(128 GiB, 45% of the device's memory): larger slices mean fewer,
+  // larger launches (a config-4 row: 64 GiB 13.6 s, 96 GiB 12.9 s, 128 GiB
+  // 12.7 s), and the rest of the memory stays for the caller and the
+  // remaining workspace
+  int64_t default_budget();
+  size_t mem_total = 0;   // device memory in bytes (queried once)
   // the SymInfo fields the planner takes from the context
   void tune_into(fp::SymInfo& s) const {
     s.tune = tune.get();

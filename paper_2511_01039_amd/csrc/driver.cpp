@@ -1050,13 +1050,9 @@ Status absorb_row(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in, const fpe
   if (sym.kind < 0 || sym.kind > 2) return fail(FPEPS_ERR_ARG, "bad symmetry");
   const int nlab = sym.kind == SYM_U1U1 ? 2 : 1;
   // one budget for the chain intermediates of all streams: up to
-  // max_streams slices are live at once, each within its share (the
-  // caller's, else the tuned one, else 64 GiB)
-  const int64_t total_budget =
-      o->slice_budget > 0 ? o->slice_budget
-                          : (ctx->tune && ctx->tune->slice_budget > 0 ? ctx->tune->slice_budget
-                                                                      : ((int64_t)64 << 30));
-  const int64_t budget = std::max<int64_t>(1, total_budget / std::max(1, ctx->max_streams));
+  // max_streams slices are live at once, each within its share
+  const int64_t budget =
+      std::max<int64_t>(1, ctx->total_budget(o) / std::max(1, ctx->max_streams));
   ctx->diag.assign(L, SiteDiag());
   ctx->peak_ws = 0;
   ctx->nslices = 0;

@@ -6,8 +6,9 @@
 // the library's streams. Every grouped GEMM step can run with any of the
 // kernel's tile shapes; the planner's padding model ranks them. Both choices
 // are measured here:
-//   1. the row is absorbed once per slice-budget candidate (library streams,
-//      the model's tiles) and the fastest budget is kept;
+//   1. the row is absorbed once per slice-budget candidate (32 and 64 GiB
+//      and the library's default, on the library's streams, with the
+//      model's tiles) and the fastest budget is kept;
 //   2. at that budget the row is absorbed once per tile rank (one stream,
 //      every GEMM launch timed by HIP events; rank r makes every step use
 //      the r-th tile of the model's ranking), and each step signature keeps
@@ -54,7 +55,12 @@ Status autotune_absorb(fpeps_ctx_s* ctx, int L, const fpeps_tensor* env_in,
   auto tab = std::make_shared<TuneTable>();
   // 1. slice budget (only when the caller leaves it to the library)
   if (o->slice_budget <= 0) {
-    static const int64_t cand[] = {(int64_t)16 << 30, (int64_t)32 << 30, (int64_t)64 << 30};
+    // 32 and 64 GiB, and the default (128 GiB on a 288 GB device); none above it
+    const int64_t dflt = ctx->default_budget();
+    std::vector<int64_t> cand;
+    for (int64_t b : {(int64_t)32 << 30, (int64_t)64 << 30})
+      if (b < dflt) cand.push_back(b);
+    cand.push_back(dflt);
     double best = std::numeric_limits<double>::infinity();
     int64_t best_b = 0;
     for (int64_t b : cand) {

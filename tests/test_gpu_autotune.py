@@ -75,7 +75,8 @@ def test_autotuned_row(ctx, tmp_path):
     n, budget = ctx.tune_info()
     print(f"tuned signatures {n}, slice budget {budget / GIB:.0f} GiB, "
           f"final run {rep['seconds'] * 1e3:.2f} ms")
-    assert n > 0 and budget in (16 * GIB, 32 * GIB, 64 * GIB)
+    # one of the candidates: 32 GiB, 64 GiB or the default (<= 128 GiB)
+    assert n > 0 and (budget in (32 * GIB, 64 * GIB) or 0 < budget <= 128 * GIB)
     check_against_oracle(ctx, row, out, glg, env, lg, info)
     # later absorptions use the table: the same result as the tuned run
     out2, glg2, _ = ctx.env_absorb(T, A, W, opts)
