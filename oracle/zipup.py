@@ -286,7 +286,7 @@ def cbe_site(sp, Umats, Rmats, sig, kept, cbe_extra, p, seed, x, row, labels, sv
 
 def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0.0,
                bra=None, record=None, max_cols=None, progress=None, sv_cut=None, workers=1,
-               cbe_extra=0):
+               cbe_extra=0, stop_after=None):
     """Absorb one row (ket A[x], PEPO W[x]) into the top environment T[x].
 
     Returns (new environment sites, log_norm, info). With ``exact_svd`` the
@@ -294,7 +294,10 @@ def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0
     (truncated SVD), which bounds the error of the randomized version.
     The sketch width of a sector starts from the previous site's kept count
     for the same sector label (the proportional share at the first site and
-    for new labels); see ``rsvd``. ``sv_cut`` replaces the rank floor."""
+    for new labels); see ``rsvd``. ``sv_cut`` replaces the rank floor.
+    ``stop_after`` = s ends the absorption after the truncation of site s - 1
+    (interior sites only; the results of sites 0 .. s-1 are those of the
+    whole row, and the returned environment is partial)."""
     L = len(T)
     R = trivial_remainder(sym, T[0], A[0], W[0])
     env = []
@@ -376,4 +379,6 @@ def absorb_row(sym, T, A, W, chi, p, q, seed, row=0, exact_svd=False, log_norm=0
             record.append(dict(x=x, sp=sp, kvec=kvec,
                                passes=info["passes"][-1] if not exact_svd else [(kvec, kept)],
                                cbe_passes=cbe_passes, cbe_kept=list(cbe_e)))
+        if stop_after is not None and x + 1 >= stop_after:
+            break
     return env, log_norm, info

@@ -5,15 +5,18 @@ Calls only the FP64 oracle (oracle/) and the seeded input generators
 file this writes; nothing in it comes from the device path.
 
     python tests/golden/make_row_golden.py --config 2 [--max-cols 8] [--workers 6]
+    python tests/golden/make_row_golden.py --config 4 --sites 2 --workers 6
 
 Stored: per site the kept count and the sketch width of every sector, the
 singular values of every sector, the log-norm, and the gauge-invariant
 network value s_row = <new environment | bottom> for a seeded random bottom
 environment (bond = the environment catalogue of the configuration, seed 5).
 
-Committed rows: config 2 (about 30 min on 8 host cores). A config-4 row is
-out of reach of the oracle on such a host (about 1.5 h per site at sketch
-widths near 570); at that shape the parity tests check sampled columns of a
+Committed rows: config 2 (about 30 min on 8 host cores). A whole config-4
+row is out of reach of the oracle on such a host (about 1.5 h per site at
+sketch widths near 570). ``--sites 2`` stores its first two sites instead
+(kept counts, widths and singular values; the sites' results do not depend
+on the later sites). Beside it, the parity tests check sampled columns of a
 full-size site and the chi = 500 lattice whose boundary MPS is exact.
 """
 from __future__ import annotations
@@ -54,6 +57,9 @@ def main():
                     help="sectors evaluated in this many processes (same results)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--sites", type=int, default=0,
+                    help="stop after this many sites (their kept counts and singular values "
+                         "are those of the whole row); 0: the whole row")
     a = ap.parse_args()
     t0 = time.time()
     row, bond = problem(a.config)
@@ -62,7 +68,24 @@ def main():
     record = []
     env, lg, info = absorb_row(row.sym, row.T, row.A, row.W, row.chi, row.oversample,
                                row.power_iters, a.seed, row=row.row, record=record,
-                               max_cols=a.max_cols, progress=log, workers=a.workers)
+                               max_cols=a.max_cols, progress=log, workers=a.workers,
+                               stop_after=a.sites or None)
+    if a.sites:
+        out = dict(config=a.config, seed=a.seed, chi=row.chi, oversample=row.oversample,
+                   power_iters=row.power_iters, row=row.row, sites=a.sites,
+                   cpu_seconds=time.time() - t0,
+                   kept=[[int(k) for k in ks] for ks in info["kept"]],
+                   k=[[int(k) for k in ks] for ks in info["k"]],
+                   m=[[int(k) for k in ks] for ks in info["m"]],
+                   n=[[int(k) for k in ks] for ks in info["n"]],
+                   gap=[float(g) for g in info["gap"]],
+                   sigma=[[list(map(float, s)) for s in ss] for ss in info["sigma"]])
+        path = a.out or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                     f"config{a.config}_row_sites{a.sites}.json")
+        with open(path, "w") as f:
+            json.dump(out, f)
+        log(f"wrote {path}: first {a.sites} sites")
+        return
     log("absorbed; flops and network value")
     flops = row_flops(record, info, row.power_iters)
     bot = wl.random_bottom_env(row.sym, env, bond, np.random.default_rng(5))

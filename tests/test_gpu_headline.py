@@ -144,3 +144,40 @@ def mirror(env):
             [Leg(t.legs[4].labels, t.legs[4].dims, -t.legs[4].dir)]
         out.append(Tensor(legs, t.blocks, t.offsets, t.data))
     return out
+
+
+SITE_GOLDENS = [c for c in sorted(ROWS)
+                if os.path.exists(os.path.join(GOLDEN, f"config{c}_row_sites2.json"))]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("cfg", SITE_GOLDENS)
+def test_row_first_sites_match_golden(ctx, cfg, precision):
+    """The headline row at full size (config 4: 8x8 SU(2)-synthetic, D = 6,
+    chi = 500, p = 20, q = 2) absorbed on the device, against the oracle's
+    first two sites of the same row (the whole row is out of the oracle's
+    reach on the host): the kept count of every sector exact (in mixed
+    precision when the cut's smallest relative gap g exceeds 1e-5, so that
+    rounding cannot move it), and the singular values of every sector within
+    1e-10 of the largest in FP64 (max(1e-6, 2^-24 / g) in mixed precision)."""
+    from paper_2511_01039_amd import opts_for
+    g = json.load(open(os.path.join(GOLDEN, f"config{cfg}_row_sites2.json")))
+    name, _ = ROWS[cfg]
+    row = getattr(wl, name)()
+    out, lg, rep = ctx.env_absorb(dev(row.T), dev(row.A), dev(row.W),
+                                  opts_for(row.sym, chi=g["chi"], oversample=g["oversample"],
+                                           power_iters=g["power_iters"], seed=g["seed"],
+                                           row=g["row"], precision=precision))
+    fp64 = precision == "fp64"
+    gaps = [x for x in g["gap"] if np.isfinite(x)]
+    tol = 1e-10 if fp64 else max(1e-6, 2.0 ** -24 / max(min(gaps) if gaps else 1.0, 1e-300))
+    for x in range(g["sites"]):
+        sig, sec, kept = ctx.absorb_diag(x)
+        if fp64 or (gaps and min(gaps) > 1e-5):
+            assert [int(v) for v in kept] == g["kept"][x], x
+        want = np.concatenate([np.asarray(s) for s in g["sigma"][x]])
+        assert sig.shape == want.shape, x
+        err = float(np.abs(sig - want).max() / want.max())
+        print(f"config {cfg} {precision} site {x}: kept {sum(g['kept'][x])}, sigma max diff "
+              f"{err:.2e} of the largest (bound {tol:.1e}), row {rep['seconds']:.2f} s")
+        assert err < tol

@@ -110,3 +110,21 @@ def test_sign_gauge_rule():
     assert np.array_equal(U2[:, 2], U[:, 2]) and np.array_equal(R2[2], R[2])
     assert np.array_equal(U2[:, :2], -U[:, :2]) and np.array_equal(R2[:2], -R[:2])
     assert np.allclose(U2 @ R2, U @ R, rtol=0, atol=0)
+
+
+def test_partial_row_equals_the_whole_row_prefix():
+    """Stopping the absorption after s sites (used for the first sites of a
+    row too large for the oracle) gives those sites' kept counts, widths and
+    singular values exactly as the whole row does: a site depends only on the
+    sites to its left."""
+    from oracle.zipup import absorb_row
+    row = wl.small_row("su2", L=4, seed=3, oversample=4, power_iters=1, env_scale=3, virt_scale=2)
+    _, _, full = absorb_row(row.sym, row.T, row.A, row.W, 10, 4, 1, 17, row=row.row)
+    env, _, part = absorb_row(row.sym, row.T, row.A, row.W, 10, 4, 1, 17, row=row.row,
+                              stop_after=2)
+    assert len(env) == 2 and len(part["kept"]) == 2
+    for x in range(2):
+        assert list(part["kept"][x]) == list(full["kept"][x])
+        assert list(part["k"][x]) == list(full["k"][x])
+        for a, b in zip(part["sigma"][x], full["sigma"][x]):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
