@@ -16,8 +16,10 @@ Committed rows: config 2 (about 30 min on 8 host cores). A whole config-4
 row is out of reach of the oracle on such a host (about 1.5 h per site at
 sketch widths near 570). ``--sites 2`` stores its first two sites instead
 (kept counts, widths and singular values; the sites' results do not depend
-on the later sites). Beside it, the parity tests check sampled columns of a
-full-size site and the chi = 500 lattice whose boundary MPS is exact.
+on the later sites), on a host with more cores: on 8 cores the oracle's
+site 1 ran for more than 3.8 hours. The parity tests check sampled
+columns of a full-size site and the chi = 500 lattice whose boundary MPS is
+exact.
 """
 from __future__ import annotations
 
